@@ -1,0 +1,246 @@
+"""Seeded synthetic inputs: gas parameters and FP64 primitive initial states.
+
+This module holds only input recipes (random draws, sinusoids, spectra).  It
+contains none of the scheme's arithmetic, so the oracle and the HIP path can
+both be fed from it.  Every array is primitive and FP64, laid out as
+``W[5, ny, nx]`` = (rho, u, v, p, E_nu) with cell (j, k) centred at
+``((j + 1/2) h, (k + 1/2) h)``; a 1D state has ``ny == 1`` and ``v == 0``.
+
+The paper runs no public dataset; all of its test problems are defined by
+formulas.  The five workloads below follow the parameter sets of the solver
+specification (1D acoustic mode, 1D multi-mode, 2D random field, a batch of
+uneven 1D instances and a served request stream); units are those of the
+paper's section 2.3 (rho_0, p_0, sqrt(p_0/rho_0)), so rho_0 = p_0 = R = T_0 = 1.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+SEED_BASE = 1805034420
+
+# Base gas of the workloads: eqs. (5)-(7) with the closures (6).
+BASE_GAS = dict(gamma=1.4, R=1.0, Cv=1.0, rho0=1.0, T0=1.0,
+                tau0=0.05, tau_rho=-1.0, tau_T=-1.0,
+                Q0=0.1, Q_rho=0.5, Q_T=1.0,
+                I0=0.1, I_rho=1.0, I_T=2.0,
+                fx=0.0, fy=0.0)
+CFL = 0.4
+
+
+def rng(config_index: int) -> np.random.Generator:
+    """PCG64 stream of one workload (config_index counts from 1)."""
+    return np.random.Generator(np.random.PCG64(SEED_BASE + int(config_index)))
+
+
+def background(gas: dict) -> dict:
+    """Uniform background: rho0, u = v = 0, p = R rho0 T0 and the vibrational
+    energy at which relaxation balances the pump in eq. (4):
+    E_nu0 = rho0 Cv T0 + rho0 tau0 Q0 (steady when Q0 = I0 in eq. (3))."""
+    rho0, T0 = gas["rho0"], gas["T0"]
+    p0 = gas["R"] * rho0 * T0
+    ev0 = rho0 * gas["Cv"] * T0 + rho0 * gas["tau0"] * gas["Q0"]
+    return dict(rho=rho0, p=p0, ev=ev0)
+
+
+def uniform_state(gas: dict, nx: int, ny: int = 1) -> np.ndarray:
+    b = background(gas)
+    W = np.zeros((5, ny, nx))
+    W[0] = b["rho"]
+    W[3] = b["p"]
+    W[4] = b["ev"]
+    return W
+
+
+def cell_centres(n: int, L: float = 1.0) -> np.ndarray:
+    h = L / n
+    return (np.arange(n) + 0.5) * h
+
+
+def _apply_density_perturbation(gas: dict, W: np.ndarray, drho: np.ndarray,
+                                du: np.ndarray | None = None) -> np.ndarray:
+    """Isentropic (frozen) companion of a density perturbation: dp = c^2 drho
+    with c^2 = gamma p0 / rho0, specific vibrational energy E_nu/rho unchanged."""
+    b = background(gas)
+    c2 = gas["gamma"] * b["p"] / b["rho"]
+    W[0] = b["rho"] + drho
+    W[3] = b["p"] + c2 * drho
+    W[4] = b["ev"] * (W[0] / b["rho"])
+    if du is not None:
+        W[1] = du
+    return W
+
+
+def acoustic_mode_1d(gas: dict, n: int, mode: int, amp: float,
+                     mode_vector=None) -> np.ndarray:
+    """One right-going sound wave of wavenumber k = 2 pi mode on [0, 1).
+
+    By default the frozen isentropic wave: drho = amp sin(k x), u = c drho/rho0,
+    dp = c^2 drho, E_nu/rho unchanged.  ``mode_vector`` may instead give the
+    complex amplitudes (rho, u, p, E_nu) of any linear mode, normalised so that
+    the density amplitude is ``amp``: field = Re(a exp(i k x)) with a the vector
+    times -i (so that the density is amp sin(k x) for a real density entry)."""
+    x = cell_centres(n)
+    W = uniform_state(gas, n)
+    k = 2.0 * math.pi * mode
+    if mode_vector is None:
+        b = background(gas)
+        c = math.sqrt(gas["gamma"] * b["p"] / b["rho"])
+        drho = amp * np.sin(k * x)
+        _apply_density_perturbation(gas, W.reshape(5, n), drho, c * drho / b["rho"])
+        return W
+    v = np.asarray(mode_vector, dtype=np.complex128)
+    v = v / v[0] * amp
+    phase = np.exp(1j * k * x) * (-1j)
+    b = background(gas)
+    W[0, 0] = b["rho"] + np.real(v[0] * phase)
+    W[1, 0] = np.real(v[1] * phase)
+    W[3, 0] = b["p"] + np.real(v[2] * phase)
+    W[4, 0] = b["ev"] + np.real(v[3] * phase)
+    return W
+
+
+def multimode_1d(gas: dict, n: int, r: np.random.Generator, nmodes: int = 64,
+                 kmax: int = 256, sigma: float = 1e-4) -> np.ndarray:
+    """Sum of ``nmodes`` distinct integer modes drawn from 1..kmax with phases
+    U[0, 2 pi) and amplitudes N(0, sigma), on the density; isentropic companion."""
+    x = cell_centres(n)
+    modes = np.sort(r.choice(np.arange(1, kmax + 1), size=nmodes, replace=False))
+    phases = r.uniform(0.0, 2.0 * math.pi, size=nmodes)
+    amps = r.normal(0.0, sigma, size=nmodes)
+    drho = np.zeros(n)
+    for m, ph, a in zip(modes, phases, amps):
+        drho += a * np.sin(2.0 * math.pi * m * x + ph)
+    W = uniform_state(gas, n)
+    _apply_density_perturbation(gas, W.reshape(5, n), drho)
+    return W
+
+
+def random_field_2d(gas: dict, n: int, r: np.random.Generator, kmax: int = 64,
+                    rms: float = 1e-3, slope: float = -2.0) -> np.ndarray:
+    """Isotropic Gaussian random density field on an n x n periodic grid:
+    integer wave-vectors with 1 <= |k| <= kmax, complex normal coefficients of
+    variance |k|^slope, Hermitian by taking the real part of the inverse FFT,
+    rescaled to the requested rms; isentropic pressure, v = 0."""
+    kx = np.fft.fftfreq(n, d=1.0 / n)
+    KX, KY = np.meshgrid(kx, kx, indexing="xy")
+    kk = np.sqrt(KX * KX + KY * KY)
+    mask = (kk >= 1.0) & (kk <= kmax)
+    amp = np.zeros((n, n))
+    amp[mask] = kk[mask] ** (slope / 2.0)
+    coef = (r.normal(size=(n, n)) + 1j * r.normal(size=(n, n))) * amp
+    field = np.real(np.fft.ifft2(coef))
+    field *= rms / np.sqrt(np.mean(field * field))
+    W = np.zeros((5, n, n))
+    b = background(gas)
+    W[0] = b["rho"]
+    W[3] = b["p"]
+    W[4] = b["ev"]
+    _apply_density_perturbation(gas, W.reshape(5, n * n), field.reshape(-1))
+    return W
+
+
+def riemann_tophat(gas: dict, n: int, left: tuple, right: tuple) -> np.ndarray:
+    """Two Riemann problems on a periodic [0, 1): state ``left`` (rho, u, p, E_nu)
+    on [1/4, 3/4) and ``right`` elsewhere, so that the interface at x = 3/4 is a
+    left/right problem and the one at 1/4 its mirror image."""
+    x = cell_centres(n)
+    inner = (x >= 0.25) & (x < 0.75)
+    W = np.zeros((5, 1, n))
+    for c, (a, b) in zip((0, 1, 3, 4), zip(left, right)):
+        W[c, 0] = np.where(inner, a, b)
+    return W
+
+
+def blast_waves_1d(n: int) -> np.ndarray:
+    """Two interacting blast waves of section 2.4 (rho = 1, u = 0; p = 1000 on
+    [0, 0.1), 0.01 on [0.1, 0.9], 100 on (0.9, 1]), no vibrational energy."""
+    x = cell_centres(n)
+    W = np.zeros((5, 1, n))
+    W[0, 0] = 1.0
+    W[3, 0] = np.where(x < 0.1, 1000.0, np.where(x <= 0.9, 0.01, 100.0))
+    return W
+
+
+# ------------------------------------------------------------------ workloads
+
+def workload_1d_acoustic():
+    """1D periodic, 1024 cells, FP64, one acoustic mode k = 2 pi * 4, amplitude
+    1e-3, base gas, 2000 steps."""
+    gas = dict(BASE_GAS)
+    W = acoustic_mode_1d(gas, 1024, 4, 1e-3)
+    return dict(name="1d_acoustic_n1024", gas=gas, W=W, nx=1024, ny=1, steps=2000,
+                precision="fp64")
+
+
+def workload_1d_multimode(n: int = 1 << 20):
+    """1D periodic, 2^20 cells, Q_T = 2, 64 random modes in 1..256 with N(0, 1e-4)
+    amplitudes, 20000 steps."""
+    gas = dict(BASE_GAS, Q_T=2.0)
+    W = multimode_1d(gas, n, rng(2))
+    return dict(name=f"1d_multimode_n{n}", gas=gas, W=W, nx=n, ny=1, steps=20000,
+                precision="fp32")
+
+
+def workload_2d_random(n: int = 4096):
+    """2D periodic n x n (4096^2), Q_T = 2, isotropic k^-2 density field with
+    |k| <= 64 and rms 1e-3, 5000 steps."""
+    gas = dict(BASE_GAS, Q_T=2.0)
+    W = random_field_2d(gas, n, rng(3))
+    return dict(name=f"2d_random_{n}x{n}", gas=gas, W=W, nx=n, ny=n, steps=5000,
+                precision="fp32")
+
+
+def batch_1d_instances(count: int = 512, nmin_log2: float = 10.0, nmax_log2: float = 16.0,
+                       steps: int = 10000):
+    """Batch of uneven 1D periodic instances: n log-uniform in [2^10, 2^16],
+    tau0 ~ U[0.005, 0.5], Q_T ~ U[0, 3], one acoustic mode m ~ U{1..16} of
+    amplitude 1e-3.  Returns a list of instance dicts (gas, W, nx, mode)."""
+    r = rng(4)
+    out = []
+    for i in range(count):
+        n = int(round(2.0 ** r.uniform(nmin_log2, nmax_log2)))
+        gas = dict(BASE_GAS, tau0=float(r.uniform(0.005, 0.5)), Q_T=float(r.uniform(0.0, 3.0)))
+        m = int(r.integers(1, 17))
+        W = acoustic_mode_1d(gas, n, m, 1e-3)
+        out.append(dict(gas=gas, W=W, nx=n, ny=1, mode=m, steps=steps))
+    return out
+
+
+def serve_trace(count: int = 2000, rate: float = 200.0, seed_offset: int = 0,
+                log2_1d=(12.0, 20.0), side_2d=(256.0, 2048.0), t_end=(0.1, 2.0),
+                frac_1d: float = 0.5):
+    """Served request stream: Poisson arrivals at ``rate`` per second; half 1D
+    (n log-uniform 2^12..2^20), half 2D (side log-uniform 256..2048); base gas
+    with Q_T = 2 and per-request tau0 ~ U[0.005, 0.5], Q_T ~ U[0, 3];
+    t_end ~ U[0.1, 2].  The initial data are drawn when a request is
+    materialised (``request_state``), from the request's own seed."""
+    r = rng(5 + seed_offset)
+    t = 0.0
+    reqs = []
+    for i in range(count):
+        t += r.exponential(1.0 / rate)
+        is1d = r.uniform() < frac_1d
+        if is1d:
+            nx = int(round(2.0 ** r.uniform(*log2_1d)))
+            ny = 1
+        else:
+            nx = int(round(2.0 ** r.uniform(math.log2(side_2d[0]), math.log2(side_2d[1]))))
+            ny = nx
+        gas = dict(BASE_GAS, Q_T=float(r.uniform(0.0, 3.0)), tau0=float(r.uniform(0.005, 0.5)))
+        reqs.append(dict(id=i, arrival=t, nx=nx, ny=ny, gas=gas,
+                         t_end=float(r.uniform(*t_end)),
+                         seed=int(r.integers(0, 2**31 - 1))))
+    return reqs
+
+
+def request_state(req: dict) -> np.ndarray:
+    """Initial state of one served request: a 1D multi-mode or 2D random field
+    drawn from the request's own seed (smaller spectra than the workloads so
+    that small grids resolve them)."""
+    r = np.random.Generator(np.random.PCG64(req["seed"]))
+    nx, ny = req["nx"], req["ny"]
+    if ny == 1:
+        return multimode_1d(req["gas"], nx, r, nmodes=16, kmax=min(256, nx // 8))
+    return random_field_2d(req["gas"], nx, r, kmax=min(64, nx // 8))
