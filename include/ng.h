@@ -1,0 +1,243 @@
+/*
+ * ng.h -- C ABI of the MI355X (gfx950) library for the Eulerian MUSCL step of a
+ * vibrationally excited gas.
+ *
+ * Method: S. S. Khrapov and A. V. Khoperskov, "Dynamics of unstable sound
+ * waves in a non-equilibrium medium at the nonlinear stage", J. Phys.: Conf.
+ * Ser. 973 (2018) 012007, arXiv:1805.03442.  The model is eqs. (1)-(5)
+ * (continuity, momentum, total energy, vibrational energy) with the closures
+ * (6) and the ideal-gas EOS (7); the step is the MUSCL predictor-corrector of
+ * eq. (15) with the limited linear face states of eq. (14) (xi = 0), the HLL
+ * flux of eq. (13) or the HLLC flux, and the time step of eq. (16).
+ *
+ * Conventions for every call:
+ *   - return NG_OK (0) on success or a negative NG_E* code; the text of the
+ *     last failure of an object is available from ng_last_error /
+ *     ng_batch_last_error (NULL objects: ng_strerror of the code);
+ *   - host pointers are plain C arrays owned by the caller; they are read or
+ *     written only during the call;
+ *   - device memory (dev_buf) and the HIP stream (hip_stream, a hipStream_t,
+ *     NULL = the default stream) are owned by the caller and must outlive the
+ *     object; the library never allocates or frees device memory other than
+ *     a few bytes of pinned host memory for status read-back;
+ *   - work is enqueued on the caller's stream; calls documented as
+ *     "synchronising" wait for the stream; errors raised inside kernels
+ *     (non-positive density or pressure, non-finite values) are reported by the
+ *     next synchronising call as NG_EPHYS, and the object keeps the last state
+ *     that passed the check;
+ *   - objects are not thread-safe: one thread per object.
+ *
+ * Layout of the host state arrays (initial data and read-out): FP64, one plane
+ * per component, cell (j, k) at index k * nx + j, centred at ((j + 1/2) h,
+ * (k + 1/2) h).  Primitive arrays are (rho, u, [v], p, E_nu); conserved arrays
+ * are (rho, rho u, [rho v], E, E_nu); 1D problems have no v plane (4 planes),
+ * 2D problems have 5.
+ */
+#ifndef NG_H
+#define NG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------- error codes */
+#define NG_OK 0
+#define NG_EINVAL (-1)  /* invalid argument or parameter                      */
+#define NG_ENOMEM (-2)  /* device buffer smaller than required                 */
+#define NG_EPHYS (-3)   /* a step produced rho <= 0, p <= 0 or a non-finite value */
+#define NG_EDEVICE (-4) /* a HIP runtime call failed                           */
+#define NG_EFULL (-5)   /* batch: no free slot or no room in the arena         */
+
+/* ------------------------------------------------------- enumerated options */
+#define NG_BC_PERIODIC 0 /* wrap-around ghost cells (the only boundary in this build) */
+#define NG_HLLC 0        /* three-wave HLLC flux (contact resolved)            */
+#define NG_HLL 1         /* two-wave HLL flux, eq. (13)                         */
+#define NG_MINMOD 0      /* minmod-limited slopes in eq. (14)                   */
+#define NG_FP64 0        /* state, flux and sources in FP64                     */
+#define NG_FP32 1        /* FP32 deviations from a uniform reference state,
+                            FP64 totals and FP64 stiff relaxation factor      */
+
+/* status flags of ng_diag.flags */
+#define NG_FLAG_NONFINITE 1u
+#define NG_FLAG_RHO 2u      /* rho <= 0 somewhere */
+#define NG_FLAG_P 4u        /* p <= 0 somewhere   */
+#define NG_FLAG_DONE 8u     /* reached t_end or the step limit */
+
+/* Gas of eqs. (1)-(7).  E_nue = rho * Cv * T (so C_k of eq. (8) is Cv / R);
+ * tau = tau0 (rho/rho0)^tau_rho (T/T0)^tau_T, Q and I likewise (eq. (6));
+ * (fx, fy) is the specific external force f of eqs. (2)-(3). */
+typedef struct {
+    double gamma, R, Cv;
+    double rho0, T0;
+    double tau0, tau_rho, tau_T;
+    double Q0, Q_rho, Q_T;
+    double I0, I_rho, I_T;
+    double fx, fy;
+} ng_gas;
+
+/* Uniform grid of square cells of size h (section 2.3): ndim = 1 (ny = 1) or
+ * 2; bc[4] = (x-low, x-high, y-low, y-high) boundary kinds. */
+typedef struct {
+    int32_t ndim;
+    int32_t reserved;
+    int64_t nx, ny;
+    double h;
+    int32_t bc[4];
+} ng_grid;
+
+/* cfl multiplies the bound of eq. (16); stiff_z is the dt/tau above which the
+ * relaxation part of the E_nu update is integrated exactly (E_nue and tau
+ * frozen over the (half) step). */
+typedef struct {
+    double cfl;
+    int32_t riemann;   /* NG_HLLC or NG_HLL */
+    int32_t limiter;   /* NG_MINMOD         */
+    int32_t precision; /* NG_FP64 or NG_FP32 */
+    int32_t reserved;
+    double stiff_z;
+} ng_numerics;
+
+/* Diagnostics.  total[] = h^d * sum over cells of (rho, rho u, rho v, E, E_nu)
+ * accumulated in FP64 after the last step; src_budget[] = h^d * sum over steps
+ * and cells of dt * Y_E (the rho (Q - I + v.f) row of Y in eq. (15)) and of the
+ * E_nu source increment, so that total[3] - total0[3] = src_budget[0] and
+ * total[4] - total0[4] = src_budget[1] up to rounding on periodic grids;
+ * smax = max over cells of max(|v| + c, 2|v|) (eq. (16)) of the current state;
+ * rho_min and p_min over cells of the current state. */
+typedef struct {
+    double t, dt_last, dt_next;
+    int64_t steps;
+    double total[5];
+    double src_budget[2];
+    double rho_min, p_min, smax;
+    uint32_t flags;
+    int32_t status;
+} ng_diag;
+
+typedef struct ng_solver ng_solver;
+typedef struct ng_batch ng_batch;
+
+const char* ng_strerror(int code);
+
+/* ------------------------------------------------------------ one solve */
+
+/* Device bytes that ng_init_state needs for this grid and precision: two state
+ * buffers of (ndim + 3) planes plus per-step reduction space.  Returns NG_EINVAL
+ * for an invalid grid. */
+int ng_state_bytes(const ng_grid* grid, const ng_numerics* num, size_t* bytes);
+
+/* Create a solver on caller-owned device memory and upload the initial state.
+ *   prim:  host FP64 primitive planes (rho, u, [v], p, E_nu), layout above;
+ *   t0:    initial time;
+ *   dev_buf, dev_bytes: device memory of at least ng_state_bytes bytes,
+ *          256-byte aligned;
+ *   hip_stream: the stream every call of this solver enqueues on.
+ * Validates gamma > 1, R > 0, h > 0, n >= 4 per dimension, 0 < cfl < 1,
+ * tau0 > 0, and rho > 0, p > 0 and finite values in prim (NG_EINVAL);
+ * dev_bytes too small gives NG_ENOMEM.  Synchronising (computes the first dt
+ * and the initial totals). */
+int ng_init_state(const ng_gas* gas, const ng_grid* grid, const ng_numerics* num,
+                  const double* prim, double t0, void* dev_buf, size_t dev_bytes,
+                  void* hip_stream, ng_solver** out);
+
+/* Same from conserved planes (rho, rho u, [rho v], E, E_nu). */
+int ng_init_conserved(const ng_gas* gas, const ng_grid* grid, const ng_numerics* num,
+                      const double* cons, double t0, void* dev_buf, size_t dev_bytes,
+                      void* hip_stream, ng_solver** out);
+
+/* Enqueue nsteps steps of eq. (15), each with dt from eq. (16) evaluated on the
+ * state it starts from (no end time).  Asynchronous. */
+int ng_step(ng_solver* s, int64_t nsteps);
+
+/* Advance until t_end (the last dt is shortened to land on it) or until
+ * max_steps more steps, whichever comes first; steps run as captured HIP
+ * graphs whose kernels read t, dt and the stop condition from device memory.
+ * Synchronising; *steps_taken (may be NULL) receives the steps done. */
+int ng_run_to_time(ng_solver* s, double t_end, int64_t max_steps, int64_t* steps_taken);
+
+/* Diagnostics of the current state.  Synchronising. */
+int ng_diagnostics(ng_solver* s, ng_diag* out);
+
+/* Read the current state as FP64 primitive / conserved planes (whatever the
+ * run precision).  Synchronising. */
+int ng_get_state(ng_solver* s, double* prim_out);
+int ng_get_conserved(ng_solver* s, double* cons_out);
+
+/* Launch shape of the step kernel: rows per work item (2D) or 60-cell
+ * segments per work item (1D), and waves per workgroup.  Results do not
+ * depend on it (every cell's arithmetic is the same); only the order of the
+ * FP64 total sums does.  0 keeps the current value. */
+int ng_set_launch(ng_solver* s, int32_t rows_per_item, int32_t waves_per_block);
+
+/* Steps per captured graph in ng_run_to_time (default 64). */
+int ng_set_graph_steps(ng_solver* s, int32_t steps);
+
+/* Average duration in milliseconds of the step kernel over the last
+ * ng_step call, measured with HIP events around each launch when timing was
+ * enabled by ng_enable_timing(s, 1).  Synchronising. */
+int ng_enable_timing(ng_solver* s, int32_t on);
+int ng_kernel_time(ng_solver* s, double* step_ms, double* finalize_ms, int64_t* launches);
+
+const char* ng_last_error(const ng_solver* s);
+
+/* Free the host-side object.  Never frees dev_buf or the stream. */
+void ng_destroy(ng_solver* s);
+
+/* ------------------------------------------------- batches of many solves */
+/*
+ * A batch advances many independent solves of one precision -- any mix of 1D
+ * and 2D grids, sizes and gas parameters -- with one step kernel per dimension
+ * per step, each solve with its own dt, t, end time and totals.  Every solve's
+ * arithmetic is the same as when it runs alone, so its results do not depend
+ * on the batch composition.  Solves live in a caller-owned device arena; the
+ * batch sub-allocates it.
+ */
+
+/* capacity: maximum number of live solves; precision: NG_FP32 or NG_FP64;
+ * dev_buf/dev_bytes: the arena (256-byte aligned). */
+int ng_batch_create(int32_t capacity, int32_t precision, void* dev_buf, size_t dev_bytes,
+                    void* hip_stream, ng_batch** out);
+
+/* Device bytes one solve of this grid occupies in a batch arena. */
+int ng_batch_solve_bytes(const ng_grid* grid, int32_t precision, size_t* bytes);
+
+/* Add a solve (validation as ng_init_state; num->precision must match the
+ * batch).  It runs until t_end (> t0) or max_steps steps.  *slot receives its
+ * slot number.  NG_EFULL when no slot or arena space is free.  Synchronising. */
+int ng_batch_add(ng_batch* b, const ng_gas* gas, const ng_grid* grid, const ng_numerics* num,
+                 const double* prim, double t0, double t_end, int64_t max_steps,
+                 int32_t* slot);
+
+/* Enqueue nsteps steps of every unfinished solve (finished ones are skipped on
+ * the device).  Asynchronous. */
+int ng_batch_run(ng_batch* b, int64_t nsteps);
+
+/* Wait for the stream and list up to cap slots whose solve has finished
+ * (reached t_end or max_steps, or failed) and not yet been reported.
+ * Synchronising. */
+int ng_batch_poll(ng_batch* b, int32_t* done_slots, int32_t cap, int32_t* ndone);
+
+/* Number of live solves that have not finished.  Synchronising. */
+int ng_batch_active(ng_batch* b, int32_t* nactive);
+
+int ng_batch_diagnostics(ng_batch* b, int32_t slot, ng_diag* out);
+int ng_batch_get_state(ng_batch* b, int32_t slot, double* prim_out);
+int ng_batch_get_conserved(ng_batch* b, int32_t slot, double* cons_out);
+
+/* Release a slot and its arena space. */
+int ng_batch_remove(ng_batch* b, int32_t slot);
+
+/* Launch shape of the batched step kernels (see ng_set_launch). */
+int ng_batch_set_launch(ng_batch* b, int32_t dim, int32_t rows_per_item,
+                        int32_t waves_per_block);
+
+const char* ng_batch_last_error(const ng_batch* b);
+void ng_batch_destroy(ng_batch* b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NG_H */

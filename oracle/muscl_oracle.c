@@ -77,18 +77,31 @@ typedef struct {
 
 /* ---------------------------------------------------------------- closures */
 
+/* x^a for the power laws of eq. (6).  libm pow in general; for the exponents
+ * 0, 1, -1, 2 and 1/2 the correctly rounded IEEE operations 1, x, 1/x, x*x and
+ * sqrt(x), i.e. the exact power rounded once. */
+static double or_pow(double x, double a)
+{
+    if (a == 0.0) return 1.0;
+    if (a == 1.0) return x;
+    if (a == -1.0) return 1.0 / x;
+    if (a == 2.0) return x * x;
+    if (a == 0.5) return sqrt(x);
+    return pow(x, a);
+}
+
 /* eq. (6) */
 static double or_tau(const or_gas* g, double rho, double T)
 {
-    return g->tau0 * pow(rho / g->rho0, g->tau_rho) * pow(T / g->T0, g->tau_T);
+    return g->tau0 * or_pow(rho / g->rho0, g->tau_rho) * or_pow(T / g->T0, g->tau_T);
 }
 static double or_Q(const or_gas* g, double rho, double T)
 {
-    return g->Q0 * pow(rho / g->rho0, g->Q_rho) * pow(T / g->T0, g->Q_T);
+    return g->Q0 * or_pow(rho / g->rho0, g->Q_rho) * or_pow(T / g->T0, g->Q_T);
 }
 static double or_I(const or_gas* g, double rho, double T)
 {
-    return g->I0 * pow(rho / g->rho0, g->I_rho) * pow(T / g->T0, g->I_T);
+    return g->I0 * or_pow(rho / g->rho0, g->I_rho) * or_pow(T / g->T0, g->I_T);
 }
 
 /* conserved -> primitive, eq. (5) solved for p */

@@ -1,0 +1,1110 @@
+// ng_api.cpp -- the C ABI of include/ng.h: validation, device-memory layout
+// inside the caller's buffer, batch bookkeeping, step sequencing (direct
+// launches or captured HIP graphs) and state read-out.
+//
+// A single solve (ng_solver) is a batch of capacity one whose arena is exactly
+// ng_state_bytes long, so one code path serves both.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/ng.h"
+#include "ng_internal.hpp"
+#include "ng_launch.hpp"
+
+using namespace ng;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kMinRows2D = 4;        // smallest rows-per-item the partial space allows
+constexpr int kDefaultRows2D = 32;
+constexpr int kDefaultSegs1D = 8;
+constexpr int kDefaultWaves = 4;
+constexpr int kDefaultGraphSteps = 64;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+int ncomp(int ndim) { return ndim == 2 ? 5 : 4; }
+size_t real_size(int prec) { return prec == NG_FP32 ? 4 : 8; }
+
+int64_t strips_of(const ng_grid* g) { return cdiv(g->nx, kInterior); }
+
+// most workgroups any allowed launch shape gives this grid (1 wave per block,
+// smallest rows per item)
+int64_t partial_cap_of(const ng_grid* g)
+{
+    if (g->ndim == 2) return strips_of(g) * cdiv(g->ny, kMinRows2D);
+    return strips_of(g);
+}
+
+size_t state_plane_bytes(const ng_grid* g, int prec)
+{
+    return align_up((size_t)(g->nx * g->ny) * ncomp(g->ndim) * real_size(prec));
+}
+
+size_t solve_bytes(const ng_grid* g, int prec)
+{
+    return 2 * state_plane_bytes(g, prec) + align_up((size_t)partial_cap_of(g) * sizeof(Partial));
+}
+
+struct Layout {
+    size_t descs, ctrls, insts, blocks1, blocks2, heap;
+};
+
+Layout header_layout(int capacity, size_t tcap1, size_t tcap2)
+{
+    Layout L;
+    size_t o = 0;
+    L.descs = o;
+    o += align_up(sizeof(InstDesc) * capacity);
+    L.ctrls = o;
+    o += align_up(sizeof(InstCtrl) * capacity);
+    L.insts = o;
+    o += align_up(sizeof(int32_t) * 3 * capacity);
+    L.blocks1 = o;
+    o += align_up(sizeof(BlockRef) * tcap1);
+    L.blocks2 = o;
+    o += align_up(sizeof(BlockRef) * tcap2);
+    L.heap = o;
+    return L;
+}
+
+bool finite_pos(double x) { return isfinite(x) && x > 0.0; }
+
+int validate(const ng_gas* gas, const ng_grid* grid, const ng_numerics* num, std::string& err)
+{
+    if (!gas || !grid || !num) {
+        err = "null argument";
+        return NG_EINVAL;
+    }
+    const double gv[] = {gas->gamma, gas->R, gas->Cv, gas->rho0, gas->T0, gas->tau0,
+                         gas->tau_rho, gas->tau_T, gas->Q0, gas->Q_rho, gas->Q_T, gas->I0,
+                         gas->I_rho, gas->I_T, gas->fx, gas->fy};
+    for (double x : gv)
+        if (!isfinite(x)) {
+            err = "non-finite gas parameter";
+            return NG_EINVAL;
+        }
+    if (!(gas->gamma > 1.0)) { err = "gamma must exceed 1"; return NG_EINVAL; }
+    if (!(gas->R > 0.0)) { err = "R must be positive"; return NG_EINVAL; }
+    if (!(gas->Cv >= 0.0)) { err = "Cv must be non-negative"; return NG_EINVAL; }
+    if (!(gas->rho0 > 0.0) || !(gas->T0 > 0.0)) { err = "rho0 and T0 must be positive"; return NG_EINVAL; }
+    if (!(gas->tau0 > 0.0)) { err = "tau0 must be positive"; return NG_EINVAL; }
+    if (!(gas->Q0 >= 0.0) || !(gas->I0 >= 0.0)) { err = "Q0 and I0 must be non-negative"; return NG_EINVAL; }
+    if (grid->ndim != 1 && grid->ndim != 2) { err = "ndim must be 1 or 2"; return NG_EINVAL; }
+    if (grid->nx < 4 || (grid->ndim == 2 && grid->ny < 4) || (grid->ndim == 1 && grid->ny != 1)) {
+        err = "need nx >= 4 (and ny >= 4 in 2D, ny == 1 in 1D)";
+        return NG_EINVAL;
+    }
+    if (grid->nx > (1LL << 31) || grid->ny > (1LL << 31) || grid->nx * grid->ny > (1LL << 33)) {
+        err = "grid too large";
+        return NG_EINVAL;
+    }
+    if (!finite_pos(grid->h)) { err = "h must be positive"; return NG_EINVAL; }
+    for (int i = 0; i < 4; i++)
+        if (grid->bc[i] != NG_BC_PERIODIC) {
+            err = "only periodic boundaries are implemented";
+            return NG_EINVAL;
+        }
+    if (grid->ndim == 1 && gas->fy != 0.0) { err = "fy must be 0 in 1D"; return NG_EINVAL; }
+    if (!(num->cfl > 0.0 && num->cfl < 1.0)) { err = "cfl must lie in (0, 1)"; return NG_EINVAL; }
+    if (num->riemann != NG_HLLC && num->riemann != NG_HLL) { err = "unknown riemann solver"; return NG_EINVAL; }
+    if (num->limiter != NG_MINMOD) { err = "unknown limiter"; return NG_EINVAL; }
+    if (num->precision != NG_FP32 && num->precision != NG_FP64) { err = "unknown precision"; return NG_EINVAL; }
+    if (!(num->stiff_z >= 0.0)) { err = "stiff_z must be >= 0"; return NG_EINVAL; }
+    return NG_OK;
+}
+
+// E = p/(gamma-1) + rho |v|^2 / 2 + E_nu  (eq. (5)); host-side conversions
+void prim_to_cons_cell(double gm1, int nc, const double* W, double* U)
+{
+    if (nc == 5) {
+        double rho = W[0], u = W[1], v = W[2], p = W[3], e = W[4];
+        U[0] = rho;
+        U[1] = rho * u;
+        U[2] = rho * v;
+        U[3] = p / gm1 + 0.5 * rho * (u * u + v * v) + e;
+        U[4] = e;
+    } else {
+        double rho = W[0], u = W[1], p = W[2], e = W[3];
+        U[0] = rho;
+        U[1] = rho * u;
+        U[2] = p / gm1 + 0.5 * rho * (u * u) + e;
+        U[3] = e;
+    }
+}
+
+void cons_to_prim_cell(double gm1, int nc, const double* U, double* W)
+{
+    double rho = U[0];
+    double u = U[1] / rho;
+    if (nc == 5) {
+        double v = U[2] / rho;
+        double ke = 0.5 * rho * (u * u + v * v);
+        W[0] = rho;
+        W[1] = u;
+        W[2] = v;
+        W[3] = gm1 * (U[3] - ke - U[4]);
+        W[4] = U[4];
+    } else {
+        double ke = 0.5 * rho * (u * u);
+        W[0] = rho;
+        W[1] = u;
+        W[2] = gm1 * (U[2] - ke - U[3]);
+        W[3] = U[3];
+    }
+}
+
+struct Slot {
+    bool live = false;
+    int dim = 0;
+    InstDesc d{};
+    size_t off = 0, bytes = 0;
+    int64_t partial_cap = 0;
+    int64_t block_off = 0;  // first entry in the dim's block table
+    int pos = 0;            // index in the dim's instance list
+    bool reported = false;
+};
+
+}  // namespace
+
+struct ng_batch {
+    int capacity = 0;
+    int prec = 0;
+    char* arena = nullptr;
+    size_t arena_bytes = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    Layout L{};
+    size_t tcap[3] = {0, 0, 0};
+    std::vector<Slot> slots;
+    std::map<size_t, size_t> free_list;  // offset -> size
+    int rows[3] = {0, kDefaultSegs1D, kDefaultRows2D};
+    int waves[3] = {0, kDefaultWaves, kDefaultWaves};
+    int remap = 1;
+    int64_t nblocks[3] = {0, 0, 0};
+    int ninst[3] = {0, 0, 0};
+    bool dirty = true;
+    // captured step sequence
+    hipGraphExec_t gexec = nullptr;
+    int gsteps = 0;
+    int graph_steps = kDefaultGraphSteps;
+    // pinned read-back of the control blocks
+    InstCtrl* h_ctrls = nullptr;
+    std::vector<BlockRef> h_blocks[3];
+    std::vector<int32_t> h_insts;
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    double t_step_ms = 0.0, t_fin_ms = 0.0;
+    int64_t t_launches = 0;
+    std::string err;
+
+    InstDesc* d_descs() { return (InstDesc*)(arena + L.descs); }
+    InstCtrl* d_ctrls() { return (InstCtrl*)(arena + L.ctrls); }
+    int32_t* d_insts(int dim) { return (int32_t*)(arena + L.insts) + dim * capacity; }
+    BlockRef* d_blocks(int dim) { return (BlockRef*)(arena + (dim == 1 ? L.blocks1 : L.blocks2)); }
+};
+
+struct ng_solver {
+    ng_batch* b = nullptr;
+    int slot = 0;
+    std::string err;
+};
+
+namespace {
+
+int dev_err(ng_batch* b, hipError_t e, const char* what)
+{
+    b->err = std::string(what) + ": " + hipGetErrorString(e);
+    return NG_EDEVICE;
+}
+#define CK(b, call)                                         \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) return dev_err((b), e_, #call); \
+    } while (0)
+
+void drop_graph(ng_batch* b)
+{
+    if (b->gexec) {
+        (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+    }
+    b->gsteps = 0;
+}
+
+bool arena_alloc(ng_batch* b, size_t bytes, size_t* off)
+{
+    for (auto it = b->free_list.begin(); it != b->free_list.end(); ++it) {
+        if (it->second >= bytes) {
+            *off = it->first;
+            size_t rest = it->second - bytes;
+            size_t noff = it->first + bytes;
+            b->free_list.erase(it);
+            if (rest) b->free_list[noff] = rest;
+            return true;
+        }
+    }
+    return false;
+}
+
+void arena_free(ng_batch* b, size_t off, size_t bytes)
+{
+    auto it = b->free_list.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != b->free_list.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        b->free_list.erase(nx);
+    }
+    if (it != b->free_list.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            b->free_list.erase(it);
+        }
+    }
+}
+
+// Work decomposition of one solve for the current launch shape of its dim.
+void shape_solve(ng_batch* b, Slot& s)
+{
+    InstDesc& d = s.d;
+    int dim = s.dim;
+    d.waves_per_block = b->waves[dim];
+    d.rows_per_item = b->rows[dim];
+    d.nstrips = (int32_t)cdiv(d.nx, kInterior);
+    if (dim == 2)
+        d.nchunks = (int32_t)cdiv(d.ny, d.rows_per_item);
+    else
+        d.nchunks = (int32_t)cdiv(d.nstrips, d.rows_per_item);
+    d.nitems = dim == 2 ? (int64_t)d.nstrips * d.nchunks : (int64_t)d.nchunks;
+    d.nblocks = cdiv(d.nitems, d.waves_per_block);
+}
+
+// Rebuild the device tables (descriptors, per-dim solve lists and workgroup
+// maps) after the set of solves or a launch shape changed.  Synchronising.
+int rebuild(ng_batch* b)
+{
+    if (!b->dirty) return NG_OK;
+    std::vector<int32_t> insts(3 * b->capacity, 0);
+    for (int dim = 1; dim <= 2; dim++) {
+        b->h_blocks[dim].clear();
+        b->ninst[dim] = 0;
+    }
+    for (int i = 0; i < b->capacity; i++) {
+        Slot& s = b->slots[i];
+        if (!s.live) continue;
+        shape_solve(b, s);
+        if (s.d.nblocks > s.partial_cap) {
+            b->err = "launch shape needs more reduction records than reserved";
+            return NG_EINVAL;
+        }
+        auto& tab = b->h_blocks[s.dim];
+        s.block_off = (int64_t)tab.size();
+        for (int64_t j = 0; j < s.d.nblocks; j++) tab.push_back(BlockRef{i, (int32_t)j});
+        s.pos = b->ninst[s.dim];
+        insts[s.dim * b->capacity + b->ninst[s.dim]] = i;
+        b->ninst[s.dim]++;
+    }
+    for (int dim = 1; dim <= 2; dim++) {
+        if (b->h_blocks[dim].size() > b->tcap[dim]) {
+            b->err = "workgroup table capacity exceeded";
+            return NG_ENOMEM;
+        }
+        b->nblocks[dim] = (int64_t)b->h_blocks[dim].size();
+    }
+    std::vector<InstDesc> descs(b->capacity);
+    for (int i = 0; i < b->capacity; i++) descs[i] = b->slots[i].d;
+    CK(b, hipMemcpyAsync(b->d_descs(), descs.data(), sizeof(InstDesc) * b->capacity,
+                         hipMemcpyHostToDevice, b->stream));
+    CK(b, hipMemcpyAsync(b->arena + b->L.insts, insts.data(), sizeof(int32_t) * insts.size(),
+                         hipMemcpyHostToDevice, b->stream));
+    for (int dim = 1; dim <= 2; dim++)
+        if (!b->h_blocks[dim].empty())
+            CK(b, hipMemcpyAsync(b->d_blocks(dim), b->h_blocks[dim].data(),
+                                 sizeof(BlockRef) * b->h_blocks[dim].size(),
+                                 hipMemcpyHostToDevice, b->stream));
+    CK(b, hipStreamSynchronize(b->stream));
+    drop_graph(b);
+    b->dirty = false;
+    return NG_OK;
+}
+
+hipEvent_t get_event(ng_batch* b, size_t i)
+{
+    while (b->ev_pool.size() <= i) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        b->ev_pool.push_back(e);
+    }
+    return b->ev_pool[i];
+}
+
+// Enqueue the kernels of one step of every active solve on stream st.
+int enqueue_one(ng_batch* b, hipStream_t st)
+{
+    for (int dim = 1; dim <= 2; dim++) {
+        if (!b->ninst[dim]) continue;
+        CK(b, launch_step(dim, b->prec == NG_FP32 ? 1 : 0, b->d_descs(), b->d_ctrls(),
+                          b->d_blocks(dim), b->nblocks[dim], b->waves[dim], b->remap, st));
+        CK(b, launch_finalize(b->d_descs(), b->d_ctrls(), b->d_insts(dim), b->ninst[dim], 0, st));
+    }
+    return NG_OK;
+}
+
+// Timed variant: events around each step and finalize kernel.
+int enqueue_timed(ng_batch* b, int64_t nsteps)
+{
+    size_t ne = 0;
+    std::vector<std::pair<size_t, size_t>> step_pairs, fin_pairs;
+    for (int64_t i = 0; i < nsteps; i++) {
+        for (int dim = 1; dim <= 2; dim++) {
+            if (!b->ninst[dim]) continue;
+            hipEvent_t e0 = get_event(b, ne), e1 = get_event(b, ne + 1), e2 = get_event(b, ne + 2);
+            if (!e0 || !e1 || !e2) return dev_err(b, hipErrorOutOfMemory, "hipEventCreate");
+            CK(b, hipEventRecord(e0, b->stream));
+            CK(b, launch_step(dim, b->prec == NG_FP32 ? 1 : 0, b->d_descs(), b->d_ctrls(),
+                              b->d_blocks(dim), b->nblocks[dim], b->waves[dim], b->remap,
+                              b->stream));
+            CK(b, hipEventRecord(e1, b->stream));
+            CK(b, launch_finalize(b->d_descs(), b->d_ctrls(), b->d_insts(dim), b->ninst[dim], 0,
+                                  b->stream));
+            CK(b, hipEventRecord(e2, b->stream));
+            step_pairs.push_back({ne, ne + 1});
+            fin_pairs.push_back({ne + 1, ne + 2});
+            ne += 3;
+        }
+    }
+    CK(b, hipStreamSynchronize(b->stream));
+    double ts = 0.0, tf = 0.0;
+    for (auto& p : step_pairs) {
+        float ms = 0.f;
+        CK(b, hipEventElapsedTime(&ms, b->ev_pool[p.first], b->ev_pool[p.second]));
+        ts += ms;
+    }
+    for (auto& p : fin_pairs) {
+        float ms = 0.f;
+        CK(b, hipEventElapsedTime(&ms, b->ev_pool[p.first], b->ev_pool[p.second]));
+        tf += ms;
+    }
+    b->t_step_ms = step_pairs.empty() ? 0.0 : ts / step_pairs.size();
+    b->t_fin_ms = fin_pairs.empty() ? 0.0 : tf / fin_pairs.size();
+    b->t_launches = (int64_t)step_pairs.size();
+    return NG_OK;
+}
+
+int ensure_graph(ng_batch* b)
+{
+    if (b->gexec && b->gsteps == b->graph_steps) return NG_OK;
+    drop_graph(b);
+    if (!b->cap_stream) CK(b, hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+    CK(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = NG_OK;
+    for (int i = 0; i < b->graph_steps && rc == NG_OK; i++) rc = enqueue_one(b, b->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+    if (rc != NG_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return dev_err(b, e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        b->gexec = nullptr;
+        return dev_err(b, e, "hipGraphInstantiate");
+    }
+    b->gsteps = b->graph_steps;
+    return NG_OK;
+}
+
+// Enqueue nsteps steps: whole graphs, then single launches for the rest.
+int enqueue_steps(ng_batch* b, int64_t nsteps)
+{
+    int rc = rebuild(b);
+    if (rc) return rc;
+    if (b->timing) return enqueue_timed(b, nsteps);
+    int64_t left = nsteps;
+    if (left >= b->graph_steps) {
+        rc = ensure_graph(b);
+        if (rc) return rc;
+        while (left >= b->gsteps) {
+            CK(b, hipGraphLaunch(b->gexec, b->stream));
+            left -= b->gsteps;
+        }
+    }
+    for (int64_t i = 0; i < left; i++) {
+        rc = enqueue_one(b, b->stream);
+        if (rc) return rc;
+    }
+    return NG_OK;
+}
+
+int read_ctrls(ng_batch* b)
+{
+    CK(b, hipMemcpyAsync(b->h_ctrls, b->d_ctrls(), sizeof(InstCtrl) * b->capacity,
+                         hipMemcpyDeviceToHost, b->stream));
+    CK(b, hipStreamSynchronize(b->stream));
+    return NG_OK;
+}
+
+int set_limits(ng_batch* b, const std::vector<int32_t>& slots, double t_end, int64_t max_steps)
+{
+    if (slots.empty()) return NG_OK;
+    // the instance list of a dim lives in device memory; use a scratch copy of
+    // the requested slots in the unused third list
+    int32_t* dl = b->d_insts(0);
+    CK(b, hipMemcpyAsync(dl, slots.data(), sizeof(int32_t) * slots.size(), hipMemcpyHostToDevice,
+                         b->stream));
+    CK(b, launch_set_limits(b->d_ctrls(), dl, (int)slots.size(), t_end, max_steps, b->stream));
+    CK(b, hipStreamSynchronize(b->stream));
+    return NG_OK;
+}
+
+// Create the batch object over an arena (shared by ng_batch_create and the
+// single-solve constructor).
+int batch_new(int32_t capacity, int32_t precision, void* dev_buf, size_t dev_bytes,
+              void* hip_stream, size_t tcap1, size_t tcap2, ng_batch** out, std::string& err)
+{
+    if (capacity < 1 || !dev_buf || !out || (precision != NG_FP32 && precision != NG_FP64)) {
+        err = "invalid batch arguments";
+        return NG_EINVAL;
+    }
+    if (((uintptr_t)dev_buf) % kAlign) {
+        err = "device buffer must be 256-byte aligned";
+        return NG_EINVAL;
+    }
+    Layout L = header_layout(capacity, tcap1, tcap2);
+    if (dev_bytes < L.heap) {
+        err = "device buffer too small for the batch header";
+        return NG_ENOMEM;
+    }
+    ng_batch* b = new ng_batch();
+    b->capacity = capacity;
+    b->prec = precision;
+    b->arena = (char*)dev_buf;
+    b->arena_bytes = dev_bytes;
+    b->stream = (hipStream_t)hip_stream;
+    b->L = L;
+    b->tcap[1] = tcap1;
+    b->tcap[2] = tcap2;
+    b->slots.resize(capacity);
+    if (dev_bytes > L.heap) b->free_list[L.heap] = dev_bytes - L.heap;
+    hipError_t e = hipHostMalloc((void**)&b->h_ctrls, sizeof(InstCtrl) * capacity, 0);
+    if (e != hipSuccess) {
+        err = std::string("hipHostMalloc: ") + hipGetErrorString(e);
+        delete b;
+        return NG_EDEVICE;
+    }
+    // zero the control blocks so that unused slots are inert
+    std::vector<InstCtrl> z(capacity);
+    for (auto& c : z) {
+        memset(&c, 0, sizeof(c));
+        c.status = -1;
+    }
+    e = hipMemcpyAsync(b->d_ctrls(), z.data(), sizeof(InstCtrl) * capacity,
+                       hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        err = std::string("init: ") + hipGetErrorString(e);
+        (void)hipHostFree(b->h_ctrls);
+        delete b;
+        return NG_EDEVICE;
+    }
+    *out = b;
+    return NG_OK;
+}
+
+void fill_desc(InstDesc& d, const ng_gas* gas, const ng_grid* grid, const ng_numerics* num,
+               int prec)
+{
+    memset(&d, 0, sizeof(d));
+    d.nx = grid->nx;
+    d.ny = grid->ndim == 2 ? grid->ny : 1;
+    d.ncell = d.nx * d.ny;
+    d.ndim = grid->ndim;
+    d.riemann = num->riemann;
+    d.h = grid->h;
+    d.cfl = num->cfl;
+    d.stiff_z = num->stiff_z;
+    d.gamma = gas->gamma;
+    d.gm1 = gas->gamma - 1.0;
+    d.R = gas->R;
+    d.Cv = gas->Cv;
+    d.rho0 = gas->rho0;
+    d.T0 = gas->T0;
+    d.tau0 = gas->tau0;
+    d.tau_rho = gas->tau_rho;
+    d.tau_T = gas->tau_T;
+    d.Q0 = gas->Q0;
+    d.Q_rho = gas->Q_rho;
+    d.Q_T = gas->Q_T;
+    d.I0 = gas->I0;
+    d.I_rho = gas->I_rho;
+    d.I_T = gas->I_T;
+    d.fx = gas->fx;
+    d.fy = gas->fy;
+    if (prec == NG_FP32) {
+        // uniform reference at rest: rho0, p = R rho0 T0 and the vibrational
+        // energy at which relaxation balances the pump in eq. (4)
+        double rho_r = gas->rho0;
+        double p_r = gas->R * gas->rho0 * gas->T0;
+        double ev_r = gas->rho0 * gas->Cv * gas->T0 + gas->rho0 * gas->tau0 * gas->Q0;
+        double E_r = p_r / d.gm1 + ev_r;
+        d.uref[0] = rho_r;
+        d.uref[3] = E_r;
+        d.uref[4] = ev_r;
+        d.p_r = p_r;
+        d.H_r = E_r + p_r;
+        d.D_r = gas->Cv / gas->R * p_r - ev_r;
+    }
+}
+
+// Validate and upload a solve's conserved state into the slot's buffer 0, run
+// the priming pass (first dt, totals, checks).  Synchronising.
+int add_solve(ng_batch* b, const ng_gas* gas, const ng_grid* grid, const ng_numerics* num,
+              const double* data, bool is_prim, double t0, double t_end, int64_t max_steps,
+              int32_t* slot_out)
+{
+    std::string err;
+    int rc = validate(gas, grid, num, err);
+    if (rc) {
+        b->err = err;
+        return rc;
+    }
+    if (num->precision != b->prec) {
+        b->err = "precision differs from the batch";
+        return NG_EINVAL;
+    }
+    if (!data || !isfinite(t0) || !(t_end > t0) || max_steps < 0) {
+        b->err = "invalid state pointer, t0, t_end or max_steps";
+        return NG_EINVAL;
+    }
+    const int nc = ncomp(grid->ndim);
+    const int64_t n = grid->nx * (grid->ndim == 2 ? grid->ny : 1);
+    const double gm1 = gas->gamma - 1.0;
+    // conserved FP64 state and checks
+    std::vector<double> U((size_t)nc * n);
+    double Wc[5], Uc[5];
+    for (int64_t i = 0; i < n; i++) {
+        for (int c = 0; c < nc; c++) (is_prim ? Wc : Uc)[c] = data[c * n + i];
+        if (is_prim)
+            prim_to_cons_cell(gm1, nc, Wc, Uc);
+        else
+            cons_to_prim_cell(gm1, nc, Uc, Wc);
+        for (int c = 0; c < nc; c++) {
+            if (!isfinite(Uc[c]) || !isfinite(Wc[c])) {
+                b->err = "non-finite initial value";
+                return NG_EINVAL;
+            }
+            U[c * n + i] = Uc[c];
+        }
+        if (!(Wc[0] > 0.0) || !(Wc[nc == 5 ? 3 : 2] > 0.0)) {
+            b->err = "initial density and pressure must be positive";
+            return NG_EINVAL;
+        }
+    }
+    int slot = -1;
+    for (int i = 0; i < b->capacity; i++)
+        if (!b->slots[i].live) {
+            slot = i;
+            break;
+        }
+    if (slot < 0) {
+        b->err = "no free slot";
+        return NG_EFULL;
+    }
+    const size_t sb = solve_bytes(grid, b->prec);
+    size_t off = 0;
+    if (!arena_alloc(b, sb, &off)) {
+        b->err = "no room in the device arena";
+        return NG_EFULL;
+    }
+    Slot& s = b->slots[slot];
+    s = Slot();
+    s.live = true;
+    s.dim = grid->ndim;
+    s.off = off;
+    s.bytes = sb;
+    s.partial_cap = partial_cap_of(grid);
+    fill_desc(s.d, gas, grid, num, b->prec);
+    const size_t pb = state_plane_bytes(grid, b->prec);
+    s.d.buf[0] = (uint64_t)(b->arena + off);
+    s.d.buf[1] = (uint64_t)(b->arena + off + pb);
+    s.d.partials = (uint64_t)(b->arena + off + 2 * pb);
+    b->dirty = true;
+
+    // upload: FP64 as is, FP32 as deviations from the reference state
+    hipError_t e;
+    if (b->prec == NG_FP64) {
+        e = hipMemcpyAsync((void*)s.d.buf[0], U.data(), sizeof(double) * U.size(),
+                           hipMemcpyHostToDevice, b->stream);
+    } else {
+        std::vector<float> D(U.size());
+        const double ref5[5] = {s.d.uref[0], 0.0, 0.0, s.d.uref[3], s.d.uref[4]};
+        const double ref4[4] = {s.d.uref[0], 0.0, s.d.uref[3], s.d.uref[4]};
+        const double* ref = nc == 5 ? ref5 : ref4;
+        for (int c = 0; c < nc; c++)
+            for (int64_t i = 0; i < n; i++) D[c * n + i] = (float)(U[c * n + i] - ref[c]);
+        e = hipMemcpyAsync((void*)s.d.buf[0], D.data(), sizeof(float) * D.size(),
+                           hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    InstCtrl c;
+    memset(&c, 0, sizeof(c));
+    c.t = t0;
+    c.t_end = t_end;
+    c.max_steps = max_steps;
+    c.cur = 0;
+    c.status = 0;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_ctrls() + slot, &c, sizeof(c), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        s.live = false;
+        arena_free(b, off, sb);
+        return dev_err(b, e, "upload");
+    }
+    rc = rebuild(b);
+    if (rc) {
+        s.live = false;
+        arena_free(b, off, sb);
+        b->dirty = true;
+        return rc;
+    }
+    // priming pass over this solve only
+    e = launch_prime(s.dim, b->prec == NG_FP32 ? 1 : 0, b->d_descs(), b->d_ctrls(),
+                     b->d_blocks(s.dim) + s.block_off, s.d.nblocks, s.d.waves_per_block,
+                     b->stream);
+    if (e == hipSuccess)
+        e = launch_finalize(b->d_descs(), b->d_ctrls(), b->d_insts(s.dim) + s.pos, 1, 1, b->stream);
+    if (e == hipSuccess) {
+        rc = read_ctrls(b);
+        if (rc) return rc;
+    } else {
+        return dev_err(b, e, "prime");
+    }
+    if (b->h_ctrls[slot].status != 0) {
+        b->err = "initial state failed the positivity check";
+        return NG_EPHYS;
+    }
+    *slot_out = slot;
+    return NG_OK;
+}
+
+int read_conserved(ng_batch* b, int slot, double* out, bool prim)
+{
+    if (slot < 0 || slot >= b->capacity || !b->slots[slot].live || !out) {
+        b->err = "invalid slot or output";
+        return NG_EINVAL;
+    }
+    int rc = read_ctrls(b);
+    if (rc) return rc;
+    Slot& s = b->slots[slot];
+    const int nc = ncomp(s.dim);
+    const int64_t n = s.d.ncell;
+    const int cur = b->h_ctrls[slot].cur;
+    std::vector<double> U((size_t)nc * n);
+    if (b->prec == NG_FP64) {
+        CK(b, hipMemcpy(U.data(), (void*)s.d.buf[cur], sizeof(double) * U.size(),
+                        hipMemcpyDeviceToHost));
+    } else {
+        std::vector<float> D((size_t)nc * n);
+        CK(b, hipMemcpy(D.data(), (void*)s.d.buf[cur], sizeof(float) * D.size(),
+                        hipMemcpyDeviceToHost));
+        const double ref5[5] = {s.d.uref[0], 0.0, 0.0, s.d.uref[3], s.d.uref[4]};
+        const double ref4[4] = {s.d.uref[0], 0.0, s.d.uref[3], s.d.uref[4]};
+        const double* ref = nc == 5 ? ref5 : ref4;
+        for (int c = 0; c < nc; c++)
+            for (int64_t i = 0; i < n; i++) U[c * n + i] = ref[c] + (double)D[c * n + i];
+    }
+    if (!prim) {
+        memcpy(out, U.data(), sizeof(double) * U.size());
+        return NG_OK;
+    }
+    double Uc[5], Wc[5];
+    for (int64_t i = 0; i < n; i++) {
+        for (int c = 0; c < nc; c++) Uc[c] = U[c * n + i];
+        cons_to_prim_cell(s.d.gm1, nc, Uc, Wc);
+        for (int c = 0; c < nc; c++) out[c * n + i] = Wc[c];
+    }
+    return NG_OK;
+}
+
+int diag_of(ng_batch* b, int slot, ng_diag* out)
+{
+    if (slot < 0 || slot >= b->capacity || !b->slots[slot].live || !out) {
+        b->err = "invalid slot or output";
+        return NG_EINVAL;
+    }
+    int rc = read_ctrls(b);
+    if (rc) return rc;
+    const InstCtrl& c = b->h_ctrls[slot];
+    const Slot& s = b->slots[slot];
+    double hd = s.dim == 2 ? s.d.h * s.d.h : s.d.h;
+    memset(out, 0, sizeof(*out));
+    out->t = c.t;
+    out->dt_last = c.dt_last;
+    double dt = c.dt_cfl;
+    if (c.t + dt > c.t_end) dt = c.t_end - c.t;
+    out->dt_next = dt;
+    out->steps = c.steps;
+    for (int q = 0; q < 5; q++) out->total[q] = c.total[q] * hd;
+    out->src_budget[0] = c.budget[0] * hd;
+    out->src_budget[1] = c.budget[1] * hd;
+    out->rho_min = c.rho_min;
+    out->p_min = c.p_min;
+    out->smax = c.smax;
+    out->status = c.status;
+    out->flags = c.flags;
+    if (c.status == 0 && (!(c.t < c.t_end) || c.steps >= c.max_steps)) out->flags |= NG_FLAG_DONE;
+    return NG_OK;
+}
+
+}  // namespace
+
+// ===================================================================== C ABI
+
+extern "C" {
+
+const char* ng_strerror(int code)
+{
+    switch (code) {
+    case NG_OK: return "ok";
+    case NG_EINVAL: return "invalid argument";
+    case NG_ENOMEM: return "device buffer too small";
+    case NG_EPHYS: return "non-physical state (rho <= 0, p <= 0 or non-finite)";
+    case NG_EDEVICE: return "HIP runtime error";
+    case NG_EFULL: return "batch full";
+    default: return "unknown error";
+    }
+}
+
+int ng_state_bytes(const ng_grid* grid, const ng_numerics* num, size_t* bytes)
+{
+    if (!grid || !num || !bytes) return NG_EINVAL;
+    if (grid->ndim != 1 && grid->ndim != 2) return NG_EINVAL;
+    if (grid->nx < 4 || (grid->ndim == 2 && grid->ny < 4) || (grid->ndim == 1 && grid->ny != 1))
+        return NG_EINVAL;
+    if (num->precision != NG_FP32 && num->precision != NG_FP64) return NG_EINVAL;
+    size_t tc = (size_t)partial_cap_of(grid);
+    Layout L = header_layout(1, grid->ndim == 1 ? tc : 0, grid->ndim == 2 ? tc : 0);
+    *bytes = L.heap + solve_bytes(grid, num->precision);
+    return NG_OK;
+}
+
+static int solver_new(const ng_gas* gas, const ng_grid* grid, const ng_numerics* num,
+                      const double* data, bool is_prim, double t0, void* dev_buf,
+                      size_t dev_bytes, void* hip_stream, ng_solver** out)
+{
+    if (!out) return NG_EINVAL;
+    *out = nullptr;
+    std::string err;
+    int rc = validate(gas, grid, num, err);
+    if (rc) return rc;
+    size_t need = 0;
+    rc = ng_state_bytes(grid, num, &need);
+    if (rc) return rc;
+    if (dev_bytes < need) return NG_ENOMEM;
+    size_t tc = (size_t)partial_cap_of(grid);
+    ng_batch* b = nullptr;
+    rc = batch_new(1, num->precision, dev_buf, need, hip_stream, grid->ndim == 1 ? tc : 0,
+                   grid->ndim == 2 ? tc : 0, &b, err);
+    if (rc) return rc;
+    int32_t slot = 0;
+    rc = add_solve(b, gas, grid, num, data, is_prim, t0, INFINITY, INT64_MAX, &slot);
+    if (rc) {
+        ng_batch_destroy(b);
+        return rc;
+    }
+    ng_solver* s = new ng_solver();
+    s->b = b;
+    s->slot = slot;
+    *out = s;
+    return NG_OK;
+}
+
+int ng_init_state(const ng_gas* gas, const ng_grid* grid, const ng_numerics* num,
+                  const double* prim, double t0, void* dev_buf, size_t dev_bytes,
+                  void* hip_stream, ng_solver** out)
+{
+    return solver_new(gas, grid, num, prim, true, t0, dev_buf, dev_bytes, hip_stream, out);
+}
+
+int ng_init_conserved(const ng_gas* gas, const ng_grid* grid, const ng_numerics* num,
+                      const double* cons, double t0, void* dev_buf, size_t dev_bytes,
+                      void* hip_stream, ng_solver** out)
+{
+    return solver_new(gas, grid, num, cons, false, t0, dev_buf, dev_bytes, hip_stream, out);
+}
+
+static int solver_rc(ng_solver* s, int rc)
+{
+    if (rc && s) s->err = s->b->err;
+    return rc;
+}
+
+int ng_step(ng_solver* s, int64_t nsteps)
+{
+    if (!s || nsteps < 0) return NG_EINVAL;
+    if (nsteps == 0) return NG_OK;
+    std::vector<int32_t> sl{s->slot};
+    int rc = set_limits(s->b, sl, INFINITY, -1);
+    if (!rc) rc = enqueue_steps(s->b, nsteps);
+    return solver_rc(s, rc);
+}
+
+int ng_run_to_time(ng_solver* s, double t_end, int64_t max_steps, int64_t* steps_taken)
+{
+    if (!s || !isfinite(t_end) || max_steps < 0) return NG_EINVAL;
+    ng_batch* b = s->b;
+    int rc = read_ctrls(b);
+    if (rc) return solver_rc(s, rc);
+    const int64_t steps0 = b->h_ctrls[s->slot].steps;
+    std::vector<int32_t> sl{s->slot};
+    rc = set_limits(b, sl, t_end, max_steps);
+    if (rc) return solver_rc(s, rc);
+    for (;;) {
+        rc = read_ctrls(b);
+        if (rc) return solver_rc(s, rc);
+        const InstCtrl& c = b->h_ctrls[s->slot];
+        if (c.status != 0) {
+            if (steps_taken) *steps_taken = c.steps - steps0;
+            s->err = "step rejected: non-physical state";
+            return NG_EPHYS;
+        }
+        int64_t left = max_steps - (c.steps - steps0);
+        if (!(c.t < t_end) || left <= 0) {
+            if (steps_taken) *steps_taken = c.steps - steps0;
+            return NG_OK;
+        }
+        // estimate of the steps still needed; the device stops by itself
+        double est = c.dt_cfl > 0.0 ? (t_end - c.t) / c.dt_cfl : (double)left;
+        int64_t chunk = (int64_t)std::min<double>((double)left, ceil(est * 1.02) + 1.0);
+        if (chunk < 1) chunk = 1;
+        rc = enqueue_steps(b, chunk);
+        if (rc) return solver_rc(s, rc);
+    }
+}
+
+int ng_diagnostics(ng_solver* s, ng_diag* out)
+{
+    if (!s) return NG_EINVAL;
+    return solver_rc(s, diag_of(s->b, s->slot, out));
+}
+
+int ng_get_state(ng_solver* s, double* prim_out)
+{
+    if (!s) return NG_EINVAL;
+    return solver_rc(s, read_conserved(s->b, s->slot, prim_out, true));
+}
+
+int ng_get_conserved(ng_solver* s, double* cons_out)
+{
+    if (!s) return NG_EINVAL;
+    return solver_rc(s, read_conserved(s->b, s->slot, cons_out, false));
+}
+
+int ng_set_launch(ng_solver* s, int32_t rows_per_item, int32_t waves_per_block)
+{
+    if (!s) return NG_EINVAL;
+    return ng_batch_set_launch(s->b, s->b->slots[s->slot].dim, rows_per_item, waves_per_block);
+}
+
+int ng_set_graph_steps(ng_solver* s, int32_t steps)
+{
+    if (!s || steps < 1 || steps > 4096) return NG_EINVAL;
+    s->b->graph_steps = steps;
+    drop_graph(s->b);
+    return NG_OK;
+}
+
+int ng_enable_timing(ng_solver* s, int32_t on)
+{
+    if (!s) return NG_EINVAL;
+    s->b->timing = on != 0;
+    return NG_OK;
+}
+
+int ng_kernel_time(ng_solver* s, double* step_ms, double* finalize_ms, int64_t* launches)
+{
+    if (!s) return NG_EINVAL;
+    if (step_ms) *step_ms = s->b->t_step_ms;
+    if (finalize_ms) *finalize_ms = s->b->t_fin_ms;
+    if (launches) *launches = s->b->t_launches;
+    return NG_OK;
+}
+
+const char* ng_last_error(const ng_solver* s)
+{
+    if (!s) return "null solver";
+    return s->err.empty() ? s->b->err.c_str() : s->err.c_str();
+}
+
+void ng_destroy(ng_solver* s)
+{
+    if (!s) return;
+    ng_batch_destroy(s->b);
+    delete s;
+}
+
+// ------------------------------------------------------------------- batch
+
+int ng_batch_create(int32_t capacity, int32_t precision, void* dev_buf, size_t dev_bytes,
+                    void* hip_stream, ng_batch** out)
+{
+    if (!out) return NG_EINVAL;
+    *out = nullptr;
+    // workgroup tables: at most one entry per 60 cells of a 1D solve (the
+    // densest decomposition); bound them by the arena size
+    size_t per = 60 * 2 * 4 * (precision == NG_FP32 ? 4 : 8);
+    size_t tcap = dev_bytes / per + 64 * (size_t)capacity;
+    std::string err;
+    return batch_new(capacity, precision, dev_buf, dev_bytes, hip_stream, tcap, tcap / 4 + 64 * capacity,
+                     out, err);
+}
+
+int ng_batch_solve_bytes(const ng_grid* grid, int32_t precision, size_t* bytes)
+{
+    if (!grid || !bytes || (grid->ndim != 1 && grid->ndim != 2)) return NG_EINVAL;
+    if (precision != NG_FP32 && precision != NG_FP64) return NG_EINVAL;
+    *bytes = solve_bytes(grid, precision);
+    return NG_OK;
+}
+
+int ng_batch_add(ng_batch* b, const ng_gas* gas, const ng_grid* grid, const ng_numerics* num,
+                 const double* prim, double t0, double t_end, int64_t max_steps, int32_t* slot)
+{
+    if (!b || !slot) return NG_EINVAL;
+    if (!isfinite(t_end)) {
+        b->err = "t_end must be finite";
+        return NG_EINVAL;
+    }
+    return add_solve(b, gas, grid, num, prim, true, t0, t_end, max_steps, slot);
+}
+
+int ng_batch_run(ng_batch* b, int64_t nsteps)
+{
+    if (!b || nsteps < 0) return NG_EINVAL;
+    return enqueue_steps(b, nsteps);
+}
+
+int ng_batch_poll(ng_batch* b, int32_t* done_slots, int32_t cap, int32_t* ndone)
+{
+    if (!b || !ndone || (cap > 0 && !done_slots)) return NG_EINVAL;
+    int rc = read_ctrls(b);
+    if (rc) return rc;
+    int32_t n = 0;
+    for (int i = 0; i < b->capacity && n < cap; i++) {
+        Slot& s = b->slots[i];
+        if (!s.live || s.reported) continue;
+        const InstCtrl& c = b->h_ctrls[i];
+        bool fin = c.status != 0 || !(c.t < c.t_end) || c.steps >= c.max_steps;
+        if (fin) {
+            s.reported = true;
+            done_slots[n++] = i;
+        }
+    }
+    *ndone = n;
+    return NG_OK;
+}
+
+int ng_batch_active(ng_batch* b, int32_t* nactive)
+{
+    if (!b || !nactive) return NG_EINVAL;
+    int rc = read_ctrls(b);
+    if (rc) return rc;
+    int32_t n = 0;
+    for (int i = 0; i < b->capacity; i++) {
+        if (!b->slots[i].live) continue;
+        const InstCtrl& c = b->h_ctrls[i];
+        if (c.status == 0 && c.t < c.t_end && c.steps < c.max_steps) n++;
+    }
+    *nactive = n;
+    return NG_OK;
+}
+
+int ng_batch_diagnostics(ng_batch* b, int32_t slot, ng_diag* out)
+{
+    if (!b) return NG_EINVAL;
+    return diag_of(b, slot, out);
+}
+
+int ng_batch_get_state(ng_batch* b, int32_t slot, double* prim_out)
+{
+    if (!b) return NG_EINVAL;
+    return read_conserved(b, slot, prim_out, true);
+}
+
+int ng_batch_get_conserved(ng_batch* b, int32_t slot, double* cons_out)
+{
+    if (!b) return NG_EINVAL;
+    return read_conserved(b, slot, cons_out, false);
+}
+
+int ng_batch_remove(ng_batch* b, int32_t slot)
+{
+    if (!b || slot < 0 || slot >= b->capacity || !b->slots[slot].live) return NG_EINVAL;
+    // nothing of this solve may still be in flight
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return dev_err(b, e, "hipStreamSynchronize");
+    Slot& s = b->slots[slot];
+    arena_free(b, s.off, s.bytes);
+    s = Slot();
+    InstCtrl c;
+    memset(&c, 0, sizeof(c));
+    c.status = -1;
+    e = hipMemcpyAsync(b->d_ctrls() + slot, &c, sizeof(c), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return dev_err(b, e, "remove");
+    b->dirty = true;
+    return NG_OK;
+}
+
+int ng_batch_set_launch(ng_batch* b, int32_t dim, int32_t rows_per_item, int32_t waves_per_block)
+{
+    if (!b || (dim != 1 && dim != 2)) return NG_EINVAL;
+    if (rows_per_item < 0 || waves_per_block < 0 || waves_per_block > 4 ||
+        (waves_per_block & (waves_per_block - 1)))
+        return NG_EINVAL;
+    if (dim == 2 && rows_per_item != 0 && rows_per_item < kMinRows2D) return NG_EINVAL;
+    int old_r = b->rows[dim], old_w = b->waves[dim];
+    if (rows_per_item) b->rows[dim] = rows_per_item;
+    if (waves_per_block) b->waves[dim] = waves_per_block;
+    b->dirty = true;
+    int rc = rebuild(b);
+    if (rc) {
+        b->rows[dim] = old_r;
+        b->waves[dim] = old_w;
+        b->dirty = true;
+        (void)rebuild(b);
+        return rc;
+    }
+    return NG_OK;
+}
+
+const char* ng_batch_last_error(const ng_batch* b) { return b ? b->err.c_str() : "null batch"; }
+
+void ng_batch_destroy(ng_batch* b)
+{
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    drop_graph(b);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    for (auto e : b->ev_pool) (void)hipEventDestroy(e);
+    if (b->h_ctrls) (void)hipHostFree(b->h_ctrls);
+    delete b;
+}
+
+}  // extern "C"

@@ -1,0 +1,560 @@
+// ng_cell.hpp -- per-cell and per-face arithmetic of the MUSCL step for the
+// vibrationally excited gas (Khrapov & Khoperskov, J. Phys.: Conf. Ser. 973
+// (2018) 012007), in the two precisions of the library.
+//
+// FP64 ("Plain64"): the full conserved state U = (rho, rho u, rho v, E, E_nu)
+// and the formulas exactly as eqs. (5), (13)-(15) state them, each written in
+// one fixed evaluation order; the library is built without multiply-add
+// contraction so that these are the IEEE results of that order.
+//
+// FP32 ("Dev32"): the state is stored as deviations dU = U - U_ref from a
+// uniform reference at rest (rho_r, 0, 0, E_r, Ev_r).  Every flux and source
+// is evaluated in a form in which the reference part cancels exactly:
+//   p - p_r       = (gamma - 1)(dE - rho|v|^2/2 - dEv)          (eq. (5))
+//   F - F(U_ref)  = (rho u, rho u^2 + dp, rho u v, u (H_r + dE + dp), u Ev)
+//   E_nue - E_nu  = (Cv/R) dp - dEv + (Cv/R p_r - Ev_r)          (eq. (7))
+//   U*_K - U_K    = q_K (rho, rho S_K, rho v, E + p + rho (S_K - u) S*, Ev)_K,
+//                   q_K = (S* - u_K)/(S_K - S*)                 (HLLC star jump)
+// so that the O(1) background never enters a difference of two fluxes.  FP32
+// rounding then acts on the perturbation, not on the background.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+namespace ng {
+
+// ------------------------------------------------------------- limiter
+
+// minmod of two undivided differences (slopes of eq. (14)): zero unless both
+// have the same strict sign, else the one of smaller magnitude.
+__device__ __forceinline__ double minmod(double a, double b)
+{
+    if (a > 0.0 && b > 0.0) return a < b ? a : b;
+    if (a < 0.0 && b < 0.0) return a > b ? a : b;
+    return 0.0;
+}
+__device__ __forceinline__ float minmod(float a, float b)
+{
+    // the median of (a, b, 0) is exactly that selection
+    return __builtin_amdgcn_fmed3f(a, b, 0.0f);
+}
+
+// ===================================================================== FP64
+
+struct K64 {
+    double gam, gm1, R, Cv, rho0, T0, tau0, tr, tT, Q0, Qr, QT, I0, Ir, IT, fx, fy;
+    double stiff_z;
+    double dt, dtdx, hdtdx, hdt;
+    int riemann;
+};
+
+// x^a of the power laws (6): exponents 0, 1, -1, 2 and 1/2 by the correctly
+// rounded IEEE operations (the exact power rounded once), others by pow.  The
+// exponent is the same for every lane, so the selection is a scalar branch.
+__device__ __forceinline__ double powr64(double x, double a)
+{
+    if (a == 0.0) return 1.0;
+    if (a == 1.0) return x;
+    if (a == -1.0) return 1.0 / x;
+    if (a == 2.0) return x * x;
+    if (a == 0.5) return sqrt(x);
+    return pow(x, a);
+}
+
+// closures of eq. (6) at (rho, T)
+__device__ __forceinline__ void closures64(const K64& k, double rho, double T, double& tau,
+                                           double& Q, double& I)
+{
+    double r = rho / k.rho0, t = T / k.T0;
+    tau = k.tau0 * powr64(r, k.tr) * powr64(t, k.tT);
+    Q = k.Q0 * powr64(r, k.Qr) * powr64(t, k.QT);
+    I = k.I0 * powr64(r, k.Ir) * powr64(t, k.IT);
+}
+
+// conserved -> primitive (eq. (5) solved for p); NC = 4 (1D) or 5 (2D)
+template <int NC>
+__device__ __forceinline__ void prim64(const K64& k, const double* U, double* W)
+{
+    double rho = U[0];
+    double u = U[1] / rho;
+    if (NC == 5) {
+        double v = U[2] / rho;
+        double ke = 0.5 * rho * (u * u + v * v);
+        W[0] = rho;
+        W[1] = u;
+        W[2] = v;
+        W[3] = k.gm1 * (U[3] - ke - U[4]);
+        W[4] = U[4];
+    } else {
+        double ke = 0.5 * rho * (u * u);
+        W[0] = rho;
+        W[1] = u;
+        W[2] = k.gm1 * (U[2] - ke - U[3]);
+        W[3] = U[3];
+    }
+}
+
+// signal speed of eq. (16): max(|v| + c, 2|v|)
+template <int NC>
+__device__ __forceinline__ double speed64(const K64& k, const double* W)
+{
+    double rho = W[0], u = W[1];
+    double vel, p;
+    if (NC == 5) {
+        vel = sqrt(u * u + W[2] * W[2]);
+        p = W[3];
+    } else {
+        vel = sqrt(u * u);
+        p = W[2];
+    }
+    double c = sqrt(k.gam * p / rho);
+    return fmax(vel + c, 2.0 * vel);
+}
+
+// Half-step predictor: quasi-linear primitive form of eqs. (1)-(5) with the
+// sources at t^n (the "predictor" of the two-step scheme of section 2.3).
+// W = (rho, u, v, p, E_nu) (2D) or (rho, u, p, E_nu) (1D); sx, sy limited slopes.
+template <int NC>
+__device__ __forceinline__ void predict64(const K64& k, const double* W, const double* sx,
+                                          const double* sy, double* Wh)
+{
+    const double gam = k.gam, gm1 = k.gm1, hdtdx = k.hdtdx, hdt = k.hdt;
+    if (NC == 5) {
+        double rho = W[0], u = W[1], v = W[2], p = W[3], ev = W[4];
+        double sr = sx[0], su = sx[1], sv = sx[2], sp = sx[3], se = sx[4];
+        double ax_r = u * sr + rho * su;
+        double ax_u = u * su + sp / rho;
+        double ax_v = u * sv;
+        double ax_p = u * sp + gam * p * su;
+        double ax_e = u * se + ev * su;
+        double tr = sy[0], tu = sy[1], tv = sy[2], tp = sy[3], te = sy[4];
+        double ay_r = v * tr + rho * tv;
+        double ay_u = v * tu;
+        double ay_v = v * tv + tp / rho;
+        double ay_p = v * tp + gam * p * tv;
+        double ay_e = v * te + ev * tv;
+        double T = p / (k.R * rho);
+        double tau, Q, I;
+        closures64(k, rho, T, tau, Q, I);
+        double Ee = rho * k.Cv * T;
+        double dEr;
+        double zh = hdt / tau;
+        if (k.dt / tau > k.stiff_z)
+            dEr = (Ee - ev) * (-expm1(-zh));
+        else
+            dEr = hdt * ((Ee - ev) / tau);
+        Wh[0] = rho - hdtdx * (ax_r + ay_r);
+        Wh[1] = u - hdtdx * (ax_u + ay_u) + hdt * k.fx;
+        Wh[2] = v - hdtdx * (ax_v + ay_v) + hdt * k.fy;
+        Wh[3] = p - hdtdx * (ax_p + ay_p) - gm1 * (dEr + hdt * (rho * I));
+        Wh[4] = ev - hdtdx * (ax_e + ay_e) + (dEr + hdt * (rho * Q));
+    } else {
+        double rho = W[0], u = W[1], p = W[2], ev = W[3];
+        double sr = sx[0], su = sx[1], sp = sx[2], se = sx[3];
+        double ax_r = u * sr + rho * su;
+        double ax_u = u * su + sp / rho;
+        double ax_p = u * sp + gam * p * su;
+        double ax_e = u * se + ev * su;
+        double T = p / (k.R * rho);
+        double tau, Q, I;
+        closures64(k, rho, T, tau, Q, I);
+        double Ee = rho * k.Cv * T;
+        double dEr;
+        double zh = hdt / tau;
+        if (k.dt / tau > k.stiff_z)
+            dEr = (Ee - ev) * (-expm1(-zh));
+        else
+            dEr = hdt * ((Ee - ev) / tau);
+        Wh[0] = rho - hdtdx * ax_r;
+        Wh[1] = u - hdtdx * ax_u + hdt * k.fx;
+        Wh[2] = p - hdtdx * ax_p - gm1 * (dEr + hdt * (rho * I));
+        Wh[3] = ev - hdtdx * ax_e + (dEr + hdt * (rho * Q));
+    }
+}
+
+// Interface flux along a normal.  Face states (rho, u_n, [u_t], p, E_nu);
+// returns (mass, normal momentum, [tangential momentum], energy, E_nu) fluxes.
+// HLL: eq. (13) with the wave speeds printed under it; HLLC: three waves, the
+// middle one from equal pressure and normal velocity across the contact.
+template <int NC>
+__device__ __forceinline__ void flux64(const K64& k, const double* WL, const double* WR,
+                                       double* F)
+{
+    const double gam = k.gam, gm1 = k.gm1;
+    double rL = WL[0], uL = WL[1], rR = WR[0], uR = WR[1];
+    double vL, vR, pL, pR, eL, eR, EL, ER;
+    if (NC == 5) {
+        vL = WL[2];
+        vR = WR[2];
+        pL = WL[3];
+        pR = WR[3];
+        eL = WL[4];
+        eR = WR[4];
+        EL = pL / gm1 + 0.5 * rL * (uL * uL + vL * vL) + eL;
+        ER = pR / gm1 + 0.5 * rR * (uR * uR + vR * vR) + eR;
+    } else {
+        vL = vR = 0.0;
+        pL = WL[2];
+        pR = WR[2];
+        eL = WL[3];
+        eR = WR[3];
+        EL = pL / gm1 + 0.5 * rL * (uL * uL) + eL;
+        ER = pR / gm1 + 0.5 * rR * (uR * uR) + eR;
+    }
+    double mL = rL * uL, mR = rR * uR;
+    // physical fluxes and conserved face states, component order (rho, m_n, [m_t], E, Ev)
+    double FL[5], FR[5], UL[5], UR[5];
+    FL[0] = mL;
+    FL[1] = mL * uL + pL;
+    FR[0] = mR;
+    FR[1] = mR * uR + pR;
+    UL[0] = rL;
+    UL[1] = rL * uL;
+    UR[0] = rR;
+    UR[1] = rR * uR;
+    const int iE = NC == 5 ? 3 : 2, iV = NC == 5 ? 4 : 3;
+    if (NC == 5) {
+        FL[2] = mL * vL;
+        FR[2] = mR * vR;
+        UL[2] = rL * vL;
+        UR[2] = rR * vR;
+    }
+    FL[iE] = uL * (EL + pL);
+    FR[iE] = uR * (ER + pR);
+    FL[iV] = uL * eL;
+    FR[iV] = uR * eR;
+    UL[iE] = EL;
+    UR[iE] = ER;
+    UL[iV] = eL;
+    UR[iV] = eR;
+
+    double cL = sqrt(gam * pL / rL);
+    double cR = sqrt(gam * pR / rR);
+    double SL = fmin(uL - cL, uR - cR);
+    double SR = fmax(uL + cL, uR + cR);
+
+    if (k.riemann == 1) {
+        // HLL, eq. (13)
+        double inv = SR - SL;
+        for (int c = 0; c < NC; c++) {
+            double fh = (SR * FL[c] - SL * FR[c] + SL * SR * (UR[c] - UL[c])) / inv;
+            F[c] = (0.0 < SL) ? FL[c] : ((SR < 0.0) ? FR[c] : fh);
+        }
+        return;
+    }
+    double dL = SL - uL, dR = SR - uR;
+    double Ss = (pR - pL + rL * uL * dL - rR * uR * dR) / (rL * dL - rR * dR);
+    // the star state on the side of the contact that the face sees
+    bool left = 0.0 < Ss;
+    double rK = left ? rL : rR, uK = left ? uL : uR, vK = left ? vL : vR;
+    double pK = left ? pL : pR, eK = left ? eL : eR, EK = left ? EL : ER;
+    double SK = left ? SL : SR, dK = left ? dL : dR;
+    double fac = rK * dK / (SK - Ss);
+    double Us[5];
+    Us[0] = fac;
+    Us[1] = fac * Ss;
+    if (NC == 5) Us[2] = fac * vK;
+    Us[iE] = fac * (EK / rK + (Ss - uK) * (Ss + pK / (rK * dK)));
+    Us[iV] = fac * (eK / rK);
+    bool star = left || (0.0 <= SR);
+    for (int c = 0; c < NC; c++) {
+        double FK = left ? FL[c] : FR[c];
+        double UK = left ? UL[c] : UR[c];
+        double fs = FK + SK * (Us[c] - UK);
+        F[c] = (0.0 < SL) ? FL[c] : (star ? fs : FR[c]);
+    }
+}
+
+// Sources Y of eq. (15) at the half-step state and the conservative update.
+// Un: conserved state at t^n; dF, dG: flux differences over the cell; Wh: the
+// half-step primitive state.  Writes Unew and the cell's contributions to the
+// source budget (dt * Y_E and the E_nu source increment).
+template <int NC>
+__device__ __forceinline__ void update64(const K64& k, const double* Un, const double* dF,
+                                         const double* dG, const double* Wh, double* Unew,
+                                         double& srcE, double& srcV)
+{
+    const double dt = k.dt, dtdx = k.dtdx;
+    double rho = Wh[0], u = Wh[1];
+    double v = 0.0, p, ev;
+    if (NC == 5) {
+        v = Wh[2];
+        p = Wh[3];
+        ev = Wh[4];
+    } else {
+        p = Wh[2];
+        ev = Wh[3];
+    }
+    double T = p / (k.R * rho);
+    double tau, Q, I;
+    closures64(k, rho, T, tau, Q, I);
+    double Ee = rho * k.Cv * T;
+    double Y[5];
+    const int iE = NC == 5 ? 3 : 2, iV = NC == 5 ? 4 : 3;
+    Y[0] = 0.0;
+    Y[1] = rho * k.fx;
+    if (NC == 5) {
+        Y[2] = rho * k.fy;
+        Y[iE] = rho * (u * k.fx + v * k.fy + Q - I);
+    } else {
+        Y[iE] = rho * (u * k.fx + Q - I);
+    }
+    Y[iV] = (Ee - ev) / tau + rho * Q;
+    for (int c = 0; c < NC; c++) {
+        if (NC == 5)
+            Unew[c] = Un[c] - dtdx * (dF[c] + dG[c]) + dt * Y[c];
+        else
+            Unew[c] = Un[c] - dtdx * dF[c] + dt * Y[c];
+    }
+    double de = dt * Y[iV];
+    double z = dt / tau;
+    if (z > k.stiff_z) {
+        // relaxation over the whole step integrated exactly from the
+        // start-of-step E_nu, with E_nue and tau frozen at t^{n+1/2}
+        double dEr = (Ee - Un[iV]) * (-expm1(-z));
+        de = dEr + dt * (rho * Q);
+        if (NC == 5)
+            Unew[iV] = Un[iV] - dtdx * (dF[iV] + dG[iV]) + de;
+        else
+            Unew[iV] = Un[iV] - dtdx * dF[iV] + de;
+    }
+    srcE = dt * Y[iE];
+    srcV = de;
+}
+
+// ===================================================================== FP32
+
+__device__ __forceinline__ float rcp32(float x) { return __builtin_amdgcn_rcpf(x); }
+
+struct K32 {
+    float gam, gm1, igm1, CvR;
+    float rho_r, p_r, ev_r, H_r, D_r;   // reference state and its cancelled constants
+    float irho0, iRT0;                  // 1/rho0, 1/(R T0)
+    float itau0, Q0, I0;                // closures of eq. (6) in log2/exp2 form
+    float tr, tT, Qr, QT, Ir, IT;
+    float fx, fy;
+    float stiff_z;
+    float dt, dtdx, hdtdx, hdt;
+    double dt64, hdt64;
+    int riemann;
+};
+
+// x^a in FP32: exact-operation exponents as in FP64, others exp2(a log2 x)
+__device__ __forceinline__ float powr32(float x, float a)
+{
+    if (a == 0.0f) return 1.0f;
+    if (a == 1.0f) return x;
+    if (a == -1.0f) return rcp32(x);
+    if (a == 2.0f) return x * x;
+    if (a == 0.5f) return __builtin_sqrtf(x);
+    return __builtin_amdgcn_exp2f(a * __builtin_amdgcn_logf(x));
+}
+
+// 1/tau, Q and I of eq. (6) at full (rho, p), T/T0 = p/(R rho T0)
+__device__ __forceinline__ void closures32(const K32& k, float rho, float p, float irho,
+                                           float& itau, float& Q, float& I)
+{
+    float r = rho * k.irho0;
+    float t = p * k.iRT0 * irho;
+    itau = k.itau0 * powr32(r, -k.tr) * powr32(t, -k.tT);
+    Q = k.Q0 * powr32(r, k.Qr) * powr32(t, k.QT);
+    I = k.I0 * powr32(r, k.Ir) * powr32(t, k.IT);
+}
+
+// deviation primitives (d rho, u, [v], dp, dEv) from deviation conserved
+template <int NC>
+__device__ __forceinline__ void prim32(const K32& k, const float* D, float* W)
+{
+    float rho = k.rho_r + D[0];
+    float ir = rcp32(rho);
+    float u = D[1] * ir;
+    if (NC == 5) {
+        float v = D[2] * ir;
+        float ke = 0.5f * rho * fmaf(u, u, v * v);
+        W[0] = D[0];
+        W[1] = u;
+        W[2] = v;
+        W[3] = k.gm1 * ((D[3] - ke) - D[4]);
+        W[4] = D[4];
+    } else {
+        float ke = 0.5f * rho * (u * u);
+        W[0] = D[0];
+        W[1] = u;
+        W[2] = k.gm1 * ((D[2] - ke) - D[3]);
+        W[3] = D[3];
+    }
+}
+
+template <int NC>
+__device__ __forceinline__ float speed32(const K32& k, const float* W)
+{
+    float rho = k.rho_r + W[0];
+    float u = W[1];
+    float v2 = NC == 5 ? W[2] * W[2] : 0.0f;
+    float p = k.p_r + W[NC == 5 ? 3 : 2];
+    float vel = __builtin_sqrtf(fmaf(u, u, v2));
+    float c = __builtin_sqrtf(k.gam * p * rcp32(rho));
+    return fmaxf(vel + c, 2.0f * vel);
+}
+
+template <int NC>
+__device__ __forceinline__ void predict32(const K32& k, const float* W, const float* sx,
+                                          const float* sy, float* Wh)
+{
+    const float gam = k.gam, hdtdx = k.hdtdx, hdt = k.hdt;
+    constexpr int iP = NC == 5 ? 3 : 2, iV = NC == 5 ? 4 : 3;
+    float dr = W[0], u = W[1], dp = W[iP], de = W[iV];
+    float rho = k.rho_r + dr, p = k.p_r + dp, ev = k.ev_r + de;
+    float irho = rcp32(rho);
+    float sr = sx[0], su = sx[1], sp = sx[iP], se = sx[iV];
+    float a_r = fmaf(u, sr, rho * su);
+    float a_u = fmaf(u, su, sp * irho);
+    float a_p = fmaf(u, sp, gam * p * su);
+    float a_e = fmaf(u, se, ev * su);
+    float a_v = 0.0f, v = 0.0f;
+    if (NC == 5) {
+        v = W[2];
+        float sv = sx[2];
+        a_v = u * sv;
+        float tr = sy[0], tu = sy[1], tv = sy[2], tp = sy[3], te = sy[4];
+        a_r += fmaf(v, tr, rho * tv);
+        a_u += v * tu;
+        a_v += fmaf(v, tv, tp * irho);
+        a_p += fmaf(v, tp, gam * p * tv);
+        a_e += fmaf(v, te, ev * tv);
+    }
+    float itau, Q, I;
+    closures32(k, rho, p, irho, itau, Q, I);
+    float relax_num = fmaf(k.CvR, dp, k.D_r - de);   // E_nue - E_nu
+    float dEr;
+    if (k.dt * itau > k.stiff_z)
+        dEr = (float)((double)relax_num * (-expm1(-k.hdt64 * (double)itau)));
+    else
+        dEr = hdt * (relax_num * itau);
+    Wh[0] = fmaf(-hdtdx, a_r, dr);
+    Wh[1] = fmaf(hdt, k.fx, fmaf(-hdtdx, a_u, u));
+    if (NC == 5) Wh[2] = fmaf(hdt, k.fy, fmaf(-hdtdx, a_v, v));
+    Wh[iP] = fmaf(-k.gm1, fmaf(hdt, rho * I, dEr), fmaf(-hdtdx, a_p, dp));
+    Wh[iV] = fmaf(hdt, rho * Q, dEr) + fmaf(-hdtdx, a_e, de);
+}
+
+// interface flux minus the flux of the reference state, face states in
+// deviation primitives
+template <int NC>
+__device__ __forceinline__ void flux32(const K32& k, const float* WL, const float* WR, float* F)
+{
+    constexpr int iP = NC == 5 ? 3 : 2, iV = NC == 5 ? 4 : 3;
+    const float gam = k.gam;
+    float rL = k.rho_r + WL[0], rR = k.rho_r + WR[0];
+    float uL = WL[1], uR = WR[1];
+    float vL = NC == 5 ? WL[2] : 0.0f, vR = NC == 5 ? WR[2] : 0.0f;
+    float dpL = WL[iP], dpR = WR[iP];
+    float deL = WL[iV], deR = WR[iV];
+    float pL = k.p_r + dpL, pR = k.p_r + dpR;
+    float evL = k.ev_r + deL, evR = k.ev_r + deR;
+    // deviation conserved face states
+    float mL = rL * uL, mR = rR * uR;
+    float keL = 0.5f * rL * (NC == 5 ? fmaf(uL, uL, vL * vL) : uL * uL);
+    float keR = 0.5f * rR * (NC == 5 ? fmaf(uR, uR, vR * vR) : uR * uR);
+    float dEL = fmaf(dpL, k.igm1, keL) + deL;
+    float dER = fmaf(dpR, k.igm1, keR) + deR;
+    float HL = k.H_r + (dEL + dpL), HR = k.H_r + (dER + dpR);   // E + p
+    float UL[5], UR[5], FL[5], FR[5];
+    UL[0] = WL[0];
+    UR[0] = WR[0];
+    UL[1] = mL;
+    UR[1] = mR;
+    FL[0] = mL;
+    FR[0] = mR;
+    FL[1] = fmaf(mL, uL, dpL);
+    FR[1] = fmaf(mR, uR, dpR);
+    if (NC == 5) {
+        UL[2] = rL * vL;
+        UR[2] = rR * vR;
+        FL[2] = mL * vL;
+        FR[2] = mR * vR;
+    }
+    UL[iP] = dEL;
+    UR[iP] = dER;
+    UL[iV] = deL;
+    UR[iV] = deR;
+    FL[iP] = uL * HL;
+    FR[iP] = uR * HR;
+    FL[iV] = uL * evL;
+    FR[iV] = uR * evR;
+
+    float cL = __builtin_sqrtf(gam * pL * rcp32(rL));
+    float cR = __builtin_sqrtf(gam * pR * rcp32(rR));
+    float SL = fminf(uL - cL, uR - cR);
+    float SR = fmaxf(uL + cL, uR + cR);
+    if (k.riemann == 1) {
+        float inv = rcp32(SR - SL);
+        float SLR = SL * SR;
+        for (int c = 0; c < NC; c++) {
+            float fh = fmaf(SLR, UR[c] - UL[c], fmaf(SR, FL[c], -(SL * FR[c]))) * inv;
+            F[c] = (0.0f < SL) ? FL[c] : ((SR < 0.0f) ? FR[c] : fh);
+        }
+        return;
+    }
+    float dL = SL - uL, dR = SR - uR;
+    float Ss = ((dpR - dpL) + (mL * dL - mR * dR)) * rcp32(rL * dL - rR * dR);
+    bool left = 0.0f < Ss;
+    float rK = left ? rL : rR, uK = left ? uL : uR;
+    float SK = left ? SL : SR, dK = left ? dL : dR;
+    float HK = left ? HL : HR, evK = left ? evL : evR;
+    float q = (Ss - uK) * rcp32(SK - Ss);
+    float rq = rK * q;
+    float dU[5];
+    dU[0] = rq;
+    dU[1] = rq * SK;
+    if (NC == 5) dU[2] = rq * (left ? vL : vR);
+    dU[iP] = q * fmaf(rK * dK, Ss, HK);
+    dU[iV] = q * evK;
+    bool star = left || (0.0f <= SR);
+    for (int c = 0; c < NC; c++) {
+        float FK = left ? FL[c] : FR[c];
+        float fs = fmaf(SK, dU[c], FK);
+        F[c] = (0.0f < SL) ? FL[c] : (star ? fs : FR[c]);
+    }
+}
+
+template <int NC>
+__device__ __forceinline__ void update32(const K32& k, const float* Un, const float* dF,
+                                         const float* dG, const float* Wh, float* Unew,
+                                         float& srcE, float& srcV)
+{
+    constexpr int iP = NC == 5 ? 3 : 2, iV = NC == 5 ? 4 : 3;
+    const float dt = k.dt, dtdx = k.dtdx;
+    float dr = Wh[0], u = Wh[1], dp = Wh[iP], de = Wh[iV];
+    float v = NC == 5 ? Wh[2] : 0.0f;
+    float rho = k.rho_r + dr, p = k.p_r + dp;
+    float irho = rcp32(rho);
+    float itau, Q, I;
+    closures32(k, rho, p, irho, itau, Q, I);
+    float Y[5];
+    Y[0] = 0.0f;
+    Y[1] = rho * k.fx;
+    if (NC == 5) Y[2] = rho * k.fy;
+    Y[iP] = rho * (fmaf(u, k.fx, v * k.fy) + (Q - I));
+    float relax_num = fmaf(k.CvR, dp, k.D_r - de);
+    Y[iV] = fmaf(relax_num, itau, rho * Q);
+    for (int c = 0; c < NC; c++) {
+        float div = NC == 5 ? dF[c] + dG[c] : dF[c];
+        Unew[c] = fmaf(dt, Y[c], fmaf(-dtdx, div, Un[c]));
+    }
+    float dv = dt * Y[iV];
+    if (k.dt * itau > k.stiff_z) {
+        // exact relaxation from the start-of-step E_nu, FP64 factor
+        float num = fmaf(k.CvR, dp, k.D_r - Un[iV]);
+        float dEr = (float)((double)num * (-expm1(-k.dt64 * (double)itau)));
+        dv = fmaf(dt, rho * Q, dEr);
+        float div = NC == 5 ? dF[iV] + dG[iV] : dF[iV];
+        Unew[iV] = dv + fmaf(-dtdx, div, Un[iV]);
+    }
+    srcE = dt * Y[iP];
+    srcV = dv;
+}
+
+}  // namespace ng

@@ -1,0 +1,76 @@
+// ng_internal.hpp -- data shared by the host side of the library and its HIP
+// kernels: per-solve descriptors, mutable per-solve control blocks and the
+// per-workgroup reduction records of one step.
+//
+// Device memory of one solve (inside the caller's buffer):
+//   [buffer A: planes x ncell reals][buffer B: same][partials][workgroup table]
+// Planes are the conserved components (rho, rho u, [rho v], E, E_nu), each a
+// contiguous row-major plane with x fastest (cell (j, k) at k*nx + j).  The FP32
+// path stores deviations from a uniform reference state U_ref.
+#pragma once
+
+#include <stdint.h>
+
+namespace ng {
+
+constexpr int kWave = 64;          // CDNA wavefront width
+constexpr int kHalo = 2;           // ghost cells per side of the stencil
+constexpr int kInterior = kWave - 2 * kHalo;  // cells a wave updates per row
+constexpr int kMaxWaves = 8;       // waves per workgroup, upper bound
+
+// Run-constant description of one solve.
+struct InstDesc {
+    int64_t nx, ny, ncell;
+    int32_t ndim, riemann;
+    int32_t nstrips;          // 2D: column strips of kInterior cells; 1D: segments
+    int32_t rows_per_item;    // 2D: rows per work item; 1D: segments per work item
+    int32_t nchunks;          // 2D: row chunks; 1D: segment groups
+    int32_t waves_per_block;
+    int64_t nitems;           // nstrips * nchunks (2D) or nchunks (1D)
+    int64_t nblocks;          // workgroups of this solve's step launch
+    uint64_t buf[2];          // device addresses of the two state buffers
+    uint64_t partials;        // device address of the per-workgroup records
+    // numerics
+    double h, cfl, stiff_z;
+    // gas, eqs. (5)-(7)
+    double gamma, gm1, R, Cv;
+    double rho0, T0, tau0, tau_rho, tau_T, Q0, Q_rho, Q_T, I0, I_rho, I_T;
+    double fx, fy;
+    // reference state of the FP32 deviation storage (zero for FP64)
+    double uref[5];           // (rho_r, 0, 0, E_r, Ev_r)
+    double p_r, H_r, D_r;     // p_r, E_r + p_r, Cv/R p_r - Ev_r
+};
+
+// Mutable per-solve state, advanced by the finalize kernel.
+struct InstCtrl {
+    double t;                 // time of the state in buf[cur]
+    double dt_cfl;            // CFL step of eq. (16) for that state
+    double dt_last;           // last step taken
+    double t_end;             // stop time (+inf: none)
+    int64_t steps;            // steps taken
+    int64_t max_steps;        // stop after this many steps
+    int32_t cur;              // buffer holding the current state
+    int32_t status;           // 0 or NG_EPHYS (sticky)
+    uint32_t flags;           // NG_FLAG_* of the current state / last failure
+    int32_t reported;         // host bookkeeping for batch polling
+    double total[5];          // sum over cells of U (full values, FP64)
+    double budget[2];         // sum over steps and cells of the source increments
+    double rho_min, p_min, smax;
+};
+
+// One workgroup's reduction record of a step (or of the priming pass).
+struct Partial {
+    double tot[5];
+    double src[2];
+    double smax, rho_min, p_min;
+    uint32_t flags;
+    uint32_t pad;
+};
+
+// Workgroup -> (solve, local workgroup) map of one batched launch.
+struct BlockRef {
+    int32_t inst;
+    int32_t local;
+};
+
+}  // namespace ng

@@ -1,0 +1,22 @@
+// ng_launch.hpp -- host-callable launchers of the HIP kernels (ng_kernels.hip).
+// dim: 1 or 2; prec: 0 = FP64, 1 = FP32.  All launches are asynchronous on s.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ng_internal.hpp"
+
+namespace ng {
+
+hipError_t launch_step(int dim, int prec, const InstDesc* descs, InstCtrl* ctrls,
+                       const BlockRef* blocks, int64_t nblocks, int waves, int remap,
+                       hipStream_t s);
+hipError_t launch_prime(int dim, int prec, const InstDesc* descs, InstCtrl* ctrls,
+                        const BlockRef* blocks, int64_t nblocks, int waves, hipStream_t s);
+hipError_t launch_finalize(const InstDesc* descs, InstCtrl* ctrls, const int32_t* insts, int n,
+                           int mode, hipStream_t s);
+hipError_t launch_set_limits(InstCtrl* ctrls, const int32_t* insts, int n, double t_end,
+                             int64_t max_steps_from_now, hipStream_t s);
+
+}  // namespace ng

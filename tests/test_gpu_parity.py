@@ -1,0 +1,204 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars (per conserved component c, over all cells):
+  FP64: max|a - b| / max|b| <= 1e-12   (bit-level agreement is expected apart
+        from the last-ulp differences of the device's log/exp against libm)
+  FP32: sum|a - b| / sum|b| <= 1e-5    (flows without shocks)
+Inputs are seeded and synthetic (paper_1805_03442_amd.workloads); sizes span
+several 60-cell strips and row chunks with ragged tails.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1805_03442_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+FP32_TOL = 1e-5
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ng():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1805_03442_amd import ng as _ng
+    _ng.lib()
+    return _ng
+
+
+def rel_linf(a, b):
+    errs = []
+    for c in range(a.shape[0]):
+        den = np.max(np.abs(b[c]))
+        num = np.max(np.abs(a[c] - b[c]))
+        errs.append(num / den if den > 0 else num)
+    return np.array(errs)
+
+
+def rel_l1(a, b):
+    errs = []
+    for c in range(a.shape[0]):
+        den = np.sum(np.abs(b[c]))
+        num = np.sum(np.abs(a[c] - b[c]))
+        errs.append(num / den if den > 0 else num)
+    return np.array(errs)
+
+
+def comps(ny):
+    return [0, 1, 3, 4] if ny == 1 else [0, 1, 2, 3, 4]
+
+
+def run_both(ng, gas, W, nx, ny, steps, precision, riemann=0, stiff_z=0.5, launch=None,
+             t_end=None):
+    import oracle
+    oracle.build()
+    P = oracle.Problem(gas, nx, ny, riemann=riemann, stiff_z=stiff_z)
+    U0 = P.prim_to_cons(W)
+    say(f"case nx={nx} ny={ny} steps={steps} prec={precision} riemann={riemann} launch={launch}")
+    s = ng.Solver(gas, nx, ny, U=U0, precision=precision, riemann=riemann, stiff_z=stiff_z)
+    if launch:
+        s.set_launch(*launch)
+    if t_end is None:
+        s.step(steps)
+        ref = P.run(U0, steps)
+    else:
+        s.run_to_time(t_end, steps)
+        ref = P.run(U0, steps, t_end=t_end)
+    U = s.conserved()
+    d = s.diagnostics()
+    s.close()
+    assert ref["status"] == 0
+    return U, ref, d, U0
+
+
+@pytest.mark.parametrize("riemann", [0, 1])
+def test_fp64_1d_acoustic_2000_steps(ng, riemann):
+    w = wl.workload_1d_acoustic()
+    U, ref, d, _ = run_both(ng, w["gas"], w["W"], 1024, 1, 2000, ng.NG_FP64, riemann)
+    assert d["steps"] == 2000 and d["status"] == 0
+    e = rel_linf(U[comps(1)], ref["U"][comps(1)])
+    say(f"fp64 1d rel_linf {e}")
+    assert np.all(e <= FP64_TOL), e
+    assert d["t"] == pytest.approx(ref["t"], rel=1e-14)
+
+
+@pytest.mark.parametrize("shape", [(150, 130), (61, 64), (256, 37)])
+def test_fp64_2d_ragged(ng, shape):
+    nx, ny = shape
+    gas = dict(wl.BASE_GAS, Q_T=2.0)
+    r = np.random.Generator(np.random.PCG64(11 + nx))
+    W = wl.random_field_2d(gas, max(nx, ny), r, kmax=8, rms=2e-2)[:, :ny, :nx].copy()
+    W[1] = 0.05 * np.sin(2 * np.pi * np.arange(nx) / nx)[None, :]
+    W[2] = 0.03 * np.cos(2 * np.pi * np.arange(ny) / ny)[:, None]
+    for riemann in (0, 1):
+        U, ref, d, _ = run_both(ng, gas, W, nx, ny, 40, ng.NG_FP64, riemann)
+        e = rel_linf(U, ref["U"])
+        say(f"fp64 2d {shape} riemann={riemann} rel_linf {e}")
+        assert np.all(e <= FP64_TOL), e
+
+
+def test_fp64_totals_and_budget(ng):
+    gas = dict(wl.BASE_GAS, Q_T=2.0)
+    n = 96
+    W = wl.random_field_2d(gas, n, np.random.Generator(np.random.PCG64(5)), kmax=6, rms=3e-2)
+    U, ref, d, U0 = run_both(ng, gas, W, n, n, 25, ng.NG_FP64)
+    h2 = (1.0 / n) ** 2
+    for c in range(5):
+        tot = ref["U"][c].sum() * h2
+        assert d["total"][c] == pytest.approx(tot, rel=1e-12, abs=1e-15)
+    assert d["src_budget"][0] == pytest.approx(ref["budget"][0] * h2, rel=1e-9, abs=1e-18)
+    assert d["src_budget"][1] == pytest.approx(ref["budget"][1] * h2, rel=1e-9, abs=1e-18)
+
+
+def test_fp64_stiff_branch(ng):
+    """tau0 small enough that dt/tau exceeds the threshold: the exact
+    exponential relaxation of both predictor and corrector."""
+    gas = dict(wl.BASE_GAS, tau0=1e-4, Q0=0.0, I0=0.0)
+    n = 256
+    W = wl.multimode_1d(gas, n, np.random.Generator(np.random.PCG64(2)), nmodes=6, kmax=10,
+                        sigma=2e-2)
+    W[4, 0] *= 1.01
+    U, ref, d, _ = run_both(ng, gas, W, n, 1, 150, ng.NG_FP64)
+    e = rel_linf(U[comps(1)], ref["U"][comps(1)])
+    say(f"fp64 stiff rel_linf {e}")
+    assert np.all(e <= FP64_TOL), e
+
+
+def test_fp64_run_to_time(ng):
+    w = wl.workload_1d_acoustic()
+    U, ref, d, _ = run_both(ng, w["gas"], w["W"], 1024, 1, 10 ** 6, ng.NG_FP64, t_end=0.05)
+    assert d["t"] == 0.05 and ref["t"] == 0.05
+    assert d["steps"] == ref["steps"]
+    e = rel_linf(U[comps(1)], ref["U"][comps(1)])
+    assert np.all(e <= FP64_TOL), e
+
+
+@pytest.mark.parametrize("case", ["1d_acoustic", "1d_multimode_small", "2d_random_small"])
+def test_fp32_against_oracle(ng, case):
+    if case == "1d_acoustic":
+        w = wl.workload_1d_acoustic()
+        gas, W, nx, ny, steps = w["gas"], w["W"], 1024, 1, 2000
+    elif case == "1d_multimode_small":
+        gas = dict(wl.BASE_GAS, Q_T=2.0)
+        nx, ny, steps = 4096, 1, 3000
+        W = wl.multimode_1d(gas, nx, wl.rng(2), nmodes=64, kmax=256)
+    else:
+        gas = dict(wl.BASE_GAS, Q_T=2.0)
+        nx = ny = 256
+        steps = 300
+        W = wl.random_field_2d(gas, nx, wl.rng(3), kmax=64)
+    U, ref, d, U0 = run_both(ng, gas, W, nx, ny, steps, ng.NG_FP32)
+    cs = comps(ny)
+    e = rel_l1(U[cs], ref["U"][cs])
+    # error on the perturbation itself (stricter, reported)
+    ed = rel_l1((U - U0)[cs], (ref["U"] - U0)[cs])
+    say(f"fp32 {case} rel_l1 {e}  perturbation rel_l1 {ed}")
+    assert np.all(e <= FP32_TOL), e
+
+
+def test_launch_shape_does_not_change_results(ng):
+    gas = dict(wl.BASE_GAS, Q_T=2.0)
+    nx, ny = 200, 90
+    W = wl.random_field_2d(gas, 200, np.random.Generator(np.random.PCG64(9)), kmax=10,
+                           rms=1e-2)[:, :ny, :].copy()
+    outs = []
+    for prec in (ng.NG_FP32, ng.NG_FP64):
+        res = []
+        for launch in ((4, 1), (32, 4), (17, 2), (90, 4)):
+            U, ref, d, _ = run_both(ng, gas, W, nx, ny, 15, prec, launch=launch)
+            res.append(U)
+        for r in res[1:]:
+            assert np.array_equal(r, res[0])
+    # 1D segment groups
+    w = wl.workload_1d_acoustic()
+    res = []
+    for launch in ((1, 1), (8, 4), (3, 2)):
+        U, ref, d, _ = run_both(ng, w["gas"], w["W"], 1024, 1, 50, ng.NG_FP32, launch=launch)
+        res.append(U)
+    for r in res[1:]:
+        assert np.array_equal(r, res[0])
+
+
+def test_translation_invariance_on_gpu(ng):
+    gas = dict(wl.BASE_GAS, Q_T=2.0)
+    n = 128
+    W = wl.random_field_2d(gas, n, np.random.Generator(np.random.PCG64(4)), kmax=10, rms=1e-2)
+    Ws = np.roll(np.roll(W, 37, axis=2), 11, axis=1)
+    for prec in (ng.NG_FP32, ng.NG_FP64):
+        a = ng.Solver(gas, n, n, W=W, precision=prec)
+        b = ng.Solver(gas, n, n, W=Ws, precision=prec)
+        a.step(20)
+        b.step(20)
+        Ua, Ub = a.conserved(), b.conserved()
+        assert np.array_equal(np.roll(np.roll(Ua, 37, axis=2), 11, axis=1), Ub)
+        a.close()
+        b.close()

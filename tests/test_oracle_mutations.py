@@ -60,7 +60,8 @@ MUTATIONS = {
     "stiff_branch_sign": [
         ("double dEr = (Ee - Un[4]) * (-expm1(-z));", "double dEr = (Ee - Un[4]) * (expm1(-z));")],
     "tau_wrong_exponent": [
-        ("pow(T / g->T0, g->tau_T);", "pow(T / g->T0, g->tau_rho);")],
+        ("or_pow(T / g->T0, g->tau_T);", "or_pow(T / g->T0, g->tau_rho);")],
+    "power_law_half_exponent": [("if (a == 0.5) return sqrt(x);", "if (a == 0.5) return x;")],
 }
 
 
