@@ -1,0 +1,203 @@
+#!/usr/bin/env python3
+"""Throughput of the fused FP32 MUSCL step on a 2D periodic 4096 x 4096 grid.
+
+One step = one pass of the whole hot path over the grid: primitive recovery,
+limited slopes, half-step predictor, HLLC face fluxes, sources, the
+conservative update of eq. (15), the signal-speed maximum for the next dt of
+eq. (16), FP64 totals and source budgets, and the per-solve reduction that
+accepts the step and advances t.
+
+Prints one JSON line:
+  value       cell-updates/s over the timed steps (state resident in HBM)
+  roofline    the step kernel's algorithmic bytes per launch (40 B per cell:
+              read 5 FP32 planes, write 5) over its mean launch time from HIP
+              events on its stream, against the 8 TB/s HBM peak; traffic from
+              the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary when it was
+              taken on the current kernel source, else null
+  fp64        the same workload through the FP64 path (comparison)
+  cpu_baseline  the serial FP64 oracle on one full step of the same grid
+Input: seeded synthetic isotropic k^-2 density field (|k| <= 64, rms 1e-3),
+isentropic pressure, fluid at rest; gas of eqs. (1)-(7) with Q_T = 2.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_CELL_FP32 = 40.0   # 5 conserved planes read + 5 written, 4 B each
+BYTES_PER_CELL_FP64 = 80.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step2d_fp32_4096_traffic.json")
+KERNEL_SOURCES = ["paper_1805_03442_amd/csrc/ng_kernels.hip",
+                  "paper_1805_03442_amd/csrc/ng_cell.hpp",
+                  "paper_1805_03442_amd/csrc/ng_internal.hpp"]
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_record():
+    """Measured HBM bytes per launch of the step kernel, if the committed
+    counter summary matches the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_hash") != kernel_hash():
+        return None
+    return rec
+
+
+def timed_run(ng, torch, gas, W, n, steps, warmup, precision, launch=None):
+    s = ng.Solver(gas, n, n, W=W, precision=precision)
+    if launch:
+        s.set_launch(*launch)
+    s.step(warmup)
+    torch.cuda.synchronize()
+    s.enable_timing(steps)
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(st)
+    s.step(steps)
+    e1.record(st)
+    torch.cuda.synchronize()
+    total_ms = e0.elapsed_time(e1)
+    step_ms, fin_ms, launches = s.kernel_time()
+    d = s.diagnostics()
+    s.close()
+    return dict(total_ms=total_ms, step_ms=step_ms, fin_ms=fin_ms, launches=launches, diag=d)
+
+
+def cpu_baseline(gas, W, n):
+    import oracle
+    oracle.build()
+    P = oracle.Problem(gas, n, n)
+    U = P.prim_to_cons(W)
+    t0 = time.perf_counter()
+    dt = P.dt(U)
+    st, V, _ = P.step(U, dt)
+    el = time.perf_counter() - t0
+    assert st == 0
+    return dict(value=n * n / el, unit="cell-updates/s", cores=1, kind="oracle",
+                sample=f"one full step (dt from eq. (16) + the update) of the {n}x{n} grid, "
+                       f"serial FP64 C oracle, {el:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--fp64-steps", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain device copy of known size (for counter scaling)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1805_03442_amd import ng, workloads as wl
+    assert torch.cuda.is_available(), "needs a GPU"
+    torch.cuda.set_device(0)
+    ng.lib()
+
+    n = args.n
+    log(f"[bench] building the {n}x{n} synthetic input")
+    gas = dict(wl.BASE_GAS, Q_T=2.0)
+    W = wl.random_field_2d(gas, n, wl.rng(3))
+
+    log(f"[bench] FP32: warmup {args.warmup}, timing {args.steps} steps")
+    r32 = timed_run(ng, torch, gas, W, n, args.steps, args.warmup, ng.NG_FP32)
+    cells = float(n) * n
+    ms_per_step = r32["total_ms"] / args.steps
+    value = cells * args.steps / (r32["total_ms"] * 1e-3)
+    achieved = BYTES_PER_CELL_FP32 * cells / (r32["step_ms"] * 1e-3) / 1e9
+    log(f"[bench] FP32 {ms_per_step:.4f} ms/step, step kernel {r32['step_ms']:.4f} ms, "
+        f"finalize {r32['fin_ms']:.4f} ms, {value:.3e} cell-updates/s")
+
+    tr = traffic_record()
+    traffic = None
+    if tr is not None:
+        traffic = tr["bytes_per_launch"]
+
+    out = {
+        "metric": "cell-updates/s (FP32 fused MUSCL step, 2D 4096^2) + %HBM roofline",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"2d_periodic_{n}x{n}_random_field_fp32", "nx": n, "ny": n,
+                   "precision": "fp32 deviations, fp64 totals", "riemann": "hllc",
+                   "cfl": 0.4, "Q_T": 2.0},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "step2d_kernel<Dev32<5>>",
+                     "kernel_ms": r32["step_ms"], "algorithmic_bytes_per_launch":
+                         BYTES_PER_CELL_FP32 * cells},
+    }
+
+    if not args.no_fp64:
+        log(f"[bench] FP64: timing {args.fp64_steps} steps")
+        r64 = timed_run(ng, torch, gas, W, n, args.fp64_steps, 5, ng.NG_FP64)
+        v64 = cells * args.fp64_steps / (r64["total_ms"] * 1e-3)
+        out["fp64"] = {"value": v64, "unit": "cell-updates/s",
+                       "ms_per_step": r64["total_ms"] / args.fp64_steps,
+                       "step_kernel_ms": r64["step_ms"],
+                       "hbm_frac": BYTES_PER_CELL_FP64 * cells / (r64["step_ms"] * 1e-3) / 1e9
+                       / HBM_PEAK_GBS,
+                       "steps": args.fp64_steps}
+        log(f"[bench] FP64 {v64:.3e} cell-updates/s")
+
+    if args.calibrate_copy:
+        nbytes = 1 << 30
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: 3 copies of {nbytes} bytes")
+
+    if not args.no_cpu_baseline:
+        log("[bench] CPU baseline: one oracle step of the full grid")
+        out["cpu_baseline"] = cpu_baseline(gas, W, n)
+        log(f"[bench] oracle {out['cpu_baseline']['value']:.3e} cell-updates/s")
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -175,10 +175,13 @@ int ng_set_launch(ng_solver* s, int32_t rows_per_item, int32_t waves_per_block);
 /* Steps per captured graph in ng_run_to_time (default 64). */
 int ng_set_graph_steps(ng_solver* s, int32_t steps);
 
-/* Average duration in milliseconds of the step kernel over the last
- * ng_step call, measured with HIP events around each launch when timing was
- * enabled by ng_enable_timing(s, 1).  Synchronising. */
-int ng_enable_timing(ng_solver* s, int32_t on);
+/* Kernel timing: ng_enable_timing(s, nsteps) with nsteps > 0 makes later
+ * ng_step calls launch each step directly with HIP events on the solver's
+ * stream around the step and finalize kernels (events for nsteps steps are
+ * created here, outside any timed region); 0 turns it off.  ng_kernel_time
+ * returns the mean durations in milliseconds over the last timed ng_step call
+ * and the number of step launches timed. */
+int ng_enable_timing(ng_solver* s, int32_t nsteps);
 int ng_kernel_time(ng_solver* s, double* step_ms, double* finalize_ms, int64_t* launches);
 
 const char* ng_last_error(const ng_solver* s);

@@ -930,10 +930,12 @@ int ng_set_graph_steps(ng_solver* s, int32_t steps)
     return NG_OK;
 }
 
-int ng_enable_timing(ng_solver* s, int32_t on)
+int ng_enable_timing(ng_solver* s, int32_t nsteps)
 {
-    if (!s) return NG_EINVAL;
-    s->b->timing = on != 0;
+    if (!s || nsteps < 0) return NG_EINVAL;
+    s->b->timing = nsteps != 0;
+    size_t need = (size_t)nsteps * 3 * 2;
+    if (need && !get_event(s->b, need - 1)) return solver_rc(s, dev_err(s->b, hipErrorOutOfMemory, "hipEventCreate"));
     return NG_OK;
 }
 

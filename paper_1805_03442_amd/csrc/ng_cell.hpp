@@ -178,7 +178,7 @@ __device__ __forceinline__ void predict64(const K64& k, const double* W, const d
 // returns (mass, normal momentum, [tangential momentum], energy, E_nu) fluxes.
 // HLL: eq. (13) with the wave speeds printed under it; HLLC: three waves, the
 // middle one from equal pressure and normal velocity across the contact.
-template <int NC>
+template <int NC, int RS>
 __device__ __forceinline__ void flux64(const K64& k, const double* WL, const double* WR,
                                        double* F)
 {
@@ -235,7 +235,7 @@ __device__ __forceinline__ void flux64(const K64& k, const double* WL, const dou
     double SL = fmin(uL - cL, uR - cR);
     double SR = fmax(uL + cL, uR + cR);
 
-    if (k.riemann == 1) {
+    if (RS == 1) {
         // HLL, eq. (13)
         double inv = SR - SL;
         for (int c = 0; c < NC; c++) {
@@ -328,6 +328,13 @@ __device__ __forceinline__ void update64(const K64& k, const double* Un, const d
 
 __device__ __forceinline__ float rcp32(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// E_nu change of an exact relaxation over a time z tau: num (1 - exp(-z)),
+// evaluated in FP64 (kept out of line: it runs only where dt/tau is large)
+__device__ __noinline__ float relax_exact(float num, double z)
+{
+    return (float)((double)num * (-expm1(-z)));
+}
+
 struct K32 {
     float gam, gm1, igm1, CvR;
     float rho_r, p_r, ev_r, H_r, D_r;   // reference state and its cancelled constants
@@ -341,26 +348,17 @@ struct K32 {
     int riemann;
 };
 
-// x^a in FP32: exact-operation exponents as in FP64, others exp2(a log2 x)
-__device__ __forceinline__ float powr32(float x, float a)
-{
-    if (a == 0.0f) return 1.0f;
-    if (a == 1.0f) return x;
-    if (a == -1.0f) return rcp32(x);
-    if (a == 2.0f) return x * x;
-    if (a == 0.5f) return __builtin_sqrtf(x);
-    return __builtin_amdgcn_exp2f(a * __builtin_amdgcn_logf(x));
-}
-
-// 1/tau, Q and I of eq. (6) at full (rho, p), T/T0 = p/(R rho T0)
+// 1/tau, Q and I of eq. (6) at full (rho, p) in FP32: with lr = log2(rho/rho0)
+// and lt = log2(T/T0), T/T0 = p/(R rho T0), each power law is one exp2 of a
+// linear form (no branch on the exponents).
 __device__ __forceinline__ void closures32(const K32& k, float rho, float p, float irho,
                                            float& itau, float& Q, float& I)
 {
-    float r = rho * k.irho0;
-    float t = p * k.iRT0 * irho;
-    itau = k.itau0 * powr32(r, -k.tr) * powr32(t, -k.tT);
-    Q = k.Q0 * powr32(r, k.Qr) * powr32(t, k.QT);
-    I = k.I0 * powr32(r, k.Ir) * powr32(t, k.IT);
+    float lr = __builtin_amdgcn_logf(rho * k.irho0);
+    float lt = __builtin_amdgcn_logf(p * k.iRT0 * irho);
+    itau = k.itau0 * __builtin_amdgcn_exp2f(-fmaf(k.tr, lr, k.tT * lt));
+    Q = k.Q0 * __builtin_amdgcn_exp2f(fmaf(k.Qr, lr, k.QT * lt));
+    I = k.I0 * __builtin_amdgcn_exp2f(fmaf(k.Ir, lr, k.IT * lt));
 }
 
 // deviation primitives (d rho, u, [v], dp, dEv) from deviation conserved
@@ -387,15 +385,17 @@ __device__ __forceinline__ void prim32(const K32& k, const float* D, float* W)
     }
 }
 
+// signal speed of eq. (16) in FP32; c = sqrt(gamma p / rho) as
+// gamma p rsqrt(gamma p rho)
 template <int NC>
 __device__ __forceinline__ float speed32(const K32& k, const float* W)
 {
     float rho = k.rho_r + W[0];
     float u = W[1];
     float v2 = NC == 5 ? W[2] * W[2] : 0.0f;
-    float p = k.p_r + W[NC == 5 ? 3 : 2];
+    float gp = k.gam * (k.p_r + W[NC == 5 ? 3 : 2]);
     float vel = __builtin_sqrtf(fmaf(u, u, v2));
-    float c = __builtin_sqrtf(k.gam * p * rcp32(rho));
+    float c = gp * __builtin_amdgcn_rsqf(gp * rho);
     return fmaxf(vel + c, 2.0f * vel);
 }
 
@@ -430,7 +430,7 @@ __device__ __forceinline__ void predict32(const K32& k, const float* W, const fl
     float relax_num = fmaf(k.CvR, dp, k.D_r - de);   // E_nue - E_nu
     float dEr;
     if (k.dt * itau > k.stiff_z)
-        dEr = (float)((double)relax_num * (-expm1(-k.hdt64 * (double)itau)));
+        dEr = relax_exact(relax_num, k.hdt64 * (double)itau);
     else
         dEr = hdt * (relax_num * itau);
     Wh[0] = fmaf(-hdtdx, a_r, dr);
@@ -440,56 +440,56 @@ __device__ __forceinline__ void predict32(const K32& k, const float* W, const fl
     Wh[iV] = fmaf(hdt, rho * Q, dEr) + fmaf(-hdtdx, a_e, de);
 }
 
-// interface flux minus the flux of the reference state, face states in
-// deviation primitives
-template <int NC>
+// Interface flux minus the flux of the reference state, face states in
+// deviation primitives.  HLLC is evaluated on one side only: the side K whose
+// flux the face takes (L if 0 < S_L or 0 < S*, else R) gives
+// F = F_K + S_K (U*_K - U_K), with the star jump zero on supersonic faces.
+template <int NC, int RS>
 __device__ __forceinline__ void flux32(const K32& k, const float* WL, const float* WR, float* F)
 {
     constexpr int iP = NC == 5 ? 3 : 2, iV = NC == 5 ? 4 : 3;
     const float gam = k.gam;
     float rL = k.rho_r + WL[0], rR = k.rho_r + WR[0];
     float uL = WL[1], uR = WR[1];
-    float vL = NC == 5 ? WL[2] : 0.0f, vR = NC == 5 ? WR[2] : 0.0f;
     float dpL = WL[iP], dpR = WR[iP];
-    float deL = WL[iV], deR = WR[iV];
-    float pL = k.p_r + dpL, pR = k.p_r + dpR;
-    float evL = k.ev_r + deL, evR = k.ev_r + deR;
-    // deviation conserved face states
-    float mL = rL * uL, mR = rR * uR;
-    float keL = 0.5f * rL * (NC == 5 ? fmaf(uL, uL, vL * vL) : uL * uL);
-    float keR = 0.5f * rR * (NC == 5 ? fmaf(uR, uR, vR * vR) : uR * uR);
-    float dEL = fmaf(dpL, k.igm1, keL) + deL;
-    float dER = fmaf(dpR, k.igm1, keR) + deR;
-    float HL = k.H_r + (dEL + dpL), HR = k.H_r + (dER + dpR);   // E + p
-    float UL[5], UR[5], FL[5], FR[5];
-    UL[0] = WL[0];
-    UR[0] = WR[0];
-    UL[1] = mL;
-    UR[1] = mR;
-    FL[0] = mL;
-    FR[0] = mR;
-    FL[1] = fmaf(mL, uL, dpL);
-    FR[1] = fmaf(mR, uR, dpR);
-    if (NC == 5) {
-        UL[2] = rL * vL;
-        UR[2] = rR * vR;
-        FL[2] = mL * vL;
-        FR[2] = mR * vR;
-    }
-    UL[iP] = dEL;
-    UR[iP] = dER;
-    UL[iV] = deL;
-    UR[iV] = deR;
-    FL[iP] = uL * HL;
-    FR[iP] = uR * HR;
-    FL[iV] = uL * evL;
-    FR[iV] = uR * evR;
-
-    float cL = __builtin_sqrtf(gam * pL * rcp32(rL));
-    float cR = __builtin_sqrtf(gam * pR * rcp32(rR));
+    float gpL = gam * (k.p_r + dpL), gpR = gam * (k.p_r + dpR);
+    float cL = gpL * __builtin_amdgcn_rsqf(gpL * rL);
+    float cR = gpR * __builtin_amdgcn_rsqf(gpR * rR);
     float SL = fminf(uL - cL, uR - cR);
     float SR = fmaxf(uL + cL, uR + cR);
-    if (k.riemann == 1) {
+    float mL = rL * uL, mR = rR * uR;
+    if (RS == 1) {
+        // HLL, eq. (13), with both physical fluxes
+        float vL = NC == 5 ? WL[2] : 0.0f, vR = NC == 5 ? WR[2] : 0.0f;
+        float deL = WL[iV], deR = WR[iV];
+        float keL = 0.5f * rL * (NC == 5 ? fmaf(uL, uL, vL * vL) : uL * uL);
+        float keR = 0.5f * rR * (NC == 5 ? fmaf(uR, uR, vR * vR) : uR * uR);
+        float dEL = fmaf(dpL, k.igm1, keL) + deL;
+        float dER = fmaf(dpR, k.igm1, keR) + deR;
+        float HL = k.H_r + (dEL + dpL), HR = k.H_r + (dER + dpR);
+        float UL[5], UR[5], FL[5], FR[5];
+        UL[0] = WL[0];
+        UR[0] = WR[0];
+        UL[1] = mL;
+        UR[1] = mR;
+        FL[0] = mL;
+        FR[0] = mR;
+        FL[1] = fmaf(mL, uL, dpL);
+        FR[1] = fmaf(mR, uR, dpR);
+        if (NC == 5) {
+            UL[2] = rL * vL;
+            UR[2] = rR * vR;
+            FL[2] = mL * vL;
+            FR[2] = mR * vR;
+        }
+        UL[iP] = dEL;
+        UR[iP] = dER;
+        UL[iV] = deL;
+        UR[iV] = deR;
+        FL[iP] = uL * HL;
+        FR[iP] = uR * HR;
+        FL[iV] = uL * (k.ev_r + deL);
+        FR[iV] = uR * (k.ev_r + deR);
         float inv = rcp32(SR - SL);
         float SLR = SL * SR;
         for (int c = 0; c < NC; c++) {
@@ -500,24 +500,23 @@ __device__ __forceinline__ void flux32(const K32& k, const float* WL, const floa
     }
     float dL = SL - uL, dR = SR - uR;
     float Ss = ((dpR - dpL) + (mL * dL - mR * dR)) * rcp32(rL * dL - rR * dR);
-    bool left = 0.0f < Ss;
-    float rK = left ? rL : rR, uK = left ? uL : uR;
-    float SK = left ? SL : SR, dK = left ? dL : dR;
-    float HK = left ? HL : HR, evK = left ? evL : evR;
-    float q = (Ss - uK) * rcp32(SK - Ss);
-    float rq = rK * q;
-    float dU[5];
-    dU[0] = rq;
-    dU[1] = rq * SK;
-    if (NC == 5) dU[2] = rq * (left ? vL : vR);
-    dU[iP] = q * fmaf(rK * dK, Ss, HK);
-    dU[iV] = q * evK;
-    bool star = left || (0.0f <= SR);
-    for (int c = 0; c < NC; c++) {
-        float FK = left ? FL[c] : FR[c];
-        float fs = fmaf(SK, dU[c], FK);
-        F[c] = (0.0f < SL) ? FL[c] : (star ? fs : FR[c]);
-    }
+    const bool supL = 0.0f < SL, supR = SR < 0.0f;
+    const bool left = supL || (!supR && 0.0f < Ss);
+    float rK = left ? rL : rR, uK = left ? uL : uR, dpK = left ? dpL : dpR;
+    float deK = left ? WL[iV] : WR[iV];
+    float vK = NC == 5 ? (left ? WL[2] : WR[2]) : 0.0f;
+    float SK = left ? SL : SR, dK = left ? dL : dR, mK = left ? mL : mR;
+    float keK = 0.5f * rK * (NC == 5 ? fmaf(uK, uK, vK * vK) : uK * uK);
+    float dEK = fmaf(dpK, k.igm1, keK) + deK;
+    float HK = k.H_r + (dEK + dpK);   // E + p
+    float evK = k.ev_r + deK;
+    float q = (supL || supR) ? 0.0f : (Ss - uK) * rcp32(SK - Ss);
+    float sq = SK * q;
+    F[0] = fmaf(sq, rK, mK);
+    F[1] = fmaf(sq * rK, SK, fmaf(mK, uK, dpK));
+    if (NC == 5) F[2] = fmaf(sq * rK, vK, mK * vK);
+    F[iP] = fmaf(sq, fmaf(rK * dK, Ss, HK), uK * HK);
+    F[iV] = fmaf(sq, evK, uK * evK);
 }
 
 template <int NC>
@@ -548,7 +547,7 @@ __device__ __forceinline__ void update32(const K32& k, const float* Un, const fl
     if (k.dt * itau > k.stiff_z) {
         // exact relaxation from the start-of-step E_nu, FP64 factor
         float num = fmaf(k.CvR, dp, k.D_r - Un[iV]);
-        float dEr = (float)((double)num * (-expm1(-k.dt64 * (double)itau)));
+        float dEr = relax_exact(num, k.dt64 * (double)itau);
         dv = fmaf(dt, rho * Q, dEr);
         float div = NC == 5 ? dF[iV] + dG[iV] : dF[iV];
         Unew[iV] = dv + fmaf(-dtdx, div, Un[iV]);

@@ -33,20 +33,48 @@ namespace ng {
 
 // ------------------------------------------------------------ cross-lane
 
-__device__ __forceinline__ float lane_get(float v, int addr)
+// Whole-wavefront DPP shifts: from_left gives lane l the value of lane l-1,
+// from_right the value of lane l+1 (the end lanes get 0 through bound_ctrl;
+// they are halo lanes whose results are never used).
+__device__ __forceinline__ int dpp_l(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true); }
+__device__ __forceinline__ int dpp_r(int v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xf, 0xf, true); }
+__device__ __forceinline__ float from_left(float v) { return __int_as_float(dpp_l(__float_as_int(v))); }
+__device__ __forceinline__ float from_right(float v) { return __int_as_float(dpp_r(__float_as_int(v))); }
+__device__ __forceinline__ double from_left(double v)
 {
-    return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+    return __hiloint2double(dpp_l(__double2hiint(v)), dpp_l(__double2loint(v)));
 }
-__device__ __forceinline__ double lane_get(double v, int addr)
+__device__ __forceinline__ double from_right(double v)
 {
-    int lo = __double2loint(v), hi = __double2hiint(v);
-    lo = __builtin_amdgcn_ds_bpermute(addr, lo);
-    hi = __builtin_amdgcn_ds_bpermute(addr, hi);
-    return __hiloint2double(hi, lo);
+    return __hiloint2double(dpp_r(__double2hiint(v)), dpp_r(__double2loint(v)));
 }
+
+// keep a value computed here (stops it from being sunk into a later block,
+// away from the DPP move it combines with)
+__device__ __forceinline__ void pin(float& v) { asm volatile("" : "+v"(v)); }
+__device__ __forceinline__ void pin(double& v) { asm volatile("" : "+v"(v)); }
+
+// lane permute through the LDS crossbar (reductions only)
 __device__ __forceinline__ double lane_xor(double v, int lane, int m)
 {
-    return lane_get(v, ((lane ^ m) & 63) << 2);
+    const int addr = ((lane ^ m) & 63) << 2;
+    int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(v));
+    int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float lane_xor(float v, int lane, int m)
+{
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(((lane ^ m) & 63) << 2, __float_as_int(v)));
+}
+
+// index of a cell coordinate in [-2, n + 62) on a periodic axis of n >= 4
+// cells (one wrap suffices when n >= 64; short axes wrap several times)
+__device__ __forceinline__ int64_t wrap_axis(int64_t x, int64_t n)
+{
+    if (x < 0) x += n;
+    if (n >= kWave) return x >= n ? x - n : x;
+    while (x >= n) x -= n;
+    return x;
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs; hand each XCD a
@@ -99,15 +127,19 @@ struct Plain64 {
     {
         predict64<NC>(k, W, sx, sy, Wh);
     }
-    static __device__ void flux(const K& k, const R* L, const R* Rr, R* F) { flux64<NC>(k, L, Rr, F); }
+    template <int RS>
+    static __device__ void flux(const K& k, const R* L, const R* Rr, R* F)
+    {
+        flux64<NC, RS>(k, L, Rr, F);
+    }
     static __device__ void update(const K& k, const R* Un, const R* dF, const R* dG, const R* Wh,
                                   R* Unew, R& sE, R& sV)
     {
         update64<NC>(k, Un, dF, dG, Wh, Unew, sE, sV);
     }
     static __device__ R half() { return 0.5; }
-    static __device__ double full_rho(const K&, R r) { return r; }
-    static __device__ double full_p(const K&, R p) { return p; }
+    static __device__ R full_rho(const K&, R r) { return r; }
+    static __device__ R full_p(const K&, R p) { return p; }
 };
 
 template <int NC>
@@ -155,40 +187,46 @@ struct Dev32 {
     {
         predict32<NC>(k, W, sx, sy, Wh);
     }
-    static __device__ void flux(const K& k, const R* L, const R* Rr, R* F) { flux32<NC>(k, L, Rr, F); }
+    template <int RS>
+    static __device__ void flux(const K& k, const R* L, const R* Rr, R* F)
+    {
+        flux32<NC, RS>(k, L, Rr, F);
+    }
     static __device__ void update(const K& k, const R* Un, const R* dF, const R* dG, const R* Wh,
                                   R* Unew, R& sE, R& sV)
     {
         update32<NC>(k, Un, dF, dG, Wh, Unew, sE, sV);
     }
     static __device__ R half() { return 0.5f; }
-    static __device__ double full_rho(const K& k, R r) { return (double)(k.rho_r + r); }
-    static __device__ double full_p(const K& k, R p) { return (double)(k.p_r + p); }
+    static __device__ R full_rho(const K& k, R r) { return k.rho_r + r; }
+    static __device__ R full_p(const K& k, R p) { return k.p_r + p; }
 };
 
 // ------------------------------------------------------ reduction records
 
+// Per-lane accumulators of one work item: FP64 sums of the updated conserved
+// values and source increments, and the extrema in the working precision.
+template <class R>
 struct Acc {
     double tot[5];
     double src[2];
-    double smax, rmin, pmin;
-    uint32_t flags;
+    R smax, rmin, pmin;
 };
 
-__device__ __forceinline__ void acc_init(Acc& a)
+template <class R>
+__device__ __forceinline__ void acc_init(Acc<R>& a)
 {
     for (int c = 0; c < 5; c++) a.tot[c] = 0.0;
     a.src[0] = a.src[1] = 0.0;
-    a.smax = 0.0;
-    a.rmin = INFINITY;
-    a.pmin = INFINITY;
-    a.flags = 0u;
+    a.smax = (R)0;
+    a.rmin = (R)INFINITY;
+    a.pmin = (R)INFINITY;
 }
 
 // Record one updated cell: NC conserved values (as stored), its primitives
 // and signal speed, and its source increments.
 template <class P, int NC>
-__device__ __forceinline__ void acc_cell(Acc& a, const typename P::K& k,
+__device__ __forceinline__ void acc_cell(Acc<typename P::R>& a, const typename P::K& k,
                                          const typename P::R* U, const typename P::R* W,
                                          typename P::R s, typename P::R sE, typename P::R sV)
 {
@@ -203,46 +241,50 @@ __device__ __forceinline__ void acc_cell(Acc& a, const typename P::K& k,
     }
     a.src[0] += (double)sE;
     a.src[1] += (double)sV;
-    double rho = P::full_rho(k, W[0]);
-    double p = P::full_p(k, W[NC == 5 ? 3 : 2]);
-    double sd = (double)s;
-    a.smax = sd > a.smax ? sd : a.smax;
-    a.rmin = rho < a.rmin ? rho : a.rmin;
-    a.pmin = p < a.pmin ? p : a.pmin;
-    bool fin = true;
-    for (int c = 0; c < NC; c++) fin = fin && isfinite(U[c]);
-    fin = fin && isfinite(sd);
-    if (!fin) a.flags |= 1u;
-    if (!(rho > 0.0)) a.flags |= 2u;
-    if (!(p > 0.0)) a.flags |= 4u;
+    a.smax = fmax(a.smax, s);
+    a.rmin = fmin(a.rmin, P::full_rho(k, W[0]));
+    a.pmin = fmin(a.pmin, P::full_p(k, W[NC == 5 ? 3 : 2]));
+}
+
+// Failure flags of a lane: a non-finite value anywhere makes its sums
+// non-finite; min/max ignore NaN, so positivity is checked on the extrema.
+template <class R>
+__device__ __forceinline__ uint32_t acc_flags(const Acc<R>& a)
+{
+    double all = a.tot[0] + a.tot[1] + a.tot[2] + a.tot[3] + a.tot[4] + a.src[0] + a.src[1];
+    uint32_t f = 0u;
+    if (!isfinite(all)) f |= 1u;
+    if (!(a.rmin > (R)0)) f |= 2u;
+    if (!(a.pmin > (R)0)) f |= 4u;
+    return f;
 }
 
 // Fold the lanes of each wave (lane 0 keeps a fixed-order result), then the
 // waves of the workgroup in wave order, and store the workgroup's record.
-__device__ void block_reduce_store(Acc& a, Partial* out, int wave, int lane, int nwaves)
+template <class R>
+__device__ void block_reduce_store(Acc<R>& a, Partial* out, int wave, int lane, int nwaves)
 {
     __shared__ double sh[kMaxWaves][11];
     __shared__ uint32_t shf[kMaxWaves];
+    uint32_t flags = acc_flags(a);
+    double smax = (double)a.smax, rmin = (double)a.rmin, pmin = (double)a.pmin;
     for (int m = 32; m >= 1; m >>= 1) {
         for (int c = 0; c < 5; c++) a.tot[c] += lane_xor(a.tot[c], lane, m);
         a.src[0] += lane_xor(a.src[0], lane, m);
         a.src[1] += lane_xor(a.src[1], lane, m);
-        double o = lane_xor(a.smax, lane, m);
-        a.smax = o > a.smax ? o : a.smax;
-        o = lane_xor(a.rmin, lane, m);
-        a.rmin = o < a.rmin ? o : a.rmin;
-        o = lane_xor(a.pmin, lane, m);
-        a.pmin = o < a.pmin ? o : a.pmin;
-        a.flags |= (uint32_t)__builtin_amdgcn_ds_bpermute(((lane ^ m) & 63) << 2, (int)a.flags);
+        smax = fmax(smax, lane_xor(smax, lane, m));
+        rmin = fmin(rmin, lane_xor(rmin, lane, m));
+        pmin = fmin(pmin, lane_xor(pmin, lane, m));
+        flags |= (uint32_t)__builtin_amdgcn_ds_bpermute(((lane ^ m) & 63) << 2, (int)flags);
     }
     if (lane == 0) {
         for (int c = 0; c < 5; c++) sh[wave][c] = a.tot[c];
         sh[wave][5] = a.src[0];
         sh[wave][6] = a.src[1];
-        sh[wave][7] = a.smax;
-        sh[wave][8] = a.rmin;
-        sh[wave][9] = a.pmin;
-        shf[wave] = a.flags;
+        sh[wave][7] = smax;
+        sh[wave][8] = rmin;
+        sh[wave][9] = pmin;
+        shf[wave] = flags;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -258,9 +300,9 @@ __device__ void block_reduce_store(Acc& a, Partial* out, int wave, int lane, int
             for (int c = 0; c < 5; c++) r.tot[c] += sh[w][c];
             r.src[0] += sh[w][5];
             r.src[1] += sh[w][6];
-            r.smax = sh[w][7] > r.smax ? sh[w][7] : r.smax;
-            r.rho_min = sh[w][8] < r.rho_min ? sh[w][8] : r.rho_min;
-            r.p_min = sh[w][9] < r.p_min ? sh[w][9] : r.p_min;
+            r.smax = fmax(r.smax, sh[w][7]);
+            r.rho_min = fmin(r.rho_min, sh[w][8]);
+            r.p_min = fmin(r.p_min, sh[w][9]);
             r.flags |= shf[w];
         }
         *out = r;
@@ -301,6 +343,180 @@ __device__ __forceinline__ void load_cell_cached(const R* __restrict__ base, int
 
 // ================================================================ 2D step
 
+// The NC conserved planes of one state buffer: uniform base addresses and a
+// 32-bit byte offset per cell (planes are < 4 GiB).
+typedef __attribute__((address_space(1))) char gchar;
+
+template <class R, int NC>
+struct Planes {
+    typedef __attribute__((address_space(1))) R gR;
+    gchar* base[NC];
+    __device__ Planes(uint64_t buf, int64_t ncell)
+    {
+        for (int c = 0; c < NC; c++) base[c] = (gchar*)(buf + (uint64_t)(c * ncell * (int64_t)sizeof(R)));
+    }
+    __device__ __forceinline__ void load(uint32_t boff, R* U) const
+    {
+        for (int c = 0; c < NC; c++) U[c] = *(const gR*)(base[c] + (uint64_t)boff);
+    }
+    __device__ __forceinline__ void store(uint32_t boff, const R* U) const
+    {
+        for (int c = 0; c < NC; c++) __builtin_nontemporal_store(U[c], (gR*)(base[c] + (uint64_t)boff));
+    }
+};
+
+// y-face flux: the normal velocity is v, so the Riemann solver sees
+// (rho, v, u, p, E_nu) and returns (., G_v, G_u, ., .)
+template <class P, int RS>
+__device__ __forceinline__ void flux_y(const typename P::K& k, const typename P::R* N,
+                                       const typename P::R* S, typename P::R* G)
+{
+    using R = typename P::R;
+    R a[5] = {N[0], N[2], N[1], N[3], N[4]};
+    R b[5] = {S[0], S[2], S[1], S[3], S[4]};
+    R f[5];
+    P::template flux<RS>(k, a, b, f);
+    G[0] = f[0];
+    G[1] = f[2];
+    G[2] = f[1];
+    G[3] = f[3];
+    G[4] = f[4];
+}
+
+// One work item of the 2D step: strip (60 columns + halo) x chunk of rows.
+template <class P, int RS>
+__device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& k, int cur,
+                                        int64_t item, int lane, Acc<typename P::R>& acc)
+{
+    using R = typename P::R;
+    constexpr int NC = 5;
+    const R half = P::half();
+    const int64_t nx = d.nx, ny = d.ny;
+    const int64_t strip = item % d.nstrips, chunk = item / d.nstrips;
+    const int64_t x0 = strip * kInterior;
+    const int64_t x = wrap_axis(x0 - kHalo + lane, nx);
+    const bool inner = lane >= kHalo && lane < kWave - kHalo && x0 + (lane - kHalo) < nx;
+    const int64_t r0 = chunk * d.rows_per_item;
+    const int64_t r1 = r0 + d.rows_per_item < ny ? r0 + d.rows_per_item : ny;
+    const Planes<R, NC> src(d.buf[cur], d.ncell);
+    const Planes<R, NC> dst(d.buf[cur ^ 1], d.ncell);
+    // byte offset of (row r, this lane's column); r within two rows of [0, ny)
+    auto boff = [&](int64_t r) -> uint32_t {
+        int64_t rr = r < 0 ? r + ny : (r >= ny ? r - ny : r);
+        return (uint32_t)((rr * nx + x) * (int64_t)sizeof(R));
+    };
+    auto slopes_x = [&](const R* W, R* sx) {
+        for (int c = 0; c < NC; c++) {
+            R l = from_left(W[c]), r = from_right(W[c]);
+            R a = W[c] - l, b = r - W[c];
+            pin(a);
+            pin(b);
+            sx[c] = minmod(a, b);
+        }
+    };
+
+    // Rolling state, in two register sets that swap roles every row:
+    //   Wd/We  primitive state of rows i+1 / i+2
+    //   Dp/Dn  y-differences W(i+1) - W(i) / W(i+2) - W(i+1)
+    //   h0/h1  half-step state of rows i / i+1;  x0s/x1s their x-slopes
+    //   Np/Nn  north face states of rows i / i+1
+    //   Gp/Gn  y-fluxes at faces i-1/2 / i+1/2
+    //   Uc/Ux  raw row i+2 (arrived) / row i+3 (in flight)
+    R WA[NC], WB[NC], DA[NC], DB[NC], HA[NC], HB[NC], XA[NC], XB[NC];
+    R NA[NC], NB[NC], GA[NC], GB[NC], UA[NC], UB[NC];
+
+    // prologue: rows r0-2 .. r0+1
+    {
+        R Wa[NC], Wb[NC], Wc[NC], t[NC], sy[NC], sx[NC], hb[NC], S[NC];
+        src.load(boff(r0 - 2), t);
+        P::prim(k, t, Wa);
+        src.load(boff(r0 - 1), t);
+        P::prim(k, t, Wb);
+        src.load(boff(r0), t);
+        P::prim(k, t, Wc);
+        src.load(boff(r0 + 1), t);
+        P::prim(k, t, WA);
+        src.load(boff(r0 + 2), UA);
+        // row r0-1: its north face state
+        slopes_x(Wb, sx);
+        for (int c = 0; c < NC; c++) sy[c] = minmod(Wb[c] - Wa[c], Wc[c] - Wb[c]);
+        P::predict(k, Wb, sx, sy, hb);
+        for (int c = 0; c < NC; c++) hb[c] = hb[c] + half * sy[c];
+        // row r0
+        slopes_x(Wc, XA);
+        for (int c = 0; c < NC; c++) {
+            R dp = Wc[c] - Wb[c];
+            DA[c] = WA[c] - Wc[c];
+            sy[c] = minmod(dp, DA[c]);
+        }
+        P::predict(k, Wc, XA, sy, HA);
+        for (int c = 0; c < NC; c++) {
+            S[c] = HA[c] - half * sy[c];
+            NA[c] = HA[c] + half * sy[c];
+        }
+        flux_y<P, RS>(k, hb, S, GA);
+    }
+
+    auto row = [&](int64_t i, R* Wd, R* We, R* Dp, R* Dn, R* h0, R* h1, R* x0s, R* x1s,
+                   R* Np, R* Nn, R* Gp, R* Gn, R* Uc, R* Ux) {
+        // row i+2 has arrived in Uc; put row i+3 in flight
+        P::prim(k, Uc, We);
+        if (i + 1 < r1) src.load(boff(i + 3), Ux);
+        // predictor of row i+1
+        R sy[NC];
+        slopes_x(Wd, x1s);
+        for (int c = 0; c < NC; c++) {
+            Dn[c] = We[c] - Wd[c];
+            sy[c] = minmod(Dp[c], Dn[c]);
+        }
+        P::predict(k, Wd, x1s, sy, h1);
+        // y-face i+1/2 between the north state of row i and the south state
+        // of row i+1
+        {
+            R S[NC];
+            for (int c = 0; c < NC; c++) {
+                S[c] = h1[c] - half * sy[c];
+                Nn[c] = h1[c] + half * sy[c];
+            }
+            flux_y<P, RS>(k, Np, S, Gn);
+        }
+        // x-faces of row i: lane j computes face j+1/2 from its east state and
+        // lane j+1's west state; face j-1/2 comes from lane j-1
+        R dF[NC], dG[NC];
+        {
+            R E[NC], Wr[NC], Fx[NC];
+            for (int c = 0; c < NC; c++) {
+                E[c] = h0[c] + half * x0s[c];
+                Wr[c] = from_right(h0[c] - half * x0s[c]);
+            }
+            P::template flux<RS>(k, E, Wr, Fx);
+            for (int c = 0; c < NC; c++) {
+                dF[c] = Fx[c] - from_left(Fx[c]);
+                pin(dF[c]);
+                dG[c] = Gn[c] - Gp[c];
+            }
+        }
+        // update of row i (U^n of row i re-read; it was loaded two rows ago)
+        R Un[NC], Uo[NC], Wn[NC], sE, sV;
+        const uint32_t o = boff(i);
+        src.load(o, Un);
+        P::update(k, Un, dF, dG, h0, Uo, sE, sV);
+        P::prim(k, Uo, Wn);
+        R s = P::speed(k, Wn);
+        if (inner) {
+            dst.store(o, Uo);
+            acc_cell<P, NC>(acc, k, Uo, Wn, s, sE, sV);
+        }
+    };
+
+    int64_t i = r0;
+    for (; i + 1 < r1; i += 2) {
+        row(i, WA, WB, DA, DB, HA, HB, XA, XB, NA, NB, GA, GB, UA, UB);
+        row(i + 1, WB, WA, DB, DA, HB, HA, XB, XA, NB, NA, GB, GA, UB, UA);
+    }
+    if (i < r1) row(i, WA, WB, DA, DB, HA, HB, XA, XB, NA, NB, GA, GB, UA, UB);
+}
+
 template <class P>
 __global__ void __launch_bounds__(256) step2d_kernel(const InstDesc* __restrict__ descs,
                                                      InstCtrl* __restrict__ ctrls,
@@ -308,7 +524,6 @@ __global__ void __launch_bounds__(256) step2d_kernel(const InstDesc* __restrict_
                                                      int remap)
 {
     using R = typename P::R;
-    constexpr int NC = 5;
     const int64_t G = gridDim.x;
     const int64_t bid = remap ? xcd_remap(blockIdx.x, G) : (int64_t)blockIdx.x;
     const BlockRef br = blocks[bid];
@@ -316,149 +531,82 @@ __global__ void __launch_bounds__(256) step2d_kernel(const InstDesc* __restrict_
     const StepCtl sc = read_ctl(ctrls[br.inst]);
     if (!sc.active) return;
     const typename P::K k = P::make(d, sc.dt);
-    const R half = P::half();
-
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int al = ((lane + 63) & 63) << 2, ar = ((lane + 1) & 63) << 2;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int nwaves = d.waves_per_block;
-    Acc acc;
+    Acc<R> acc;
     acc_init(acc);
-
     const int64_t item = (int64_t)br.local * nwaves + wave;
     if (item < d.nitems) {
-        const int64_t nx = d.nx, ny = d.ny, ncell = d.ncell;
-        const int64_t strip = item % d.nstrips, chunk = item / d.nstrips;
-        const int64_t x0 = strip * kInterior;
-        int64_t x = x0 - kHalo + lane;
-        x = ((x % nx) + nx) % nx;
-        const bool inner = lane >= kHalo && lane < kWave - kHalo && x0 + (lane - kHalo) < nx;
-        const int64_t r0 = chunk * d.rows_per_item;
-        const int64_t r1 = r0 + d.rows_per_item < ny ? r0 + d.rows_per_item : ny;
-        const R* __restrict__ src = (const R*)d.buf[sc.cur];
-        R* __restrict__ dst = (R*)d.buf[sc.cur ^ 1];
-        auto rowi = [&](int64_t r) -> int64_t {
-            int64_t rr = ((r % ny) + ny) % ny;
-            return rr * nx + x;
-        };
-
-        R Wc[NC], Wd[NC], We[NC], Ut[NC], Un[NC];
-        R h0[NC], sx0[NC], Nprev[NC], Gprev[NC];
-        R sx[NC], sy[NC], h1[NC], Wl[NC], Wr[NC];
-
-        // prologue: rows r0-2 .. r0+1, the half-step state of rows r0-1 and r0
-        {
-            R Wa[NC], Wb[NC];
-            load_cell<R, NC>(src, ncell, rowi(r0 - 2), Ut);
-            P::prim(k, Ut, Wa);
-            load_cell<R, NC>(src, ncell, rowi(r0 - 1), Ut);
-            P::prim(k, Ut, Wb);
-            load_cell<R, NC>(src, ncell, rowi(r0), Ut);
-            P::prim(k, Ut, Wc);
-            load_cell<R, NC>(src, ncell, rowi(r0 + 1), Ut);
-            P::prim(k, Ut, Wd);
-            // row r0-1
-            for (int c = 0; c < NC; c++) {
-                Wl[c] = lane_get(Wb[c], al);
-                Wr[c] = lane_get(Wb[c], ar);
-                sx[c] = minmod(Wb[c] - Wl[c], Wr[c] - Wb[c]);
-                sy[c] = minmod(Wb[c] - Wa[c], Wc[c] - Wb[c]);
-            }
-            P::predict(k, Wb, sx, sy, h1);
-            for (int c = 0; c < NC; c++) Nprev[c] = h1[c] + half * sy[c];
-            // row r0
-            for (int c = 0; c < NC; c++) {
-                Wl[c] = lane_get(Wc[c], al);
-                Wr[c] = lane_get(Wc[c], ar);
-                sx0[c] = minmod(Wc[c] - Wl[c], Wr[c] - Wc[c]);
-                sy[c] = minmod(Wc[c] - Wb[c], Wd[c] - Wc[c]);
-            }
-            P::predict(k, Wc, sx0, sy, h0);
-            R S[NC], Nr[NC], Sr[NC], Fy[NC];
-            for (int c = 0; c < NC; c++) S[c] = h0[c] - half * sy[c];
-            // y-face r0-1/2: normal velocity is v -> swap (u, v)
-            Nr[0] = Nprev[0]; Nr[1] = Nprev[2]; Nr[2] = Nprev[1]; Nr[3] = Nprev[3]; Nr[4] = Nprev[4];
-            Sr[0] = S[0]; Sr[1] = S[2]; Sr[2] = S[1]; Sr[3] = S[3]; Sr[4] = S[4];
-            P::flux(k, Nr, Sr, Fy);
-            Gprev[0] = Fy[0]; Gprev[1] = Fy[2]; Gprev[2] = Fy[1]; Gprev[3] = Fy[3]; Gprev[4] = Fy[4];
-            for (int c = 0; c < NC; c++) Nprev[c] = h0[c] + half * sy[c];
-        }
-        load_cell<R, NC>(src, ncell, rowi(r0 + 2), Ut);   // prefetched row
-
-        for (int64_t i = r0; i < r1; i++) {
-            // row i+2 arrives; issue row i+3
-            for (int c = 0; c < NC; c++) Un[c] = Ut[c];
-            P::prim(k, Un, We);
-            if (i + 1 < r1) load_cell<R, NC>(src, ncell, rowi(i + 3), Ut);
-
-            // predictor of row i+1
-            for (int c = 0; c < NC; c++) {
-                Wl[c] = lane_get(Wd[c], al);
-                Wr[c] = lane_get(Wd[c], ar);
-                sx[c] = minmod(Wd[c] - Wl[c], Wr[c] - Wd[c]);
-                sy[c] = minmod(Wd[c] - Wc[c], We[c] - Wd[c]);
-            }
-            P::predict(k, Wd, sx, sy, h1);
-
-            // y-face i+1/2
-            R Gn[NC];
-            {
-                R Nr[NC], Sr[NC], Fy[NC];
-                Nr[0] = Nprev[0]; Nr[1] = Nprev[2]; Nr[2] = Nprev[1]; Nr[3] = Nprev[3]; Nr[4] = Nprev[4];
-                Sr[0] = h1[0] - half * sy[0];
-                Sr[1] = h1[2] - half * sy[2];
-                Sr[2] = h1[1] - half * sy[1];
-                Sr[3] = h1[3] - half * sy[3];
-                Sr[4] = h1[4] - half * sy[4];
-                P::flux(k, Nr, Sr, Fy);
-                Gn[0] = Fy[0]; Gn[1] = Fy[2]; Gn[2] = Fy[1]; Gn[3] = Fy[3]; Gn[4] = Fy[4];
-            }
-
-            // x-faces of row i: lane j computes face j+1/2 from its east state
-            // and lane j+1's west state; face j-1/2 comes from lane j-1
-            R dF[NC], dG[NC];
-            {
-                R E[NC], Wf[NC], Fx[NC];
-                for (int c = 0; c < NC; c++) {
-                    E[c] = h0[c] + half * sx0[c];
-                    Wf[c] = h0[c] - half * sx0[c];
-                }
-                for (int c = 0; c < NC; c++) Wr[c] = lane_get(Wf[c], ar);
-                P::flux(k, E, Wr, Fx);
-                for (int c = 0; c < NC; c++) {
-                    R Fl = lane_get(Fx[c], al);
-                    dF[c] = Fx[c] - Fl;
-                    dG[c] = Gn[c] - Gprev[c];
-                }
-            }
-
-            // update of row i
-            R Uo[NC], Wn[NC], sE, sV;
-            const int64_t idx = rowi(i);
-            load_cell_cached<R, NC>(src, ncell, idx, Un);
-            P::update(k, Un, dF, dG, h0, Uo, sE, sV);
-            P::prim(k, Uo, Wn);
-            R s = P::speed(k, Wn);
-            if (inner) {
-                for (int c = 0; c < NC; c++) __builtin_nontemporal_store(Uo[c], dst + c * ncell + idx);
-                acc_cell<P, NC>(acc, k, Uo, Wn, s, sE, sV);
-            }
-
-            // rotate the rolling window
-            for (int c = 0; c < NC; c++) {
-                Gprev[c] = Gn[c];
-                Nprev[c] = h1[c] + half * sy[c];
-                h0[c] = h1[c];
-                sx0[c] = sx[c];
-                Wc[c] = Wd[c];
-                Wd[c] = We[c];
-            }
-        }
+        if (d.riemann == 1)
+            march2d<P, 1>(d, k, sc.cur, item, lane, acc);
+        else
+            march2d<P, 0>(d, k, sc.cur, item, lane, acc);
     }
     Partial* parts = (Partial*)d.partials;
     block_reduce_store(acc, parts + br.local, wave, lane, nwaves);
 }
 
 // ================================================================ 1D step
+
+// One work item of the 1D step: a group of consecutive 60-cell segments.
+template <class P, int RS>
+__device__ __forceinline__ void march1d(const InstDesc& d, const typename P::K& k, int cur,
+                                        int64_t item, int lane, Acc<typename P::R>& acc)
+{
+    using R = typename P::R;
+    constexpr int NC = 4;
+    const R half = P::half();
+    const int64_t n = d.nx;
+    const Planes<R, NC> src(d.buf[cur], n);
+    const Planes<R, NC> dst(d.buf[cur ^ 1], n);
+    const int64_t s0 = item * d.rows_per_item;
+    const int64_t s1 = s0 + d.rows_per_item < d.nstrips ? s0 + d.rows_per_item : d.nstrips;
+    auto boff = [&](int64_t sg) -> uint32_t {
+        return (uint32_t)(wrap_axis(sg * kInterior - kHalo + lane, n) * (int64_t)sizeof(R));
+    };
+    R UA[NC], UB[NC];
+    src.load(boff(s0), UA);
+    auto seg = [&](int64_t sg, R* Uc, R* Ux) {
+        R W[NC], sx[NC], h[NC];
+        const uint32_t o = boff(sg);
+        if (sg + 1 < s1) src.load(boff(sg + 1), Ux);
+        P::prim(k, Uc, W);
+        for (int c = 0; c < NC; c++) {
+            R l = from_left(W[c]), r = from_right(W[c]);
+            R a = W[c] - l, b = r - W[c];
+            pin(a);
+            pin(b);
+            sx[c] = minmod(a, b);
+        }
+        P::predict(k, W, sx, sx, h);
+        R E[NC], Wr[NC], Fx[NC], dF[NC];
+        for (int c = 0; c < NC; c++) {
+            E[c] = h[c] + half * sx[c];
+            Wr[c] = from_right(h[c] - half * sx[c]);
+        }
+        P::template flux<RS>(k, E, Wr, Fx);
+        for (int c = 0; c < NC; c++) {
+            dF[c] = Fx[c] - from_left(Fx[c]);
+            pin(dF[c]);
+        }
+        R Uo[NC], Wn[NC], sE, sV;
+        P::update(k, Uc, dF, dF, h, Uo, sE, sV);
+        P::prim(k, Uo, Wn);
+        R s = P::speed(k, Wn);
+        const bool inner =
+            lane >= kHalo && lane < kWave - kHalo && sg * kInterior + (lane - kHalo) < n;
+        if (inner) {
+            dst.store(o, Uo);
+            acc_cell<P, NC>(acc, k, Uo, Wn, s, sE, sV);
+        }
+    };
+    int64_t sg = s0;
+    for (; sg + 1 < s1; sg += 2) {
+        seg(sg, UA, UB);
+        seg(sg + 1, UB, UA);
+    }
+    if (sg < s1) seg(sg, UA, UB);
+}
 
 template <class P>
 __global__ void __launch_bounds__(256) step1d_kernel(const InstDesc* __restrict__ descs,
@@ -467,7 +615,6 @@ __global__ void __launch_bounds__(256) step1d_kernel(const InstDesc* __restrict_
                                                      int remap)
 {
     using R = typename P::R;
-    constexpr int NC = 4;
     const int64_t G = gridDim.x;
     const int64_t bid = remap ? xcd_remap(blockIdx.x, G) : (int64_t)blockIdx.x;
     const BlockRef br = blocks[bid];
@@ -475,58 +622,16 @@ __global__ void __launch_bounds__(256) step1d_kernel(const InstDesc* __restrict_
     const StepCtl sc = read_ctl(ctrls[br.inst]);
     if (!sc.active) return;
     const typename P::K k = P::make(d, sc.dt);
-    const R half = P::half();
-
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int al = ((lane + 63) & 63) << 2, ar = ((lane + 1) & 63) << 2;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int nwaves = d.waves_per_block;
-    Acc acc;
+    Acc<R> acc;
     acc_init(acc);
-
     const int64_t item = (int64_t)br.local * nwaves + wave;
     if (item < d.nitems) {
-        const int64_t n = d.nx;
-        const R* __restrict__ src = (const R*)d.buf[sc.cur];
-        R* __restrict__ dst = (R*)d.buf[sc.cur ^ 1];
-        const int64_t s0 = item * d.rows_per_item;
-        const int64_t s1 = s0 + d.rows_per_item < d.nstrips ? s0 + d.rows_per_item : d.nstrips;
-        auto cell = [&](int64_t sg) -> int64_t {
-            int64_t xx = sg * kInterior - kHalo + lane;
-            return ((xx % n) + n) % n;
-        };
-        R Ut[NC];
-        load_cell<R, NC>(src, n, cell(s0), Ut);
-        for (int64_t sg = s0; sg < s1; sg++) {
-            R Un[NC], W[NC], Wl[NC], Wr[NC], sx[NC], h[NC];
-            for (int c = 0; c < NC; c++) Un[c] = Ut[c];
-            const int64_t idx = cell(sg);
-            if (sg + 1 < s1) load_cell<R, NC>(src, n, cell(sg + 1), Ut);
-            P::prim(k, Un, W);
-            for (int c = 0; c < NC; c++) {
-                Wl[c] = lane_get(W[c], al);
-                Wr[c] = lane_get(W[c], ar);
-                sx[c] = minmod(W[c] - Wl[c], Wr[c] - W[c]);
-            }
-            P::predict(k, W, sx, sx, h);
-            R E[NC], Wf[NC], Fx[NC], dF[NC];
-            for (int c = 0; c < NC; c++) {
-                E[c] = h[c] + half * sx[c];
-                Wf[c] = h[c] - half * sx[c];
-            }
-            for (int c = 0; c < NC; c++) Wr[c] = lane_get(Wf[c], ar);
-            P::flux(k, E, Wr, Fx);
-            for (int c = 0; c < NC; c++) dF[c] = Fx[c] - lane_get(Fx[c], al);
-            R Uo[NC], Wn[NC], sE, sV;
-            P::update(k, Un, dF, dF, h, Uo, sE, sV);
-            P::prim(k, Uo, Wn);
-            R s = P::speed(k, Wn);
-            const bool inner = lane >= kHalo && lane < kWave - kHalo &&
-                               sg * kInterior + (lane - kHalo) < n;
-            if (inner) {
-                for (int c = 0; c < NC; c++) __builtin_nontemporal_store(Uo[c], dst + c * n + idx);
-                acc_cell<P, NC>(acc, k, Uo, Wn, s, sE, sV);
-            }
-        }
+        if (d.riemann == 1)
+            march1d<P, 1>(d, k, sc.cur, item, lane, acc);
+        else
+            march1d<P, 0>(d, k, sc.cur, item, lane, acc);
     }
     Partial* parts = (Partial*)d.partials;
     block_reduce_store(acc, parts + br.local, wave, lane, nwaves);
@@ -547,9 +652,9 @@ __global__ void __launch_bounds__(256) prime_kernel(const InstDesc* __restrict__
     const InstCtrl& cc = ctrls[br.inst];
     if (cc.status != 0) return;
     const typename P::K k = P::make(d, 0.0);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int nwaves = d.waves_per_block;
-    Acc acc;
+    Acc<R> acc;
     acc_init(acc);
     const int64_t item = (int64_t)br.local * nwaves + wave;
     if (item < d.nitems) {
@@ -593,7 +698,7 @@ __global__ void __launch_bounds__(256) prime_kernel(const InstDesc* __restrict__
 // One workgroup per solve: fold the step's records in a fixed order, accept
 // (swap buffers, advance t, next dt from eq. (16)) or reject (sticky NG_EPHYS,
 // the state before the step is kept).  mode 0: after a step; 1: priming.
-__global__ void __launch_bounds__(256) finalize_kernel(const InstDesc* __restrict__ descs,
+__global__ void __launch_bounds__(1024) finalize_kernel(const InstDesc* __restrict__ descs,
                                                        InstCtrl* __restrict__ ctrls,
                                                        const int32_t* __restrict__ insts,
                                                        int mode)
@@ -606,39 +711,52 @@ __global__ void __launch_bounds__(256) finalize_kernel(const InstDesc* __restric
     if (mode == 1 && c.status != 0) return;
     const Partial* parts = (const Partial*)d.partials;
     const int64_t nb = d.nblocks;
-    __shared__ double sh[256][10];
-    __shared__ uint32_t shf[256];
+    __shared__ double sh[16][10];
+    __shared__ uint32_t shf[16];
     double tot[5] = {0, 0, 0, 0, 0}, src0 = 0.0, src1 = 0.0, smax = 0.0, rmin = INFINITY,
            pmin = INFINITY;
     uint32_t flags = 0;
+#pragma unroll 4
     for (int64_t b = threadIdx.x; b < nb; b += blockDim.x) {
         const Partial& p = parts[b];
         for (int q = 0; q < 5; q++) tot[q] += p.tot[q];
         src0 += p.src[0];
         src1 += p.src[1];
-        smax = p.smax > smax ? p.smax : smax;
-        rmin = p.rho_min < rmin ? p.rho_min : rmin;
-        pmin = p.p_min < pmin ? p.p_min : pmin;
+        smax = fmax(smax, p.smax);
+        rmin = fmin(rmin, p.rho_min);
+        pmin = fmin(pmin, p.p_min);
         flags |= p.flags;
     }
-    const int t = threadIdx.x;
-    for (int q = 0; q < 5; q++) sh[t][q] = tot[q];
-    sh[t][5] = src0;
-    sh[t][6] = src1;
-    sh[t][7] = smax;
-    sh[t][8] = rmin;
-    sh[t][9] = pmin;
-    shf[t] = flags;
+    // fixed-order fold: lanes (butterfly, lane 0's order is fixed), then waves
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    for (int m = 32; m >= 1; m >>= 1) {
+        for (int q = 0; q < 5; q++) tot[q] += lane_xor(tot[q], lane, m);
+        src0 += lane_xor(src0, lane, m);
+        src1 += lane_xor(src1, lane, m);
+        smax = fmax(smax, lane_xor(smax, lane, m));
+        rmin = fmin(rmin, lane_xor(rmin, lane, m));
+        pmin = fmin(pmin, lane_xor(pmin, lane, m));
+        flags |= (uint32_t)__builtin_amdgcn_ds_bpermute(((lane ^ m) & 63) << 2, (int)flags);
+    }
+    if (lane == 0) {
+        for (int q = 0; q < 5; q++) sh[wave][q] = tot[q];
+        sh[wave][5] = src0;
+        sh[wave][6] = src1;
+        sh[wave][7] = smax;
+        sh[wave][8] = rmin;
+        sh[wave][9] = pmin;
+        shf[wave] = flags;
+    }
     __syncthreads();
-    for (int w = blockDim.x / 2; w >= 1; w >>= 1) {
-        if (t < w) {
-            for (int q = 0; q < 7; q++) sh[t][q] += sh[t + w][q];
-            sh[t][7] = sh[t + w][7] > sh[t][7] ? sh[t + w][7] : sh[t][7];
-            sh[t][8] = sh[t + w][8] < sh[t][8] ? sh[t + w][8] : sh[t][8];
-            sh[t][9] = sh[t + w][9] < sh[t][9] ? sh[t + w][9] : sh[t][9];
-            shf[t] |= shf[t + w];
+    if (t == 0) {
+        const int nw = blockDim.x >> 6;
+        for (int w = 1; w < nw; w++) {
+            for (int q = 0; q < 7; q++) sh[0][q] += sh[w][q];
+            sh[0][7] = fmax(sh[0][7], sh[w][7]);
+            sh[0][8] = fmin(sh[0][8], sh[w][8]);
+            sh[0][9] = fmin(sh[0][9], sh[w][9]);
+            shf[0] |= shf[w];
         }
-        __syncthreads();
     }
     if (t != 0) return;
     const double n = (double)d.ncell;
@@ -723,7 +841,7 @@ hipError_t launch_finalize(const InstDesc* descs, InstCtrl* ctrls, const int32_t
                            int mode, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)n), dim3(256), 0, s, descs, ctrls, insts,
+    hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)n), dim3(1024), 0, s, descs, ctrls, insts,
                        mode);
     return hipGetLastError();
 }

@@ -249,8 +249,8 @@ class Solver:
     def set_graph_steps(self, k: int):
         check(lib().ng_set_graph_steps(self.h, int(k)), "ng_set_graph_steps", self._err())
 
-    def enable_timing(self, on: bool = True):
-        check(lib().ng_enable_timing(self.h, 1 if on else 0), "ng_enable_timing")
+    def enable_timing(self, nsteps: int):
+        check(lib().ng_enable_timing(self.h, int(nsteps)), "ng_enable_timing")
 
     def kernel_time(self):
         a, b, n = C.c_double(0), C.c_double(0), C.c_int64(0)
