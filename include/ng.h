@@ -175,6 +175,17 @@ int ng_set_launch(ng_solver* s, int32_t rows_per_item, int32_t waves_per_block);
 /* Steps per captured graph in ng_run_to_time (default 64). */
 int ng_set_graph_steps(ng_solver* s, int32_t steps);
 
+/* Solves of at most max_cells cells are advanced by a persistent kernel in
+ * which one workgroup runs many steps per launch (no launch or host round trip
+ * per step); larger ones take one launch per step over the whole GPU.  -1
+ * restores the default (4096 cells in FP32, 2048 in FP64), 0 turns the
+ * persistent path off.  Both paths give bitwise the same state. */
+int ng_set_small_limit(ng_solver* s, int64_t max_cells);
+
+/* Step acceptance inside the step kernel (1, default) or by a separate
+ * kernel (0); see ng_batch_set_fused_accept. */
+int ng_set_fused_accept(ng_solver* s, int32_t on);
+
 /* Kernel timing: ng_enable_timing(s, nsteps) with nsteps > 0 makes later
  * ng_step calls launch each step directly with HIP events on the solver's
  * stream around the step and finalize kernels (events for nsteps steps are
@@ -232,6 +243,16 @@ int ng_batch_get_conserved(ng_batch* b, int32_t slot, double* cons_out);
 
 /* Release a slot and its arena space. */
 int ng_batch_remove(ng_batch* b, int32_t slot);
+
+/* How a step is accepted (dt, t and totals advanced): on = 1 (default) lets
+ * solves of up to 256 step workgroups be accepted by the last workgroup of the
+ * step kernel itself (one launch per step); larger solves, and all solves when
+ * on = 0, are accepted by a separate one-workgroup kernel after the step.
+ * The state, t and dt are identical either way. */
+int ng_batch_set_fused_accept(ng_batch* b, int32_t on);
+
+/* Persistent-path size limit of a batch (see ng_set_small_limit). */
+int ng_batch_set_small_limit(ng_batch* b, int64_t max_cells);
 
 /* Launch shape of the batched step kernels (see ng_set_launch). */
 int ng_batch_set_launch(ng_batch* b, int32_t dim, int32_t rows_per_item,

@@ -29,6 +29,18 @@ constexpr int kDefaultRows2D = 32;
 constexpr int kDefaultSegs1D = 8;
 constexpr int kDefaultWaves = 4;
 constexpr int kDefaultGraphSteps = 64;
+// Solves up to this many cells run in the persistent one-workgroup kernel
+// (many steps per launch); larger ones take one launch per step over the
+// whole GPU.  Per-cell arithmetic is the same on both paths.
+constexpr int64_t kSmallCells32 = 4096;
+constexpr int64_t kSmallCells64 = 2048;
+constexpr int kSmallRows2D = 8;
+constexpr int kSmallSegs1D = 1;
+constexpr int kSmallWaves = 8;
+// Big solves of at most this many workgroups accept their steps inside the
+// step kernel (last workgroup); beyond it the per-workgroup release fence costs
+// more than the separate finalize launch.
+constexpr int64_t kFusedMaxBlocks = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -69,7 +81,7 @@ Layout header_layout(int capacity, size_t tcap1, size_t tcap2)
     L.ctrls = o;
     o += align_up(sizeof(InstCtrl) * capacity);
     L.insts = o;
-    o += align_up(sizeof(int32_t) * 3 * capacity);
+    o += align_up(sizeof(int32_t) * 5 * capacity);
     L.blocks1 = o;
     o += align_up(sizeof(BlockRef) * tcap1);
     L.blocks2 = o;
@@ -171,7 +183,8 @@ struct Slot {
     size_t off = 0, bytes = 0;
     int64_t partial_cap = 0;
     int64_t block_off = 0;  // first entry in the dim's block table
-    int pos = 0;            // index in the dim's instance list
+    int pos = 0;            // index in the dim's instance list (big or small)
+    bool small = false;     // advanced by the persistent one-workgroup kernel
     bool reported = false;
 };
 
@@ -191,8 +204,12 @@ struct ng_batch {
     int rows[3] = {0, kDefaultSegs1D, kDefaultRows2D};
     int waves[3] = {0, kDefaultWaves, kDefaultWaves};
     int remap = 1;
-    int64_t nblocks[3] = {0, 0, 0};
-    int ninst[3] = {0, 0, 0};
+    int64_t small_limit = -1;  // cells; -1: by precision, 0: persistent path off
+    int fused = 1;             // step kernels accept their own step (last workgroup)
+    int64_t nblocks[3] = {0, 0, 0};   // workgroups of the per-step launch (big solves)
+    int ninst[3] = {0, 0, 0};         // big solves per dim
+    int nsep[3] = {0, 0, 0};          // big solves accepted by the finalize kernel
+    int nsmall[3] = {0, 0, 0};        // small solves per dim
     bool dirty = true;
     // captured step sequence
     hipGraphExec_t gexec = nullptr;
@@ -212,6 +229,7 @@ struct ng_batch {
     InstDesc* d_descs() { return (InstDesc*)(arena + L.descs); }
     InstCtrl* d_ctrls() { return (InstCtrl*)(arena + L.ctrls); }
     int32_t* d_insts(int dim) { return (int32_t*)(arena + L.insts) + dim * capacity; }
+    int32_t* d_small(int dim) { return (int32_t*)(arena + L.insts) + (2 + dim) * capacity; }
     BlockRef* d_blocks(int dim) { return (BlockRef*)(arena + (dim == 1 ? L.blocks1 : L.blocks2)); }
 };
 
@@ -280,8 +298,8 @@ void shape_solve(ng_batch* b, Slot& s)
 {
     InstDesc& d = s.d;
     int dim = s.dim;
-    d.waves_per_block = b->waves[dim];
-    d.rows_per_item = b->rows[dim];
+    d.waves_per_block = s.small ? 1 : b->waves[dim];
+    d.rows_per_item = s.small ? (dim == 2 ? kSmallRows2D : kSmallSegs1D) : b->rows[dim];
     d.nstrips = (int32_t)cdiv(d.nx, kInterior);
     if (dim == 2)
         d.nchunks = (int32_t)cdiv(d.ny, d.rows_per_item);
@@ -289,6 +307,7 @@ void shape_solve(ng_batch* b, Slot& s)
         d.nchunks = (int32_t)cdiv(d.nstrips, d.rows_per_item);
     d.nitems = dim == 2 ? (int64_t)d.nstrips * d.nchunks : (int64_t)d.nchunks;
     d.nblocks = cdiv(d.nitems, d.waves_per_block);
+    d.fused = (b->fused && !s.small && d.nblocks <= kFusedMaxBlocks) ? 1 : 0;
 }
 
 // Rebuild the device tables (descriptors, per-dim solve lists and workgroup
@@ -296,32 +315,48 @@ void shape_solve(ng_batch* b, Slot& s)
 int rebuild(ng_batch* b)
 {
     if (!b->dirty) return NG_OK;
-    std::vector<int32_t> insts(3 * b->capacity, 0);
+    std::vector<int32_t> insts(5 * b->capacity, 0);
     for (int dim = 1; dim <= 2; dim++) {
         b->h_blocks[dim].clear();
         b->ninst[dim] = 0;
+        b->nsep[dim] = 0;
+        b->nsmall[dim] = 0;
     }
-    for (int i = 0; i < b->capacity; i++) {
-        Slot& s = b->slots[i];
-        if (!s.live) continue;
-        shape_solve(b, s);
-        if (s.d.nblocks > s.partial_cap) {
-            b->err = "launch shape needs more reduction records than reserved";
-            return NG_EINVAL;
+    // per dim: the workgroups of big solves first (the per-step launch covers
+    // exactly those), then those of small solves (used by the priming pass only)
+    const int64_t lim = b->small_limit >= 0 ? b->small_limit
+                                            : (b->prec == NG_FP32 ? kSmallCells32 : kSmallCells64);
+    for (int i = 0; i < b->capacity; i++)
+        if (b->slots[i].live) b->slots[i].small = b->slots[i].d.ncell <= lim;
+    for (int pass = 0; pass < 2; pass++) {
+        for (int i = 0; i < b->capacity; i++) {
+            Slot& s = b->slots[i];
+            if (!s.live || (int)s.small != pass) continue;
+            shape_solve(b, s);
+            if (s.d.nblocks > s.partial_cap) {
+                b->err = "launch shape needs more reduction records than reserved";
+                return NG_EINVAL;
+            }
+            auto& tab = b->h_blocks[s.dim];
+            s.block_off = (int64_t)tab.size();
+            for (int64_t j = 0; j < s.d.nblocks; j++) tab.push_back(BlockRef{i, (int32_t)j});
+            if (s.small) {
+                s.pos = b->nsmall[s.dim]++;
+                insts[(2 + s.dim) * b->capacity + s.pos] = i;
+            } else {
+                s.pos = b->ninst[s.dim]++;
+                insts[s.dim * b->capacity + s.pos] = i;
+                b->nblocks[s.dim] = (int64_t)tab.size();
+                if (!s.d.fused) b->nsep[s.dim]++;
+            }
         }
-        auto& tab = b->h_blocks[s.dim];
-        s.block_off = (int64_t)tab.size();
-        for (int64_t j = 0; j < s.d.nblocks; j++) tab.push_back(BlockRef{i, (int32_t)j});
-        s.pos = b->ninst[s.dim];
-        insts[s.dim * b->capacity + b->ninst[s.dim]] = i;
-        b->ninst[s.dim]++;
     }
     for (int dim = 1; dim <= 2; dim++) {
         if (b->h_blocks[dim].size() > b->tcap[dim]) {
             b->err = "workgroup table capacity exceeded";
             return NG_ENOMEM;
         }
-        b->nblocks[dim] = (int64_t)b->h_blocks[dim].size();
+        if (!b->ninst[dim]) b->nblocks[dim] = 0;
     }
     std::vector<InstDesc> descs(b->capacity);
     for (int i = 0; i < b->capacity; i++) descs[i] = b->slots[i].d;
@@ -356,18 +391,50 @@ int enqueue_one(ng_batch* b, hipStream_t st)
     for (int dim = 1; dim <= 2; dim++) {
         if (!b->ninst[dim]) continue;
         CK(b, launch_step(dim, b->prec == NG_FP32 ? 1 : 0, b->d_descs(), b->d_ctrls(),
-                          b->d_blocks(dim), b->nblocks[dim], b->waves[dim], b->remap, st));
-        CK(b, launch_finalize(b->d_descs(), b->d_ctrls(), b->d_insts(dim), b->ninst[dim], 0, st));
+                          b->d_blocks(dim), b->nblocks[dim], b->waves[dim], b->remap, b->fused,
+                          st));
+        if (b->nsep[dim])
+            CK(b, launch_finalize(b->d_descs(), b->d_ctrls(), b->d_insts(dim), b->ninst[dim], 0,
+                                  st));
     }
     return NG_OK;
 }
 
-// Timed variant: events around each step and finalize kernel.
+// Launch the persistent kernel of the small solves for nsteps steps.
+int enqueue_small(ng_batch* b, int64_t nsteps, hipStream_t st)
+{
+    for (int dim = 1; dim <= 2; dim++) {
+        if (!b->nsmall[dim]) continue;
+        CK(b, launch_small(dim, b->prec == NG_FP32 ? 1 : 0, b->d_descs(), b->d_ctrls(),
+                           b->d_small(dim), b->nsmall[dim], kSmallWaves, nsteps, st));
+    }
+    return NG_OK;
+}
+
+bool any_big(const ng_batch* b) { return b->ninst[1] + b->ninst[2] > 0; }
+bool any_small(const ng_batch* b) { return b->nsmall[1] + b->nsmall[2] > 0; }
+
+// Timed variant: events around each step and finalize kernel (big solves), or
+// around the persistent launch (small solves; reported per step).
 int enqueue_timed(ng_batch* b, int64_t nsteps)
 {
     size_t ne = 0;
     std::vector<std::pair<size_t, size_t>> step_pairs, fin_pairs;
-    for (int64_t i = 0; i < nsteps; i++) {
+    double small_ms = 0.0;
+    if (any_small(b)) {
+        hipEvent_t e0 = get_event(b, 0), e1 = get_event(b, 1);
+        if (!e0 || !e1) return dev_err(b, hipErrorOutOfMemory, "hipEventCreate");
+        CK(b, hipEventRecord(e0, b->stream));
+        int rc = enqueue_small(b, nsteps, b->stream);
+        if (rc) return rc;
+        CK(b, hipEventRecord(e1, b->stream));
+        CK(b, hipStreamSynchronize(b->stream));
+        float ms = 0.f;
+        CK(b, hipEventElapsedTime(&ms, e0, e1));
+        small_ms = ms;
+        ne = 2;
+    }
+    for (int64_t i = 0; i < nsteps && any_big(b); i++) {
         for (int dim = 1; dim <= 2; dim++) {
             if (!b->ninst[dim]) continue;
             hipEvent_t e0 = get_event(b, ne), e1 = get_event(b, ne + 1), e2 = get_event(b, ne + 2);
@@ -375,10 +442,11 @@ int enqueue_timed(ng_batch* b, int64_t nsteps)
             CK(b, hipEventRecord(e0, b->stream));
             CK(b, launch_step(dim, b->prec == NG_FP32 ? 1 : 0, b->d_descs(), b->d_ctrls(),
                               b->d_blocks(dim), b->nblocks[dim], b->waves[dim], b->remap,
-                              b->stream));
+                              b->fused, b->stream));
             CK(b, hipEventRecord(e1, b->stream));
-            CK(b, launch_finalize(b->d_descs(), b->d_ctrls(), b->d_insts(dim), b->ninst[dim], 0,
-                                  b->stream));
+            if (b->nsep[dim])
+                CK(b, launch_finalize(b->d_descs(), b->d_ctrls(), b->d_insts(dim), b->ninst[dim],
+                                      0, b->stream));
             CK(b, hipEventRecord(e2, b->stream));
             step_pairs.push_back({ne, ne + 1});
             fin_pairs.push_back({ne + 1, ne + 2});
@@ -397,9 +465,15 @@ int enqueue_timed(ng_batch* b, int64_t nsteps)
         CK(b, hipEventElapsedTime(&ms, b->ev_pool[p.first], b->ev_pool[p.second]));
         tf += ms;
     }
-    b->t_step_ms = step_pairs.empty() ? 0.0 : ts / step_pairs.size();
-    b->t_fin_ms = fin_pairs.empty() ? 0.0 : tf / fin_pairs.size();
-    b->t_launches = (int64_t)step_pairs.size();
+    if (!step_pairs.empty()) {
+        b->t_step_ms = ts / step_pairs.size();
+        b->t_fin_ms = tf / fin_pairs.size();
+        b->t_launches = (int64_t)step_pairs.size();
+    } else {
+        b->t_step_ms = nsteps > 0 ? small_ms / nsteps : 0.0;
+        b->t_fin_ms = 0.0;
+        b->t_launches = any_small(b) ? 1 : 0;
+    }
     return NG_OK;
 }
 
@@ -428,12 +502,15 @@ int ensure_graph(ng_batch* b)
     return NG_OK;
 }
 
-// Enqueue nsteps steps: whole graphs, then single launches for the rest.
+// Enqueue nsteps steps: the small solves in one persistent launch, the big
+// ones as whole captured graphs, then single launches for the rest.
 int enqueue_steps(ng_batch* b, int64_t nsteps)
 {
     int rc = rebuild(b);
     if (rc) return rc;
     if (b->timing) return enqueue_timed(b, nsteps);
+    rc = enqueue_small(b, nsteps, b->stream);
+    if (rc || !any_big(b)) return rc;
     int64_t left = nsteps;
     if (left >= b->graph_steps) {
         rc = ensure_graph(b);
@@ -688,7 +765,9 @@ int add_solve(ng_batch* b, const ng_gas* gas, const ng_grid* grid, const ng_nume
                      b->d_blocks(s.dim) + s.block_off, s.d.nblocks, s.d.waves_per_block,
                      b->stream);
     if (e == hipSuccess)
-        e = launch_finalize(b->d_descs(), b->d_ctrls(), b->d_insts(s.dim) + s.pos, 1, 1, b->stream);
+        e = launch_finalize(b->d_descs(), b->d_ctrls(),
+                            (s.small ? b->d_small(s.dim) : b->d_insts(s.dim)) + s.pos, 1, 1,
+                            b->stream);
     if (e == hipSuccess) {
         rc = read_ctrls(b);
         if (rc) return rc;
@@ -922,6 +1001,26 @@ int ng_set_launch(ng_solver* s, int32_t rows_per_item, int32_t waves_per_block)
     return ng_batch_set_launch(s->b, s->b->slots[s->slot].dim, rows_per_item, waves_per_block);
 }
 
+int ng_batch_set_fused_accept(ng_batch* b, int32_t on)
+{
+    if (!b) return NG_EINVAL;
+    b->fused = on != 0;
+    b->dirty = true;
+    return rebuild(b);
+}
+
+int ng_set_fused_accept(ng_solver* s, int32_t on)
+{
+    if (!s) return NG_EINVAL;
+    return ng_batch_set_fused_accept(s->b, on);
+}
+
+int ng_set_small_limit(ng_solver* s, int64_t max_cells)
+{
+    if (!s) return NG_EINVAL;
+    return solver_rc(s, ng_batch_set_small_limit(s->b, max_cells));
+}
+
 int ng_set_graph_steps(ng_solver* s, int32_t steps)
 {
     if (!s || steps < 1 || steps > 4096) return NG_EINVAL;
@@ -1094,6 +1193,14 @@ int ng_batch_set_launch(ng_batch* b, int32_t dim, int32_t rows_per_item, int32_t
         return rc;
     }
     return NG_OK;
+}
+
+int ng_batch_set_small_limit(ng_batch* b, int64_t max_cells)
+{
+    if (!b || max_cells < -1) return NG_EINVAL;
+    b->small_limit = max_cells;
+    b->dirty = true;
+    return rebuild(b);
 }
 
 const char* ng_batch_last_error(const ng_batch* b) { return b ? b->err.c_str() : "null batch"; }

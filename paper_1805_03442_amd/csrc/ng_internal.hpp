@@ -26,6 +26,8 @@ struct InstDesc {
     int32_t rows_per_item;    // 2D: rows per work item; 1D: segments per work item
     int32_t nchunks;          // 2D: row chunks; 1D: segment groups
     int32_t waves_per_block;
+    int32_t fused;            // the step kernel accepts the step (last workgroup)
+    int32_t pad0;
     int64_t nitems;           // nstrips * nchunks (2D) or nchunks (1D)
     int64_t nblocks;          // workgroups of this solve's step launch
     uint64_t buf[2];          // device addresses of the two state buffers
@@ -56,6 +58,8 @@ struct InstCtrl {
     double total[5];          // sum over cells of U (full values, FP64)
     double budget[2];         // sum over steps and cells of the source increments
     double rho_min, p_min, smax;
+    uint32_t arrive;          // workgroups of the current step that have finished
+    uint32_t pad;
 };
 
 // One workgroup's reduction record of a step (or of the priming pass).

@@ -341,6 +341,146 @@ __device__ __forceinline__ void load_cell_cached(const R* __restrict__ base, int
     for (int c = 0; c < NC; c++) U[c] = base[c * ncell + idx];
 }
 
+// ==================================================== accepting a step
+
+// Apply a folded step record v = (tot[5], src[2], smax, rho_min, p_min) with
+// flags to a solve: reject (sticky NG_EPHYS, buffers not swapped) or accept
+// (swap buffers, advance t, next dt from eq. (16)).  mode 1: priming (no step
+// taken, only the totals and the first dt).
+__device__ void accept_step(const InstDesc& d, InstCtrl& c, const StepCtl& sc, const double* v,
+                            uint32_t flags, int mode)
+{
+    const double n = (double)d.ncell;
+    const uint32_t bad = flags & 7u;
+    if (bad) {
+        c.status = -3;  // NG_EPHYS
+        c.flags = bad;
+        return;
+    }
+    if (mode == 0) {
+        c.cur = sc.cur ^ 1;
+        c.t = c.t + sc.dt;
+        c.steps = c.steps + 1;
+        c.dt_last = sc.dt;
+        c.budget[0] += v[5];
+        c.budget[1] += v[6];
+    }
+    for (int q = 0; q < 5; q++) c.total[q] = v[q] + n * d.uref[q];
+    c.smax = v[7];
+    c.rho_min = v[8];
+    c.p_min = v[9];
+    c.dt_cfl = d.cfl * d.h / v[7];
+    c.flags = 0u;
+}
+
+// ================================================================ finalize
+
+// One workgroup per solve: fold the step's records in a fixed order, accept
+// (swap buffers, advance t, next dt from eq. (16)) or reject (sticky NG_EPHYS,
+// the state before the step is kept).  mode 0: after a step; 1: priming.
+// Fold a solve's workgroup records in a fixed order with all threads of the
+// calling workgroup (up to 16 waves): strided per-thread sums, then lanes
+// (butterfly; lane 0's order is fixed), then waves in order.  The result is in
+// out[10] / *oflags, valid in thread 0 after the call.
+__device__ void fold_partials(const InstDesc& d, double* out, uint32_t* oflags)
+{
+    __shared__ double sh[16][10];
+    __shared__ uint32_t shf[16];
+    const Partial* parts = (const Partial*)d.partials;
+    const int64_t nb = d.nblocks;
+    double tot[5] = {0, 0, 0, 0, 0}, src0 = 0.0, src1 = 0.0, smax = 0.0, rmin = INFINITY,
+           pmin = INFINITY;
+    uint32_t flags = 0;
+#pragma unroll 4
+    for (int64_t b = threadIdx.x; b < nb; b += blockDim.x) {
+        const Partial& p = parts[b];
+        for (int q = 0; q < 5; q++) tot[q] += p.tot[q];
+        src0 += p.src[0];
+        src1 += p.src[1];
+        smax = fmax(smax, p.smax);
+        rmin = fmin(rmin, p.rho_min);
+        pmin = fmin(pmin, p.p_min);
+        flags |= p.flags;
+    }
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    for (int m = 32; m >= 1; m >>= 1) {
+        for (int q = 0; q < 5; q++) tot[q] += lane_xor(tot[q], lane, m);
+        src0 += lane_xor(src0, lane, m);
+        src1 += lane_xor(src1, lane, m);
+        smax = fmax(smax, lane_xor(smax, lane, m));
+        rmin = fmin(rmin, lane_xor(rmin, lane, m));
+        pmin = fmin(pmin, lane_xor(pmin, lane, m));
+        flags |= (uint32_t)__builtin_amdgcn_ds_bpermute(((lane ^ m) & 63) << 2, (int)flags);
+    }
+    if (lane == 0) {
+        for (int q = 0; q < 5; q++) sh[wave][q] = tot[q];
+        sh[wave][5] = src0;
+        sh[wave][6] = src1;
+        sh[wave][7] = smax;
+        sh[wave][8] = rmin;
+        sh[wave][9] = pmin;
+        shf[wave] = flags;
+    }
+    __syncthreads();
+    if (t == 0) {
+        const int nw = blockDim.x >> 6;
+        for (int w = 1; w < nw; w++) {
+            for (int q = 0; q < 7; q++) sh[0][q] += sh[w][q];
+            sh[0][7] = fmax(sh[0][7], sh[w][7]);
+            sh[0][8] = fmin(sh[0][8], sh[w][8]);
+            sh[0][9] = fmin(sh[0][9], sh[w][9]);
+            shf[0] |= shf[w];
+        }
+        for (int q = 0; q < 10; q++) out[q] = sh[0][q];
+        *oflags = shf[0];
+    }
+}
+
+__global__ void __launch_bounds__(1024) finalize_kernel(const InstDesc* __restrict__ descs,
+                                                        InstCtrl* __restrict__ ctrls,
+                                                        const int32_t* __restrict__ insts,
+                                                        int mode)
+{
+    const int inst = insts[blockIdx.x];
+    const InstDesc& d = descs[inst];
+    InstCtrl& c = ctrls[inst];
+    if (mode == 0 && d.fused) return;   // accepted by the step kernel itself
+    const StepCtl sc = read_ctl(c);
+    if (mode == 0 && !sc.active) return;
+    if (mode == 1 && c.status != 0) return;
+    double v[10];
+    uint32_t flags;
+    fold_partials(d, v, &flags);
+    if (threadIdx.x == 0) accept_step(d, c, sc, v, flags, mode);
+}
+
+// The last workgroup of a solve to finish a step folds the solve's records and
+// accepts the step, so that a step is a single launch.  Each workgroup
+// releases its record (agent-scope release fence) before it counts itself in;
+// only the last one acquires (agent-scope acquire fence) before reading all
+// records, so the other workgroups never invalidate their caches.  The counter
+// is reset by the last one.
+__device__ void last_block_accept(const InstDesc& d, InstCtrl& c, const StepCtl& sc)
+{
+    __shared__ int last;
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const uint32_t prev =
+            __hip_atomic_fetch_add(&c.arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        last = prev == (uint32_t)(d.nblocks - 1);
+    }
+    __syncthreads();
+    if (!last) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    double v[10];
+    uint32_t flags;
+    fold_partials(d, v, &flags);
+    if (threadIdx.x == 0) {
+        accept_step(d, c, sc, v, flags, 0);
+        c.arrive = 0u;
+    }
+}
+
 // ================================================================ 2D step
 
 // The NC conserved planes of one state buffer: uniform base addresses and a
@@ -521,7 +661,7 @@ template <class P>
 __global__ void __launch_bounds__(256) step2d_kernel(const InstDesc* __restrict__ descs,
                                                      InstCtrl* __restrict__ ctrls,
                                                      const BlockRef* __restrict__ blocks,
-                                                     int remap)
+                                                     int remap, int fused)
 {
     using R = typename P::R;
     const int64_t G = gridDim.x;
@@ -544,6 +684,7 @@ __global__ void __launch_bounds__(256) step2d_kernel(const InstDesc* __restrict_
     }
     Partial* parts = (Partial*)d.partials;
     block_reduce_store(acc, parts + br.local, wave, lane, nwaves);
+    if (fused && d.fused) last_block_accept(d, ctrls[br.inst], sc);
 }
 
 // ================================================================ 1D step
@@ -612,7 +753,7 @@ template <class P>
 __global__ void __launch_bounds__(256) step1d_kernel(const InstDesc* __restrict__ descs,
                                                      InstCtrl* __restrict__ ctrls,
                                                      const BlockRef* __restrict__ blocks,
-                                                     int remap)
+                                                     int remap, int fused)
 {
     using R = typename P::R;
     const int64_t G = gridDim.x;
@@ -635,6 +776,7 @@ __global__ void __launch_bounds__(256) step1d_kernel(const InstDesc* __restrict_
     }
     Partial* parts = (Partial*)d.partials;
     block_reduce_store(acc, parts + br.local, wave, lane, nwaves);
+    if (fused && d.fused) last_block_accept(d, ctrls[br.inst], sc);
 }
 
 // ============================================================ priming pass
@@ -693,95 +835,6 @@ __global__ void __launch_bounds__(256) prime_kernel(const InstDesc* __restrict__
     block_reduce_store(acc, parts + br.local, wave, lane, nwaves);
 }
 
-// ================================================================ finalize
-
-// One workgroup per solve: fold the step's records in a fixed order, accept
-// (swap buffers, advance t, next dt from eq. (16)) or reject (sticky NG_EPHYS,
-// the state before the step is kept).  mode 0: after a step; 1: priming.
-__global__ void __launch_bounds__(1024) finalize_kernel(const InstDesc* __restrict__ descs,
-                                                       InstCtrl* __restrict__ ctrls,
-                                                       const int32_t* __restrict__ insts,
-                                                       int mode)
-{
-    const int inst = insts[blockIdx.x];
-    const InstDesc& d = descs[inst];
-    InstCtrl& c = ctrls[inst];
-    const StepCtl sc = read_ctl(c);
-    if (mode == 0 && !sc.active) return;
-    if (mode == 1 && c.status != 0) return;
-    const Partial* parts = (const Partial*)d.partials;
-    const int64_t nb = d.nblocks;
-    __shared__ double sh[16][10];
-    __shared__ uint32_t shf[16];
-    double tot[5] = {0, 0, 0, 0, 0}, src0 = 0.0, src1 = 0.0, smax = 0.0, rmin = INFINITY,
-           pmin = INFINITY;
-    uint32_t flags = 0;
-#pragma unroll 4
-    for (int64_t b = threadIdx.x; b < nb; b += blockDim.x) {
-        const Partial& p = parts[b];
-        for (int q = 0; q < 5; q++) tot[q] += p.tot[q];
-        src0 += p.src[0];
-        src1 += p.src[1];
-        smax = fmax(smax, p.smax);
-        rmin = fmin(rmin, p.rho_min);
-        pmin = fmin(pmin, p.p_min);
-        flags |= p.flags;
-    }
-    // fixed-order fold: lanes (butterfly, lane 0's order is fixed), then waves
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    for (int m = 32; m >= 1; m >>= 1) {
-        for (int q = 0; q < 5; q++) tot[q] += lane_xor(tot[q], lane, m);
-        src0 += lane_xor(src0, lane, m);
-        src1 += lane_xor(src1, lane, m);
-        smax = fmax(smax, lane_xor(smax, lane, m));
-        rmin = fmin(rmin, lane_xor(rmin, lane, m));
-        pmin = fmin(pmin, lane_xor(pmin, lane, m));
-        flags |= (uint32_t)__builtin_amdgcn_ds_bpermute(((lane ^ m) & 63) << 2, (int)flags);
-    }
-    if (lane == 0) {
-        for (int q = 0; q < 5; q++) sh[wave][q] = tot[q];
-        sh[wave][5] = src0;
-        sh[wave][6] = src1;
-        sh[wave][7] = smax;
-        sh[wave][8] = rmin;
-        sh[wave][9] = pmin;
-        shf[wave] = flags;
-    }
-    __syncthreads();
-    if (t == 0) {
-        const int nw = blockDim.x >> 6;
-        for (int w = 1; w < nw; w++) {
-            for (int q = 0; q < 7; q++) sh[0][q] += sh[w][q];
-            sh[0][7] = fmax(sh[0][7], sh[w][7]);
-            sh[0][8] = fmin(sh[0][8], sh[w][8]);
-            sh[0][9] = fmin(sh[0][9], sh[w][9]);
-            shf[0] |= shf[w];
-        }
-    }
-    if (t != 0) return;
-    const double n = (double)d.ncell;
-    const uint32_t bad = shf[0] & 7u;
-    if (bad) {
-        c.status = -3;  // NG_EPHYS
-        c.flags = bad;
-        return;
-    }
-    if (mode == 0) {
-        c.cur = sc.cur ^ 1;
-        c.t = c.t + sc.dt;
-        c.steps = c.steps + 1;
-        c.dt_last = sc.dt;
-        c.budget[0] += sh[0][5];
-        c.budget[1] += sh[0][6];
-    }
-    for (int q = 0; q < 5; q++) c.total[q] = sh[0][q] + n * d.uref[q];
-    c.smax = sh[0][7];
-    c.rho_min = sh[0][8];
-    c.p_min = sh[0][9];
-    c.dt_cfl = d.cfl * d.h / sh[0][7];
-    c.flags = 0u;
-}
-
 // Set the stop condition of a set of solves (a kernel, so that it can sit in
 // the stream between captured graphs without a host copy).
 __global__ void set_limits_kernel(InstCtrl* __restrict__ ctrls, const int32_t* __restrict__ insts,
@@ -794,26 +847,101 @@ __global__ void set_limits_kernel(InstCtrl* __restrict__ ctrls, const int32_t* _
     c.max_steps = max_steps_from_now < 0 ? INT64_MAX : c.steps + max_steps_from_now;
 }
 
+// ====================================================== small solves
+
+// One workgroup advances one small solve through up to nsteps steps without
+// returning to the host: its waves share the solve's work items, fold their
+// records through LDS in wave order, and wave 0 accepts the step before the
+// next one starts.  Per-cell arithmetic is that of the step kernels, so the
+// state is bitwise the same as with one launch per step.
+template <class P, int NC>
+__global__ void __launch_bounds__(512) run_small_kernel(const InstDesc* __restrict__ descs,
+                                                        InstCtrl* __restrict__ ctrls,
+                                                        const int32_t* __restrict__ insts,
+                                                        int64_t nsteps)
+{
+    using R = typename P::R;
+    const int inst = insts[blockIdx.x];
+    const InstDesc& d = descs[inst];
+    InstCtrl& c = ctrls[inst];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int nw = blockDim.x >> 6;
+    __shared__ double sh[kMaxWaves][10];
+    __shared__ uint32_t shf[kMaxWaves];
+    for (int64_t st = 0; st < nsteps; st++) {
+        const StepCtl sc = read_ctl(c);
+        if (!sc.active) break;
+        const typename P::K k = P::make(d, sc.dt);
+        Acc<R> acc;
+        acc_init(acc);
+        for (int64_t item = wave; item < d.nitems; item += nw) {
+            if constexpr (NC == 5) {
+                if (d.riemann == 1)
+                    march2d<P, 1>(d, k, sc.cur, item, lane, acc);
+                else
+                    march2d<P, 0>(d, k, sc.cur, item, lane, acc);
+            } else {
+                if (d.riemann == 1)
+                    march1d<P, 1>(d, k, sc.cur, item, lane, acc);
+                else
+                    march1d<P, 0>(d, k, sc.cur, item, lane, acc);
+            }
+        }
+        uint32_t flags = acc_flags(acc);
+        double smax = (double)acc.smax, rmin = (double)acc.rmin, pmin = (double)acc.pmin;
+        for (int m = 32; m >= 1; m >>= 1) {
+            for (int q = 0; q < 5; q++) acc.tot[q] += lane_xor(acc.tot[q], lane, m);
+            acc.src[0] += lane_xor(acc.src[0], lane, m);
+            acc.src[1] += lane_xor(acc.src[1], lane, m);
+            smax = fmax(smax, lane_xor(smax, lane, m));
+            rmin = fmin(rmin, lane_xor(rmin, lane, m));
+            pmin = fmin(pmin, lane_xor(pmin, lane, m));
+            flags |= (uint32_t)__builtin_amdgcn_ds_bpermute(((lane ^ m) & 63) << 2, (int)flags);
+        }
+        if (lane == 0) {
+            for (int q = 0; q < 5; q++) sh[wave][q] = acc.tot[q];
+            sh[wave][5] = acc.src[0];
+            sh[wave][6] = acc.src[1];
+            sh[wave][7] = smax;
+            sh[wave][8] = rmin;
+            sh[wave][9] = pmin;
+            shf[wave] = flags;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int w = 1; w < nw; w++) {
+                for (int q = 0; q < 7; q++) sh[0][q] += sh[w][q];
+                sh[0][7] = fmax(sh[0][7], sh[w][7]);
+                sh[0][8] = fmin(sh[0][8], sh[w][8]);
+                sh[0][9] = fmin(sh[0][9], sh[w][9]);
+                shf[0] |= shf[w];
+            }
+            accept_step(d, c, sc, sh[0], shf[0], 0);
+        }
+        __syncthreads();
+    }
+}
+
 // ================================================================ launchers
 
 static inline bool grid_ok(int64_t nblocks) { return nblocks > 0 && nblocks < (1LL << 31); }
 
 hipError_t launch_step(int dim, int prec, const InstDesc* descs, InstCtrl* ctrls,
-                       const BlockRef* blocks, int64_t nblocks, int waves, int remap,
+                       const BlockRef* blocks, int64_t nblocks, int waves, int remap, int fused,
                        hipStream_t s)
 {
     if (!grid_ok(nblocks) || waves < 1 || waves > 4) return hipErrorInvalidValue;
     dim3 g((unsigned)nblocks), b((unsigned)(64 * waves));
     if (dim == 2) {
         if (prec == 0)
-            hipLaunchKernelGGL(step2d_kernel<Plain64<5>>, g, b, 0, s, descs, ctrls, blocks, remap);
+            hipLaunchKernelGGL(step2d_kernel<Plain64<5>>, g, b, 0, s, descs, ctrls, blocks, remap, fused);
         else
-            hipLaunchKernelGGL(step2d_kernel<Dev32<5>>, g, b, 0, s, descs, ctrls, blocks, remap);
+            hipLaunchKernelGGL(step2d_kernel<Dev32<5>>, g, b, 0, s, descs, ctrls, blocks, remap, fused);
     } else {
         if (prec == 0)
-            hipLaunchKernelGGL(step1d_kernel<Plain64<4>>, g, b, 0, s, descs, ctrls, blocks, remap);
+            hipLaunchKernelGGL(step1d_kernel<Plain64<4>>, g, b, 0, s, descs, ctrls, blocks, remap, fused);
         else
-            hipLaunchKernelGGL(step1d_kernel<Dev32<4>>, g, b, 0, s, descs, ctrls, blocks, remap);
+            hipLaunchKernelGGL(step1d_kernel<Dev32<4>>, g, b, 0, s, descs, ctrls, blocks, remap, fused);
     }
     return hipGetLastError();
 }
@@ -843,6 +971,26 @@ hipError_t launch_finalize(const InstDesc* descs, InstCtrl* ctrls, const int32_t
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)n), dim3(1024), 0, s, descs, ctrls, insts,
                        mode);
+    return hipGetLastError();
+}
+
+hipError_t launch_small(int dim, int prec, const InstDesc* descs, InstCtrl* ctrls,
+                        const int32_t* insts, int n, int waves, int64_t nsteps, hipStream_t s)
+{
+    if (n <= 0 || nsteps <= 0) return hipSuccess;
+    if (waves < 1 || waves > kMaxWaves) return hipErrorInvalidValue;
+    dim3 g((unsigned)n), b((unsigned)(64 * waves));
+    if (dim == 2) {
+        if (prec == 0)
+            hipLaunchKernelGGL((run_small_kernel<Plain64<5>, 5>), g, b, 0, s, descs, ctrls, insts, nsteps);
+        else
+            hipLaunchKernelGGL((run_small_kernel<Dev32<5>, 5>), g, b, 0, s, descs, ctrls, insts, nsteps);
+    } else {
+        if (prec == 0)
+            hipLaunchKernelGGL((run_small_kernel<Plain64<4>, 4>), g, b, 0, s, descs, ctrls, insts, nsteps);
+        else
+            hipLaunchKernelGGL((run_small_kernel<Dev32<4>, 4>), g, b, 0, s, descs, ctrls, insts, nsteps);
+    }
     return hipGetLastError();
 }
 

@@ -10,12 +10,14 @@
 namespace ng {
 
 hipError_t launch_step(int dim, int prec, const InstDesc* descs, InstCtrl* ctrls,
-                       const BlockRef* blocks, int64_t nblocks, int waves, int remap,
+                       const BlockRef* blocks, int64_t nblocks, int waves, int remap, int fused,
                        hipStream_t s);
 hipError_t launch_prime(int dim, int prec, const InstDesc* descs, InstCtrl* ctrls,
                         const BlockRef* blocks, int64_t nblocks, int waves, hipStream_t s);
 hipError_t launch_finalize(const InstDesc* descs, InstCtrl* ctrls, const int32_t* insts, int n,
                            int mode, hipStream_t s);
+hipError_t launch_small(int dim, int prec, const InstDesc* descs, InstCtrl* ctrls,
+                        const int32_t* insts, int n, int waves, int64_t nsteps, hipStream_t s);
 hipError_t launch_set_limits(InstCtrl* ctrls, const int32_t* insts, int n, double t_end,
                              int64_t max_steps_from_now, hipStream_t s);
 

@@ -30,10 +30,12 @@ GAS_FIELDS = ("gamma", "R", "Cv", "rho0", "T0", "tau0", "tau_rho", "tau_T",
 EXPORTED = (
     "ng_strerror", "ng_state_bytes", "ng_init_state", "ng_init_conserved", "ng_step",
     "ng_run_to_time", "ng_diagnostics", "ng_get_state", "ng_get_conserved", "ng_set_launch",
-    "ng_set_graph_steps", "ng_enable_timing", "ng_kernel_time", "ng_last_error", "ng_destroy",
+    "ng_set_graph_steps", "ng_set_small_limit", "ng_set_fused_accept", "ng_enable_timing", "ng_kernel_time", "ng_last_error", "ng_destroy",
     "ng_batch_create", "ng_batch_solve_bytes", "ng_batch_add", "ng_batch_run", "ng_batch_poll",
     "ng_batch_active", "ng_batch_diagnostics", "ng_batch_get_state", "ng_batch_get_conserved",
-    "ng_batch_remove", "ng_batch_set_launch", "ng_batch_last_error", "ng_batch_destroy",
+    "ng_batch_remove", "ng_batch_set_launch", "ng_batch_set_small_limit",
+    "ng_batch_set_fused_accept", "ng_batch_last_error",
+    "ng_batch_destroy",
 )
 
 
@@ -98,6 +100,8 @@ def lib():
             "ng_get_conserved": ([vp, dp], C.c_int),
             "ng_set_launch": ([vp, i32, i32], C.c_int),
             "ng_set_graph_steps": ([vp, i32], C.c_int),
+            "ng_set_small_limit": ([vp, i64], C.c_int),
+            "ng_set_fused_accept": ([vp, i32], C.c_int),
             "ng_enable_timing": ([vp, i32], C.c_int),
             "ng_kernel_time": ([vp, dp, dp, C.POINTER(i64)], C.c_int),
             "ng_last_error": ([vp], C.c_char_p),
@@ -114,6 +118,8 @@ def lib():
             "ng_batch_get_conserved": ([vp, i32, dp], C.c_int),
             "ng_batch_remove": ([vp, i32], C.c_int),
             "ng_batch_set_launch": ([vp, i32, i32, i32], C.c_int),
+            "ng_batch_set_small_limit": ([vp, i64], C.c_int),
+            "ng_batch_set_fused_accept": ([vp, i32], C.c_int),
             "ng_batch_last_error": ([vp], C.c_char_p),
             "ng_batch_destroy": ([vp], None),
         }
@@ -246,6 +252,12 @@ class Solver:
     def set_launch(self, rows: int = 0, waves: int = 0):
         check(lib().ng_set_launch(self.h, int(rows), int(waves)), "ng_set_launch", self._err())
 
+    def set_small_limit(self, max_cells: int):
+        check(lib().ng_set_small_limit(self.h, int(max_cells)), "ng_set_small_limit", self._err())
+
+    def set_fused_accept(self, on: bool):
+        check(lib().ng_set_fused_accept(self.h, 1 if on else 0), "ng_set_fused_accept")
+
     def set_graph_steps(self, k: int):
         check(lib().ng_set_graph_steps(self.h, int(k)), "ng_set_graph_steps", self._err())
 
@@ -351,6 +363,13 @@ class Batch:
     def set_launch(self, dim: int, rows: int = 0, waves: int = 0):
         check(lib().ng_batch_set_launch(self.h, int(dim), int(rows), int(waves)),
               "ng_batch_set_launch", self._err())
+
+    def set_small_limit(self, max_cells: int):
+        check(lib().ng_batch_set_small_limit(self.h, int(max_cells)), "ng_batch_set_small_limit",
+              self._err())
+
+    def set_fused_accept(self, on: bool):
+        check(lib().ng_batch_set_fused_accept(self.h, 1 if on else 0), "ng_batch_set_fused_accept")
 
     def close(self):
         if self.h:

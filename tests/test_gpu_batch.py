@@ -1,0 +1,149 @@
+"""GPU tests of batched solves (ng_batch_*): many uneven 1D and 2D solves
+advanced together, each with its own dt, end time and totals.
+
+Bars: a solve's result in a batch is bitwise equal to the same solve run
+alone (its arithmetic does not depend on the batch); FP64 batch members equal
+the oracle bitwise as the single-solve path does; slots are reused after
+removal; solves stop exactly at their own t_end.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1805_03442_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ng():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1805_03442_amd import ng as _ng
+    _ng.lib()
+    return _ng
+
+
+def instances(seed=1, count=7):
+    """Mixed 1D/2D solves with different sizes, gas parameters and end times."""
+    r = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(count):
+        gas = dict(wl.BASE_GAS, tau0=float(r.uniform(0.01, 0.3)), Q_T=float(r.uniform(0, 3)))
+        if i % 3 == 2:
+            n = int(r.integers(40, 140))
+            W = wl.random_field_2d(gas, n, r, kmax=6, rms=1e-2)
+            out.append(dict(gas=gas, nx=n, ny=n, W=W, t_end=float(r.uniform(0.002, 0.01))))
+        else:
+            n = int(r.integers(64, 3000))
+            W = wl.acoustic_mode_1d(gas, n, int(r.integers(1, 6)), 1e-3)
+            out.append(dict(gas=gas, nx=n, ny=1, W=W, t_end=float(r.uniform(0.002, 0.02))))
+    return out
+
+
+def run_alone(ng, inst, precision):
+    s = ng.Solver(inst["gas"], inst["nx"], inst["ny"], W=inst["W"], precision=precision)
+    s.run_to_time(inst["t_end"])
+    U = s.conserved()
+    d = s.diagnostics()
+    s.close()
+    return U, d
+
+
+def arena_bytes(ng, insts, precision):
+    tot = sum(ng.Batch.solve_bytes(i["nx"], i["ny"], precision) for i in insts)
+    return int(tot * 1.1) + (64 << 20)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_batch_equals_alone_bitwise(ng, precision):
+    prec = ng.NG_FP32 if precision == "fp32" else ng.NG_FP64
+    insts = instances()
+    say(f"batch of {len(insts)} solves, {precision}")
+    b = ng.Batch(len(insts), arena_bytes(ng, insts, prec), precision=prec)
+    slots = [b.add(i["gas"], i["nx"], i["ny"], i["W"], t_end=i["t_end"]) for i in insts]
+    assert all(s is not None for s in slots)
+    done = set()
+    for _ in range(10000):
+        b.run(32)
+        done.update(b.poll())
+        if len(done) == len(insts):
+            break
+    assert len(done) == len(insts)
+    for inst, slot in zip(insts, slots):
+        Ub = b.conserved(slot)
+        db = b.diagnostics(slot)
+        Ua, da = run_alone(ng, inst, prec)
+        assert db["t"] == inst["t_end"] == da["t"]
+        assert db["steps"] == da["steps"]
+        assert np.array_equal(Ub, Ua), (inst["nx"], inst["ny"])
+    b.close()
+
+
+def test_batch_fp64_matches_oracle(ng):
+    import oracle
+    oracle.build()
+    insts = instances(seed=3, count=4)
+    b = ng.Batch(len(insts), arena_bytes(ng, insts, ng.NG_FP64), precision=ng.NG_FP64)
+    slots = [b.add(i["gas"], i["nx"], i["ny"], i["W"], t_end=i["t_end"]) for i in insts]
+    for _ in range(10000):
+        b.run(64)
+        if b.active() == 0:
+            break
+    for inst, slot in zip(insts, slots):
+        P = oracle.Problem(inst["gas"], inst["nx"], inst["ny"])
+        ref = P.run(P.prim_to_cons(inst["W"]), 10 ** 7, t_end=inst["t_end"])
+        U = b.conserved(slot)
+        comps = [0, 1, 3, 4] if inst["ny"] == 1 else [0, 1, 2, 3, 4]
+        assert np.array_equal(U[comps], ref["U"][comps])
+    b.close()
+
+
+def test_slot_reuse_and_arena_limits(ng):
+    gas = dict(wl.BASE_GAS)
+    W = wl.acoustic_mode_1d(gas, 512, 2, 1e-3)
+    per = ng.Batch.solve_bytes(512, 1, ng.NG_FP32)
+    b = ng.Batch(2, 3 * per + (16 << 20), precision=ng.NG_FP32)
+    s0 = b.add(gas, 512, 1, W, t_end=0.01)
+    s1 = b.add(gas, 512, 1, W, t_end=0.02)
+    assert b.add(gas, 512, 1, W, t_end=0.01) is None   # no free slot
+    b.remove(s0)
+    s2 = b.add(gas, 512, 1, W, t_end=0.005)
+    assert s2 == s0
+    for _ in range(1000):
+        b.run(16)
+        if b.active() == 0:
+            break
+    assert b.diagnostics(s2)["t"] == 0.005
+    assert b.diagnostics(s1)["t"] == 0.02
+    # a solve larger than the arena is refused, not truncated
+    big = wl.acoustic_mode_1d(gas, 1 << 20, 2, 1e-3)
+    b.remove(s2)
+    b.remove(s1)
+    assert b.add(gas, 1 << 20, 1, big, t_end=0.01) is None
+    b.close()
+
+
+def test_graph_replay_equals_direct_launches(ng):
+    """Steps run as captured graphs (ng_run_to_time, long ng_step) give the
+    same bits as direct launches; replays repeat with eager work between."""
+    gas = dict(wl.BASE_GAS, Q_T=2.0)
+    n = 200
+    W = wl.random_field_2d(gas, n, np.random.Generator(np.random.PCG64(8)), kmax=8, rms=1e-2)
+    for prec in (ng.NG_FP32, ng.NG_FP64):
+        a = ng.Solver(gas, n, n, W=W, precision=prec)
+        a.set_graph_steps(16)
+        for _ in range(5):
+            a.step(16)          # one graph launch each
+            _ = a.diagnostics()  # synchronising read between replays
+        b = ng.Solver(gas, n, n, W=W, precision=prec)
+        b.set_graph_steps(4096)
+        b.step(80)              # direct launches (below the graph length)
+        assert np.array_equal(a.conserved(), b.conserved())
+        a.close()
+        b.close()

@@ -58,13 +58,15 @@ def comps(ny):
 
 
 def run_both(ng, gas, W, nx, ny, steps, precision, riemann=0, stiff_z=0.5, launch=None,
-             t_end=None):
+             t_end=None, small_limit=None):
     import oracle
     oracle.build()
     P = oracle.Problem(gas, nx, ny, riemann=riemann, stiff_z=stiff_z)
     U0 = P.prim_to_cons(W)
     say(f"case nx={nx} ny={ny} steps={steps} prec={precision} riemann={riemann} launch={launch}")
     s = ng.Solver(gas, nx, ny, U=U0, precision=precision, riemann=riemann, stiff_z=stiff_z)
+    if small_limit is not None:
+        s.set_small_limit(small_limit)
     if launch:
         s.set_launch(*launch)
     if t_end is None:
@@ -174,7 +176,7 @@ def test_launch_shape_does_not_change_results(ng):
     for prec in (ng.NG_FP32, ng.NG_FP64):
         res = []
         for launch in ((4, 1), (32, 4), (17, 2), (90, 4)):
-            U, ref, d, _ = run_both(ng, gas, W, nx, ny, 15, prec, launch=launch)
+            U, ref, d, _ = run_both(ng, gas, W, nx, ny, 15, prec, launch=launch, small_limit=0)
             res.append(U)
         for r in res[1:]:
             assert np.array_equal(r, res[0])
@@ -182,7 +184,8 @@ def test_launch_shape_does_not_change_results(ng):
     w = wl.workload_1d_acoustic()
     res = []
     for launch in ((1, 1), (8, 4), (3, 2)):
-        U, ref, d, _ = run_both(ng, w["gas"], w["W"], 1024, 1, 50, ng.NG_FP32, launch=launch)
+        U, ref, d, _ = run_both(ng, w["gas"], w["W"], 1024, 1, 50, ng.NG_FP32, launch=launch,
+                                small_limit=0)
         res.append(U)
     for r in res[1:]:
         assert np.array_equal(r, res[0])
@@ -202,3 +205,63 @@ def test_translation_invariance_on_gpu(ng):
         assert np.array_equal(np.roll(np.roll(Ua, 37, axis=2), 11, axis=1), Ub)
         a.close()
         b.close()
+
+
+@pytest.mark.parametrize("case", ["1d_fp64", "1d_fp32", "2d_fp32", "2d_fp64_hll"])
+def test_persistent_small_path_equals_per_step_path(ng, case):
+    """Small solves run many steps per launch in one workgroup; the state is
+    bitwise that of one launch per step, and both match the oracle."""
+    gas = dict(wl.BASE_GAS, Q_T=2.0)
+    riemann = 1 if case.endswith("hll") else 0
+    prec = ng.NG_FP64 if "fp64" in case else ng.NG_FP32
+    if case.startswith("1d"):
+        nx, ny = 1024, 1
+        W = wl.acoustic_mode_1d(gas, nx, 4, 1e-3)
+    else:
+        nx, ny = 61, 47
+        W = wl.random_field_2d(gas, 64, np.random.Generator(np.random.PCG64(21)), kmax=6,
+                               rms=2e-2)[:, :ny, :nx].copy()
+    outs = []
+    for limit in (-1, 0):
+        U, ref, d, _ = run_both(ng, gas, W, nx, ny, 300, prec, riemann=riemann,
+                                small_limit=limit)
+        outs.append((U, d))
+        if prec == ng.NG_FP64:
+            e = rel_linf(U[comps(ny)], ref["U"][comps(ny)])
+            assert np.all(e <= FP64_TOL), e
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert outs[0][1]["t"] == outs[1][1]["t"] and outs[0][1]["steps"] == 300
+    # run_to_time on the persistent path lands on t_end
+    s = ng.Solver(gas, nx, ny, W=W, precision=prec, riemann=riemann)
+    s.run_to_time(0.01)
+    assert s.diagnostics()["t"] == 0.01
+    s.close()
+
+
+def test_fused_accept_equals_separate_finalize(ng):
+    """Accepting a step in the step kernel's last workgroup or in a separate
+    kernel gives the same state, t and dt."""
+    gas = dict(wl.BASE_GAS, Q_T=2.0)
+    for nx, ny in ((300, 140), (50000, 1)):
+        if ny == 1:
+            W = wl.multimode_1d(gas, nx, np.random.Generator(np.random.PCG64(4)), nmodes=8,
+                                kmax=64, sigma=1e-3)
+        else:
+            W = wl.random_field_2d(gas, 300, np.random.Generator(np.random.PCG64(4)), kmax=10,
+                                   rms=1e-2)[:, :ny, :].copy()
+        for prec in (ng.NG_FP32, ng.NG_FP64):
+            res = []
+            for fused in (True, False):
+                s = ng.Solver(gas, nx, ny, W=W, precision=prec)
+                s.set_small_limit(0)
+                s.set_fused_accept(fused)
+                s.step(40)
+                s.run_to_time(s.diagnostics()["t"] + 1e-3)
+                res.append((s.conserved(), s.diagnostics()))
+                s.close()
+            assert np.array_equal(res[0][0], res[1][0])
+            for key in ("t", "steps", "dt_last", "smax", "rho_min", "p_min"):
+                assert res[0][1][key] == res[1][1][key], key
+            for q in range(5):
+                assert res[0][1]["total"][q] == pytest.approx(res[1][1]["total"][q], rel=1e-13,
+                                                              abs=1e-13)
