@@ -22,7 +22,6 @@ isentropic pressure, fluid at rest; gas of eqs. (1)-(7) with Q_T = 2.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -34,27 +33,17 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_CELL_FP32 = 40.0   # 5 conserved planes read + 5 written, 4 B each
 BYTES_PER_CELL_FP64 = 80.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step2d_fp32_4096_traffic.json")
-KERNEL_SOURCES = ["paper_1805_03442_amd/csrc/ng_kernels.hip",
-                  "paper_1805_03442_amd/csrc/ng_cell.hpp",
-                  "paper_1805_03442_amd/csrc/ng_internal.hpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step2d_fp32_4096_traffic.txt")
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_hash() -> str:
-    h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
-
-
 def traffic_record():
     """Measured HBM bytes per launch of the step kernel, if the committed
-    counter summary matches the current kernel source."""
+    counter summary was taken on the current kernel source."""
+    from paper_1805_03442_amd.profiling import kernel_hash
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
@@ -65,10 +54,10 @@ def traffic_record():
     return rec
 
 
-def timed_run(ng, torch, gas, W, n, steps, warmup, precision, launch=None):
+def timed_run(ng, torch, gas, W, n, steps, warmup, precision):
+    from paper_1805_03442_amd import autotune
     s = ng.Solver(gas, n, n, W=W, precision=precision)
-    if launch:
-        s.set_launch(*launch)
+    autotune.apply(s)
     s.step(warmup)
     torch.cuda.synchronize()
     s.enable_timing(steps)
@@ -111,6 +100,7 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--accuracy-steps", type=int, default=100)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain device copy of known size (for counter scaling)")
     args = ap.parse_args()
@@ -181,6 +171,28 @@ def main():
                        / HBM_PEAK_GBS,
                        "steps": args.fp64_steps}
         log(f"[bench] FP64 {v64:.3e} cell-updates/s")
+
+    if not args.no_fp64:
+        # error of the FP32 result against the FP64 path after the same steps
+        m = args.accuracy_steps
+        log(f"[bench] FP32 vs FP64 after {m} steps")
+        outs = []
+        for prec in (ng.NG_FP32, ng.NG_FP64):
+            s = ng.Solver(gas, n, n, W=W, precision=prec)
+            s.step(m)
+            outs.append(s.conserved())
+            s.close()
+        U32, U64 = outs
+        U0 = ng.Solver(gas, n, n, W=W, precision=ng.NG_FP64)
+        Ub = U0.conserved()
+        U0.close()
+        names = ["rho", "rho_u", "rho_v", "E", "E_nu"]
+        full = {nm: float(np.abs(U32[c] - U64[c]).sum() / np.abs(U64[c]).sum())
+                for c, nm in enumerate(names)}
+        pert = {nm: float(np.abs(U32[c] - U64[c]).sum() / np.abs(U64[c] - Ub[c]).sum())
+                for c, nm in enumerate(names)}
+        out["fp32_vs_fp64"] = {"steps": m, "rel_l1": full, "rel_l1_of_perturbation": pert}
+        log(f"[bench] FP32 vs FP64 rel L1 {full}")
 
     if args.calibrate_copy:
         nbytes = 1 << 30

@@ -1,0 +1,128 @@
+"""Summaries of rocprofv3 output for the step kernels.
+
+``python -m paper_1805_03442_amd.profiling stats <kernel_stats.csv> --command ...``
+    markdown table of per-kernel durations (``--kernel-trace --stats``);
+``python -m paper_1805_03442_amd.profiling traffic <fetch.csv> <write.csv> ...``
+    HBM bytes per launch of one kernel from a ``--pmc FETCH_SIZE`` and a
+    ``--pmc WRITE_SIZE`` run (KiB per dispatch), each scaled by what the same
+    counter reads for a device-to-device copy of known size in the same run.
+
+The traffic record is written as JSON text with the hash of the kernel sources
+it was measured on; bench.py reports it only while that hash still matches.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+import statistics
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+KERNEL_SOURCES = ["paper_1805_03442_amd/csrc/ng_kernels.hip",
+                  "paper_1805_03442_amd/csrc/ng_cell.hpp",
+                  "paper_1805_03442_amd/csrc/ng_internal.hpp"]
+
+
+def kernel_hash(root: str = ROOT) -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(root, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def stats_markdown(path: str, command: str, top: int = 12) -> str:
+    rows = list(csv.DictReader(open(path)))
+    out = [f"Command: `{command}`", "",
+           "| kernel | calls | mean us | min us | max us | share |",
+           "|---|---|---|---|---|---|"]
+    for r in rows[:top]:
+        name = r["Name"].replace("|", "/")
+        if len(name) > 90:
+            name = name[:87] + "..."
+        out.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                   f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
+                   f"{float(r['Percentage']):.1f}% |")
+    return "\n".join(out) + "\n"
+
+
+def _per_dispatch(path: str):
+    rows = list(csv.DictReader(open(path)))
+    out = []
+    for r in rows:
+        out.append(dict(name=r["Kernel_Name"], grid=int(r["Grid_Size"]),
+                        value=float(r["Counter_Value"]), counter=r["Counter_Name"],
+                        dur=int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    return out
+
+
+def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int, alg_bytes: float):
+    """Bytes per launch of ``kernel`` (substring of the kernel name)."""
+    res = {}
+    for tag, path in (("fetch", fetch_csv), ("write", write_csv)):
+        d = _per_dispatch(path)
+        # calibration: the copies are the largest copyBuffer dispatches
+        copies = [x for x in d if "copyBuffer" in x["name"]]
+        copies.sort(key=lambda x: x["value"], reverse=True)
+        cal = [x["value"] for x in copies[:3]]
+        kib_copy = statistics.mean(cal)
+        # a device-to-device copy reads and writes copy_bytes
+        factor = (copy_bytes / 1024.0) / kib_copy
+        ks = [x["value"] for x in d if kernel in x["name"]]
+        res[tag] = dict(kib_per_launch=statistics.mean(ks), launches=len(ks),
+                        copy_kib=kib_copy, factor=factor,
+                        bytes_per_launch=statistics.mean(ks) * 1024.0 * factor)
+    total = res["fetch"]["bytes_per_launch"] + res["write"]["bytes_per_launch"]
+    return dict(kernel=kernel, bytes_per_launch=total, algorithmic_bytes=alg_bytes,
+                ratio=total / alg_bytes, fetch=res["fetch"], write=res["write"],
+                kernel_hash=kernel_hash())
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a = sub.add_parser("stats")
+    a.add_argument("csv")
+    a.add_argument("--command", required=True)
+    a.add_argument("--out", required=True)
+    b = sub.add_parser("traffic")
+    b.add_argument("fetch_csv")
+    b.add_argument("write_csv")
+    b.add_argument("--kernel", default="step2d_kernel<ng::Dev32<5> >")
+    b.add_argument("--copy-bytes", type=int, default=1 << 30)
+    b.add_argument("--alg-bytes", type=float, default=40.0 * 4096 * 4096)
+    b.add_argument("--command", required=True)
+    b.add_argument("--out-json", required=True)
+    b.add_argument("--out-md", required=True)
+    args = ap.parse_args(argv)
+    if args.cmd == "stats":
+        md = stats_markdown(args.csv, args.command)
+        with open(args.out, "w") as f:
+            f.write(md)
+        print(md)
+        return
+    rec = traffic(args.fetch_csv, args.write_csv, args.kernel, args.copy_bytes, args.alg_bytes)
+    rec["command"] = args.command
+    with open(args.out_json, "w") as f:
+        json.dump(rec, f, indent=1)
+    md = [f"Command (one pass per counter): `{args.command}`", "",
+          f"Kernel: `{args.kernel}`", "",
+          "| counter | KiB/launch | copy KiB (1 GiB D2D) | scale | bytes/launch |",
+          "|---|---|---|---|---|"]
+    for tag, name in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE")):
+        r = rec[tag]
+        md.append(f"| {name} | {r['kib_per_launch']:.0f} | {r['copy_kib']:.0f} | "
+                  f"{r['factor']:.3f} | {r['bytes_per_launch'] / 1e6:.1f} MB |")
+    md += ["", f"Total HBM traffic {rec['bytes_per_launch'] / 1e6:.1f} MB per launch against "
+           f"{rec['algorithmic_bytes'] / 1e6:.1f} MB algorithmic ({rec['ratio']:.2f}x).",
+           f"Kernel source hash: {rec['kernel_hash']}"]
+    with open(args.out_md, "w") as f:
+        f.write("\n".join(md) + "\n")
+    print("\n".join(md))
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])

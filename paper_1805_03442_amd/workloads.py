@@ -235,12 +235,44 @@ def serve_trace(count: int = 2000, rate: float = 200.0, seed_offset: int = 0,
     return reqs
 
 
+def modes_2d(gas: dict, n: int, r: np.random.Generator, nmodes: int = 8, kmax: int = 16,
+             rms: float = 1e-3) -> np.ndarray:
+    """A few random plane waves on an n x n periodic grid: integer wave-vectors
+    with components in [-kmax, kmax], random phases, Gaussian amplitudes,
+    rescaled to the requested rms; isentropic pressure, v = 0.  Built as one
+    (n x 2m) by (2m x n) product of separable factors, for request streams."""
+    x = cell_centres(n)
+    Y = np.zeros((2 * nmodes, n))
+    X = np.zeros((2 * nmodes, n))
+    for m in range(nmodes):
+        kx, ky = r.integers(-kmax, kmax + 1, size=2)
+        if kx == 0 and ky == 0:
+            kx = 1
+        ph = r.uniform(0.0, 2.0 * math.pi)
+        a = r.normal()
+        # sin(p + q) = sin p cos q + cos p sin q, p along x, q along y
+        px = 2.0 * math.pi * kx * x + ph
+        qy = 2.0 * math.pi * ky * x
+        Y[2 * m] = a * np.cos(qy)
+        X[2 * m] = np.sin(px)
+        Y[2 * m + 1] = a * np.sin(qy)
+        X[2 * m + 1] = np.cos(px)
+    field = Y.T @ X
+    field *= rms / max(np.sqrt(np.mean(field * field)), 1e-300)
+    W = np.empty((5, n, n))
+    b = background(gas)
+    W[1] = 0.0
+    W[2] = 0.0
+    _apply_density_perturbation(gas, W.reshape(5, n * n), field.reshape(-1))
+    return W
+
+
 def request_state(req: dict) -> np.ndarray:
-    """Initial state of one served request: a 1D multi-mode or 2D random field
-    drawn from the request's own seed (smaller spectra than the workloads so
-    that small grids resolve them)."""
+    """Initial state of one served request, drawn from the request's own seed:
+    16 random modes in 1D, 8 random plane waves in 2D (wavenumbers small enough
+    for the request's grid)."""
     r = np.random.Generator(np.random.PCG64(req["seed"]))
     nx, ny = req["nx"], req["ny"]
     if ny == 1:
         return multimode_1d(req["gas"], nx, r, nmodes=16, kmax=min(256, nx // 8))
-    return random_field_2d(req["gas"], nx, r, kmax=min(64, nx // 8))
+    return modes_2d(req["gas"], nx, r, nmodes=8, kmax=max(1, min(16, nx // 16)))
