@@ -342,10 +342,12 @@ struct K32 {
     float itau0, Q0, I0;                // closures of eq. (6) in log2/exp2 form
     float tr, tT, Qr, QT, Ir, IT;
     float fx, fy;
-    float stiff_z;
+    float stiff_z, hstiff_z;            // stiffness threshold on dt/tau, and half of it
     float dt, dtdx, hdtdx, hdt;
+    float hdtfx, hdtfy;                 // (dt/2) f, the body force of the predictor
     double dt64, hdt64;
     int riemann;
+    bool force;                         // f != 0
 };
 
 // 1/tau, Q and I of eq. (6) at full (rho, p) in FP32: with lr = log2(rho/rho0)
@@ -361,32 +363,30 @@ __device__ __forceinline__ void closures32(const K32& k, float rho, float p, flo
     I = k.I0 * __builtin_amdgcn_exp2f(fmaf(k.Ir, lr, k.IT * lt));
 }
 
-// deviation primitives (d rho, u, [v], dp, dEv) from deviation conserved
+// deviation primitives (d rho, u, [v], dp, dEv) from deviation conserved;
+// rho |v|^2 is formed as m.v, the momentum times the velocity
 template <int NC>
 __device__ __forceinline__ void prim32(const K32& k, const float* D, float* W)
 {
     float rho = k.rho_r + D[0];
     float ir = rcp32(rho);
     float u = D[1] * ir;
+    W[0] = D[0];
+    W[1] = u;
     if (NC == 5) {
         float v = D[2] * ir;
-        float ke = 0.5f * rho * fmaf(u, u, v * v);
-        W[0] = D[0];
-        W[1] = u;
+        float m2 = fmaf(D[1], u, D[2] * v);
         W[2] = v;
-        W[3] = k.gm1 * ((D[3] - ke) - D[4]);
+        W[3] = k.gm1 * (fmaf(-0.5f, m2, D[3]) - D[4]);
         W[4] = D[4];
     } else {
-        float ke = 0.5f * rho * (u * u);
-        W[0] = D[0];
-        W[1] = u;
-        W[2] = k.gm1 * ((D[2] - ke) - D[3]);
+        W[2] = k.gm1 * (fmaf(-0.5f, D[1] * u, D[2]) - D[3]);
         W[3] = D[3];
     }
 }
 
-// signal speed of eq. (16) in FP32; c = sqrt(gamma p / rho) as
-// gamma p rsqrt(gamma p rho)
+// signal speed of eq. (16) in FP32, max(|v| + c, 2|v|) = |v| + max(c, |v|)
+// (the same rounded value); c = sqrt(gamma p / rho) as gamma p rsqrt(gamma p rho)
 template <int NC>
 __device__ __forceinline__ float speed32(const K32& k, const float* W)
 {
@@ -396,46 +396,58 @@ __device__ __forceinline__ float speed32(const K32& k, const float* W)
     float gp = k.gam * (k.p_r + W[NC == 5 ? 3 : 2]);
     float vel = __builtin_sqrtf(fmaf(u, u, v2));
     float c = gp * __builtin_amdgcn_rsqf(gp * rho);
-    return fmaxf(vel + c, 2.0f * vel);
+    return vel + fmaxf(c, vel);
 }
 
+// half-step predictor in primitive form: W + (dt/2)(-A_x dW/dx - A_y dW/dy + S(W))
+// with undivided slopes sx, sy and the divergence su + tv shared by the
+// density, pressure and E_nu rows
 template <int NC>
 __device__ __forceinline__ void predict32(const K32& k, const float* W, const float* sx,
                                           const float* sy, float* Wh)
 {
-    const float gam = k.gam, hdtdx = k.hdtdx, hdt = k.hdt;
+    const float hdtdx = k.hdtdx, hdt = k.hdt;
     constexpr int iP = NC == 5 ? 3 : 2, iV = NC == 5 ? 4 : 3;
     float dr = W[0], u = W[1], dp = W[iP], de = W[iV];
     float rho = k.rho_r + dr, p = k.p_r + dp, ev = k.ev_r + de;
     float irho = rcp32(rho);
+    float gp = k.gam * p;
     float sr = sx[0], su = sx[1], sp = sx[iP], se = sx[iV];
-    float a_r = fmaf(u, sr, rho * su);
-    float a_u = fmaf(u, su, sp * irho);
-    float a_p = fmaf(u, sp, gam * p * su);
-    float a_e = fmaf(u, se, ev * su);
-    float a_v = 0.0f, v = 0.0f;
+    float a_r, a_u, a_v = 0.0f, a_p, a_e, v = 0.0f;
     if (NC == 5) {
         v = W[2];
         float sv = sx[2];
-        a_v = u * sv;
         float tr = sy[0], tu = sy[1], tv = sy[2], tp = sy[3], te = sy[4];
-        a_r += fmaf(v, tr, rho * tv);
-        a_u += v * tu;
-        a_v += fmaf(v, tv, tp * irho);
-        a_p += fmaf(v, tp, gam * p * tv);
-        a_e += fmaf(v, te, ev * tv);
+        float dv = su + tv;
+        a_r = fmaf(u, sr, fmaf(v, tr, rho * dv));
+        a_u = fmaf(u, su, fmaf(v, tu, sp * irho));
+        a_v = fmaf(u, sv, fmaf(v, tv, tp * irho));
+        a_p = fmaf(u, sp, fmaf(v, tp, gp * dv));
+        a_e = fmaf(u, se, fmaf(v, te, ev * dv));
+    } else {
+        a_r = fmaf(u, sr, rho * su);
+        a_u = fmaf(u, su, sp * irho);
+        a_p = fmaf(u, sp, gp * su);
+        a_e = fmaf(u, se, ev * su);
     }
     float itau, Q, I;
     closures32(k, rho, p, irho, itau, Q, I);
     float relax_num = fmaf(k.CvR, dp, k.D_r - de);   // E_nue - E_nu
+    // (dt/2)/tau against half the threshold: the same decision as dt/tau
+    // against the threshold (both sides scaled by exactly 1/2)
+    float z = hdt * itau;
     float dEr;
-    if (k.dt * itau > k.stiff_z)
+    if (z > k.hstiff_z)
         dEr = relax_exact(relax_num, k.hdt64 * (double)itau);
     else
-        dEr = hdt * (relax_num * itau);
+        dEr = relax_num * z;
     Wh[0] = fmaf(-hdtdx, a_r, dr);
-    Wh[1] = fmaf(hdt, k.fx, fmaf(-hdtdx, a_u, u));
-    if (NC == 5) Wh[2] = fmaf(hdt, k.fy, fmaf(-hdtdx, a_v, v));
+    Wh[1] = fmaf(-hdtdx, a_u, u);
+    if (NC == 5) Wh[2] = fmaf(-hdtdx, a_v, v);
+    if (k.force) {
+        Wh[1] += k.hdtfx;
+        if (NC == 5) Wh[2] += k.hdtfy;
+    }
     Wh[iP] = fmaf(-k.gm1, fmaf(hdt, rho * I, dEr), fmaf(-hdtdx, a_p, dp));
     Wh[iV] = fmaf(hdt, rho * Q, dEr) + fmaf(-hdtdx, a_e, de);
 }
@@ -444,6 +456,9 @@ __device__ __forceinline__ void predict32(const K32& k, const float* W, const fl
 // deviation primitives.  HLLC is evaluated on one side only: the side K whose
 // flux the face takes (L if 0 < S_L or 0 < S*, else R) gives
 // F = F_K + S_K (U*_K - U_K), with the star jump zero on supersonic faces.
+// With sq = S_K q_K the components factor as
+//   rho (u + sq) = F_rho,  F_rho v,  (E + p)(u + sq) + sq rho (S_K - u) S*,
+//   E_nu (u + sq).
 template <int NC, int RS>
 __device__ __forceinline__ void flux32(const K32& k, const float* WL, const float* WR, float* F)
 {
@@ -462,10 +477,10 @@ __device__ __forceinline__ void flux32(const K32& k, const float* WL, const floa
         // HLL, eq. (13), with both physical fluxes
         float vL = NC == 5 ? WL[2] : 0.0f, vR = NC == 5 ? WR[2] : 0.0f;
         float deL = WL[iV], deR = WR[iV];
-        float keL = 0.5f * rL * (NC == 5 ? fmaf(uL, uL, vL * vL) : uL * uL);
-        float keR = 0.5f * rR * (NC == 5 ? fmaf(uR, uR, vR * vR) : uR * uR);
-        float dEL = fmaf(dpL, k.igm1, keL) + deL;
-        float dER = fmaf(dpR, k.igm1, keR) + deR;
+        float m2L = NC == 5 ? fmaf(mL, uL, (rL * vL) * vL) : mL * uL;
+        float m2R = NC == 5 ? fmaf(mR, uR, (rR * vR) * vR) : mR * uR;
+        float dEL = fmaf(0.5f, m2L, fmaf(dpL, k.igm1, deL));
+        float dER = fmaf(0.5f, m2R, fmaf(dpR, k.igm1, deR));
         float HL = k.H_r + (dEL + dpL), HR = k.H_r + (dER + dpR);
         float UL[5], UR[5], FL[5], FR[5];
         UL[0] = WL[0];
@@ -499,26 +514,30 @@ __device__ __forceinline__ void flux32(const K32& k, const float* WL, const floa
         return;
     }
     float dL = SL - uL, dR = SR - uR;
-    float Ss = ((dpR - dpL) + (mL * dL - mR * dR)) * rcp32(rL * dL - rR * dR);
+    float Ss = fmaf(mL, dL, fmaf(-mR, dR, dpR - dpL)) * rcp32(fmaf(rL, dL, -(rR * dR)));
     const bool supL = 0.0f < SL, supR = SR < 0.0f;
     const bool left = supL || (!supR && 0.0f < Ss);
     float rK = left ? rL : rR, uK = left ? uL : uR, dpK = left ? dpL : dpR;
     float deK = left ? WL[iV] : WR[iV];
     float vK = NC == 5 ? (left ? WL[2] : WR[2]) : 0.0f;
     float SK = left ? SL : SR, dK = left ? dL : dR, mK = left ? mL : mR;
-    float keK = 0.5f * rK * (NC == 5 ? fmaf(uK, uK, vK * vK) : uK * uK);
-    float dEK = fmaf(dpK, k.igm1, keK) + deK;
+    float m2K = NC == 5 ? fmaf(mK, uK, (rK * vK) * vK) : mK * uK;   // rho |v|^2
+    float dEK = fmaf(0.5f, m2K, fmaf(dpK, k.igm1, deK));
     float HK = k.H_r + (dEK + dpK);   // E + p
     float evK = k.ev_r + deK;
     float q = (supL || supR) ? 0.0f : (Ss - uK) * rcp32(SK - Ss);
-    float sq = SK * q;
-    F[0] = fmaf(sq, rK, mK);
-    F[1] = fmaf(sq * rK, SK, fmaf(mK, uK, dpK));
-    if (NC == 5) F[2] = fmaf(sq * rK, vK, mK * vK);
-    F[iP] = fmaf(sq, fmaf(rK * dK, Ss, HK), uK * HK);
-    F[iV] = fmaf(sq, evK, uK * evK);
+    float sq = SK * q, sqr = sq * rK;
+    float us = uK + sq;
+    float F0 = fmaf(sq, rK, mK);
+    F[0] = F0;
+    F[1] = fmaf(sqr, SK, fmaf(mK, uK, dpK));
+    if (NC == 5) F[2] = F0 * vK;
+    F[iP] = fmaf(HK, us, sqr * (dK * Ss));
+    F[iV] = evK * us;
 }
 
+// corrector of eq. (15): U^n - dt/h (dF + dG) + dt Y(W^{n+1/2}); the source
+// rows without a body force reduce to rho (Q - I) and (E_nue - E_nu)/tau + rho Q
 template <int NC>
 __device__ __forceinline__ void update32(const K32& k, const float* Un, const float* dF,
                                          const float* dG, const float* Wh, float* Unew,
@@ -532,27 +551,29 @@ __device__ __forceinline__ void update32(const K32& k, const float* Un, const fl
     float irho = rcp32(rho);
     float itau, Q, I;
     closures32(k, rho, p, irho, itau, Q, I);
-    float Y[5];
-    Y[0] = 0.0f;
-    Y[1] = rho * k.fx;
-    if (NC == 5) Y[2] = rho * k.fy;
-    Y[iP] = rho * (fmaf(u, k.fx, v * k.fy) + (Q - I));
+    float yE = rho * (Q - I);
     float relax_num = fmaf(k.CvR, dp, k.D_r - de);
-    Y[iV] = fmaf(relax_num, itau, rho * Q);
-    for (int c = 0; c < NC; c++) {
-        float div = NC == 5 ? dF[c] + dG[c] : dF[c];
-        Unew[c] = fmaf(dt, Y[c], fmaf(-dtdx, div, Un[c]));
+    float yV = fmaf(relax_num, itau, rho * Q);
+    float div[NC];
+    for (int c = 0; c < NC; c++) div[c] = NC == 5 ? dF[c] + dG[c] : dF[c];
+    for (int c = 0; c < NC; c++) Unew[c] = fmaf(-dtdx, div[c], Un[c]);
+    if (k.force) {
+        Unew[1] = fmaf(dt, rho * k.fx, Unew[1]);
+        if (NC == 5) Unew[2] = fmaf(dt, rho * k.fy, Unew[2]);
+        yE = fmaf(rho, fmaf(u, k.fx, v * k.fy), yE);
     }
-    float dv = dt * Y[iV];
+    Unew[iP] = fmaf(dt, yE, Unew[iP]);
+    float dv = dt * yV;
     if (k.dt * itau > k.stiff_z) {
         // exact relaxation from the start-of-step E_nu, FP64 factor
         float num = fmaf(k.CvR, dp, k.D_r - Un[iV]);
         float dEr = relax_exact(num, k.dt64 * (double)itau);
         dv = fmaf(dt, rho * Q, dEr);
-        float div = NC == 5 ? dF[iV] + dG[iV] : dF[iV];
-        Unew[iV] = dv + fmaf(-dtdx, div, Un[iV]);
+        Unew[iV] = dv + Unew[iV];
+    } else {
+        Unew[iV] = fmaf(dt, yV, Unew[iV]);
     }
-    srcE = dt * Y[iP];
+    srcE = dt * yE;
     srcV = dv;
 }
 

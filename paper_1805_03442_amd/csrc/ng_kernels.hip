@@ -49,6 +49,12 @@ __device__ __forceinline__ double from_right(double v)
     return __hiloint2double(dpp_r(__double2hiint(v)), dpp_r(__double2loint(v)));
 }
 
+// face value W + s/2 of a limited linear profile (eq. (14)) as one fused
+// multiply-add: the product by 1/2 is exact, so this is the correctly rounded
+// W + s/2, the value of the separate multiply and add
+__device__ __forceinline__ float face(float w, float s) { return __builtin_fmaf(0.5f, s, w); }
+__device__ __forceinline__ double face(double w, double s) { return __builtin_fma(0.5, s, w); }
+
 // keep a value computed here (stops it from being sunk into a later block,
 // away from the DPP move it combines with)
 __device__ __forceinline__ void pin(float& v) { asm volatile("" : "+v"(v)); }
@@ -137,7 +143,6 @@ struct Plain64 {
     {
         update64<NC>(k, Un, dF, dG, Wh, Unew, sE, sV);
     }
-    static __device__ R half() { return 0.5; }
     static __device__ R full_rho(const K&, R r) { return r; }
     static __device__ R full_p(const K&, R p) { return p; }
 };
@@ -172,10 +177,14 @@ struct Dev32 {
         k.fx = (float)d.fx;
         k.fy = (float)d.fy;
         k.stiff_z = (float)d.stiff_z;
+        k.hstiff_z = 0.5f * k.stiff_z;
         k.dt = (float)dt;
         k.dtdx = (float)(dt / d.h);
         k.hdtdx = 0.5f * k.dtdx;
         k.hdt = 0.5f * k.dt;
+        k.hdtfx = k.hdt * k.fx;
+        k.hdtfy = k.hdt * k.fy;
+        k.force = d.fx != 0.0 || d.fy != 0.0;
         k.dt64 = (double)k.dt;
         k.hdt64 = (double)k.hdt;
         k.riemann = d.riemann;
@@ -197,7 +206,6 @@ struct Dev32 {
     {
         update32<NC>(k, Un, dF, dG, Wh, Unew, sE, sV);
     }
-    static __device__ R half() { return 0.5f; }
     static __device__ R full_rho(const K& k, R r) { return k.rho_r + r; }
     static __device__ R full_p(const K& k, R p) { return k.p_r + p; }
 };
@@ -530,7 +538,6 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
 {
     using R = typename P::R;
     constexpr int NC = 5;
-    const R half = P::half();
     const int64_t nx = d.nx, ny = d.ny;
     const int64_t strip = item % d.nstrips, chunk = item / d.nstrips;
     const int64_t x0 = strip * kInterior;
@@ -581,7 +588,7 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
         slopes_x(Wb, sx);
         for (int c = 0; c < NC; c++) sy[c] = minmod(Wb[c] - Wa[c], Wc[c] - Wb[c]);
         P::predict(k, Wb, sx, sy, hb);
-        for (int c = 0; c < NC; c++) hb[c] = hb[c] + half * sy[c];
+        for (int c = 0; c < NC; c++) hb[c] = face(hb[c], sy[c]);
         // row r0
         slopes_x(Wc, XA);
         for (int c = 0; c < NC; c++) {
@@ -591,8 +598,8 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
         }
         P::predict(k, Wc, XA, sy, HA);
         for (int c = 0; c < NC; c++) {
-            S[c] = HA[c] - half * sy[c];
-            NA[c] = HA[c] + half * sy[c];
+            S[c] = face(HA[c], -sy[c]);
+            NA[c] = face(HA[c], sy[c]);
         }
         flux_y<P, RS>(k, hb, S, GA);
     }
@@ -615,8 +622,8 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
         {
             R S[NC];
             for (int c = 0; c < NC; c++) {
-                S[c] = h1[c] - half * sy[c];
-                Nn[c] = h1[c] + half * sy[c];
+                S[c] = face(h1[c], -sy[c]);
+                Nn[c] = face(h1[c], sy[c]);
             }
             flux_y<P, RS>(k, Np, S, Gn);
         }
@@ -626,8 +633,8 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
         {
             R E[NC], Wr[NC], Fx[NC];
             for (int c = 0; c < NC; c++) {
-                E[c] = h0[c] + half * x0s[c];
-                Wr[c] = from_right(h0[c] - half * x0s[c]);
+                E[c] = face(h0[c], x0s[c]);
+                Wr[c] = from_right(face(h0[c], -x0s[c]));
             }
             P::template flux<RS>(k, E, Wr, Fx);
             for (int c = 0; c < NC; c++) {
@@ -696,7 +703,6 @@ __device__ __forceinline__ void march1d(const InstDesc& d, const typename P::K& 
 {
     using R = typename P::R;
     constexpr int NC = 4;
-    const R half = P::half();
     const int64_t n = d.nx;
     const Planes<R, NC> src(d.buf[cur], n);
     const Planes<R, NC> dst(d.buf[cur ^ 1], n);
@@ -722,8 +728,8 @@ __device__ __forceinline__ void march1d(const InstDesc& d, const typename P::K& 
         P::predict(k, W, sx, sx, h);
         R E[NC], Wr[NC], Fx[NC], dF[NC];
         for (int c = 0; c < NC; c++) {
-            E[c] = h[c] + half * sx[c];
-            Wr[c] = from_right(h[c] - half * sx[c]);
+            E[c] = face(h[c], sx[c]);
+            Wr[c] = from_right(face(h[c], -sx[c]));
         }
         P::template flux<RS>(k, E, Wr, Fx);
         for (int c = 0; c < NC; c++) {

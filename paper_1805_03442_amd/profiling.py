@@ -2,6 +2,9 @@
 
 ``python -m paper_1805_03442_amd.profiling stats <kernel_stats.csv> --command ...``
     markdown table of per-kernel durations (``--kernel-trace --stats``);
+``python -m paper_1805_03442_amd.profiling counters <counter_collection.csv> ...``
+    mean per dispatch of every counter of one kernel (e.g. the SQ_ instruction
+    counts);
 ``python -m paper_1805_03442_amd.profiling traffic <fetch.csv> <write.csv> ...``
     HBM bytes per launch of one kernel from a ``--pmc FETCH_SIZE`` and a
     ``--pmc WRITE_SIZE`` run (KiB per dispatch), each scaled by what the same
@@ -81,6 +84,19 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int, alg_by
                 kernel_hash=kernel_hash())
 
 
+def counters_markdown(path: str, kernel: str, command: str) -> str:
+    by = {}
+    for x in _per_dispatch(path):
+        if kernel in x["name"]:
+            by.setdefault(x["counter"], []).append(x["value"])
+    out = [f"Command: `{command}`", "", f"Kernel: `{kernel}`", "",
+           "| counter | dispatches | mean per dispatch |", "|---|---|---|"]
+    for c in sorted(by):
+        out.append(f"| {c} | {len(by[c])} | {statistics.mean(by[c]):.6g} |")
+    out += ["", f"Kernel source hash: {kernel_hash()}"]
+    return "\n".join(out) + "\n"
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -97,7 +113,18 @@ def main(argv=None):
     b.add_argument("--command", required=True)
     b.add_argument("--out-json", required=True)
     b.add_argument("--out-md", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("csv")
+    c.add_argument("--kernel", default="step2d_kernel<ng::Dev32<5> >")
+    c.add_argument("--command", required=True)
+    c.add_argument("--out", required=True)
     args = ap.parse_args(argv)
+    if args.cmd == "counters":
+        md = counters_markdown(args.csv, args.kernel, args.command)
+        with open(args.out, "w") as f:
+            f.write(md)
+        print(md)
+        return
     if args.cmd == "stats":
         md = stats_markdown(args.csv, args.command)
         with open(args.out, "w") as f:
