@@ -218,9 +218,21 @@ int ng_batch_create(int32_t capacity, int32_t precision, void* dev_buf, size_t d
 /* Device bytes one solve of this grid occupies in a batch arena. */
 int ng_batch_solve_bytes(const ng_grid* grid, int32_t precision, size_t* bytes);
 
+/* *fits = 1 if a solve of this grid would find a free slot and a free block
+ * of ng_batch_solve_bytes() in the arena now, else 0 (a caller can defer
+ * preparing the initial state of a solve that cannot be added yet).
+ * NG_EINVAL on a null pointer or a grid that is not 1D or 2D. */
+int ng_batch_fits(const ng_batch* b, const ng_grid* grid, int32_t* fits);
+
 /* Add a solve (validation as ng_init_state; num->precision must match the
  * batch).  It runs until t_end (> t0) or max_steps steps.  *slot receives its
- * slot number.  NG_EFULL when no slot or arena space is free.  Synchronising. */
+ * slot number.  NG_EFULL when no slot or arena space is free; NG_EINVAL when a
+ * cell of the initial state is non-finite or has rho <= 0 or p <= 0.
+ * Does not wait for steps in flight: the host converts and checks `prim`
+ * while they run, the upload runs on a second stream of the library, and the
+ * solve's priming pass is ordered on the batch stream behind it; the solve
+ * joins the next ng_batch_run.  `prim` may be reused on return.  A state that
+ * the device check rejects shows as NG_EPHYS in its diagnostics. */
 int ng_batch_add(ng_batch* b, const ng_gas* gas, const ng_grid* grid, const ng_numerics* num,
                  const double* prim, double t0, double t_end, int64_t max_steps,
                  int32_t* slot);

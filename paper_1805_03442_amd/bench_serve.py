@@ -13,6 +13,12 @@ Two runs:
           2D 64..256, t_end in [0.005, 0.02]) run to completion: p50/p99
           latency, solves/s and cell-updates/s.
 
+The client side prepares each request's initial state on host threads up to
+0.25 s before its arrival; latency is counted from arrival to completion.
+Reported beside p50/p99: solves/s, the cell-updates/s of the completed solves
+and of all work done (running solves included), and the host time spent
+admitting (waiting for states, converting and uploading them).
+
 ``python -m paper_1805_03442_amd.bench_serve [--budget-gb 200] [--full-wall 60]``
 """
 from __future__ import annotations
@@ -45,8 +51,10 @@ def offered_load(recs) -> float:
 def run(recs, budget, capacity, tick, max_wall):
     reqs = serve.requests_from_trace(recs, wl.request_state)
     be = serve.GpuBackend(capacity=capacity, budget_bytes=budget)
-    srv = serve.Server(be, capacity=capacity, tick_steps=tick)
-    st = srv.run_trace(reqs, max_wall=max_wall)
+    srv = serve.Server(be, capacity=capacity, tick_steps=tick, prefetch=16,
+                       prefetch_threads=8)
+    st = srv.run_trace(reqs, max_wall=max_wall, lookahead=0.25)
+    st["state_wait_s"], st["add_s"] = be.state_s, be.add_s
     be.close()
     span = recs[-1]["arrival"] if recs else 0.0
     st["offered_cell_updates"] = offered_load(recs)

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <map>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/ng.h"
@@ -41,6 +42,11 @@ constexpr int kSmallWaves = 8;
 // step kernel (last workgroup); beyond it the per-workgroup release fence costs
 // more than the separate finalize launch.
 constexpr int64_t kFusedMaxBlocks = 256;
+// Pinned staging buffers of the initial-state upload (two, used in turn).
+constexpr size_t kStageBytes = size_t(16) << 20;
+// Host threads converting one staging chunk, and the cells each takes at least.
+constexpr int kHostThreads = 8;
+constexpr int64_t kCellsPerThread = 65536;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -69,7 +75,7 @@ size_t solve_bytes(const ng_grid* g, int prec)
 }
 
 struct Layout {
-    size_t descs, ctrls, insts, blocks1, blocks2, heap;
+    size_t descs, ctrls, insts, iota, blocks1, blocks2, heap;
 };
 
 Layout header_layout(int capacity, size_t tcap1, size_t tcap2)
@@ -82,6 +88,8 @@ Layout header_layout(int capacity, size_t tcap1, size_t tcap2)
     o += align_up(sizeof(InstCtrl) * capacity);
     L.insts = o;
     o += align_up(sizeof(int32_t) * 5 * capacity);
+    L.iota = o;
+    o += align_up(sizeof(int32_t) * capacity);
     L.blocks1 = o;
     o += align_up(sizeof(BlockRef) * tcap1);
     L.blocks2 = o;
@@ -217,6 +225,17 @@ struct ng_batch {
     int graph_steps = kDefaultGraphSteps;
     // pinned read-back of the control blocks
     InstCtrl* h_ctrls = nullptr;
+    // initial-state uploads run on a second stream, so that admitting a solve
+    // overlaps the steps in flight: chunks are converted into two pinned
+    // staging buffers in turn; descriptor and control block go through pinned
+    // per-slot copies; ev_ready marks the end of the last upload
+    hipStream_t up_stream = nullptr;
+    void* stage[2] = {nullptr, nullptr};
+    size_t stage_bytes = 0;
+    hipEvent_t ev_stage[2] = {nullptr, nullptr};
+    hipEvent_t ev_ready = nullptr;
+    InstDesc* h_desc_up = nullptr;
+    InstCtrl* h_ctrl_up = nullptr;
     std::vector<BlockRef> h_blocks[3];
     std::vector<int32_t> h_insts;
     // timing
@@ -230,6 +249,7 @@ struct ng_batch {
     InstCtrl* d_ctrls() { return (InstCtrl*)(arena + L.ctrls); }
     int32_t* d_insts(int dim) { return (int32_t*)(arena + L.insts) + dim * capacity; }
     int32_t* d_small(int dim) { return (int32_t*)(arena + L.insts) + (2 + dim) * capacity; }
+    int32_t* d_iota() { return (int32_t*)(arena + L.iota); }
     BlockRef* d_blocks(int dim) { return (BlockRef*)(arena + (dim == 1 ? L.blocks1 : L.blocks2)); }
 };
 
@@ -291,6 +311,17 @@ void arena_free(ng_batch* b, size_t off, size_t bytes)
             b->free_list.erase(it);
         }
     }
+}
+
+// A free slot and a free arena block of `bytes` exist.
+bool has_room(const ng_batch* b, size_t bytes)
+{
+    bool slot = false;
+    for (int i = 0; i < b->capacity && !slot; i++) slot = !b->slots[i].live;
+    if (!slot) return false;
+    for (const auto& kv : b->free_list)
+        if (kv.second >= bytes) return true;
+    return false;
 }
 
 // Work decomposition of one solve for the current launch shape of its dim.
@@ -578,24 +609,34 @@ int batch_new(int32_t capacity, int32_t precision, void* dev_buf, size_t dev_byt
     b->slots.resize(capacity);
     if (dev_bytes > L.heap) b->free_list[L.heap] = dev_bytes - L.heap;
     hipError_t e = hipHostMalloc((void**)&b->h_ctrls, sizeof(InstCtrl) * capacity, 0);
-    if (e != hipSuccess) {
-        err = std::string("hipHostMalloc: ") + hipGetErrorString(e);
-        delete b;
-        return NG_EDEVICE;
-    }
-    // zero the control blocks so that unused slots are inert
+    if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_desc_up, sizeof(InstDesc) * capacity, 0);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_ctrl_up, sizeof(InstCtrl) * capacity, 0);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->up_stream, hipStreamNonBlocking);
+    for (int k = 0; k < 2 && e == hipSuccess; k++)
+        e = hipEventCreateWithFlags(&b->ev_stage[k], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_ready, hipEventDisableTiming);
+    // recorded once so that the first waits on them return at once
+    for (int k = 0; k < 2 && e == hipSuccess; k++) e = hipEventRecord(b->ev_stage[k], b->up_stream);
+    if (e == hipSuccess) e = hipEventRecord(b->ev_ready, b->up_stream);
+    // zero the control blocks so that unused slots are inert; slot index list
     std::vector<InstCtrl> z(capacity);
     for (auto& c : z) {
         memset(&c, 0, sizeof(c));
         c.status = -1;
     }
-    e = hipMemcpyAsync(b->d_ctrls(), z.data(), sizeof(InstCtrl) * capacity,
-                       hipMemcpyHostToDevice, b->stream);
+    std::vector<int32_t> iota(capacity);
+    for (int i = 0; i < capacity; i++) iota[i] = i;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_ctrls(), z.data(), sizeof(InstCtrl) * capacity,
+                           hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_iota(), iota.data(), sizeof(int32_t) * capacity,
+                           hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->up_stream);
     if (e != hipSuccess) {
         err = std::string("init: ") + hipGetErrorString(e);
-        (void)hipHostFree(b->h_ctrls);
-        delete b;
+        ng_batch_destroy(b);
         return NG_EDEVICE;
     }
     *out = b;
@@ -649,6 +690,109 @@ void fill_desc(InstDesc& d, const ng_gas* gas, const ng_grid* grid, const ng_num
 
 // Validate and upload a solve's conserved state into the slot's buffer 0, run
 // the priming pass (first dt, totals, checks).  Synchronising.
+int64_t small_limit_of(const ng_batch* b)
+{
+    return b->small_limit >= 0 ? b->small_limit
+                               : (b->prec == NG_FP32 ? kSmallCells32 : kSmallCells64);
+}
+
+// Pinned staging of at least `bytes` (at most kStageBytes), both buffers idle.
+int ensure_stage(ng_batch* b, size_t bytes)
+{
+    bytes = bytes < kStageBytes ? bytes : kStageBytes;
+    if (b->stage_bytes >= bytes) return NG_OK;
+    for (int k = 0; k < 2; k++) {
+        CK(b, hipEventSynchronize(b->ev_stage[k]));
+        if (b->stage[k]) CK(b, hipHostFree(b->stage[k]));
+        b->stage[k] = nullptr;
+    }
+    b->stage_bytes = 0;
+    for (int k = 0; k < 2; k++) CK(b, hipHostMalloc(&b->stage[k], bytes, 0));
+    b->stage_bytes = bytes;
+    return NG_OK;
+}
+
+// Convert cells [a, b) of a chunk starting at cell i0 of the caller's FP64
+// state (primitive or conserved planes) to the stored form: FP64 conserved, or
+// FP32 deviations from the reference.  Checks each cell (finite, rho > 0,
+// p > 0); on failure returns the reason.
+template <class R>
+const char* convert_cells(const double* data, int64_t n, int nc, double gm1, const double* ref,
+                          bool is_prim, int64_t i0, int64_t a, int64_t b, R* st, int64_t m)
+{
+    double Wc[5], Uc[5];
+    for (int64_t i = a; i < b; i++) {
+        for (int c = 0; c < nc; c++) (is_prim ? Wc : Uc)[c] = data[c * n + i0 + i];
+        if (is_prim)
+            prim_to_cons_cell(gm1, nc, Wc, Uc);
+        else
+            cons_to_prim_cell(gm1, nc, Uc, Wc);
+        for (int c = 0; c < nc; c++) {
+            if (!isfinite(Uc[c]) || !isfinite(Wc[c])) return "non-finite initial value";
+            st[c * m + i] = (R)(Uc[c] - ref[c]);
+        }
+        if (!(Wc[0] > 0.0) || !(Wc[nc == 5 ? 3 : 2] > 0.0))
+            return "initial density and pressure must be positive";
+    }
+    return nullptr;
+}
+
+// Convert the initial state chunk by chunk into the pinned staging (large
+// chunks split over host threads) and copy each chunk to buffer 0 of the solve
+// on the upload stream.
+template <class R>
+int upload_state(ng_batch* b, const Slot& s, const double* data, bool is_prim)
+{
+    const int nc = ncomp(s.dim);
+    const int64_t n = s.d.ncell;
+    const double gm1 = s.d.gm1;
+    const double ref5[5] = {s.d.uref[0], 0.0, 0.0, s.d.uref[3], s.d.uref[4]};
+    const double ref4[4] = {s.d.uref[0], 0.0, s.d.uref[3], s.d.uref[4]};
+    const double* ref = nc == 5 ? ref5 : ref4;
+    int rc = ensure_stage(b, sizeof(R) * nc * (size_t)n);
+    if (rc) return rc;
+    const int64_t per = (int64_t)(b->stage_bytes / (sizeof(R) * nc));
+    char* dst = (char*)s.d.buf[0];
+    const int hw = (int)std::thread::hardware_concurrency();
+    const int max_threads = hw < 1 ? 1 : (hw > kHostThreads ? kHostThreads : hw);
+    int k = 0;
+    for (int64_t i0 = 0; i0 < n; i0 += per, k ^= 1) {
+        const int64_t m = n - i0 < per ? n - i0 : per;
+        CK(b, hipEventSynchronize(b->ev_stage[k]));
+        R* st = (R*)b->stage[k];
+        int nt = (int)(m / kCellsPerThread);
+        nt = nt < 1 ? 1 : (nt > max_threads ? max_threads : nt);
+        std::vector<const char*> why(nt, nullptr);
+        if (nt == 1) {
+            why[0] = convert_cells<R>(data, n, nc, gm1, ref, is_prim, i0, 0, m, st, m);
+        } else {
+            std::vector<std::thread> th;
+            for (int t = 0; t < nt; t++)
+                th.emplace_back([&, t] {
+                    why[t] = convert_cells<R>(data, n, nc, gm1, ref, is_prim, i0, m * t / nt,
+                                              m * (t + 1) / nt, st, m);
+                });
+            for (auto& x : th) x.join();
+        }
+        for (const char* w : why)
+            if (w) {
+                b->err = w;
+                return NG_EINVAL;
+            }
+        for (int c = 0; c < nc; c++)
+            CK(b, hipMemcpyAsync(dst + sizeof(R) * (c * n + i0), st + c * m, sizeof(R) * m,
+                                 hipMemcpyHostToDevice, b->up_stream));
+        CK(b, hipEventRecord(b->ev_stage[k], b->up_stream));
+    }
+    return NG_OK;
+}
+
+// Admit a solve.  The host converts and checks the initial state while the
+// steps already enqueued run; the upload goes on the upload stream, and the
+// priming pass of this solve (its totals, signal speed and first dt) is
+// enqueued on the batch stream behind it.  The solve joins the per-step
+// launches at the next run (the tables are rebuilt then).  Nothing here waits
+// for the batch stream.
 int add_solve(ng_batch* b, const ng_gas* gas, const ng_grid* grid, const ng_numerics* num,
               const double* data, bool is_prim, double t0, double t_end, int64_t max_steps,
               int32_t* slot_out)
@@ -666,30 +810,6 @@ int add_solve(ng_batch* b, const ng_gas* gas, const ng_grid* grid, const ng_nume
     if (!data || !isfinite(t0) || !(t_end > t0) || max_steps < 0) {
         b->err = "invalid state pointer, t0, t_end or max_steps";
         return NG_EINVAL;
-    }
-    const int nc = ncomp(grid->ndim);
-    const int64_t n = grid->nx * (grid->ndim == 2 ? grid->ny : 1);
-    const double gm1 = gas->gamma - 1.0;
-    // conserved FP64 state and checks
-    std::vector<double> U((size_t)nc * n);
-    double Wc[5], Uc[5];
-    for (int64_t i = 0; i < n; i++) {
-        for (int c = 0; c < nc; c++) (is_prim ? Wc : Uc)[c] = data[c * n + i];
-        if (is_prim)
-            prim_to_cons_cell(gm1, nc, Wc, Uc);
-        else
-            cons_to_prim_cell(gm1, nc, Uc, Wc);
-        for (int c = 0; c < nc; c++) {
-            if (!isfinite(Uc[c]) || !isfinite(Wc[c])) {
-                b->err = "non-finite initial value";
-                return NG_EINVAL;
-            }
-            U[c * n + i] = Uc[c];
-        }
-        if (!(Wc[0] > 0.0) || !(Wc[nc == 5 ? 3 : 2] > 0.0)) {
-            b->err = "initial density and pressure must be positive";
-            return NG_EINVAL;
-        }
     }
     int slot = -1;
     for (int i = 0; i < b->capacity; i++)
@@ -709,7 +829,6 @@ int add_solve(ng_batch* b, const ng_gas* gas, const ng_grid* grid, const ng_nume
     }
     Slot& s = b->slots[slot];
     s = Slot();
-    s.live = true;
     s.dim = grid->ndim;
     s.off = off;
     s.bytes = sb;
@@ -719,65 +838,51 @@ int add_solve(ng_batch* b, const ng_gas* gas, const ng_grid* grid, const ng_nume
     s.d.buf[0] = (uint64_t)(b->arena + off);
     s.d.buf[1] = (uint64_t)(b->arena + off + pb);
     s.d.partials = (uint64_t)(b->arena + off + 2 * pb);
-    b->dirty = true;
-
-    // upload: FP64 as is, FP32 as deviations from the reference state
-    hipError_t e;
-    if (b->prec == NG_FP64) {
-        e = hipMemcpyAsync((void*)s.d.buf[0], U.data(), sizeof(double) * U.size(),
-                           hipMemcpyHostToDevice, b->stream);
-    } else {
-        std::vector<float> D(U.size());
-        const double ref5[5] = {s.d.uref[0], 0.0, 0.0, s.d.uref[3], s.d.uref[4]};
-        const double ref4[4] = {s.d.uref[0], 0.0, s.d.uref[3], s.d.uref[4]};
-        const double* ref = nc == 5 ? ref5 : ref4;
-        for (int c = 0; c < nc; c++)
-            for (int64_t i = 0; i < n; i++) D[c * n + i] = (float)(U[c * n + i] - ref[c]);
-        e = hipMemcpyAsync((void*)s.d.buf[0], D.data(), sizeof(float) * D.size(),
-                           hipMemcpyHostToDevice, b->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    s.small = s.d.ncell <= small_limit_of(b);
+    shape_solve(b, s);
+    auto fail = [&](int code) {
+        // copies of this solve may still be queued: let them land before the
+        // arena block can be handed out again
+        (void)hipStreamSynchronize(b->up_stream);
+        arena_free(b, off, sb);
+        s = Slot();
+        return code;
+    };
+    if (s.d.nblocks > s.partial_cap) {
+        b->err = "launch shape needs more reduction records than reserved";
+        return fail(NG_EINVAL);
     }
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-    InstCtrl c;
+    // the previous admission's copies have left the per-slot staging
+    hipError_t e = hipEventSynchronize(b->ev_ready);
+    if (e != hipSuccess) return fail(dev_err(b, e, "hipEventSynchronize"));
+    rc = b->prec == NG_FP32 ? upload_state<float>(b, s, data, is_prim)
+                            : upload_state<double>(b, s, data, is_prim);
+    if (rc) return fail(rc);
+    InstCtrl& c = b->h_ctrl_up[slot];
     memset(&c, 0, sizeof(c));
     c.t = t0;
     c.t_end = t_end;
     c.max_steps = max_steps;
-    c.cur = 0;
-    c.status = 0;
+    b->h_desc_up[slot] = s.d;
+    e = hipMemcpyAsync(b->d_descs() + slot, &b->h_desc_up[slot], sizeof(InstDesc),
+                       hipMemcpyHostToDevice, b->up_stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(b->d_ctrls() + slot, &c, sizeof(c), hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        e = hipMemcpyAsync(b->d_ctrls() + slot, &c, sizeof(InstCtrl), hipMemcpyHostToDevice,
+                           b->up_stream);
+    if (e == hipSuccess) e = hipEventRecord(b->ev_ready, b->up_stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->ev_ready, 0);
+    if (e != hipSuccess) return fail(dev_err(b, e, "upload"));
+    // priming pass over this solve only: its own workgroups, listed by index
+    e = launch_prime(s.dim, b->prec == NG_FP32 ? 1 : 0, b->d_descs(), b->d_ctrls(), nullptr, slot,
+                     s.d.nblocks, s.d.waves_per_block, b->stream);
+    if (e == hipSuccess)
+        e = launch_finalize(b->d_descs(), b->d_ctrls(), b->d_iota() + slot, 1, 1, b->stream);
     if (e != hipSuccess) {
-        s.live = false;
-        arena_free(b, off, sb);
-        return dev_err(b, e, "upload");
+        (void)hipStreamSynchronize(b->stream);
+        return fail(dev_err(b, e, "prime"));
     }
-    rc = rebuild(b);
-    if (rc) {
-        s.live = false;
-        arena_free(b, off, sb);
-        b->dirty = true;
-        return rc;
-    }
-    // priming pass over this solve only
-    e = launch_prime(s.dim, b->prec == NG_FP32 ? 1 : 0, b->d_descs(), b->d_ctrls(),
-                     b->d_blocks(s.dim) + s.block_off, s.d.nblocks, s.d.waves_per_block,
-                     b->stream);
-    if (e == hipSuccess)
-        e = launch_finalize(b->d_descs(), b->d_ctrls(),
-                            (s.small ? b->d_small(s.dim) : b->d_insts(s.dim)) + s.pos, 1, 1,
-                            b->stream);
-    if (e == hipSuccess) {
-        rc = read_ctrls(b);
-        if (rc) return rc;
-    } else {
-        return dev_err(b, e, "prime");
-    }
-    if (b->h_ctrls[slot].status != 0) {
-        b->err = "initial state failed the positivity check";
-        return NG_EPHYS;
-    }
+    s.live = true;
+    b->dirty = true;
     *slot_out = slot;
     return NG_OK;
 }
@@ -903,6 +1008,8 @@ static int solver_new(const ng_gas* gas, const ng_grid* grid, const ng_numerics*
     if (rc) return rc;
     int32_t slot = 0;
     rc = add_solve(b, gas, grid, num, data, is_prim, t0, INFINITY, INT64_MAX, &slot);
+    if (!rc) rc = read_ctrls(b);
+    if (!rc && b->h_ctrls[slot].status != 0) rc = NG_EPHYS;
     if (rc) {
         ng_batch_destroy(b);
         return rc;
@@ -1084,6 +1191,14 @@ int ng_batch_solve_bytes(const ng_grid* grid, int32_t precision, size_t* bytes)
     return NG_OK;
 }
 
+int ng_batch_fits(const ng_batch* b, const ng_grid* grid, int32_t* fits)
+{
+    if (!b || !grid || !fits || (grid->ndim != 1 && grid->ndim != 2)) return NG_EINVAL;
+    if (grid->nx < 1 || (grid->ndim == 2 && grid->ny < 1)) return NG_EINVAL;
+    *fits = has_room(b, solve_bytes(grid, b->prec)) ? 1 : 0;
+    return NG_OK;
+}
+
 int ng_batch_add(ng_batch* b, const ng_gas* gas, const ng_grid* grid, const ng_numerics* num,
                  const double* prim, double t0, double t_end, int64_t max_steps, int32_t* slot)
 {
@@ -1212,7 +1327,16 @@ void ng_batch_destroy(ng_batch* b)
     drop_graph(b);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     for (auto e : b->ev_pool) (void)hipEventDestroy(e);
+    if (b->up_stream) (void)hipStreamSynchronize(b->up_stream);
     if (b->h_ctrls) (void)hipHostFree(b->h_ctrls);
+    if (b->h_desc_up) (void)hipHostFree(b->h_desc_up);
+    if (b->h_ctrl_up) (void)hipHostFree(b->h_ctrl_up);
+    for (int k = 0; k < 2; k++) {
+        if (b->stage[k]) (void)hipHostFree(b->stage[k]);
+        if (b->ev_stage[k]) (void)hipEventDestroy(b->ev_stage[k]);
+    }
+    if (b->ev_ready) (void)hipEventDestroy(b->ev_ready);
+    if (b->up_stream) (void)hipStreamDestroy(b->up_stream);
     delete b;
 }
 

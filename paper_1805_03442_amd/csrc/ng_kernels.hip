@@ -792,10 +792,11 @@ __global__ void __launch_bounds__(256) step1d_kernel(const InstDesc* __restrict_
 template <class P, int NC>
 __global__ void __launch_bounds__(256) prime_kernel(const InstDesc* __restrict__ descs,
                                                     InstCtrl* __restrict__ ctrls,
-                                                    const BlockRef* __restrict__ blocks)
+                                                    const BlockRef* __restrict__ blocks, int inst)
 {
     using R = typename P::R;
-    const BlockRef br = blocks[blockIdx.x];
+    // without a workgroup table the launch covers the workgroups of one solve
+    const BlockRef br = blocks ? blocks[blockIdx.x] : BlockRef{inst, (int32_t)blockIdx.x};
     const InstDesc& d = descs[br.inst];
     const InstCtrl& cc = ctrls[br.inst];
     if (cc.status != 0) return;
@@ -953,20 +954,21 @@ hipError_t launch_step(int dim, int prec, const InstDesc* descs, InstCtrl* ctrls
 }
 
 hipError_t launch_prime(int dim, int prec, const InstDesc* descs, InstCtrl* ctrls,
-                        const BlockRef* blocks, int64_t nblocks, int waves, hipStream_t s)
+                        const BlockRef* blocks, int inst, int64_t nblocks, int waves,
+                        hipStream_t s)
 {
     if (!grid_ok(nblocks) || waves < 1 || waves > 4) return hipErrorInvalidValue;
     dim3 g((unsigned)nblocks), b((unsigned)(64 * waves));
     if (dim == 2) {
         if (prec == 0)
-            hipLaunchKernelGGL((prime_kernel<Plain64<5>, 5>), g, b, 0, s, descs, ctrls, blocks);
+            hipLaunchKernelGGL((prime_kernel<Plain64<5>, 5>), g, b, 0, s, descs, ctrls, blocks, inst);
         else
-            hipLaunchKernelGGL((prime_kernel<Dev32<5>, 5>), g, b, 0, s, descs, ctrls, blocks);
+            hipLaunchKernelGGL((prime_kernel<Dev32<5>, 5>), g, b, 0, s, descs, ctrls, blocks, inst);
     } else {
         if (prec == 0)
-            hipLaunchKernelGGL((prime_kernel<Plain64<4>, 4>), g, b, 0, s, descs, ctrls, blocks);
+            hipLaunchKernelGGL((prime_kernel<Plain64<4>, 4>), g, b, 0, s, descs, ctrls, blocks, inst);
         else
-            hipLaunchKernelGGL((prime_kernel<Dev32<4>, 4>), g, b, 0, s, descs, ctrls, blocks);
+            hipLaunchKernelGGL((prime_kernel<Dev32<4>, 4>), g, b, 0, s, descs, ctrls, blocks, inst);
     }
     return hipGetLastError();
 }

@@ -12,8 +12,11 @@ namespace ng {
 hipError_t launch_step(int dim, int prec, const InstDesc* descs, InstCtrl* ctrls,
                        const BlockRef* blocks, int64_t nblocks, int waves, int remap, int fused,
                        hipStream_t s);
+// Priming pass: totals, checks and signal speed of the current state.  With
+// blocks == nullptr the launch covers solve `inst`'s own workgroups 0..nblocks-1.
 hipError_t launch_prime(int dim, int prec, const InstDesc* descs, InstCtrl* ctrls,
-                        const BlockRef* blocks, int64_t nblocks, int waves, hipStream_t s);
+                        const BlockRef* blocks, int inst, int64_t nblocks, int waves,
+                        hipStream_t s);
 hipError_t launch_finalize(const InstDesc* descs, InstCtrl* ctrls, const int32_t* insts, int n,
                            int mode, hipStream_t s);
 hipError_t launch_small(int dim, int prec, const InstDesc* descs, InstCtrl* ctrls,

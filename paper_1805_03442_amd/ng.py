@@ -31,7 +31,7 @@ EXPORTED = (
     "ng_strerror", "ng_state_bytes", "ng_init_state", "ng_init_conserved", "ng_step",
     "ng_run_to_time", "ng_diagnostics", "ng_get_state", "ng_get_conserved", "ng_set_launch",
     "ng_set_graph_steps", "ng_set_small_limit", "ng_set_fused_accept", "ng_enable_timing", "ng_kernel_time", "ng_last_error", "ng_destroy",
-    "ng_batch_create", "ng_batch_solve_bytes", "ng_batch_add", "ng_batch_run", "ng_batch_poll",
+    "ng_batch_create", "ng_batch_solve_bytes", "ng_batch_fits", "ng_batch_add", "ng_batch_run", "ng_batch_poll",
     "ng_batch_active", "ng_batch_diagnostics", "ng_batch_get_state", "ng_batch_get_conserved",
     "ng_batch_remove", "ng_batch_set_launch", "ng_batch_set_small_limit",
     "ng_batch_set_fused_accept", "ng_batch_last_error",
@@ -108,6 +108,7 @@ def lib():
             "ng_destroy": ([vp], None),
             "ng_batch_create": ([i32, i32, vp, C.c_size_t, vp, C.POINTER(vp)], C.c_int),
             "ng_batch_solve_bytes": ([C.POINTER(NgGrid), i32, C.POINTER(C.c_size_t)], C.c_int),
+            "ng_batch_fits": ([vp, C.POINTER(NgGrid), C.POINTER(i32)], C.c_int),
             "ng_batch_add": ([vp, C.POINTER(NgGas), C.POINTER(NgGrid), C.POINTER(NgNumerics), dp,
                               C.c_double, C.c_double, i64, C.POINTER(i32)], C.c_int),
             "ng_batch_run": ([vp, i64], C.c_int),
@@ -304,6 +305,13 @@ class Batch:
         check(lib().ng_batch_solve_bytes(C.byref(g), int(precision), C.byref(n)),
               "ng_batch_solve_bytes")
         return n.value
+
+    def fits(self, nx: int, ny: int) -> bool:
+        """A solve of this grid would be admitted now (free slot and arena block)."""
+        g = make_grid(nx, ny)
+        f = C.c_int32(0)
+        check(lib().ng_batch_fits(self.h, C.byref(g), C.byref(f)), "ng_batch_fits", self._err())
+        return bool(f.value)
 
     def add(self, gas: dict, nx: int, ny: int, W, t_end: float, max_steps: int = 2**62,
             h=None, cfl=0.4, riemann=NG_HLLC, stiff_z=0.5, t0=0.0):

@@ -5,10 +5,13 @@ time.  The server keeps one batch (``ng_batch_*``) resident on the GPU and, at
 every tick:
   1. admits waiting requests, in arrival order, whenever a batch slot and
      enough of the device arena (the HBM budget) are free -- a small request
-     may pass a large one that is still waiting for memory;
+     may pass a large one that is still waiting for memory; a request's
+     initial state is prepared only once it fits, or ahead of time on host
+     threads for the first ``prefetch`` requests of the queue;
   2. advances every admitted, unfinished solve by ``tick_steps`` steps, each
      with its own dt (eq. (16)) and end time, in one step kernel per
-     dimension;
+     dimension -- enqueued before the admissions of step 1, so that the host
+     work of admitting overlaps the steps on the GPU;
   3. collects the solves that reached their end time, releases their slots
      and arena space, and records their latency (finish - arrival).
 A solve's arithmetic does not depend on what else is in the batch, so each
@@ -22,6 +25,7 @@ from __future__ import annotations
 import collections
 import math
 import time
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -42,7 +46,17 @@ class Request:
     slot: int = -1
     result: object = None
 
+    _future: object = field(default=None, repr=False)
+
+    def prefetch(self, pool):
+        """Start preparing the initial state on a host thread."""
+        if self._future is None and callable(self.W):
+            self._future = pool.submit(self.W)
+
     def state(self):
+        if self._future is not None:
+            f, self._future = self._future, None
+            return f.result()
         return self.W() if callable(self.W) else self.W
 
 
@@ -53,7 +67,10 @@ class Stats:
     ticks: int = 0
     queued_max: int = 0
     resident_max: int = 0
-    cell_updates: float = 0.0
+    cell_updates: float = 0.0          # work of the completed solves
+    cell_updates_all: float = 0.0      # work of every solve, finished or not
+    admit_s: float = 0.0               # host time spent admitting
+    step_s: float = 0.0                # time spent in run + poll
 
     def summary(self, pending: int, waiting: int, unsubmitted: int) -> dict:
         lat = np.array([r.finished - r.arrival for r in self.completed])
@@ -61,6 +78,9 @@ class Stats:
         out = dict(completed=len(self.completed), wall_s=self.wall, ticks=self.ticks,
                    solves_per_s=len(self.completed) / self.wall if self.wall > 0 else 0.0,
                    cell_updates_per_s=self.cell_updates / self.wall if self.wall > 0 else 0.0,
+                   cell_updates_per_s_all=(self.cell_updates_all / self.wall
+                                           if self.wall > 0 else 0.0),
+                   admit_s=self.admit_s, step_s=self.step_s,
                    resident_max=self.resident_max, queued_max=self.queued_max,
                    still_running=pending, still_queued=waiting, not_yet_arrived=unsubmitted)
         if len(lat):
@@ -79,12 +99,23 @@ class GpuBackend:
         self.precision = ng.NG_FP32 if precision is None else precision
         self.batch = ng.Batch(capacity, int(budget_bytes), precision=self.precision)
         self.keep_results = keep_results
+        self.state_s = 0.0      # host time waiting for initial states
+        self.add_s = 0.0        # host time in ng_batch_add (conversion, upload)
 
     def solve_bytes(self, nx, ny):
         return self.ng.Batch.solve_bytes(nx, ny, self.precision)
 
+    def fits(self, nx, ny):
+        return self.batch.fits(nx, ny)
+
     def add(self, req: Request):
-        return self.batch.add(req.gas, req.nx, req.ny, req.state(), t_end=req.t_end)
+        t0 = time.perf_counter()
+        W = req.state()
+        t1 = time.perf_counter()
+        slot = self.batch.add(req.gas, req.nx, req.ny, W, t_end=req.t_end)
+        self.state_s += t1 - t0
+        self.add_s += time.perf_counter() - t1
+        return slot
 
     def run(self, nsteps: int):
         self.batch.run(nsteps)
@@ -107,8 +138,10 @@ class GpuBackend:
 
 class Server:
     def __init__(self, backend, capacity: int, tick_steps: int = 32, clock=time.perf_counter,
-                 sleep=time.sleep):
+                 sleep=time.sleep, prefetch: int = 0, prefetch_threads: int = 4):
         self.backend = backend
+        self.prefetch = prefetch
+        self._pool = ThreadPoolExecutor(max_workers=prefetch_threads) if prefetch > 0 else None
         self.capacity = capacity
         self.tick_steps = tick_steps
         self.clock = clock
@@ -132,11 +165,11 @@ class Server:
         keep = collections.deque()
         while self.queue:
             req = self.queue.popleft()
-            if len(self.running) >= self.capacity:
-                keep.append(req)
+            if len(self.running) >= self.capacity or not self.backend.fits(req.nx, req.ny):
+                keep.append(req)    # no slot or arena space yet: keep waiting
                 continue
             slot = self.backend.add(req)
-            if slot is None:        # no arena space yet: keep waiting
+            if slot is None:
                 keep.append(req)
                 continue
             req.slot = slot
@@ -147,13 +180,26 @@ class Server:
             self.rejected.extend(keep)
             keep = collections.deque()
         self.queue = keep
+        if self._pool is not None:
+            for req in list(self.queue)[:self.prefetch]:
+                req.prefetch(self._pool)
         self.stats.resident_max = max(self.stats.resident_max, len(self.running))
 
     def tick(self):
-        self._admit()
+        # the steps of the resident solves are enqueued first, so that the
+        # admission work on the host (state preparation, conversion, upload)
+        # overlaps them; solves admitted now join at the next tick
+        t0 = self.clock()
         if self.running:
             self.backend.run(self.tick_steps)
-            for slot in self.backend.poll():
+        t1 = self.clock()
+        self._admit()
+        t2 = self.clock()
+        self.stats.admit_s += t2 - t1
+        if self.running:
+            done = self.backend.poll()
+            self.stats.step_s += (t1 - t0) + (self.clock() - t2)
+            for slot in done:
                 req = self.running.pop(slot)
                 req.finished = self.now()
                 req.steps = self.backend.steps(slot)
@@ -163,14 +209,23 @@ class Server:
                 self.stats.cell_updates += float(req.nx) * req.ny * req.steps
         self.stats.ticks += 1
 
-    def run_trace(self, trace, max_wall: float = 60.0, drain: bool = True) -> dict:
+    def run_trace(self, trace, max_wall: float = 60.0, drain: bool = True,
+                  lookahead: float = 0.0) -> dict:
         """Replay ``trace`` (requests sorted by arrival) in real time; stop at
-        ``max_wall`` seconds, or when every request has finished."""
+        ``max_wall`` seconds, or when every request has finished.  With a
+        prefetch pool, the states of requests arriving within ``lookahead``
+        seconds are prepared before they arrive (a client that has its data
+        ready when it submits)."""
         self.t0 = self.clock()
         pending = list(trace)
         i = 0
+        ahead = 0
         while True:
             now = self.now()
+            if self._pool is not None:
+                while ahead < len(pending) and pending[ahead].arrival <= now + lookahead:
+                    pending[ahead].prefetch(self._pool)
+                    ahead += 1
             while i < len(pending) and pending[i].arrival <= now:
                 self.submit(pending[i])
                 i += 1
@@ -188,6 +243,10 @@ class Server:
             if not drain and i >= len(pending):
                 break
         self.stats.wall = self.now()
+        self.stats.cell_updates_all = self.stats.cell_updates + sum(
+            float(r.nx) * r.ny * self.backend.steps(slot) for slot, r in self.running.items())
+        if self._pool is not None:
+            self._pool.shutdown(wait=False, cancel_futures=True)
         out = self.stats.summary(len(self.running), len(self.queue), len(pending) - i)
         out["rejected"] = len(self.rejected)
         return out

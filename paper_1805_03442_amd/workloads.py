@@ -104,14 +104,19 @@ def acoustic_mode_1d(gas: dict, n: int, mode: int, amp: float,
 def multimode_1d(gas: dict, n: int, r: np.random.Generator, nmodes: int = 64,
                  kmax: int = 256, sigma: float = 1e-4) -> np.ndarray:
     """Sum of ``nmodes`` distinct integer modes drawn from 1..kmax with phases
-    U[0, 2 pi) and amplitudes N(0, sigma), on the density; isentropic companion."""
-    x = cell_centres(n)
+    U[0, 2 pi) and amplitudes N(0, sigma), on the density; isentropic companion.
+
+    The sum of sines a_m sin(2 pi m x_j + phi_m), x_j = (j + 1/2)/n, is
+    synthesised by one inverse real FFT: it is Re sum_m X_m exp(2 pi i m j / n)
+    with X_m = -i a_m exp(i (phi_m + pi m / n)) (modes below n/2)."""
     modes = np.sort(r.choice(np.arange(1, kmax + 1), size=nmodes, replace=False))
     phases = r.uniform(0.0, 2.0 * math.pi, size=nmodes)
     amps = r.normal(0.0, sigma, size=nmodes)
-    drho = np.zeros(n)
-    for m, ph, a in zip(modes, phases, amps):
-        drho += a * np.sin(2.0 * math.pi * m * x + ph)
+    if 2 * int(modes.max()) >= n:
+        raise ValueError("modes must lie below n/2")
+    X = np.zeros(n // 2 + 1, dtype=np.complex128)
+    X[modes] = -1j * amps * np.exp(1j * (phases + math.pi * modes / n)) * (n / 2.0)
+    drho = np.fft.irfft(X, n)
     W = uniform_state(gas, n)
     _apply_density_perturbation(gas, W.reshape(5, n), drho)
     return W

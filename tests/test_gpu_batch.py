@@ -109,10 +109,13 @@ def test_slot_reuse_and_arena_limits(ng):
     W = wl.acoustic_mode_1d(gas, 512, 2, 1e-3)
     per = ng.Batch.solve_bytes(512, 1, ng.NG_FP32)
     b = ng.Batch(2, 3 * per + (16 << 20), precision=ng.NG_FP32)
+    assert b.fits(512, 1)
     s0 = b.add(gas, 512, 1, W, t_end=0.01)
     s1 = b.add(gas, 512, 1, W, t_end=0.02)
+    assert not b.fits(512, 1)
     assert b.add(gas, 512, 1, W, t_end=0.01) is None   # no free slot
     b.remove(s0)
+    assert b.fits(512, 1)
     s2 = b.add(gas, 512, 1, W, t_end=0.005)
     assert s2 == s0
     for _ in range(1000):
@@ -125,6 +128,7 @@ def test_slot_reuse_and_arena_limits(ng):
     big = wl.acoustic_mode_1d(gas, 1 << 20, 2, 1e-3)
     b.remove(s2)
     b.remove(s1)
+    assert not b.fits(1 << 20, 1)
     assert b.add(gas, 1 << 20, 1, big, t_end=0.01) is None
     b.close()
 

@@ -31,10 +31,14 @@ class FakeBackend:
     def solve_bytes(self, nx, ny):
         return nx * ny * 40
 
+    def fits(self, nx, ny):
+        return len(self.slots) < self.capacity and self.solve_bytes(nx, ny) <= self.free
+
     def add(self, req):
         b = self.solve_bytes(req.nx, req.ny)
-        if len(self.slots) >= self.capacity or b > self.free:
+        if not self.fits(req.nx, req.ny):
             return None
+        req.state()
         slot = min(set(range(self.capacity)) - set(self.slots))
         need = int(math.ceil(req.t_end * 2.96 * max(req.nx, req.ny)))
         self.slots[slot] = dict(bytes=b, need=need, done=0, reported=False)
@@ -139,3 +143,45 @@ def test_request_larger_than_the_arena_is_rejected():
     st = srv.run_trace(trace, max_wall=1e9)
     assert st["completed"] == 1 and st["rejected"] == 1
     assert srv.rejected[0].id == 0
+
+
+def test_states_prepared_only_for_admitted_requests():
+    """A request waiting for arena space does not have its initial state
+    prepared again at every tick; each admitted request's state is prepared
+    exactly once."""
+    clock = FakeClock()
+    be = FakeBackend(capacity=4, budget=40 * 3000, clock=clock)
+    srv = Server(be, capacity=4, tick_steps=50, clock=clock, sleep=clock.sleep)
+    calls = {}
+
+    def state_of(i):
+        def f():
+            calls[i] = calls.get(i, 0) + 1
+            return None
+        return f
+
+    specs = [(0.0, 2000, 1, 0.3), (0.0, 2000, 1, 0.3), (0.0, 500, 1, 0.1)]
+    trace = [Request(id=i, arrival=a, nx=nx, ny=ny, gas={}, t_end=te, W=state_of(i))
+             for i, (a, nx, ny, te) in enumerate(specs)]
+    st = srv.run_trace(trace, max_wall=1e9)
+    assert st["completed"] == 3
+    assert calls == {0: 1, 1: 1, 2: 1}
+
+
+def test_prefetched_states_are_used_once():
+    clock = FakeClock()
+    be = FakeBackend(capacity=1, budget=40 * 5000, clock=clock)
+    srv = Server(be, capacity=1, tick_steps=50, clock=clock, sleep=clock.sleep, prefetch=2)
+    calls = {}
+
+    def state_of(i):
+        def f():
+            calls[i] = calls.get(i, 0) + 1
+            return i
+        return f
+
+    trace = [Request(id=i, arrival=0.0, nx=1000, ny=1, gas={}, t_end=0.1, W=state_of(i))
+             for i in range(5)]
+    st = srv.run_trace(trace, max_wall=1e9)
+    assert st["completed"] == 5
+    assert calls == {i: 1 for i in range(5)}
