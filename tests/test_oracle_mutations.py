@@ -62,6 +62,11 @@ MUTATIONS = {
     "tau_wrong_exponent": [
         ("or_pow(T / g->T0, g->tau_T);", "or_pow(T / g->T0, g->tau_rho);")],
     "power_law_half_exponent": [("if (a == 0.5) return sqrt(x);", "if (a == 0.5) return x;")],
+    "wall_keeps_normal_momentum": [("            if (fx_) Uc[1] = -Uc[1];\n", "")],
+    "wall_mirror_off_by_one": [("return j < 0 ? -1 - j : 2 * n - 1 - j;",
+                                "return j < 0 ? -j : 2 * n - 2 - j;")],
+    "outflow_copies_wrong_cell": [("if (bc == OR_BC_OUTFLOW) return j < 0 ? 0 : n - 1;",
+                                   "if (bc == OR_BC_OUTFLOW) return j < 0 ? 1 : n - 2;")],
 }
 
 

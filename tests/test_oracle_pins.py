@@ -521,3 +521,140 @@ def test_time_step_respects_eq16_supersonic(oracle_lib):
         bound = min(P.h / (2 * vel), P.h / (vel + c))
         assert dt < bound
         assert dt > 0.89 * bound
+
+
+# ------------------------------------------ boundaries: reflecting walls, outflow
+
+def test_woodward_colella_blast_waves_between_walls(oracle_lib):
+    """Section 2.4: two blast waves between reflecting walls (Euler limit,
+    n = 1000).  They collide near x = 0.7 at t = 0.028, the time and place the
+    paper gives; the walls conserve mass and energy; at t = 0.038 the density
+    peak of the well-known solution (about 6, near x = 0.78) is there."""
+    n = 1000
+    P = oracle_lib.Problem(dict(EULER_GAS), n, bc=(oracle_lib.BC_WALL,) * 2 + (0, 0))
+    U0 = P.prim_to_cons(wl.blast_waves_1d(n))
+    x = wl.cell_centres(n)
+    r = P.run(U0, 10 ** 6, t_end=0.028)
+    assert r["status"] == 0
+    V = P.cons_to_prim(r["U"])[:, 0, :]
+    assert 0.68 <= x[np.argmax(V[3])] <= 0.71
+    for c in (0, 3):
+        assert abs(r["U"][c].sum() - U0[c].sum()) <= 1e-12 * abs(U0[c].sum())
+    r = P.run(U0, 10 ** 6, t_end=0.038)
+    assert r["status"] == 0
+    V = P.cons_to_prim(r["U"])[:, 0, :]
+    assert 5.0 < V[0].max() < 7.0
+    assert 0.76 <= x[np.argmax(V[0])] <= 0.80
+    assert V[0].min() > 0.0 and V[3].min() > 0.0
+
+
+def test_wall_is_a_mirror_plane(oracle_lib):
+    """A walled domain evolves as one half of a periodic domain of twice the
+    length whose data are mirrored (density, pressure even; velocity odd)."""
+    gas = dict(wl.BASE_GAS, Q_T=2.0)
+    n = 96
+    W = wl.multimode_1d(gas, n, np.random.Generator(np.random.PCG64(9)), nmodes=6,
+                        kmax=10, sigma=3e-2)
+    W[1, 0] = 0.1 * np.sin(2 * np.pi * 2 * wl.cell_centres(n)) + 0.05
+    Wd = np.concatenate([W, W[:, :, ::-1]], axis=2)
+    Wd[1, 0, n:] = -W[1, 0, ::-1]
+    Pw = oracle_lib.Problem(gas, n, bc=(oracle_lib.BC_WALL,) * 2 + (0, 0))
+    Pp = oracle_lib.Problem(gas, 2 * n, h=1.0 / n)
+    a = Pw.run(Pw.prim_to_cons(W), 40)
+    b = Pp.run(Pp.prim_to_cons(Wd), 40)
+    assert a["status"] == 0 and b["status"] == 0
+    assert a["t"] == pytest.approx(b["t"], rel=1e-13)
+    assert np.max(np.abs(a["U"][:, :, :] - b["U"][:, :, :n])) < 1e-12
+
+
+def test_outflow_lets_a_shock_leave(oracle_lib):
+    """Sod with one interface at x = 1/2 and outflow ends: before any wave
+    reaches an end the solution is the exact one; after the shock has left
+    through x = 1 the state behind it is still the exact post-shock state
+    (a reflecting end would send it back)."""
+    n = 800
+    gas = dict(EULER_GAS)
+    x = wl.cell_centres(n)
+    W = np.zeros((5, 1, n))
+    left = x < 0.5
+    W[0, 0] = np.where(left, 1.0, 0.125)
+    W[3, 0] = np.where(left, 1.0, 0.1)
+    P = oracle_lib.Problem(gas, n, bc=(oracle_lib.BC_OUTFLOW,) * 2 + (0, 0))
+    U0 = P.prim_to_cons(W)
+    st = ER.star_state((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), 1.4)
+    r = P.run(U0, 10 ** 6, t_end=0.2)
+    V = P.cons_to_prim(r["U"])[:, 0, :]
+    ex = np.array([ER.sample((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), 1.4, (xi - 0.5) / 0.2)
+                   for xi in x])
+    assert np.mean(np.abs(V[0] - ex[:, 0])) < 5e-3
+    tail = (x > 0.92) & (x < 0.99)
+    r = P.run(U0, 10 ** 6, t_end=0.34)
+    V = P.cons_to_prim(r["U"])[:, 0, :]
+    # zero-gradient ends reflect weakly (a few per cent)
+    assert np.all(np.abs(V[0][tail] - st["rho_R"]) < 0.05 * st["rho_R"])
+    assert np.all(np.abs(V[3][tail] - st["p"]) < 0.05 * st["p"])
+    # a wall at x = 1 sends the shock back: the same check fails there
+    Pw = oracle_lib.Problem(gas, n, bc=(oracle_lib.BC_OUTFLOW, oracle_lib.BC_WALL, 0, 0))
+    rw = Pw.run(U0, 10 ** 6, t_end=0.34)
+    Vw = Pw.cons_to_prim(rw["U"])[:, 0, :]
+    assert np.max(np.abs(Vw[3][tail] - st["p"])) > 0.5 * st["p"]
+
+
+def test_uniform_flow_through_outflow_ends_bitwise(oracle_lib):
+    gas = dict(wl.BASE_GAS)
+    W = wl.uniform_state(gas, 70, 40)
+    W[1] = 0.3
+    W[2] = -0.2
+    P = oracle_lib.Problem(gas, 70, 40, bc=(oracle_lib.BC_OUTFLOW,) * 4)
+    U = P.prim_to_cons(W)
+    r = P.run(U, 25)
+    assert r["status"] == 0
+    assert np.array_equal(r["U"], U)
+
+
+def _pad_ghosts(W, kind, axis):
+    """Two ghost cells on both ends of one axis of primitive planes W, as the
+    boundary kind defines them: copies of the edge cell (outflow) or the mirror
+    image with the normal velocity negated (wall)."""
+    n = W.shape[axis]
+    idx = [0, 0] + list(range(n)) + [n - 1, n - 1] if kind == "outflow" else \
+        [1, 0] + list(range(n)) + [n - 1, n - 2]
+    P = np.take(W, idx, axis=axis).copy()
+    if kind == "wall":
+        comp = 1 if axis == 2 else 2
+        sl = [slice(None)] * 3
+        for j in (0, 1, n + 2, n + 3):
+            sl[axis] = j
+            P[comp][tuple(sl[1:])] *= -1.0
+    return P
+
+
+@pytest.mark.parametrize("kind", ["outflow", "wall"])
+@pytest.mark.parametrize("twod", [False, True])
+def test_boundary_ghosts_embed_bitwise(oracle_lib, kind, twod):
+    """One step on a bounded grid equals, cell for cell and bit for bit, one
+    step on a grid two cells larger on every bounded end whose extra cells
+    hold the ghost values (the update of a cell reaches two cells out)."""
+    gas = dict(wl.BASE_GAS, Q_T=2.0)
+    r = np.random.Generator(np.random.PCG64(21))
+    nx, ny = (40, 30) if twod else (50, 1)
+    W = wl.uniform_state(gas, nx, ny)
+    W[0] += 0.05 * r.standard_normal((ny, nx))
+    W[1] = 0.1 * r.standard_normal((ny, nx))
+    if twod:
+        W[2] = 0.1 * r.standard_normal((ny, nx))
+    W[3] += 0.05 * r.standard_normal((ny, nx))
+    W[4] *= 1.0 + 0.05 * r.standard_normal((ny, nx))
+    b = oracle_lib.BC_OUTFLOW if kind == "outflow" else oracle_lib.BC_WALL
+    bc = (b, b, b, b) if twod else (b, b, 0, 0)
+    big = _pad_ghosts(W, kind, 2)
+    if twod:
+        big = _pad_ghosts(big, kind, 1)
+    Ps = oracle_lib.Problem(gas, nx, ny, bc=bc)
+    Pb = oracle_lib.Problem(gas, nx + 4, ny + 4 if twod else 1, h=1.0 / nx, bc=bc)
+    a = Ps.run(Ps.prim_to_cons(W), 1)
+    c = Pb.run(Pb.prim_to_cons(big), 1)
+    assert a["status"] == 0 and c["status"] == 0
+    assert a["t"] == c["t"]
+    inner = c["U"][:, 2:ny + 2, 2:nx + 2] if twod else c["U"][:, :, 2:nx + 2]
+    assert np.array_equal(a["U"], inner)
