@@ -52,7 +52,10 @@ extern "C" {
 #define NG_EFULL (-5)   /* batch: no free slot or no room in the arena         */
 
 /* ------------------------------------------------------- enumerated options */
-#define NG_BC_PERIODIC 0 /* wrap-around ghost cells (the only boundary in this build) */
+#define NG_BC_PERIODIC 0 /* wrap-around ghost cells                             */
+#define NG_BC_WALL 1     /* reflecting wall: mirrored ghosts, normal momentum
+                            negated (the solid walls of section 2.4)          */
+#define NG_BC_OUTFLOW 2  /* free outflow: ghosts copy the edge cell           */
 #define NG_HLLC 0        /* three-wave HLLC flux (contact resolved)            */
 #define NG_HLL 1         /* two-wave HLL flux, eq. (13)                         */
 #define NG_MINMOD 0      /* minmod-limited slopes in eq. (14)                   */
@@ -79,7 +82,9 @@ typedef struct {
 } ng_gas;
 
 /* Uniform grid of square cells of size h (section 2.3): ndim = 1 (ny = 1) or
- * 2; bc[4] = (x-low, x-high, y-low, y-high) boundary kinds. */
+ * 2; bc[4] = (x-low, x-high, y-low, y-high) boundary kinds NG_BC_* (y ends
+ * ignored in 1D).  Planes are addressed with 32-bit byte offsets: at most
+ * 2^30 cells in FP32 and 2^29 in FP64. */
 typedef struct {
     int32_t ndim;
     int32_t reserved;

@@ -130,11 +130,25 @@ int validate(const ng_gas* gas, const ng_grid* grid, const ng_numerics* num, std
         return NG_EINVAL;
     }
     if (!finite_pos(grid->h)) { err = "h must be positive"; return NG_EINVAL; }
-    for (int i = 0; i < 4; i++)
-        if (grid->bc[i] != NG_BC_PERIODIC) {
-            err = "only periodic boundaries are implemented";
+    for (int i = 0; i < (grid->ndim == 2 ? 4 : 2); i++)
+        if (grid->bc[i] != NG_BC_PERIODIC && grid->bc[i] != NG_BC_WALL &&
+            grid->bc[i] != NG_BC_OUTFLOW) {
+            err = "unknown boundary kind";
             return NG_EINVAL;
         }
+    for (int a = 0; a < 2; a++)
+        if ((grid->bc[2 * a] == NG_BC_PERIODIC) != (grid->bc[2 * a + 1] == NG_BC_PERIODIC) &&
+            (a == 0 || grid->ndim == 2)) {
+            err = "a periodic axis needs both ends periodic";
+            return NG_EINVAL;
+        }
+    if (num->precision == NG_FP32 || num->precision == NG_FP64) {
+        const uint64_t cells = (uint64_t)grid->nx * (uint64_t)(grid->ndim == 2 ? grid->ny : 1);
+        if (cells * (num->precision == NG_FP32 ? 4u : 8u) > (1ULL << 32)) {
+            err = "grid too large for 32-bit plane offsets";
+            return NG_EINVAL;
+        }
+    }
     if (grid->ndim == 1 && gas->fy != 0.0) { err = "fy must be 0 in 1D"; return NG_EINVAL; }
     if (!(num->cfl > 0.0 && num->cfl < 1.0)) { err = "cfl must lie in (0, 1)"; return NG_EINVAL; }
     if (num->riemann != NG_HLLC && num->riemann != NG_HLL) { err = "unknown riemann solver"; return NG_EINVAL; }
@@ -258,6 +272,10 @@ struct ng_solver {
     int slot = 0;
     std::string err;
 };
+
+static_assert(NG_BC_PERIODIC == ng::kBcPeriodic && NG_BC_WALL == ng::kBcWall &&
+                  NG_BC_OUTFLOW == ng::kBcOutflow,
+              "boundary kinds of the ABI and the kernels");
 
 namespace {
 
@@ -652,6 +670,11 @@ void fill_desc(InstDesc& d, const ng_gas* gas, const ng_grid* grid, const ng_num
     d.ncell = d.nx * d.ny;
     d.ndim = grid->ndim;
     d.riemann = num->riemann;
+    d.any_bc = 0;
+    for (int i = 0; i < 4; i++) {
+        d.bc[i] = (i < 2 || grid->ndim == 2) ? grid->bc[i] : NG_BC_PERIODIC;
+        if (d.bc[i] != NG_BC_PERIODIC) d.any_bc = 1;
+    }
     d.h = grid->h;
     d.cfl = num->cfl;
     d.stiff_z = num->stiff_z;

@@ -18,6 +18,13 @@ constexpr int kHalo = 2;           // ghost cells per side of the stencil
 constexpr int kInterior = kWave - 2 * kHalo;  // cells a wave updates per row
 constexpr int kMaxWaves = 8;       // waves per workgroup, upper bound
 
+// Boundary kinds of an axis end (the values of NG_BC_*): ghost cells wrap
+// around, mirror the interior with the normal momentum negated, or copy the
+// edge cell.
+constexpr int kBcPeriodic = 0;
+constexpr int kBcWall = 1;
+constexpr int kBcOutflow = 2;
+
 // Run-constant description of one solve.
 struct InstDesc {
     int64_t nx, ny, ncell;
@@ -27,6 +34,8 @@ struct InstDesc {
     int32_t nchunks;          // 2D: row chunks; 1D: segment groups
     int32_t waves_per_block;
     int32_t fused;            // the step kernel accepts the step (last workgroup)
+    int32_t bc[4];            // boundary kinds: x-low, x-high, y-low, y-high
+    int32_t any_bc;           // some end is not periodic
     int32_t pad0;
     int64_t nitems;           // nstrips * nchunks (2D) or nchunks (1D)
     int64_t nblocks;          // workgroups of this solve's step launch

@@ -83,6 +83,24 @@ __device__ __forceinline__ int64_t wrap_axis(int64_t x, int64_t n)
     return x;
 }
 
+// Cell of coordinate j in [-2, n + 62) on an axis of n >= 4 cells whose ends
+// have boundary kinds lo and hi, and whether the normal momentum of the value
+// loaded there is to be negated.  Ghosts of a periodic end wrap around, of a
+// wall mirror the edge cells (-1 -> 0, -2 -> 1), of an outflow end copy the
+// edge cell; coordinates beyond the ghost layer (lanes that feed no interior
+// cell) are clamped into the axis.
+__device__ __forceinline__ int64_t axis_cell(int64_t j, int64_t n, int lo, int hi, bool& flip)
+{
+    flip = false;
+    if (j >= 0 && j < n) return j;
+    const int bc = j < 0 ? lo : hi;
+    if (bc == kBcPeriodic) return wrap_axis(j, n);
+    if (bc == kBcOutflow) return j < 0 ? 0 : n - 1;
+    flip = true;
+    const int64_t m = j < 0 ? -1 - j : 2 * n - 1 - j;
+    return m < 0 ? 0 : (m >= n ? n - 1 : m);
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs; hand each XCD a
 // contiguous range of logical workgroups so that neighbouring tiles (which
 // share halo rows and columns) meet in the same L2.
@@ -532,7 +550,7 @@ __device__ __forceinline__ void flux_y(const typename P::K& k, const typename P:
 }
 
 // One work item of the 2D step: strip (60 columns + halo) x chunk of rows.
-template <class P, int RS>
+template <class P, int RS, bool BC>
 __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& k, int cur,
                                         int64_t item, int lane, Acc<typename P::R>& acc)
 {
@@ -541,7 +559,9 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
     const int64_t nx = d.nx, ny = d.ny;
     const int64_t strip = item % d.nstrips, chunk = item / d.nstrips;
     const int64_t x0 = strip * kInterior;
-    const int64_t x = wrap_axis(x0 - kHalo + lane, nx);
+    bool flipx = false;
+    const int64_t x = BC ? axis_cell(x0 - kHalo + lane, nx, d.bc[0], d.bc[1], flipx)
+                         : wrap_axis(x0 - kHalo + lane, nx);
     const bool inner = lane >= kHalo && lane < kWave - kHalo && x0 + (lane - kHalo) < nx;
     const int64_t r0 = chunk * d.rows_per_item;
     const int64_t r1 = r0 + d.rows_per_item < ny ? r0 + d.rows_per_item : ny;
@@ -549,8 +569,24 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
     const Planes<R, NC> dst(d.buf[cur ^ 1], d.ncell);
     // byte offset of (row r, this lane's column); r within two rows of [0, ny)
     auto boff = [&](int64_t r) -> uint32_t {
-        int64_t rr = r < 0 ? r + ny : (r >= ny ? r - ny : r);
+        int64_t rr;
+        if (BC) {
+            bool f;
+            rr = axis_cell(r, ny, d.bc[2], d.bc[3], f);
+        } else {
+            rr = r < 0 ? r + ny : (r >= ny ? r - ny : r);
+        }
         return (uint32_t)((rr * nx + x) * (int64_t)sizeof(R));
+    };
+    // a loaded row r as ghost values: wall ghosts carry the mirrored normal
+    // momentum (x ends: rho u, y ends: rho v)
+    auto ghost = [&](int64_t r, R* U) {
+        if (BC) {
+            bool fy;
+            (void)axis_cell(r, ny, d.bc[2], d.bc[3], fy);
+            if (flipx) U[1] = -U[1];
+            if (fy) U[2] = -U[2];
+        }
     };
     auto slopes_x = [&](const R* W, R* sx) {
         for (int c = 0; c < NC; c++) {
@@ -576,12 +612,16 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
     {
         R Wa[NC], Wb[NC], Wc[NC], t[NC], sy[NC], sx[NC], hb[NC], S[NC];
         src.load(boff(r0 - 2), t);
+        ghost(r0 - 2, t);
         P::prim(k, t, Wa);
         src.load(boff(r0 - 1), t);
+        ghost(r0 - 1, t);
         P::prim(k, t, Wb);
         src.load(boff(r0), t);
+        ghost(r0, t);
         P::prim(k, t, Wc);
         src.load(boff(r0 + 1), t);
+        ghost(r0 + 1, t);
         P::prim(k, t, WA);
         src.load(boff(r0 + 2), UA);
         // row r0-1: its north face state
@@ -607,6 +647,7 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
     auto row = [&](int64_t i, R* Wd, R* We, R* Dp, R* Dn, R* h0, R* h1, R* x0s, R* x1s,
                    R* Np, R* Nn, R* Gp, R* Gn, R* Uc, R* Ux) {
         // row i+2 has arrived in Uc; put row i+3 in flight
+        ghost(i + 2, Uc);
         P::prim(k, Uc, We);
         if (i + 1 < r1) src.load(boff(i + 3), Ux);
         // predictor of row i+1
@@ -664,6 +705,18 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
     if (i < r1) row(i, WA, WB, DA, DB, HA, HB, XA, XB, NA, NB, GA, GB, UA, UB);
 }
 
+// periodic solves take the plain wrap-around indexing; solves with a wall or
+// outflow end the ghost mapping (a uniform choice per solve)
+template <class P, int RS>
+__device__ __forceinline__ void march2d_bc(const InstDesc& d, const typename P::K& k, int cur,
+                                           int64_t item, int lane, Acc<typename P::R>& acc)
+{
+    if (d.any_bc)
+        march2d<P, RS, true>(d, k, cur, item, lane, acc);
+    else
+        march2d<P, RS, false>(d, k, cur, item, lane, acc);
+}
+
 template <class P>
 __global__ void __launch_bounds__(256) step2d_kernel(const InstDesc* __restrict__ descs,
                                                      InstCtrl* __restrict__ ctrls,
@@ -685,9 +738,9 @@ __global__ void __launch_bounds__(256) step2d_kernel(const InstDesc* __restrict_
     const int64_t item = (int64_t)br.local * nwaves + wave;
     if (item < d.nitems) {
         if (d.riemann == 1)
-            march2d<P, 1>(d, k, sc.cur, item, lane, acc);
+            march2d_bc<P, 1>(d, k, sc.cur, item, lane, acc);
         else
-            march2d<P, 0>(d, k, sc.cur, item, lane, acc);
+            march2d_bc<P, 0>(d, k, sc.cur, item, lane, acc);
     }
     Partial* parts = (Partial*)d.partials;
     block_reduce_store(acc, parts + br.local, wave, lane, nwaves);
@@ -697,7 +750,7 @@ __global__ void __launch_bounds__(256) step2d_kernel(const InstDesc* __restrict_
 // ================================================================ 1D step
 
 // One work item of the 1D step: a group of consecutive 60-cell segments.
-template <class P, int RS>
+template <class P, int RS, bool BC>
 __device__ __forceinline__ void march1d(const InstDesc& d, const typename P::K& k, int cur,
                                         int64_t item, int lane, Acc<typename P::R>& acc)
 {
@@ -709,7 +762,10 @@ __device__ __forceinline__ void march1d(const InstDesc& d, const typename P::K& 
     const int64_t s0 = item * d.rows_per_item;
     const int64_t s1 = s0 + d.rows_per_item < d.nstrips ? s0 + d.rows_per_item : d.nstrips;
     auto boff = [&](int64_t sg) -> uint32_t {
-        return (uint32_t)(wrap_axis(sg * kInterior - kHalo + lane, n) * (int64_t)sizeof(R));
+        bool f;
+        const int64_t x = BC ? axis_cell(sg * kInterior - kHalo + lane, n, d.bc[0], d.bc[1], f)
+                             : wrap_axis(sg * kInterior - kHalo + lane, n);
+        return (uint32_t)(x * (int64_t)sizeof(R));
     };
     R UA[NC], UB[NC];
     src.load(boff(s0), UA);
@@ -717,6 +773,12 @@ __device__ __forceinline__ void march1d(const InstDesc& d, const typename P::K& 
         R W[NC], sx[NC], h[NC];
         const uint32_t o = boff(sg);
         if (sg + 1 < s1) src.load(boff(sg + 1), Ux);
+        if (BC) {
+            // wall ghosts carry the mirrored momentum
+            bool f;
+            (void)axis_cell(sg * kInterior - kHalo + lane, n, d.bc[0], d.bc[1], f);
+            if (f) Uc[1] = -Uc[1];
+        }
         P::prim(k, Uc, W);
         for (int c = 0; c < NC; c++) {
             R l = from_left(W[c]), r = from_right(W[c]);
@@ -755,6 +817,16 @@ __device__ __forceinline__ void march1d(const InstDesc& d, const typename P::K& 
     if (sg < s1) seg(sg, UA, UB);
 }
 
+template <class P, int RS>
+__device__ __forceinline__ void march1d_bc(const InstDesc& d, const typename P::K& k, int cur,
+                                           int64_t item, int lane, Acc<typename P::R>& acc)
+{
+    if (d.any_bc)
+        march1d<P, RS, true>(d, k, cur, item, lane, acc);
+    else
+        march1d<P, RS, false>(d, k, cur, item, lane, acc);
+}
+
 template <class P>
 __global__ void __launch_bounds__(256) step1d_kernel(const InstDesc* __restrict__ descs,
                                                      InstCtrl* __restrict__ ctrls,
@@ -776,9 +848,9 @@ __global__ void __launch_bounds__(256) step1d_kernel(const InstDesc* __restrict_
     const int64_t item = (int64_t)br.local * nwaves + wave;
     if (item < d.nitems) {
         if (d.riemann == 1)
-            march1d<P, 1>(d, k, sc.cur, item, lane, acc);
+            march1d_bc<P, 1>(d, k, sc.cur, item, lane, acc);
         else
-            march1d<P, 0>(d, k, sc.cur, item, lane, acc);
+            march1d_bc<P, 0>(d, k, sc.cur, item, lane, acc);
     }
     Partial* parts = (Partial*)d.partials;
     block_reduce_store(acc, parts + br.local, wave, lane, nwaves);
@@ -884,14 +956,14 @@ __global__ void __launch_bounds__(512) run_small_kernel(const InstDesc* __restri
         for (int64_t item = wave; item < d.nitems; item += nw) {
             if constexpr (NC == 5) {
                 if (d.riemann == 1)
-                    march2d<P, 1>(d, k, sc.cur, item, lane, acc);
+                    march2d_bc<P, 1>(d, k, sc.cur, item, lane, acc);
                 else
-                    march2d<P, 0>(d, k, sc.cur, item, lane, acc);
+                    march2d_bc<P, 0>(d, k, sc.cur, item, lane, acc);
             } else {
                 if (d.riemann == 1)
-                    march1d<P, 1>(d, k, sc.cur, item, lane, acc);
+                    march1d_bc<P, 1>(d, k, sc.cur, item, lane, acc);
                 else
-                    march1d<P, 0>(d, k, sc.cur, item, lane, acc);
+                    march1d_bc<P, 0>(d, k, sc.cur, item, lane, acc);
             }
         }
         uint32_t flags = acc_flags(acc);

@@ -58,13 +58,15 @@ def comps(ny):
 
 
 def run_both(ng, gas, W, nx, ny, steps, precision, riemann=0, stiff_z=0.5, launch=None,
-             t_end=None, small_limit=None):
+             t_end=None, small_limit=None, bc=(0, 0, 0, 0)):
     import oracle
     oracle.build()
-    P = oracle.Problem(gas, nx, ny, riemann=riemann, stiff_z=stiff_z)
+    P = oracle.Problem(gas, nx, ny, riemann=riemann, stiff_z=stiff_z, bc=bc)
     U0 = P.prim_to_cons(W)
-    say(f"case nx={nx} ny={ny} steps={steps} prec={precision} riemann={riemann} launch={launch}")
-    s = ng.Solver(gas, nx, ny, U=U0, precision=precision, riemann=riemann, stiff_z=stiff_z)
+    say(f"case nx={nx} ny={ny} steps={steps} prec={precision} riemann={riemann} launch={launch} "
+        f"bc={bc} small_limit={small_limit}")
+    s = ng.Solver(gas, nx, ny, U=U0, precision=precision, riemann=riemann, stiff_z=stiff_z,
+                  bc=bc)
     if small_limit is not None:
         s.set_small_limit(small_limit)
     if launch:
@@ -265,3 +267,109 @@ def test_fused_accept_equals_separate_finalize(ng):
             for q in range(5):
                 assert res[0][1]["total"][q] == pytest.approx(res[1][1]["total"][q], rel=1e-13,
                                                               abs=1e-13)
+
+
+# ------------------------------------------------ reflecting walls, outflow ends
+
+W_, O_ = 1, 2
+BC_CASES_1D = [(W_, W_, 0, 0), (O_, O_, 0, 0), (W_, O_, 0, 0)]
+BC_CASES_2D = [(W_, W_, O_, O_), (0, 0, W_, W_), (O_, W_, W_, O_)]
+
+
+def _moving_state(gas, nx, ny, seed):
+    """Non-uniform state with flow towards and away from every end."""
+    r = np.random.Generator(np.random.PCG64(seed))
+    W = wl.uniform_state(gas, nx, ny)
+    W[0] += 0.05 * r.standard_normal((ny, nx))
+    W[1] = 0.2 * np.sin(2 * np.pi * (np.arange(nx) + 0.5) / nx)[None, :] + \
+        0.05 * r.standard_normal((ny, nx))
+    if ny > 1:
+        W[2] = 0.2 * np.cos(2 * np.pi * (np.arange(ny) + 0.5) / ny)[:, None]
+    W[3] += 0.05 * r.standard_normal((ny, nx))
+    return W
+
+
+@pytest.mark.parametrize("bc", BC_CASES_1D)
+@pytest.mark.parametrize("small_limit", [None, 0])
+def test_fp64_1d_boundaries_bitwise(ng, bc, small_limit):
+    gas = dict(wl.BASE_GAS, Q_T=2.0)
+    n = 1500
+    W = _moving_state(gas, n, 1, 31)
+    for riemann in (0, 1):
+        U, ref, d, _ = run_both(ng, gas, W, n, 1, 300, ng.NG_FP64, riemann,
+                                small_limit=small_limit, bc=bc)
+        assert d["status"] == 0
+        assert np.array_equal(U[comps(1)], ref["U"][comps(1)]), rel_linf(U, ref["U"])
+        assert d["t"] == ref["t"]
+
+
+@pytest.mark.parametrize("bc", BC_CASES_2D)
+@pytest.mark.parametrize("shape", [(150, 130), (61, 64)])
+def test_fp64_2d_boundaries_bitwise(ng, bc, shape):
+    nx, ny = shape
+    gas = dict(wl.BASE_GAS, Q_T=2.0)
+    W = _moving_state(gas, nx, ny, 41 + nx)
+    for riemann in (0, 1):
+        U, ref, d, _ = run_both(ng, gas, W, nx, ny, 40, ng.NG_FP64, riemann, bc=bc,
+                                small_limit=0)
+        assert d["status"] == 0
+        assert np.array_equal(U, ref["U"]), rel_linf(U, ref["U"])
+
+
+def test_fp64_2d_boundaries_small_path_bitwise(ng):
+    gas = dict(wl.BASE_GAS, Q_T=2.0)
+    W = _moving_state(gas, 40, 36, 5)
+    U, ref, d, _ = run_both(ng, gas, W, 40, 36, 60, ng.NG_FP64, 0, bc=(W_, O_, O_, W_))
+    assert np.array_equal(U, ref["U"]), rel_linf(U, ref["U"])
+
+
+@pytest.mark.parametrize("small_limit", [None, 0])
+def test_fp64_woodward_colella_bitwise(ng, small_limit):
+    """Section 2.4's interacting blast waves between walls (Euler limit,
+    n = 1000) to t = 0.038, about 3900 steps through strong shocks."""
+    gas = dict(wl.BASE_GAS, Cv=0.0, tau_rho=0.0, tau_T=0.0, Q0=0.0, Q_rho=0.0, Q_T=0.0,
+               I0=0.0, I_rho=0.0, I_T=0.0, tau0=1.0)
+    W = wl.blast_waves_1d(1000)
+    U, ref, d, _ = run_both(ng, gas, W, 1000, 1, 10 ** 6, ng.NG_FP64, 0, t_end=0.038,
+                            small_limit=small_limit, bc=(W_, W_, 0, 0))
+    say(f"woodward-colella steps {d['steps']} t {d['t']}")
+    assert d["status"] == 0 and d["t"] == 0.038
+    assert np.array_equal(U[comps(1)], ref["U"][comps(1)]), rel_linf(U, ref["U"])
+
+
+def test_fp32_woodward_colella(ng):
+    """FP32 through the same strong shocks: positive, and the shock pattern of
+    the FP64 run (relative L1 difference reported; shocks move errors by a
+    cell, so the bar is looser than for smooth flows)."""
+    gas = dict(wl.BASE_GAS, Cv=0.0, tau_rho=0.0, tau_T=0.0, Q0=0.0, Q_rho=0.0, Q_T=0.0,
+               I0=0.0, I_rho=0.0, I_T=0.0, tau0=1.0)
+    W = wl.blast_waves_1d(1000)
+    U, ref, d, _ = run_both(ng, gas, W, 1000, 1, 10 ** 6, ng.NG_FP32, 0, t_end=0.038,
+                            bc=(W_, W_, 0, 0))
+    assert d["status"] == 0 and d["rho_min"] > 0 and d["p_min"] > 0
+    e = rel_l1(U[[0, 1, 3]], ref["U"][[0, 1, 3]])
+    say(f"fp32 woodward-colella rel_l1 {e}")
+    assert np.all(e <= 1e-3), e
+
+
+@pytest.mark.parametrize("bc", [(W_, W_, O_, O_), (O_, O_, W_, W_)])
+def test_fp32_2d_boundaries(ng, bc):
+    gas = dict(wl.BASE_GAS, Q_T=2.0)
+    W = wl.uniform_state(gas, 150, 130)
+    r = np.random.Generator(np.random.PCG64(3))
+    W[0] += 1e-3 * r.standard_normal((130, 150))
+    W[3] += 1.4e-3 * r.standard_normal((130, 150))
+    U, ref, d, U0 = run_both(ng, gas, W, 150, 130, 30, ng.NG_FP32, 0, bc=bc, small_limit=0)
+    e = rel_l1(U, ref["U"])
+    ed = rel_l1(U - U0, ref["U"] - U0)
+    say(f"fp32 2d bc={bc} rel_l1 {e}  perturbation rel_l1 {ed}")
+    assert np.all(e <= FP32_TOL), e
+
+
+def test_invalid_boundaries_rejected(ng):
+    gas = dict(wl.BASE_GAS)
+    W = wl.uniform_state(gas, 64, 1)
+    with pytest.raises(ng.NgError):
+        ng.Solver(gas, 64, 1, W=W, bc=(3, 3, 0, 0))
+    with pytest.raises(ng.NgError):
+        ng.Solver(gas, 64, 1, W=W, bc=(0, W_, 0, 0))
