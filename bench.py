@@ -13,9 +13,15 @@ Prints one JSON line:
               read 5 FP32 planes, write 5) over its mean launch time from HIP
               events on its stream, against the 8 TB/s HBM peak; traffic from
               the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary when it was
-              taken on the current kernel source, else null
+              taken on the current kernel source, else null; "alu": vector
+              lane-operations per second (committed SQ_INSTS_VALU count x 64
+              over the same launch time) against the non-packed FP32 issue
+              peak, the limit this kernel actually runs into
   fp64        the same workload through the FP64 path (comparison)
-  cpu_baseline  the serial FP64 oracle on one full step of the same grid
+  bounded_ends  the FP32 step on the same grid with wall and outflow ends
+  fp32_vs_fp64  relative L1 difference of the two paths after the same steps
+  cpu_baseline  the serial FP64 oracle on whole steps of the same grid (about
+              10 s of one host core)
 Input: seeded synthetic isotropic k^-2 density field (|k| <= 64, rms 1e-3),
 isentropic pressure, fluid at rest; gas of eqs. (1)-(7) with Q_T = 2.
 """
@@ -34,18 +40,22 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_CELL_FP32 = 40.0   # 5 conserved planes read + 5 written, 4 B each
 BYTES_PER_CELL_FP64 = 80.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step2d_fp32_4096_traffic.txt")
+VALU_FILE = os.path.join(ROOT, "profiles", "step2d_fp32_4096_valu.txt")
+# non-packed FP32 vector issue of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# (the published 157.3 TFLOP/s counts a packed FMA as 4 flops per lane-cycle)
+VALU_PEAK_TLANEOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def traffic_record():
-    """Measured HBM bytes per launch of the step kernel, if the committed
-    counter summary was taken on the current kernel source."""
+def counter_record(path):
+    """A committed rocprofv3 counter summary, if it was taken on the current
+    kernel source."""
     from paper_1805_03442_amd.profiling import kernel_hash
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
@@ -54,9 +64,14 @@ def traffic_record():
     return rec
 
 
-def timed_run(ng, torch, gas, W, n, steps, warmup, precision):
+def traffic_record():
+    """Measured HBM bytes per launch of the step kernel."""
+    return counter_record(TRAFFIC_FILE)
+
+
+def timed_run(ng, torch, gas, W, n, steps, warmup, precision, bc=(0, 0, 0, 0)):
     from paper_1805_03442_amd import autotune
-    s = ng.Solver(gas, n, n, W=W, precision=precision)
+    s = ng.Solver(gas, n, n, W=W, precision=precision, bc=bc)
     autotune.apply(s)
     s.step(warmup)
     torch.cuda.synchronize()
@@ -106,6 +121,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--accuracy-steps", type=int, default=100)
+    ap.add_argument("--bounded-steps", type=int, default=200)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain device copy of known size (for counter scaling)")
     args = ap.parse_args()
@@ -164,6 +180,15 @@ def main():
                      "kernel_ms": r32["step_ms"], "algorithmic_bytes_per_launch":
                          BYTES_PER_CELL_FP32 * cells},
     }
+    # the step is limited by vector ALU issue: lane-operations per second from
+    # the committed SQ_INSTS_VALU count of this kernel over the same launch time
+    vr = counter_record(VALU_FILE)
+    if vr is not None and "SQ_INSTS_VALU" in vr["mean_per_dispatch"]:
+        insts = vr["mean_per_dispatch"]["SQ_INSTS_VALU"]
+        ach = insts * 64 / (r32["step_ms"] * 1e-3) / 1e12
+        out["roofline"]["alu"] = {"achieved": ach, "peak": VALU_PEAK_TLANEOPS,
+                                  "unit": "T lane-op/s", "frac": ach / VALU_PEAK_TLANEOPS,
+                                  "valu_insts_per_launch": insts}
 
     if not args.no_fp64:
         log(f"[bench] FP64: timing {args.fp64_steps} steps")
@@ -176,6 +201,19 @@ def main():
                        / HBM_PEAK_GBS,
                        "steps": args.fp64_steps}
         log(f"[bench] FP64 {v64:.3e} cell-updates/s")
+
+    if args.bounded_steps > 0:
+        # the same grid between reflecting walls (x) and outflow ends (y):
+        # ghost cells from the boundary rules instead of wrap-around
+        k = args.bounded_steps
+        log(f"[bench] FP32 with wall/outflow ends: timing {k} steps")
+        rb = timed_run(ng, torch, gas, W, n, k, 5, ng.NG_FP32,
+                       bc=(ng.NG_BC_WALL, ng.NG_BC_WALL, ng.NG_BC_OUTFLOW, ng.NG_BC_OUTFLOW))
+        out["bounded_ends"] = {"bc": "x walls, y outflow", "steps": k,
+                               "value": cells * k / (rb["total_ms"] * 1e-3),
+                               "unit": "cell-updates/s", "step_kernel_ms": rb["step_ms"],
+                               "hbm_frac": BYTES_PER_CELL_FP32 * cells / (rb["step_ms"] * 1e-3)
+                               / 1e9 / HBM_PEAK_GBS}
 
     if not args.no_fp64:
         # error of the FP32 result against the FP64 path after the same steps
@@ -209,7 +247,7 @@ def main():
         log(f"[bench] copy calibration: 3 copies of {nbytes} bytes")
 
     if not args.no_cpu_baseline:
-        log("[bench] CPU baseline: one oracle step of the full grid")
+        log("[bench] CPU baseline: oracle steps of the full grid")
         out["cpu_baseline"] = cpu_baseline(gas, W, n)
         log(f"[bench] oracle {out['cpu_baseline']['value']:.3e} cell-updates/s")
 

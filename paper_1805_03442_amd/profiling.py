@@ -84,11 +84,16 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int, alg_by
                 kernel_hash=kernel_hash())
 
 
-def counters_markdown(path: str, kernel: str, command: str) -> str:
+def counters_by_name(path: str, kernel: str) -> dict:
     by = {}
     for x in _per_dispatch(path):
         if kernel in x["name"]:
             by.setdefault(x["counter"], []).append(x["value"])
+    return by
+
+
+def counters_markdown(path: str, kernel: str, command: str) -> str:
+    by = counters_by_name(path, kernel)
     out = [f"Command: `{command}`", "", f"Kernel: `{kernel}`", "",
            "| counter | dispatches | mean per dispatch |", "|---|---|---|"]
     for c in sorted(by):
@@ -118,11 +123,18 @@ def main(argv=None):
     c.add_argument("--kernel", default="step2d_kernel<ng::Dev32<5> >")
     c.add_argument("--command", required=True)
     c.add_argument("--out", required=True)
+    c.add_argument("--out-json", default=None)
     args = ap.parse_args(argv)
     if args.cmd == "counters":
         md = counters_markdown(args.csv, args.kernel, args.command)
         with open(args.out, "w") as f:
             f.write(md)
+        if args.out_json:
+            by = counters_by_name(args.csv, args.kernel)
+            rec = dict(kernel=args.kernel, command=args.command, kernel_hash=kernel_hash(),
+                       mean_per_dispatch={k: statistics.mean(v) for k, v in by.items()})
+            with open(args.out_json, "w") as f:
+                json.dump(rec, f, indent=1)
         print(md)
         return
     if args.cmd == "stats":
