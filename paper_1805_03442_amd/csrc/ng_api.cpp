@@ -343,7 +343,10 @@ bool has_room(const ng_batch* b, size_t bytes)
 }
 
 // Work decomposition of one solve for the current launch shape of its dim.
-void shape_solve(ng_batch* b, Slot& s)
+// A solve accepts its own steps inside the step kernel only when it is the one
+// big solve of its dim: with several, each of their workgroups would pay the
+// release fence, which costs more than one finalize launch for all of them.
+void shape_solve(ng_batch* b, Slot& s, bool alone = true)
 {
     InstDesc& d = s.d;
     int dim = s.dim;
@@ -356,7 +359,7 @@ void shape_solve(ng_batch* b, Slot& s)
         d.nchunks = (int32_t)cdiv(d.nstrips, d.rows_per_item);
     d.nitems = dim == 2 ? (int64_t)d.nstrips * d.nchunks : (int64_t)d.nchunks;
     d.nblocks = cdiv(d.nitems, d.waves_per_block);
-    d.fused = (b->fused && !s.small && d.nblocks <= kFusedMaxBlocks) ? 1 : 0;
+    d.fused = (b->fused && alone && !s.small && d.nblocks <= kFusedMaxBlocks) ? 1 : 0;
 }
 
 // Rebuild the device tables (descriptors, per-dim solve lists and workgroup
@@ -375,13 +378,17 @@ int rebuild(ng_batch* b)
     // exactly those), then those of small solves (used by the priming pass only)
     const int64_t lim = b->small_limit >= 0 ? b->small_limit
                                             : (b->prec == NG_FP32 ? kSmallCells32 : kSmallCells64);
+    int nbig[3] = {0, 0, 0};
     for (int i = 0; i < b->capacity; i++)
-        if (b->slots[i].live) b->slots[i].small = b->slots[i].d.ncell <= lim;
+        if (b->slots[i].live) {
+            b->slots[i].small = b->slots[i].d.ncell <= lim;
+            if (!b->slots[i].small) nbig[b->slots[i].dim]++;
+        }
     for (int pass = 0; pass < 2; pass++) {
         for (int i = 0; i < b->capacity; i++) {
             Slot& s = b->slots[i];
             if (!s.live || (int)s.small != pass) continue;
-            shape_solve(b, s);
+            shape_solve(b, s, nbig[s.dim] <= 1);
             if (s.d.nblocks > s.partial_cap) {
                 b->err = "launch shape needs more reduction records than reserved";
                 return NG_EINVAL;
