@@ -18,8 +18,9 @@ Prints one JSON line:
               over the same launch time) against the non-packed FP32 issue
               peak, the limit this kernel actually runs into
   fp64        the same workload through the FP64 path (comparison)
+  mixed       the same workload with FP32 arithmetic on an FP64 deviation state
   bounded_ends  the FP32 step on the same grid with wall and outflow ends
-  fp32_vs_fp64  relative L1 difference of the two paths after the same steps
+  fp32_vs_fp64, mixed_vs_fp64  relative L1 differences after the same steps
   cpu_baseline  the serial FP64 oracle on whole steps of the same grid (about
               10 s of one host core)
 Input: seeded synthetic isotropic k^-2 density field (|k| <= 64, rms 1e-3),
@@ -202,6 +203,16 @@ def main():
                        "steps": args.fp64_steps}
         log(f"[bench] FP64 {v64:.3e} cell-updates/s")
 
+    if not args.no_fp64:
+        # FP32 arithmetic on an FP64 deviation state: 80 B per cell of state traffic
+        k = args.fp64_steps
+        log(f"[bench] mixed (FP32 arithmetic, FP64 state): timing {k} steps")
+        rm = timed_run(ng, torch, gas, W, n, k, 5, ng.NG_MIXED)
+        out["mixed"] = {"value": cells * k / (rm["total_ms"] * 1e-3), "unit": "cell-updates/s",
+                        "ms_per_step": rm["total_ms"] / k, "step_kernel_ms": rm["step_ms"],
+                        "hbm_frac": BYTES_PER_CELL_FP64 * cells / (rm["step_ms"] * 1e-3) / 1e9
+                        / HBM_PEAK_GBS, "steps": k}
+
     if args.bounded_steps > 0:
         # the same grid between reflecting walls (x) and outflow ends (y):
         # ghost cells from the boundary rules instead of wrap-around
@@ -220,12 +231,12 @@ def main():
         m = args.accuracy_steps
         log(f"[bench] FP32 vs FP64 after {m} steps")
         outs = []
-        for prec in (ng.NG_FP32, ng.NG_FP64):
+        for prec in (ng.NG_FP32, ng.NG_FP64, ng.NG_MIXED):
             s = ng.Solver(gas, n, n, W=W, precision=prec)
             s.step(m)
             outs.append(s.conserved())
             s.close()
-        U32, U64 = outs
+        U32, U64, Umx = outs
         U0 = ng.Solver(gas, n, n, W=W, precision=ng.NG_FP64)
         Ub = U0.conserved()
         U0.close()
@@ -235,6 +246,11 @@ def main():
         pert = {nm: float(np.abs(U32[c] - U64[c]).sum() / np.abs(U64[c] - Ub[c]).sum())
                 for c, nm in enumerate(names)}
         out["fp32_vs_fp64"] = {"steps": m, "rel_l1": full, "rel_l1_of_perturbation": pert}
+        out["mixed_vs_fp64"] = {
+            "steps": m,
+            "rel_l1_of_perturbation": {
+                nm: float(np.abs(Umx[c] - U64[c]).sum() / np.abs(U64[c] - Ub[c]).sum())
+                for c, nm in enumerate(names)}}
         log(f"[bench] FP32 vs FP64 rel L1 {full}")
 
     if args.calibrate_copy:

@@ -62,6 +62,8 @@ extern "C" {
 #define NG_FP64 0        /* state, flux and sources in FP64                     */
 #define NG_FP32 1        /* FP32 deviations from a uniform reference state,
                             FP64 totals and FP64 stiff relaxation factor      */
+#define NG_MIXED 2       /* as NG_FP32, but the deviations are stored in FP64
+                            and each step's FP32 increment is added in FP64   */
 
 /* status flags of ng_diag.flags */
 #define NG_FLAG_NONFINITE 1u
@@ -84,7 +86,7 @@ typedef struct {
 /* Uniform grid of square cells of size h (section 2.3): ndim = 1 (ny = 1) or
  * 2; bc[4] = (x-low, x-high, y-low, y-high) boundary kinds NG_BC_* (y ends
  * ignored in 1D).  Planes are addressed with 32-bit byte offsets: at most
- * 2^30 cells in FP32 and 2^29 in FP64. */
+ * 2^30 cells in FP32 and 2^29 in FP64 and NG_MIXED. */
 typedef struct {
     int32_t ndim;
     int32_t reserved;
@@ -100,7 +102,7 @@ typedef struct {
     double cfl;
     int32_t riemann;   /* NG_HLLC or NG_HLL */
     int32_t limiter;   /* NG_MINMOD         */
-    int32_t precision; /* NG_FP64 or NG_FP32 */
+    int32_t precision; /* NG_FP64, NG_FP32 or NG_MIXED */
     int32_t reserved;
     double stiff_z;
 } ng_numerics;
@@ -215,7 +217,7 @@ void ng_destroy(ng_solver* s);
  * batch sub-allocates it.
  */
 
-/* capacity: maximum number of live solves; precision: NG_FP32 or NG_FP64;
+/* capacity: maximum number of live solves; precision: NG_FP32, NG_FP64 or NG_MIXED;
  * dev_buf/dev_bytes: the arena (256-byte aligned). */
 int ng_batch_create(int32_t capacity, int32_t precision, void* dev_buf, size_t dev_bytes,
                     void* hip_stream, ng_batch** out);

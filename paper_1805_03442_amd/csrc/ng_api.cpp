@@ -53,6 +53,10 @@ int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 int ncomp(int ndim) { return ndim == 2 ? 5 : 4; }
 size_t real_size(int prec) { return prec == NG_FP32 ? 4 : 8; }
+bool prec_ok(int prec) { return prec == NG_FP32 || prec == NG_FP64 || prec == NG_MIXED; }
+// kernel family of a precision: FP64 throughout, FP32 deviations, FP32
+// arithmetic on FP64 deviations
+int kind_of(int prec) { return prec == NG_FP64 ? 0 : (prec == NG_FP32 ? 1 : 2); }
 
 int64_t strips_of(const ng_grid* g) { return cdiv(g->nx, kInterior); }
 
@@ -142,9 +146,9 @@ int validate(const ng_gas* gas, const ng_grid* grid, const ng_numerics* num, std
             err = "a periodic axis needs both ends periodic";
             return NG_EINVAL;
         }
-    if (num->precision == NG_FP32 || num->precision == NG_FP64) {
+    if (prec_ok(num->precision)) {
         const uint64_t cells = (uint64_t)grid->nx * (uint64_t)(grid->ndim == 2 ? grid->ny : 1);
-        if (cells * (num->precision == NG_FP32 ? 4u : 8u) > (1ULL << 32)) {
+        if (cells * real_size(num->precision) > (1ULL << 32)) {
             err = "grid too large for 32-bit plane offsets";
             return NG_EINVAL;
         }
@@ -153,7 +157,7 @@ int validate(const ng_gas* gas, const ng_grid* grid, const ng_numerics* num, std
     if (!(num->cfl > 0.0 && num->cfl < 1.0)) { err = "cfl must lie in (0, 1)"; return NG_EINVAL; }
     if (num->riemann != NG_HLLC && num->riemann != NG_HLL) { err = "unknown riemann solver"; return NG_EINVAL; }
     if (num->limiter != NG_MINMOD) { err = "unknown limiter"; return NG_EINVAL; }
-    if (num->precision != NG_FP32 && num->precision != NG_FP64) { err = "unknown precision"; return NG_EINVAL; }
+    if (!prec_ok(num->precision)) { err = "unknown precision"; return NG_EINVAL; }
     if (!(num->stiff_z >= 0.0)) { err = "stiff_z must be >= 0"; return NG_EINVAL; }
     return NG_OK;
 }
@@ -377,7 +381,7 @@ int rebuild(ng_batch* b)
     // per dim: the workgroups of big solves first (the per-step launch covers
     // exactly those), then those of small solves (used by the priming pass only)
     const int64_t lim = b->small_limit >= 0 ? b->small_limit
-                                            : (b->prec == NG_FP32 ? kSmallCells32 : kSmallCells64);
+                                            : (b->prec != NG_FP64 ? kSmallCells32 : kSmallCells64);
     int nbig[3] = {0, 0, 0};
     for (int i = 0; i < b->capacity; i++)
         if (b->slots[i].live) {
@@ -446,7 +450,7 @@ int enqueue_one(ng_batch* b, hipStream_t st)
 {
     for (int dim = 1; dim <= 2; dim++) {
         if (!b->ninst[dim]) continue;
-        CK(b, launch_step(dim, b->prec == NG_FP32 ? 1 : 0, b->d_descs(), b->d_ctrls(),
+        CK(b, launch_step(dim, kind_of(b->prec), b->d_descs(), b->d_ctrls(),
                           b->d_blocks(dim), b->nblocks[dim], b->waves[dim], b->remap, b->fused,
                           st));
         if (b->nsep[dim])
@@ -461,7 +465,7 @@ int enqueue_small(ng_batch* b, int64_t nsteps, hipStream_t st)
 {
     for (int dim = 1; dim <= 2; dim++) {
         if (!b->nsmall[dim]) continue;
-        CK(b, launch_small(dim, b->prec == NG_FP32 ? 1 : 0, b->d_descs(), b->d_ctrls(),
+        CK(b, launch_small(dim, kind_of(b->prec), b->d_descs(), b->d_ctrls(),
                            b->d_small(dim), b->nsmall[dim], kSmallWaves, nsteps, st));
     }
     return NG_OK;
@@ -496,7 +500,7 @@ int enqueue_timed(ng_batch* b, int64_t nsteps)
             hipEvent_t e0 = get_event(b, ne), e1 = get_event(b, ne + 1), e2 = get_event(b, ne + 2);
             if (!e0 || !e1 || !e2) return dev_err(b, hipErrorOutOfMemory, "hipEventCreate");
             CK(b, hipEventRecord(e0, b->stream));
-            CK(b, launch_step(dim, b->prec == NG_FP32 ? 1 : 0, b->d_descs(), b->d_ctrls(),
+            CK(b, launch_step(dim, kind_of(b->prec), b->d_descs(), b->d_ctrls(),
                               b->d_blocks(dim), b->nblocks[dim], b->waves[dim], b->remap,
                               b->fused, b->stream));
             CK(b, hipEventRecord(e1, b->stream));
@@ -609,7 +613,7 @@ int set_limits(ng_batch* b, const std::vector<int32_t>& slots, double t_end, int
 int batch_new(int32_t capacity, int32_t precision, void* dev_buf, size_t dev_bytes,
               void* hip_stream, size_t tcap1, size_t tcap2, ng_batch** out, std::string& err)
 {
-    if (capacity < 1 || !dev_buf || !out || (precision != NG_FP32 && precision != NG_FP64)) {
+    if (capacity < 1 || !dev_buf || !out || !prec_ok(precision)) {
         err = "invalid batch arguments";
         return NG_EINVAL;
     }
@@ -702,7 +706,7 @@ void fill_desc(InstDesc& d, const ng_gas* gas, const ng_grid* grid, const ng_num
     d.I_T = gas->I_T;
     d.fx = gas->fx;
     d.fy = gas->fy;
-    if (prec == NG_FP32) {
+    if (prec != NG_FP64) {
         // uniform reference at rest: rho0, p = R rho0 T0 and the vibrational
         // energy at which relaxation balances the pump in eq. (4)
         double rho_r = gas->rho0;
@@ -723,7 +727,7 @@ void fill_desc(InstDesc& d, const ng_gas* gas, const ng_grid* grid, const ng_num
 int64_t small_limit_of(const ng_batch* b)
 {
     return b->small_limit >= 0 ? b->small_limit
-                               : (b->prec == NG_FP32 ? kSmallCells32 : kSmallCells64);
+                               : (b->prec != NG_FP64 ? kSmallCells32 : kSmallCells64);
 }
 
 // Pinned staging of at least `bytes` (at most kStageBytes), both buffers idle.
@@ -903,7 +907,7 @@ int add_solve(ng_batch* b, const ng_gas* gas, const ng_grid* grid, const ng_nume
     if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->ev_ready, 0);
     if (e != hipSuccess) return fail(dev_err(b, e, "upload"));
     // priming pass over this solve only: its own workgroups, listed by index
-    e = launch_prime(s.dim, b->prec == NG_FP32 ? 1 : 0, b->d_descs(), b->d_ctrls(), nullptr, slot,
+    e = launch_prime(s.dim, kind_of(b->prec), b->d_descs(), b->d_ctrls(), nullptr, slot,
                      s.d.nblocks, s.d.waves_per_block, b->stream);
     if (e == hipSuccess)
         e = launch_finalize(b->d_descs(), b->d_ctrls(), b->d_iota() + slot, 1, 1, b->stream);
@@ -930,9 +934,17 @@ int read_conserved(ng_batch* b, int slot, double* out, bool prim)
     const int64_t n = s.d.ncell;
     const int cur = b->h_ctrls[slot].cur;
     std::vector<double> U((size_t)nc * n);
-    if (b->prec == NG_FP64) {
+    if (b->prec != NG_FP32) {
+        // FP64 state (deviations from the reference for the mixed path)
         CK(b, hipMemcpy(U.data(), (void*)s.d.buf[cur], sizeof(double) * U.size(),
                         hipMemcpyDeviceToHost));
+        if (b->prec == NG_MIXED) {
+            const double ref5[5] = {s.d.uref[0], 0.0, 0.0, s.d.uref[3], s.d.uref[4]};
+            const double ref4[4] = {s.d.uref[0], 0.0, s.d.uref[3], s.d.uref[4]};
+            const double* ref = nc == 5 ? ref5 : ref4;
+            for (int c = 0; c < nc; c++)
+                for (int64_t i = 0; i < n; i++) U[c * n + i] += ref[c];
+        }
     } else {
         std::vector<float> D((size_t)nc * n);
         CK(b, hipMemcpy(D.data(), (void*)s.d.buf[cur], sizeof(float) * D.size(),
@@ -1011,7 +1023,7 @@ int ng_state_bytes(const ng_grid* grid, const ng_numerics* num, size_t* bytes)
     if (grid->ndim != 1 && grid->ndim != 2) return NG_EINVAL;
     if (grid->nx < 4 || (grid->ndim == 2 && grid->ny < 4) || (grid->ndim == 1 && grid->ny != 1))
         return NG_EINVAL;
-    if (num->precision != NG_FP32 && num->precision != NG_FP64) return NG_EINVAL;
+    if (!prec_ok(num->precision)) return NG_EINVAL;
     size_t tc = (size_t)partial_cap_of(grid);
     Layout L = header_layout(1, grid->ndim == 1 ? tc : 0, grid->ndim == 2 ? tc : 0);
     *bytes = L.heap + solve_bytes(grid, num->precision);
@@ -1216,7 +1228,7 @@ int ng_batch_create(int32_t capacity, int32_t precision, void* dev_buf, size_t d
 int ng_batch_solve_bytes(const ng_grid* grid, int32_t precision, size_t* bytes)
 {
     if (!grid || !bytes || (grid->ndim != 1 && grid->ndim != 2)) return NG_EINVAL;
-    if (precision != NG_FP32 && precision != NG_FP64) return NG_EINVAL;
+    if (!prec_ok(precision)) return NG_EINVAL;
     *bytes = solve_bytes(grid, precision);
     return NG_OK;
 }

@@ -578,4 +578,43 @@ __device__ __forceinline__ void update32(const K32& k, const float* Un, const fl
     srcV = dv;
 }
 
+// The change of one step, -dt/h (dF + dG) + dt Y(W^{n+1/2}) (eq. (15)), for a
+// state kept in another precision: the same sources and stiff branch as
+// update32; ev_n is the start-of-step E_nu deviation the stiff branch relaxes.
+template <int NC>
+__device__ __forceinline__ void increment32(const K32& k, float ev_n, const float* dF,
+                                            const float* dG, const float* Wh, float* dU,
+                                            float& srcE, float& srcV)
+{
+    constexpr int iP = NC == 5 ? 3 : 2, iV = NC == 5 ? 4 : 3;
+    const float dt = k.dt, dtdx = k.dtdx;
+    float dr = Wh[0], u = Wh[1], dp = Wh[iP], de = Wh[iV];
+    float v = NC == 5 ? Wh[2] : 0.0f;
+    float rho = k.rho_r + dr, p = k.p_r + dp;
+    float irho = rcp32(rho);
+    float itau, Q, I;
+    closures32(k, rho, p, irho, itau, Q, I);
+    float yE = rho * (Q - I);
+    float relax_num = fmaf(k.CvR, dp, k.D_r - de);
+    float yV = fmaf(relax_num, itau, rho * Q);
+    for (int c = 0; c < NC; c++) dU[c] = -dtdx * (NC == 5 ? dF[c] + dG[c] : dF[c]);
+    if (k.force) {
+        dU[1] = fmaf(dt, rho * k.fx, dU[1]);
+        if (NC == 5) dU[2] = fmaf(dt, rho * k.fy, dU[2]);
+        yE = fmaf(rho, fmaf(u, k.fx, v * k.fy), yE);
+    }
+    dU[iP] = fmaf(dt, yE, dU[iP]);
+    float dv = dt * yV;
+    if (k.dt * itau > k.stiff_z) {
+        float num = fmaf(k.CvR, dp, k.D_r - ev_n);
+        float dEr = relax_exact(num, k.dt64 * (double)itau);
+        dv = fmaf(dt, rho * Q, dEr);
+        dU[iV] = dv + dU[iV];
+    } else {
+        dU[iV] = fmaf(dt, yV, dU[iV]);
+    }
+    srcE = dt * yE;
+    srcV = dv;
+}
+
 }  // namespace ng

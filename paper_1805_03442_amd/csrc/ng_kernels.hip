@@ -116,6 +116,7 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t G)
 template <int NC>
 struct Plain64 {
     using R = double;
+    using St = double;
     using K = K64;
     static __device__ K make(const InstDesc& d, double dt)
     {
@@ -168,6 +169,7 @@ struct Plain64 {
 template <int NC>
 struct Dev32 {
     using R = float;
+    using St = float;   // stored state: FP32 deviations
     using K = K32;
     static __device__ K make(const InstDesc& d, double dt)
     {
@@ -228,6 +230,43 @@ struct Dev32 {
     static __device__ R full_p(const K& k, R p) { return k.p_r + p; }
 };
 
+// FP32 arithmetic on an FP64 state: the deviations from the reference are
+// stored in FP64 and rounded to FP32 where the stencil reads them; the step's
+// FP32 increment is added in FP64, so rounding no longer accumulates in the
+// stored state (the FP32 store loses ~1e-8 of a perturbation per step).
+template <int NC>
+struct Mix32 {
+    using R = float;
+    using St = double;
+    using K = K32;
+    static __device__ K make(const InstDesc& d, double dt) { return Dev32<NC>::make(d, dt); }
+    static __device__ void prim(const K& k, const St* U, R* W)
+    {
+        R D[NC];
+        for (int c = 0; c < NC; c++) D[c] = (R)U[c];
+        prim32<NC>(k, D, W);
+    }
+    static __device__ R speed(const K& k, const R* W) { return speed32<NC>(k, W); }
+    static __device__ void predict(const K& k, const R* W, const R* sx, const R* sy, R* Wh)
+    {
+        predict32<NC>(k, W, sx, sy, Wh);
+    }
+    template <int RS>
+    static __device__ void flux(const K& k, const R* L, const R* Rr, R* F)
+    {
+        flux32<NC, RS>(k, L, Rr, F);
+    }
+    static __device__ void update(const K& k, const St* Un, const R* dF, const R* dG, const R* Wh,
+                                  St* Unew, R& sE, R& sV)
+    {
+        R dU[NC];
+        increment32<NC>(k, (R)Un[NC == 5 ? 4 : 3], dF, dG, Wh, dU, sE, sV);
+        for (int c = 0; c < NC; c++) Unew[c] = Un[c] + (St)dU[c];
+    }
+    static __device__ R full_rho(const K& k, R r) { return k.rho_r + r; }
+    static __device__ R full_p(const K& k, R p) { return k.p_r + p; }
+};
+
 // ------------------------------------------------------ reduction records
 
 // Per-lane accumulators of one work item: FP64 sums of the updated conserved
@@ -253,7 +292,7 @@ __device__ __forceinline__ void acc_init(Acc<R>& a)
 // and signal speed, and its source increments.
 template <class P, int NC>
 __device__ __forceinline__ void acc_cell(Acc<typename P::R>& a, const typename P::K& k,
-                                         const typename P::R* U, const typename P::R* W,
+                                         const typename P::St* U, const typename P::R* W,
                                          typename P::R s, typename P::R sE, typename P::R sV)
 {
     // component slots (rho, m_x, m_y, E, E_nu)
@@ -565,8 +604,9 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
     const bool inner = lane >= kHalo && lane < kWave - kHalo && x0 + (lane - kHalo) < nx;
     const int64_t r0 = chunk * d.rows_per_item;
     const int64_t r1 = r0 + d.rows_per_item < ny ? r0 + d.rows_per_item : ny;
-    const Planes<R, NC> src(d.buf[cur], d.ncell);
-    const Planes<R, NC> dst(d.buf[cur ^ 1], d.ncell);
+    using St = typename P::St;
+    const Planes<St, NC> src(d.buf[cur], d.ncell);
+    const Planes<St, NC> dst(d.buf[cur ^ 1], d.ncell);
     // byte offset of (row r, this lane's column); r within two rows of [0, ny)
     auto boff = [&](int64_t r) -> uint32_t {
         int64_t rr;
@@ -576,11 +616,11 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
         } else {
             rr = r < 0 ? r + ny : (r >= ny ? r - ny : r);
         }
-        return (uint32_t)((rr * nx + x) * (int64_t)sizeof(R));
+        return (uint32_t)((rr * nx + x) * (int64_t)sizeof(St));
     };
     // a loaded row r as ghost values: wall ghosts carry the mirrored normal
     // momentum (x ends: rho u, y ends: rho v)
-    auto ghost = [&](int64_t r, R* U) {
+    auto ghost = [&](int64_t r, St* U) {
         if (BC) {
             bool fy;
             (void)axis_cell(r, ny, d.bc[2], d.bc[3], fy);
@@ -606,11 +646,13 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
     //   Gp/Gn  y-fluxes at faces i-1/2 / i+1/2
     //   Uc/Ux  raw row i+2 (arrived) / row i+3 (in flight)
     R WA[NC], WB[NC], DA[NC], DB[NC], HA[NC], HB[NC], XA[NC], XB[NC];
-    R NA[NC], NB[NC], GA[NC], GB[NC], UA[NC], UB[NC];
+    R NA[NC], NB[NC], GA[NC], GB[NC];
+    St UA[NC], UB[NC];
 
     // prologue: rows r0-2 .. r0+1
     {
-        R Wa[NC], Wb[NC], Wc[NC], t[NC], sy[NC], sx[NC], hb[NC], S[NC];
+        R Wa[NC], Wb[NC], Wc[NC], sy[NC], sx[NC], hb[NC], S[NC];
+        St t[NC];
         src.load(boff(r0 - 2), t);
         ghost(r0 - 2, t);
         P::prim(k, t, Wa);
@@ -645,7 +687,7 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
     }
 
     auto row = [&](int64_t i, R* Wd, R* We, R* Dp, R* Dn, R* h0, R* h1, R* x0s, R* x1s,
-                   R* Np, R* Nn, R* Gp, R* Gn, R* Uc, R* Ux) {
+                   R* Np, R* Nn, R* Gp, R* Gn, St* Uc, St* Ux) {
         // row i+2 has arrived in Uc; put row i+3 in flight
         ghost(i + 2, Uc);
         P::prim(k, Uc, We);
@@ -685,7 +727,8 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
             }
         }
         // update of row i (U^n of row i re-read; it was loaded two rows ago)
-        R Un[NC], Uo[NC], Wn[NC], sE, sV;
+        St Un[NC], Uo[NC];
+        R Wn[NC], sE, sV;
         const uint32_t o = boff(i);
         src.load(o, Un);
         P::update(k, Un, dF, dG, h0, Uo, sE, sV);
@@ -757,19 +800,20 @@ __device__ __forceinline__ void march1d(const InstDesc& d, const typename P::K& 
     using R = typename P::R;
     constexpr int NC = 4;
     const int64_t n = d.nx;
-    const Planes<R, NC> src(d.buf[cur], n);
-    const Planes<R, NC> dst(d.buf[cur ^ 1], n);
+    using St = typename P::St;
+    const Planes<St, NC> src(d.buf[cur], n);
+    const Planes<St, NC> dst(d.buf[cur ^ 1], n);
     const int64_t s0 = item * d.rows_per_item;
     const int64_t s1 = s0 + d.rows_per_item < d.nstrips ? s0 + d.rows_per_item : d.nstrips;
     auto boff = [&](int64_t sg) -> uint32_t {
         bool f;
         const int64_t x = BC ? axis_cell(sg * kInterior - kHalo + lane, n, d.bc[0], d.bc[1], f)
                              : wrap_axis(sg * kInterior - kHalo + lane, n);
-        return (uint32_t)(x * (int64_t)sizeof(R));
+        return (uint32_t)(x * (int64_t)sizeof(St));
     };
-    R UA[NC], UB[NC];
+    St UA[NC], UB[NC];
     src.load(boff(s0), UA);
-    auto seg = [&](int64_t sg, R* Uc, R* Ux) {
+    auto seg = [&](int64_t sg, St* Uc, St* Ux) {
         R W[NC], sx[NC], h[NC];
         const uint32_t o = boff(sg);
         if (sg + 1 < s1) src.load(boff(sg + 1), Ux);
@@ -798,7 +842,8 @@ __device__ __forceinline__ void march1d(const InstDesc& d, const typename P::K& 
             dF[c] = Fx[c] - from_left(Fx[c]);
             pin(dF[c]);
         }
-        R Uo[NC], Wn[NC], sE, sV;
+        St Uo[NC];
+        R Wn[NC], sE, sV;
         P::update(k, Uc, dF, dF, h, Uo, sE, sV);
         P::prim(k, Uo, Wn);
         R s = P::speed(k, Wn);
@@ -879,7 +924,8 @@ __global__ void __launch_bounds__(256) prime_kernel(const InstDesc* __restrict__
     acc_init(acc);
     const int64_t item = (int64_t)br.local * nwaves + wave;
     if (item < d.nitems) {
-        const R* __restrict__ src = (const R*)d.buf[cc.cur];
+        using St = typename P::St;
+        const St* __restrict__ src = (const St*)d.buf[cc.cur];
         const int64_t nx = d.nx, ncell = d.ncell;
         int64_t xs, rows0, rows1, seg0, seg1;
         if (NC == 5) {
@@ -902,8 +948,9 @@ __global__ void __launch_bounds__(256) prime_kernel(const InstDesc* __restrict__
             const bool inner = lane >= kHalo && lane < kWave - kHalo && xo < nx;
             if (!inner) continue;
             for (int64_t r = rows0; r < rows1; r++) {
-                R U[NC], W[NC];
-                load_cell_cached<R, NC>(src, ncell, r * nx + xo, U);
+                St U[NC];
+                R W[NC];
+                load_cell_cached<St, NC>(src, ncell, r * nx + xo, U);
                 P::prim(k, U, W);
                 R s = P::speed(k, W);
                 acc_cell<P, NC>(acc, k, U, W, s, (R)0, (R)0);
@@ -1014,13 +1061,17 @@ hipError_t launch_step(int dim, int prec, const InstDesc* descs, InstCtrl* ctrls
     if (dim == 2) {
         if (prec == 0)
             hipLaunchKernelGGL(step2d_kernel<Plain64<5>>, g, b, 0, s, descs, ctrls, blocks, remap, fused);
-        else
+        else if (prec == 1)
             hipLaunchKernelGGL(step2d_kernel<Dev32<5>>, g, b, 0, s, descs, ctrls, blocks, remap, fused);
+        else
+            hipLaunchKernelGGL(step2d_kernel<Mix32<5>>, g, b, 0, s, descs, ctrls, blocks, remap, fused);
     } else {
         if (prec == 0)
             hipLaunchKernelGGL(step1d_kernel<Plain64<4>>, g, b, 0, s, descs, ctrls, blocks, remap, fused);
-        else
+        else if (prec == 1)
             hipLaunchKernelGGL(step1d_kernel<Dev32<4>>, g, b, 0, s, descs, ctrls, blocks, remap, fused);
+        else
+            hipLaunchKernelGGL(step1d_kernel<Mix32<4>>, g, b, 0, s, descs, ctrls, blocks, remap, fused);
     }
     return hipGetLastError();
 }
@@ -1034,13 +1085,17 @@ hipError_t launch_prime(int dim, int prec, const InstDesc* descs, InstCtrl* ctrl
     if (dim == 2) {
         if (prec == 0)
             hipLaunchKernelGGL((prime_kernel<Plain64<5>, 5>), g, b, 0, s, descs, ctrls, blocks, inst);
-        else
+        else if (prec == 1)
             hipLaunchKernelGGL((prime_kernel<Dev32<5>, 5>), g, b, 0, s, descs, ctrls, blocks, inst);
+        else
+            hipLaunchKernelGGL((prime_kernel<Mix32<5>, 5>), g, b, 0, s, descs, ctrls, blocks, inst);
     } else {
         if (prec == 0)
             hipLaunchKernelGGL((prime_kernel<Plain64<4>, 4>), g, b, 0, s, descs, ctrls, blocks, inst);
-        else
+        else if (prec == 1)
             hipLaunchKernelGGL((prime_kernel<Dev32<4>, 4>), g, b, 0, s, descs, ctrls, blocks, inst);
+        else
+            hipLaunchKernelGGL((prime_kernel<Mix32<4>, 4>), g, b, 0, s, descs, ctrls, blocks, inst);
     }
     return hipGetLastError();
 }
@@ -1063,13 +1118,17 @@ hipError_t launch_small(int dim, int prec, const InstDesc* descs, InstCtrl* ctrl
     if (dim == 2) {
         if (prec == 0)
             hipLaunchKernelGGL((run_small_kernel<Plain64<5>, 5>), g, b, 0, s, descs, ctrls, insts, nsteps);
-        else
+        else if (prec == 1)
             hipLaunchKernelGGL((run_small_kernel<Dev32<5>, 5>), g, b, 0, s, descs, ctrls, insts, nsteps);
+        else
+            hipLaunchKernelGGL((run_small_kernel<Mix32<5>, 5>), g, b, 0, s, descs, ctrls, insts, nsteps);
     } else {
         if (prec == 0)
             hipLaunchKernelGGL((run_small_kernel<Plain64<4>, 4>), g, b, 0, s, descs, ctrls, insts, nsteps);
-        else
+        else if (prec == 1)
             hipLaunchKernelGGL((run_small_kernel<Dev32<4>, 4>), g, b, 0, s, descs, ctrls, insts, nsteps);
+        else
+            hipLaunchKernelGGL((run_small_kernel<Mix32<4>, 4>), g, b, 0, s, descs, ctrls, insts, nsteps);
     }
     return hipGetLastError();
 }

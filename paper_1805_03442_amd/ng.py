@@ -21,7 +21,7 @@ NG_OK, NG_EINVAL, NG_ENOMEM, NG_EPHYS, NG_EDEVICE, NG_EFULL = 0, -1, -2, -3, -4,
 NG_BC_PERIODIC, NG_BC_WALL, NG_BC_OUTFLOW = 0, 1, 2
 NG_HLLC, NG_HLL = 0, 1
 NG_MINMOD = 0
-NG_FP64, NG_FP32 = 0, 1
+NG_FP64, NG_FP32, NG_MIXED = 0, 1, 2
 NG_FLAG_NONFINITE, NG_FLAG_RHO, NG_FLAG_P, NG_FLAG_DONE = 1, 2, 4, 8
 
 GAS_FIELDS = ("gamma", "R", "Cv", "rho0", "T0", "tau0", "tau_rho", "tau_T",

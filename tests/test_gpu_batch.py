@@ -60,9 +60,9 @@ def arena_bytes(ng, insts, precision):
     return int(tot * 1.1) + (64 << 20)
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("precision", ["fp32", "fp64", "mixed"])
 def test_batch_equals_alone_bitwise(ng, precision):
-    prec = ng.NG_FP32 if precision == "fp32" else ng.NG_FP64
+    prec = {"fp32": ng.NG_FP32, "fp64": ng.NG_FP64, "mixed": ng.NG_MIXED}[precision]
     insts = instances()
     say(f"batch of {len(insts)} solves, {precision}")
     b = ng.Batch(len(insts), arena_bytes(ng, insts, prec), precision=prec)
