@@ -357,7 +357,7 @@ def test_fp32_woodward_colella(ng):
     assert d["status"] == 0 and d["rho_min"] > 0 and d["p_min"] > 0
     e = rel_l1(U[[0, 1, 3]], ref["U"][[0, 1, 3]])
     say(f"fp32 woodward-colella rel_l1 {e}")
-    assert np.all(e <= 1e-3), e
+    assert np.all(e <= 1e-4), e
 
 
 @pytest.mark.parametrize("bc", [(W_, W_, O_, O_), (O_, O_, W_, W_)])
@@ -381,3 +381,81 @@ def test_invalid_boundaries_rejected(ng):
         ng.Solver(gas, 64, 1, W=W, bc=(3, 3, 0, 0))
     with pytest.raises(ng.NgError):
         ng.Solver(gas, 64, 1, W=W, bc=(0, W_, 0, 0))
+
+
+# --------------------------------------------------- rejected steps (NG_EPHYS)
+
+def _sink_case(ny):
+    """A strong energy sink independent of temperature (I0 = 20, I_T = 0)
+    drives the pressure negative after some tens of steps."""
+    gas = dict(wl.BASE_GAS, I0=20.0, I_T=0.0)
+    if ny == 1:
+        return gas, wl.acoustic_mode_1d(gas, 300, 3, 1e-2), 300
+    W = wl.random_field_2d(gas, 40, np.random.Generator(np.random.PCG64(3)), kmax=4, rms=1e-2)
+    return gas, W, 40
+
+
+@pytest.mark.parametrize("ny", [1, 40])
+@pytest.mark.parametrize("small_limit", [None, 0])
+def test_fp64_rejected_step_keeps_last_good_state(ng, ny, small_limit):
+    """The step that produces p <= 0 is rejected at the oracle's step; the
+    solve keeps the oracle's last good state bit for bit and does not move on."""
+    import oracle
+    oracle.build()
+    gas, W, n = _sink_case(ny)
+    P = oracle.Problem(gas, n, ny if ny > 1 else 1)
+    U0 = P.prim_to_cons(W)
+    ref = P.run(U0, 2000)
+    assert ref["status"] != 0
+    say(f"sink case ny={ny} small_limit={small_limit}: oracle stops after {ref['steps']} steps")
+    s = ng.Solver(gas, n, ny if ny > 1 else 1, U=U0, precision=ng.NG_FP64)
+    if small_limit is not None:
+        s.set_small_limit(small_limit)
+    with pytest.raises(ng.NgError) as err:
+        s.run_to_time(10.0, 2000)
+    assert err.value.code == ng.NG_EPHYS
+    d = s.diagnostics()
+    assert d["status"] != 0 and d["steps"] == ref["steps"]
+    assert d["t"] == ref["t"]
+    cs = comps(ny if ny > 1 else 1)
+    assert np.array_equal(s.conserved()[cs], ref["U"][cs])
+    s.step(5)
+    assert s.diagnostics()["steps"] == ref["steps"]
+    s.close()
+
+
+def test_fp32_rejected_step_keeps_a_physical_state(ng):
+    gas, W, n = _sink_case(1)
+    s = ng.Solver(gas, n, 1, W=W, precision=ng.NG_FP32)
+    with pytest.raises(ng.NgError) as err:
+        s.run_to_time(10.0, 2000)
+    assert err.value.code == ng.NG_EPHYS
+    d = s.diagnostics()
+    assert d["rho_min"] > 0 and d["p_min"] > 0
+    assert np.all(np.isfinite(s.conserved()))
+    s.close()
+
+
+def test_batch_rejected_member_does_not_disturb_others(ng):
+    gas, W, n = _sink_case(1)
+    good = dict(wl.BASE_GAS, Q_T=2.0)
+    Wg = wl.acoustic_mode_1d(good, 500, 2, 1e-3)
+    for prec in (ng.NG_FP32, ng.NG_FP64):
+        b = ng.Batch(2, 64 << 20, precision=prec)
+        sb = b.add(gas, n, 1, W, t_end=10.0, max_steps=2000)
+        sg = b.add(good, 500, 1, Wg, t_end=0.2)
+        done = set()
+        for _ in range(2000):
+            b.run(16)
+            done.update(b.poll())
+            if len(done) == 2:
+                break
+        assert done == {sb, sg}
+        assert b.diagnostics(sb)["status"] != 0
+        dg = b.diagnostics(sg)
+        assert dg["status"] == 0 and dg["t"] == 0.2
+        s = ng.Solver(good, 500, 1, W=Wg, precision=prec)
+        s.run_to_time(0.2)
+        assert np.array_equal(b.conserved(sg), s.conserved())
+        s.close()
+        b.close()
