@@ -33,7 +33,7 @@ def bucket(n: int) -> int:
 
 def key(nx: int, ny: int, precision: int) -> str:
     dim = 1 if ny == 1 else 2
-    p = "fp32" if precision == ng.NG_FP32 else "fp64"
+    p = {ng.NG_FP32: "fp32", ng.NG_FP64: "fp64", ng.NG_MIXED: "mixed"}[precision]
     return f"{dim}d_{p}_{bucket(nx)}x{bucket(ny)}"
 
 
@@ -123,8 +123,9 @@ def tune(nx: int, ny: int, precision: int, gas: dict | None = None, W=None, step
 def main():
     import argparse
     ap = argparse.ArgumentParser(description="tune step-kernel launch shapes")
-    ap.add_argument("--shapes", default="4096x4096:fp32,4096x4096:fp64,1048576x1:fp32,"
-                                        "1048576x1:fp64,1024x1:fp64,16384x1:fp32,256x256:fp32,"
+    ap.add_argument("--shapes", default="4096x4096:fp32,4096x4096:fp64,4096x4096:mixed,"
+                                        "1048576x1:fp32,1048576x1:fp64,1048576x1:mixed,"
+                                        "1024x1:fp64,16384x1:fp32,256x256:fp32,"
                                         "1024x1024:fp32,2048x2048:fp32")
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--out", default=CACHE, help="tuning cache to update")
@@ -134,7 +135,7 @@ def main():
     for item in args.shapes.split(","):
         shape, p = item.split(":")
         nx, ny = (int(v) for v in shape.split("x"))
-        prec = ng.NG_FP32 if p == "fp32" else ng.NG_FP64
+        prec = {"fp32": ng.NG_FP32, "fp64": ng.NG_FP64, "mixed": ng.NG_MIXED}[p]
         print(f"[tune] {shape} {p}", flush=True)
         r = tune(nx, ny, prec, steps=args.steps, verbose=True, path=args.out)
         print(f"[tune] {shape} {p}: rows {r['rows']} waves {r['waves']} "
