@@ -20,6 +20,8 @@ Prints one JSON line:
   fp64        the same workload through the FP64 path (comparison)
   mixed       the same workload with FP32 arithmetic on an FP64 deviation state
   bounded_ends  the FP32 step on the same grid with wall and outflow ends
+  periodic_1d_2e20  the 1D 2^20-cell multi-mode run (20000 steps) in FP32,
+              FP64 and mixed, with the FP32 / mixed error against FP64
   fp32_vs_fp64, mixed_vs_fp64  relative L1 differences after the same steps
   cpu_baseline  the serial FP64 oracle on whole steps of the same grid (about
               10 s of one host core)
@@ -123,6 +125,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--accuracy-steps", type=int, default=100)
     ap.add_argument("--bounded-steps", type=int, default=200)
+    ap.add_argument("--steps-1d", type=int, default=20000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain device copy of known size (for counter scaling)")
     args = ap.parse_args()
@@ -212,6 +215,42 @@ def main():
                         "ms_per_step": rm["total_ms"] / k, "step_kernel_ms": rm["step_ms"],
                         "hbm_frac": BYTES_PER_CELL_FP64 * cells / (rm["step_ms"] * 1e-3) / 1e9
                         / HBM_PEAK_GBS, "steps": k}
+
+    if args.steps_1d > 0:
+        # 1D periodic 2^20 cells, 64 random modes, Q_T = 2: the whole run of
+        # steps_1d steps in each precision (graph-launched, no per-launch
+        # events), and the FP32 / mixed error against FP64 at the end
+        k = args.steps_1d
+        w1 = wl.workload_1d_multimode()
+        n1 = w1["nx"]
+        res1, fin1 = {}, {}
+        for name, prec in (("fp32", ng.NG_FP32), ("fp64", ng.NG_FP64), ("mixed", ng.NG_MIXED)):
+            from paper_1805_03442_amd import autotune
+            s = ng.Solver(w1["gas"], n1, 1, W=w1["W"], precision=prec)
+            autotune.apply(s)
+            s.step(20)
+            torch.cuda.synchronize()
+            st = torch.cuda.current_stream()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            s.step(k)
+            e1.record(st)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            res1[name] = {"value": n1 * k / (ms * 1e-3), "unit": "cell-updates/s",
+                          "us_per_step": 1e3 * ms / k}
+            fin1[name] = s.conserved()
+            s.close()
+            log(f"[bench] 1D 2^20 {name}: {res1[name]['value']:.3e} cell-updates/s")
+        s0 = ng.Solver(w1["gas"], n1, 1, W=w1["W"], precision=ng.NG_FP64)
+        U0 = s0.conserved()
+        s0.close()
+        for name in ("fp32", "mixed"):
+            res1[name]["rel_l1_of_perturbation_vs_fp64"] = max(
+                float(np.abs(fin1[name][c] - fin1["fp64"][c]).sum()
+                      / np.abs(fin1["fp64"][c] - U0[c]).sum()) for c in (0, 1, 3, 4))
+        out["periodic_1d_2e20"] = dict(res1, steps=k + 20, workload=w1["name"])
 
     if args.bounded_steps > 0:
         # the same grid between reflecting walls (x) and outflow ends (y):
