@@ -59,7 +59,8 @@ def test_state_bytes(ng):
 
 @pytest.mark.parametrize("field,value", [("gamma", 1.0), ("tau0", 0.0), ("R", -1.0),
                                          ("cfl", 1.5), ("nx", 3), ("riemann", 7),
-                                         ("fy_1d", 0.1), ("precision", 5)])
+                                         ("fy_1d", 0.1), ("precision", 5), ("bc", (3, 3)),
+                                         ("bc", (0, 1)), ("huge", 1 << 30)])
 def test_invalid_arguments_rejected_before_device_use(ng, field, value):
     import numpy as np
     from paper_1805_03442_amd import workloads as wl
@@ -79,10 +80,18 @@ def test_invalid_arguments_rejected_before_device_use(ng, field, value):
         gas["fy"] = value
     elif field == "precision":
         prec = value
+    bc = (0, 0, 0, 0)
+    if field == "bc":
+        bc = tuple(value) + (0, 0)
+    grid = ng.make_grid(nx, ny, bc=bc)
+    if field == "huge":
+        # 2^30 cells of FP64: byte offsets beyond 32 bits (the state is never read)
+        grid = ng.make_grid(value, 1)
+        nx = 64
     W = wl.uniform_state(dict(wl.BASE_GAS), max(nx, 4))[:, :, :nx]
     arr = np.ascontiguousarray(W[[0, 1, 3, 4]].reshape(4, -1))
     h = C.c_void_p(0)
-    rc = L.ng_init_state(C.byref(ng.make_gas(gas)), C.byref(ng.make_grid(nx, ny)),
+    rc = L.ng_init_state(C.byref(ng.make_gas(gas)), C.byref(grid),
                          C.byref(ng.make_numerics(cfl, riemann, prec)),
                          arr.ctypes.data_as(C.POINTER(C.c_double)), 0.0, C.c_void_p(256),
                          1 << 30, None, C.byref(h))

@@ -459,3 +459,54 @@ def test_batch_rejected_member_does_not_disturb_others(ng):
         assert np.array_equal(b.conserved(sg), s.conserved())
         s.close()
         b.close()
+
+
+# ------------------------------------------------------------ checkpoint / resume
+
+@pytest.mark.parametrize("prec_name", ["fp64", "fp32"])
+def test_resume_from_checkpoint_is_bitwise(ng, prec_name):
+    """Stop after 37 steps, read the conserved state and t, start a new solve
+    from them, run 43 more: the state equals 80 uninterrupted steps bit for bit.
+    (An FP32 deviation plus its reference is exact in FP64, so the read-back
+    state re-enters unchanged; the mixed state's FP64 deviation is not, once
+    added to the reference.)"""
+    prec = {"fp64": ng.NG_FP64, "fp32": ng.NG_FP32, "mixed": ng.NG_MIXED}[prec_name]
+    gas = dict(wl.BASE_GAS, Q_T=2.0)
+    nx, ny = 150, 70
+    W = wl.random_field_2d(gas, 150, np.random.Generator(np.random.PCG64(17)), kmax=8,
+                           rms=1e-2)[:, :ny, :].copy()
+    a = ng.Solver(gas, nx, ny, W=W, precision=prec)
+    a.set_small_limit(0)
+    a.step(80)
+    Ua, da = a.conserved(), a.diagnostics()
+    a.close()
+    b = ng.Solver(gas, nx, ny, W=W, precision=prec)
+    b.set_small_limit(0)
+    b.step(37)
+    Uc, t = b.conserved(), b.diagnostics()["t"]
+    b.close()
+    c = ng.Solver(gas, nx, ny, U=Uc, t0=t, precision=prec)
+    c.set_small_limit(0)
+    c.step(43)
+    assert np.array_equal(c.conserved(), Ua)
+    assert c.diagnostics()["t"] == da["t"]
+    c.close()
+
+
+@pytest.mark.parametrize("bad", ["negative_pressure", "nan_density"])
+def test_unphysical_initial_state_rejected(ng, bad):
+    gas = dict(wl.BASE_GAS)
+    W = wl.acoustic_mode_1d(gas, 128, 1, 1e-3)
+    if bad == "negative_pressure":
+        W[3, 0, 17] = -0.1
+    else:
+        W[0, 0, 99] = np.nan
+    with pytest.raises(ng.NgError) as err:
+        ng.Solver(gas, 128, 1, W=W, precision=ng.NG_FP32)
+    assert err.value.code == ng.NG_EINVAL
+    b = ng.Batch(2, 16 << 20, precision=ng.NG_FP32)
+    with pytest.raises(ng.NgError) as err:
+        b.add(gas, 128, 1, W, t_end=0.1)
+    assert err.value.code == ng.NG_EINVAL
+    assert b.fits(128, 1)       # the refused solve left nothing behind
+    b.close()
