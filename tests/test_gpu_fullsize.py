@@ -1,0 +1,128 @@
+"""Parity at the benchmark's full sizes, in the launch shape the benchmark
+uses (the autotuned one), on sampled cells: the oracle cannot run a 4096^2
+grid quickly, but one step of a cell depends only on the 5 x 5 cells around it
+(two per side), so for each sampled cell the oracle steps an 11 x 11 window cut
+from the same initial state (periodic wrap) with the GPU's dt and its centre is
+compared with the GPU's cell.  Samples include the grid's corners and edges.
+
+Bars as in test_gpu_parity: FP64 bit for bit; FP32 within 1e-5 relative L1
+over the samples.  The 1D 2^20-cell workload is checked the same way.
+"""
+import numpy as np
+import pytest
+
+from paper_1805_03442_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+R = 5   # window half-width: the update reaches 2 cells, the window edges are wrong
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ng():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1805_03442_amd import ng as _ng
+    _ng.lib()
+    return _ng
+
+
+@pytest.fixture(scope="module")
+def oracle_mod():
+    import oracle
+    oracle.build()
+    return oracle
+
+
+def samples_2d(n, count, seed):
+    r = np.random.Generator(np.random.PCG64(seed))
+    pts = [(0, 0), (0, n - 1), (n - 1, 0), (n - 1, n - 1), (0, n // 2), (n // 2, 0),
+           (59, 61), (60, 60), (n - 1, 2048)]
+    pts += [tuple(int(v) for v in r.integers(0, n, size=2)) for _ in range(count)]
+    return pts
+
+
+def one_step_gpu(ng, gas, W, nx, ny, prec):
+    from paper_1805_03442_amd import autotune
+    s = ng.Solver(gas, nx, ny, W=W, precision=prec)
+    autotune.apply(s)
+    U0 = s.conserved()
+    s.step(1)
+    U1 = s.conserved()
+    dt = s.diagnostics()["dt_last"]
+    s.close()
+    return U0, U1, dt
+
+
+@pytest.mark.parametrize("prec_name", ["fp64", "fp32"])
+def test_2d_4096_sampled_cells(ng, oracle_mod, prec_name):
+    prec = ng.NG_FP64 if prec_name == "fp64" else ng.NG_FP32
+    w = wl.workload_2d_random(4096)
+    n = 4096
+    say(f"full-size 2D {n}^2 {prec_name}: one GPU step")
+    U0, U1, dt = one_step_gpu(ng, w["gas"], w["W"], n, n, prec)
+    # the oracle steps windows of the state the GPU started from (as read back)
+    P = oracle_mod.Problem(w["gas"], 2 * R + 1, 2 * R + 1, h=1.0 / n)
+    num, den, worst = 0.0, 0.0, 0.0
+    for (k, j) in samples_2d(n, 48, 5):
+        rows = np.arange(k - R, k + R + 1) % n
+        cols = np.arange(j - R, j + R + 1) % n
+        win = U0[:, rows][:, :, cols]
+        st, V, _ = P.step(win, dt)
+        assert st == 0
+        a, b = U1[:, k, j], V[:, R, R]
+        if prec == ng.NG_FP64:
+            assert np.array_equal(a, b), (k, j, a, b)
+        num += float(np.abs(a - b).sum())
+        den += float(np.abs(b).sum())
+        worst = max(worst, float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300))))
+    say(f"full-size 2D {prec_name}: sampled rel L1 {num / den:.3e}, worst cell {worst:.3e}")
+    assert num / den <= 1e-5
+
+
+@pytest.mark.parametrize("prec_name", ["fp64", "fp32"])
+def test_1d_2e20_sampled_cells(ng, oracle_mod, prec_name):
+    prec = ng.NG_FP64 if prec_name == "fp64" else ng.NG_FP32
+    w = wl.workload_1d_multimode()
+    n = w["nx"]
+    say(f"full-size 1D {n} {prec_name}: one GPU step")
+    U0, U1, dt = one_step_gpu(ng, w["gas"], w["W"], n, 1, prec)
+    P = oracle_mod.Problem(w["gas"], 2 * R + 1, 1, h=1.0 / n)
+    r = np.random.Generator(np.random.PCG64(6))
+    pts = [0, 1, n - 1, n - 2, 59, 60, 61] + [int(v) for v in r.integers(0, n, size=64)]
+    num, den = 0.0, 0.0
+    for j in pts:
+        cols = np.arange(j - R, j + R + 1) % n
+        st, V, _ = P.step(U0[:, :, cols], dt)
+        assert st == 0
+        a, b = U1[:, 0, j], V[:, 0, R]
+        if prec == ng.NG_FP64:
+            assert np.array_equal(a, b), (j, a, b)
+        num += float(np.abs(a - b).sum())
+        den += float(np.abs(b).sum())
+    say(f"full-size 1D {prec_name}: sampled rel L1 {num / den:.3e}")
+    assert num / den <= 1e-5
+
+
+def test_2d_4096_totals_follow_the_source_budget(ng):
+    """Property at full size: on a periodic grid the fluxes cancel, so the
+    change of the FP64 totals over the run equals the FP64 source budget."""
+    w = wl.workload_2d_random(4096)
+    s = ng.Solver(w["gas"], 4096, 4096, W=w["W"], precision=ng.NG_FP32)
+    d0 = s.diagnostics()
+    s.step(200)
+    d1 = s.diagnostics()
+    s.close()
+    assert d1["status"] == 0 and d1["steps"] == 200
+    for c in (0, 1, 2):
+        assert abs(d1["total"][c] - d0["total"][c]) <= 1e-9
+    dE = d1["total"][3] - d0["total"][3]
+    dV = d1["total"][4] - d0["total"][4]
+    say(f"full-size totals: dE {dE:.3e} vs budget {d1['src_budget'][0]:.3e}, "
+        f"dEnu {dV:.3e} vs {d1['src_budget'][1]:.3e}")
+    assert abs(dE - d1["src_budget"][0]) <= 1e-9 + 1e-6 * abs(dE)
+    assert abs(dV - d1["src_budget"][1]) <= 1e-9 + 1e-6 * abs(dV)
