@@ -126,3 +126,32 @@ def test_2d_4096_totals_follow_the_source_budget(ng):
         f"dEnu {dV:.3e} vs {d1['src_budget'][1]:.3e}")
     assert abs(dE - d1["src_budget"][0]) <= 1e-9 + 1e-6 * abs(dE)
     assert abs(dV - d1["src_budget"][1]) <= 1e-9 + 1e-6 * abs(dV)
+
+
+def test_batch_512_instances_sampled_fp64(ng, oracle_mod):
+    """The 512-instance batch workload, all instances together in FP64 for 200
+    steps; six instances (the smallest, the largest and four others) equal the
+    oracle bit for bit."""
+    insts = wl.batch_1d_instances(512, steps=200)
+    arena = int(sum(ng.Batch.solve_bytes(i["nx"], 1, ng.NG_FP64) for i in insts) * 1.05)
+    arena += 64 << 20
+    b = ng.Batch(len(insts), arena, precision=ng.NG_FP64)
+    slots = [b.add(i["gas"], i["nx"], 1, i["W"], t_end=1e30, max_steps=200) for i in insts]
+    assert all(s is not None for s in slots)
+    for _ in range(100):
+        b.run(50)
+        if b.active() == 0:
+            break
+    assert b.active() == 0
+    sizes = [i["nx"] for i in insts]
+    pick = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 3, 100, 257, 511})
+    for j in pick:
+        i = insts[j]
+        P = oracle_mod.Problem(i["gas"], i["nx"], 1)
+        ref = P.run(P.prim_to_cons(i["W"]), 200)
+        assert ref["status"] == 0
+        U = b.conserved(slots[j])
+        say(f"batch instance {j}: n={i['nx']}")
+        assert np.array_equal(U[[0, 1, 3, 4]], ref["U"][[0, 1, 3, 4]])
+        assert b.diagnostics(slots[j])["t"] == ref["t"]
+    b.close()
