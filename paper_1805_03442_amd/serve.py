@@ -43,6 +43,7 @@ class Request:
     admitted: float = math.nan
     finished: float = math.nan
     steps: int = 0
+    failed: bool = False    # a step was rejected (non-physical state), or the request was refused
     slot: int = -1
     result: object = None
 
@@ -75,7 +76,9 @@ class Stats:
     def summary(self, pending: int, waiting: int, unsubmitted: int) -> dict:
         lat = np.array([r.finished - r.arrival for r in self.completed])
         qd = np.array([r.admitted - r.arrival for r in self.completed])
-        out = dict(completed=len(self.completed), wall_s=self.wall, ticks=self.ticks,
+        out = dict(completed=len(self.completed),
+                   failed=sum(1 for r in self.completed if r.failed),
+                   wall_s=self.wall, ticks=self.ticks,
                    solves_per_s=len(self.completed) / self.wall if self.wall > 0 else 0.0,
                    cell_updates_per_s=self.cell_updates / self.wall if self.wall > 0 else 0.0,
                    cell_updates_per_s_all=(self.cell_updates_all / self.wall
@@ -109,12 +112,20 @@ class GpuBackend:
         return self.batch.fits(nx, ny)
 
     def add(self, req: Request):
+        """The slot, None when there is no room yet; ValueError for a request
+        the library refuses (invalid parameters or initial state)."""
         t0 = time.perf_counter()
         W = req.state()
         t1 = time.perf_counter()
-        slot = self.batch.add(req.gas, req.nx, req.ny, W, t_end=req.t_end)
-        self.state_s += t1 - t0
-        self.add_s += time.perf_counter() - t1
+        try:
+            slot = self.batch.add(req.gas, req.nx, req.ny, W, t_end=req.t_end)
+        except self.ng.NgError as e:
+            if e.code == self.ng.NG_EINVAL:
+                raise ValueError(str(e)) from e
+            raise
+        finally:
+            self.state_s += t1 - t0
+            self.add_s += time.perf_counter() - t1
         return slot
 
     def run(self, nsteps: int):
@@ -125,6 +136,9 @@ class GpuBackend:
 
     def steps(self, slot):
         return self.batch.diagnostics(slot)["steps"]
+
+    def failed(self, slot):
+        return self.batch.diagnostics(slot)["status"] != 0
 
     def result(self, slot):
         return self.batch.conserved(slot) if self.keep_results else None
@@ -168,7 +182,12 @@ class Server:
             if len(self.running) >= self.capacity or not self.backend.fits(req.nx, req.ny):
                 keep.append(req)    # no slot or arena space yet: keep waiting
                 continue
-            slot = self.backend.add(req)
+            try:
+                slot = self.backend.add(req)
+            except ValueError:
+                req.failed = True       # refused by the library: never admitted
+                self.rejected.append(req)
+                continue
             if slot is None:
                 keep.append(req)
                 continue
@@ -203,6 +222,7 @@ class Server:
                 req = self.running.pop(slot)
                 req.finished = self.now()
                 req.steps = self.backend.steps(slot)
+                req.failed = self.backend.failed(slot)
                 req.result = self.backend.result(slot)
                 self.backend.remove(slot)
                 self.stats.completed.append(req)

@@ -37,3 +37,36 @@ def test_served_results_equal_alone_runs():
         s.close()
         assert np.array_equal(U, r.result), (r.id, r.nx, r.ny)
     be.close()
+
+
+def test_served_stream_with_refused_and_failing_requests():
+    """A request with an unphysical initial state is refused, one whose gas
+    drives the pressure negative fails mid-run; both are accounted for and
+    every other request is served with its alone-run result."""
+    import torch
+    from paper_1805_03442_amd import ng, serve
+    assert torch.cuda.is_available()
+    recs = small_trace(8)
+    reqs = serve.requests_from_trace(recs, wl.request_state)
+    bad_state = reqs[2]
+    W = wl.request_state(recs[2])
+    W[3].flat[5] = -1.0
+    bad_state.W = W
+    sink = reqs[5]
+    sink.gas = dict(sink.gas, I0=20.0, I_T=0.0)
+    sink.t_end = 10.0
+    budget = sum(ng.Batch.solve_bytes(r.nx, r.ny) for r in reqs) + (64 << 20)
+    be = serve.GpuBackend(capacity=4, budget_bytes=budget, keep_results=True)
+    srv = serve.Server(be, capacity=4, tick_steps=16)
+    st = srv.run_trace(reqs, max_wall=120.0)
+    print("serve stats", st, flush=True)
+    assert st["rejected"] == 1 and bad_state.failed
+    assert st["completed"] == len(reqs) - 1 and st["failed"] == 1 and sink.failed
+    for r in srv.stats.completed:
+        if r is sink:
+            continue
+        s = ng.Solver(r.gas, r.nx, r.ny, W=r.state(), precision=ng.NG_FP32)
+        s.run_to_time(r.t_end)
+        assert np.array_equal(s.conserved(), r.result), (r.id, r.nx, r.ny)
+        s.close()
+    be.close()

@@ -63,6 +63,9 @@ class FakeBackend:
     def steps(self, slot):
         return self.slots[slot]["done"]
 
+    def failed(self, slot):
+        return False
+
     def result(self, slot):
         return None
 
@@ -185,3 +188,21 @@ def test_prefetched_states_are_used_once():
     st = srv.run_trace(trace, max_wall=1e9)
     assert st["completed"] == 5
     assert calls == {i: 1 for i in range(5)}
+
+
+def test_refused_request_is_rejected_and_others_proceed():
+    """A request the library refuses (ValueError from the backend) is counted
+    as rejected; the rest of the stream is served."""
+    clock = FakeClock()
+
+    class Refusing(FakeBackend):
+        def add(self, req):
+            if req.nx == 777:
+                raise ValueError("invalid initial state")
+            return super().add(req)
+
+    be = Refusing(capacity=4, budget=40 * 10000, clock=clock)
+    srv = Server(be, capacity=4, tick_steps=50, clock=clock, sleep=clock.sleep)
+    trace = make_trace([(0.0, 1000, 1, 0.1), (0.0, 777, 1, 0.1), (0.01, 1200, 1, 0.1)])
+    st = srv.run_trace(trace, max_wall=1e9)
+    assert st["completed"] == 2 and st["rejected"] == 1 and st["failed"] == 0
