@@ -693,6 +693,13 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
 
     auto row = [&](int64_t i, R* Wd, R* We, R* Dp, R* Dn, R* h0, R* h1, R* x0s, R* x1s,
                    R* Np, R* Nn, R* Gp, R* Gn, St* Uc, St* Ux) {
+        // U^n of row i (loaded two rows ago) is re-read from cache for the
+        // update.  Loads complete in order, so an FP64 state asks for it before
+        // row i+3 and waiting for it does not also wait for the row in flight;
+        // an FP32 state asks late and keeps the registers free meanwhile
+        constexpr bool early = sizeof(St) == 8;
+        St Un[NC];
+        if (early) src.load(boff(i), Un);
         // row i+2 has arrived in Uc; put row i+3 in flight
         ghost(i + 2, Uc);
         P::prim(k, Uc, We);
@@ -731,11 +738,11 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
                 dG[c] = Gn[c] - Gp[c];
             }
         }
-        // update of row i (U^n of row i re-read; it was loaded two rows ago)
-        St Un[NC], Uo[NC];
+        // update of row i
+        St Uo[NC];
         R Wn[NC], sE, sV;
         const uint32_t o = boff(i);
-        src.load(o, Un);
+        if (!early) src.load(o, Un);
         P::update(k, Un, dF, dG, h0, Uo, sE, sV);
         P::prim(k, Uo, Wn);
         R s = P::speed(k, Wn);
