@@ -119,6 +119,8 @@ struct Plain64 {
     // the FP64 step needs more than 128 registers; asking for two waves per
     // SIMD trades a few spills for latency hiding (13 % faster at 4096^2)
     static constexpr int kMinWaves = 2;
+    // U^n of the updated row is re-read from cache (no registers to spare)
+    static constexpr bool kKeepRows = false;
     using St = double;
     using K = K64;
     static __device__ K make(const InstDesc& d, double dt)
@@ -175,6 +177,8 @@ struct Dev32 {
     using St = float;   // stored state: FP32 deviations
     using K = K32;
     static constexpr int kMinWaves = 1;
+    // the raw rows stay in registers until their update
+    static constexpr bool kKeepRows = true;
     static __device__ K make(const InstDesc& d, double dt)
     {
         K k;
@@ -244,6 +248,7 @@ struct Mix32 {
     using St = double;
     using K = K32;
     static constexpr int kMinWaves = 1;
+    static constexpr bool kKeepRows = true;
     static __device__ K make(const InstDesc& d, double dt) { return Dev32<NC>::make(d, dt); }
     static __device__ void prim(const K& k, const St* U, R* W)
     {
@@ -650,27 +655,32 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
     //   Np/Nn  north face states of rows i / i+1
     //   Gp/Gn  y-fluxes at faces i-1/2 / i+1/2
     //   Uc/Ux  raw row i+2 (arrived) / row i+3 (in flight)
+    // Policies that keep the raw rows hold four of them (rows i .. i+3) in a
+    // ring U0..U3, so U^n of row i is still in registers at its update;
+    // the others re-read it and use U2/U3 only.
     R WA[NC], WB[NC], DA[NC], DB[NC], HA[NC], HB[NC], XA[NC], XB[NC];
     R NA[NC], NB[NC], GA[NC], GB[NC];
-    St UA[NC], UB[NC];
+    St U0[NC], U1[NC], U2[NC], U3[NC];
 
     // prologue: rows r0-2 .. r0+1
     {
         R Wa[NC], Wb[NC], Wc[NC], sy[NC], sx[NC], hb[NC], S[NC];
         St t[NC];
+        St* t0 = P::kKeepRows ? U0 : t;
+        St* t1 = P::kKeepRows ? U1 : t;
         src.load(boff(r0 - 2), t);
         ghost(r0 - 2, t);
         P::prim(k, t, Wa);
         src.load(boff(r0 - 1), t);
         ghost(r0 - 1, t);
         P::prim(k, t, Wb);
-        src.load(boff(r0), t);
-        ghost(r0, t);
-        P::prim(k, t, Wc);
-        src.load(boff(r0 + 1), t);
-        ghost(r0 + 1, t);
-        P::prim(k, t, WA);
-        src.load(boff(r0 + 2), UA);
+        src.load(boff(r0), t0);
+        ghost(r0, t0);
+        P::prim(k, t0, Wc);
+        src.load(boff(r0 + 1), t1);
+        ghost(r0 + 1, t1);
+        P::prim(k, t1, WA);
+        src.load(boff(r0 + 2), U2);
         // row r0-1: its north face state
         slopes_x(Wb, sx);
         for (int c = 0; c < NC; c++) sy[c] = minmod(Wb[c] - Wa[c], Wc[c] - Wb[c]);
@@ -692,14 +702,17 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
     }
 
     auto row = [&](int64_t i, R* Wd, R* We, R* Dp, R* Dn, R* h0, R* h1, R* x0s, R* x1s,
-                   R* Np, R* Nn, R* Gp, R* Gn, St* Uc, St* Ux) {
-        // U^n of row i (loaded two rows ago) is re-read from cache for the
-        // update.  Loads complete in order, so an FP64 state asks for it before
-        // row i+3 and waiting for it does not also wait for the row in flight;
-        // an FP32 state asks late and keeps the registers free meanwhile
-        constexpr bool early = sizeof(St) == 8;
-        St Un[NC];
-        if (early) src.load(boff(i), Un);
+                   R* Np, R* Nn, R* Gp, R* Gn, St* Uk, St* Uc, St* Ux) {
+        // U^n of row i: kept in the ring (Uk), or else re-read from cache
+        // for the update (it was loaded two rows ago).  Loads complete in
+        // order, so an FP64 state asks for it before row i+3 and waiting for
+        // it does not also wait for the row in flight; an FP32 state asks late
+        // and keeps the registers free meanwhile
+        constexpr bool reread = !P::kKeepRows;
+        constexpr bool early = reread && sizeof(St) == 8;
+        St Ul[NC];
+        St* Un = reread ? Ul : Uk;
+        if (early) src.load(boff(i), Ul);
         // row i+2 has arrived in Uc; put row i+3 in flight
         ghost(i + 2, Uc);
         P::prim(k, Uc, We);
@@ -742,7 +755,7 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
         St Uo[NC];
         R Wn[NC], sE, sV;
         const uint32_t o = boff(i);
-        if (!early) src.load(o, Un);
+        if (reread && !early) src.load(o, Ul);
         P::update(k, Un, dF, dG, h0, Uo, sE, sV);
         P::prim(k, Uo, Wn);
         R s = P::speed(k, Wn);
@@ -753,11 +766,23 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
     };
 
     int64_t i = r0;
-    for (; i + 1 < r1; i += 2) {
-        row(i, WA, WB, DA, DB, HA, HB, XA, XB, NA, NB, GA, GB, UA, UB);
-        row(i + 1, WB, WA, DB, DA, HB, HA, XB, XA, NB, NA, GB, GA, UB, UA);
+    if constexpr (P::kKeepRows) {
+        for (; i < r1; i += 4) {
+            row(i, WA, WB, DA, DB, HA, HB, XA, XB, NA, NB, GA, GB, U0, U2, U3);
+            if (i + 1 >= r1) break;
+            row(i + 1, WB, WA, DB, DA, HB, HA, XB, XA, NB, NA, GB, GA, U1, U3, U0);
+            if (i + 2 >= r1) break;
+            row(i + 2, WA, WB, DA, DB, HA, HB, XA, XB, NA, NB, GA, GB, U2, U0, U1);
+            if (i + 3 >= r1) break;
+            row(i + 3, WB, WA, DB, DA, HB, HA, XB, XA, NB, NA, GB, GA, U3, U1, U2);
+        }
+    } else {
+        for (; i + 1 < r1; i += 2) {
+            row(i, WA, WB, DA, DB, HA, HB, XA, XB, NA, NB, GA, GB, U0, U2, U3);
+            row(i + 1, WB, WA, DB, DA, HB, HA, XB, XA, NB, NA, GB, GA, U0, U3, U2);
+        }
+        if (i < r1) row(i, WA, WB, DA, DB, HA, HB, XA, XB, NA, NB, GA, GB, U0, U2, U3);
     }
-    if (i < r1) row(i, WA, WB, DA, DB, HA, HB, XA, XB, NA, NB, GA, GB, UA, UB);
 }
 
 // periodic solves take the plain wrap-around indexing; solves with a wall or
