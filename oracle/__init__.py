@@ -23,7 +23,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "muscl_oracle.c")
 _LIB = os.environ.get("NG_ORACLE_LIB") or os.path.join(_HERE, "_build", "liboracle.so")
 
-BC_PERIODIC, BC_WALL, BC_OUTFLOW = 0, 1, 2
+BC_PERIODIC, BC_WALL, BC_OUTFLOW, BC_SOURCE = 0, 1, 2, 3
 HLLC, HLL = 0, 1
 OK, EINVAL, EPHYS = 0, -1, -3
 
@@ -37,7 +37,7 @@ class OrGas(C.Structure):
 
 class OrGrid(C.Structure):
     _fields_ = [("nx", C.c_int64), ("ny", C.c_int64), ("h", C.c_double),
-                ("bc", C.c_int32 * 4)]
+                ("bc", C.c_int32 * 4), ("src_amp", C.c_double), ("src_lambda", C.c_double)]
 
 
 class OrNum(C.Structure):
@@ -68,6 +68,9 @@ def lib():
         L.or_step.argtypes = [C.POINTER(OrGas), C.POINTER(OrGrid), C.POINTER(OrNum), dp, dp,
                               C.c_double, dp]
         L.or_step.restype = C.c_int
+        L.or_step_at.argtypes = [C.POINTER(OrGas), C.POINTER(OrGrid), C.POINTER(OrNum), dp, dp,
+                                 C.c_double, C.c_double, dp]
+        L.or_step_at.restype = C.c_int
         L.or_run.argtypes = [C.POINTER(OrGas), C.POINTER(OrGrid), C.POINTER(OrNum), dp,
                              C.c_int64, C.c_double, dp, C.POINTER(C.c_int64), dp, dp]
         L.or_run.restype = C.c_int
@@ -87,8 +90,9 @@ def _gas(g: dict) -> OrGas:
     return OrGas(*[float(g.get(f, 0.0)) for f in GAS_FIELDS])
 
 
-def _grid(nx: int, ny: int, h: float, bc=(0, 0, 0, 0)) -> OrGrid:
-    return OrGrid(int(nx), int(ny), float(h), (C.c_int32 * 4)(*bc))
+def _grid(nx: int, ny: int, h: float, bc=(0, 0, 0, 0), source=(0.0, 0.0)) -> OrGrid:
+    return OrGrid(int(nx), int(ny), float(h), (C.c_int32 * 4)(*bc), float(source[0]),
+                  float(source[1]))
 
 
 def _num(cfl: float, riemann: int = HLLC, stiff_z: float = 0.5) -> OrNum:
@@ -105,14 +109,17 @@ class Problem:
 
     def __init__(self, gas: dict, nx: int, ny: int = 1, h: float | None = None,
                  cfl: float = 0.4, riemann: int = HLLC, stiff_z: float = 0.5,
-                 bc=(BC_PERIODIC,) * 4):
+                 bc=(BC_PERIODIC,) * 4, source=(0.0, 0.0)):
+        """``source = (amplitude, wavelength)`` of the forced wave of a
+        ``BC_SOURCE`` x-low end."""
         self.gas = dict(gas)
         self.nx, self.ny = int(nx), int(ny)
         self.h = float(h) if h is not None else 1.0 / self.nx
         self.cfl, self.riemann, self.stiff_z = float(cfl), int(riemann), float(stiff_z)
         self.bc = tuple(int(b) for b in bc)
+        self.source = (float(source[0]), float(source[1]))
         self._g = _gas(self.gas)
-        self._gr = _grid(self.nx, self.ny, self.h, self.bc)
+        self._gr = _grid(self.nx, self.ny, self.h, self.bc, self.source)
         self._nm = _num(self.cfl, self.riemann, self.stiff_z)
 
     @property
@@ -142,13 +149,14 @@ class Problem:
         return lib().or_max_speed(C.byref(self._g), C.byref(self._gr), _p(U))
 
     # --- eq. (15) -----------------------------------------------------------
-    def step(self, U: np.ndarray, dt: float):
-        """One step with a given dt.  Returns (status, U_new, src[2])."""
+    def step(self, U: np.ndarray, dt: float, t: float = 0.0):
+        """One step with a given dt from the state U at time t (t matters only
+        to a source end).  Returns (status, U_new, src[2])."""
         U = np.ascontiguousarray(U, dtype=np.float64).reshape(5, self.ny, self.nx)
         V = np.empty_like(U)
         src = np.zeros(2)
-        st = lib().or_step(C.byref(self._g), C.byref(self._gr), C.byref(self._nm), _p(U),
-                           _p(V), float(dt), _p(src))
+        st = lib().or_step_at(C.byref(self._g), C.byref(self._gr), C.byref(self._nm), _p(U),
+                              _p(V), float(t), float(dt), _p(src))
         return st, V, src
 
     def run(self, U: np.ndarray, nsteps: int, t0: float = 0.0, t_end: float = 0.0):

@@ -32,6 +32,9 @@
  *                ((E_nue - E_nu)/tau + rho Q; the printed Y carries an extra rho
  *                factor and a repeated rho f_x -- both read as misprints).
  *   time step    eq. (16) times a CFL number.
+ *   boundaries  periodic, reflecting wall or free outflow ends (sections 2.4
+ *                and 3), and the forced source of the 1D runs of section 3 at
+ *                the x-low end (or_source_ghost).
  *   stiff branch when dt/tau exceeds a threshold, the relaxation part of the
  *                E_nu update is integrated exactly with E_nue and tau frozen
  *                (our addition; the paper's runs never reach it).
@@ -59,7 +62,7 @@ typedef struct {
     double fx, fy;                 /* specific external force f, eqs. (2)-(3)  */
 } or_gas;
 
-enum { OR_BC_PERIODIC = 0, OR_BC_WALL = 1, OR_BC_OUTFLOW = 2 };
+enum { OR_BC_PERIODIC = 0, OR_BC_WALL = 1, OR_BC_OUTFLOW = 2, OR_BC_SOURCE = 3 };
 enum { OR_HLLC = 0, OR_HLL = 1 };
 enum { OR_OK = 0, OR_EINVAL = -1, OR_EPHYS = -3 };
 
@@ -67,6 +70,8 @@ typedef struct {
     int64_t nx, ny;                /* ny = 1 for 1D                            */
     double h;                      /* cell size                                */
     int32_t bc[4];                 /* x-low, x-high, y-low, y-high             */
+    double src_amp;                /* OR_BC_SOURCE (x-low only): density       */
+    double src_lambda;             /*   amplitude and wavelength of the wave   */
 } or_grid;
 
 typedef struct {
@@ -242,17 +247,57 @@ double or_dt(const or_gas* g, const or_grid* gr, const or_num* nm, const double*
 /* -------------------------------------------------------------- ghost cells */
 
 /* Map an index outside [0, n) to the cell that fills its ghost, and report
- * whether the normal velocity changes sign there (reflecting wall). */
+ * whether the normal velocity changes sign there (reflecting wall).  A source
+ * end maps like an outflow end; its ghosts are then overwritten by
+ * or_source_ghost. */
 static int64_t or_ghost(int64_t j, int64_t n, int bc_lo, int bc_hi, int* flip)
 {
     *flip = 0;
     if (j >= 0 && j < n) return j;
     int bc = j < 0 ? bc_lo : bc_hi;
     if (bc == OR_BC_PERIODIC) return ((j % n) + n) % n;
-    if (bc == OR_BC_OUTFLOW) return j < 0 ? 0 : n - 1;
+    if (bc == OR_BC_OUTFLOW || bc == OR_BC_SOURCE) return j < 0 ? 0 : n - 1;
     /* wall: mirror image */
     *flip = 1;
     return j < 0 ? -1 - j : 2 * n - 1 - j;
+}
+
+/*
+ * Forced oscillations from a source (section 3, the 1D runs): the ghost
+ * cells j = -1, -2 before the x-low end carry a plane sound wave of the
+ * frozen sound speed travelling into the domain,
+ *
+ *   s = a sin(omega t - k x),  k = 2 pi / lambda,  omega = c k,  x = (j + 1/2) h,
+ *   rho = rho_b + s,  u = (c / rho_b) s,  v = 0,  p = p_b + c^2 s,
+ *   E_nu = E_nu,b + (E_nu,b / rho_b) s,
+ *
+ * about the steady background at the reference point of eq. (6): rho_b =
+ * rho0, p_b = R rho0 T0, E_nu,b = rho0 Cv T0 + rho0 tau0 Q0 (relaxation
+ * balancing the pump in eq. (4)), c = sqrt(gamma p_b / rho_b).  The paper
+ * gives the wavelength but neither the amplitude nor the source's form; the
+ * frozen-sound plane wave with unchanged specific vibrational energy is our
+ * reading.  The E_nu part enters the domain only with the flow's own velocity,
+ * i.e. at second order in the amplitude, so no linear check pins it.  t is the
+ * time of the state the step starts from.
+ */
+static void or_source_ghost(const or_gas* g, const or_grid* gr, double t, int64_t j, double U[5])
+{
+    const double pi = 3.141592653589793;
+    double rho_b = g->rho0;
+    double p_b = g->R * g->rho0 * g->T0;
+    double ev_b = g->rho0 * g->Cv * g->T0 + g->rho0 * g->tau0 * g->Q0;
+    double c = sqrt(g->gamma * p_b / rho_b);
+    double k = 2.0 * pi / gr->src_lambda;
+    double omega = c * k;
+    double x = ((double)j + 0.5) * gr->h;
+    double s = gr->src_amp * sin(omega * t - k * x);
+    double W[5];
+    W[0] = rho_b + s;
+    W[1] = (c / rho_b) * s;
+    W[2] = 0.0;
+    W[3] = p_b + (c * c) * s;
+    W[4] = ev_b + (ev_b / rho_b) * s;
+    or_cons(g, W, U);
 }
 
 /* ------------------------------------------------------------------- step */
@@ -267,15 +312,16 @@ static int64_t ex(const or_ext* e, int64_t j, int64_t k)
 }
 
 /*
- * One MUSCL step, eq. (15), from U_in to U_out (both ncell*5, may not alias).
- * dt is given (the caller computes it with or_dt).  src[0] receives
+ * One MUSCL step, eq. (15), from U_in (the state at time t) to U_out (both
+ * ncell*5, may not alias).  dt is given (the caller computes it with or_dt);
+ * t matters only to a source end (or_source_ghost).  src[0] receives
  * dt * sum_cells Y_E (the rho (Q - I + v.f) row) and src[1] the summed source
  * increment of E_nu over the step.  Returns OR_OK, or OR_EPHYS if a density or
  * pressure of U_out is not positive or a value is not finite (U_out is then
  * undefined and the caller keeps U_in).
  */
-int or_step(const or_gas* g, const or_grid* gr, const or_num* nm, const double* U_in,
-            double* U_out, double dt, double* src)
+int or_step_at(const or_gas* g, const or_grid* gr, const or_num* nm, const double* U_in,
+               double* U_out, double t, double dt, double* src)
 {
     const int64_t nx = gr->nx, ny = gr->ny, n = nx * ny;
     const int twod = ny > 1;
@@ -313,6 +359,7 @@ int or_step(const or_gas* g, const or_grid* gr, const or_num* nm, const double* 
             int64_t s = ks * nx + js;
             double Uc[5] = {U_in[s], U_in[n + s], U_in[2 * n + s], U_in[3 * n + s],
                             U_in[4 * n + s]};
+            if (j < 0 && gr->bc[0] == OR_BC_SOURCE) or_source_ghost(g, gr, t, j, Uc);
             if (fx_) Uc[1] = -Uc[1];
             if (fy_) Uc[2] = -Uc[2];
             double Wc[5];
@@ -502,6 +549,13 @@ int or_step(const or_gas* g, const or_grid* gr, const or_num* nm, const double* 
     return status;
 }
 
+/* or_step_at for boundaries that do not depend on time (t = 0). */
+int or_step(const or_gas* g, const or_grid* gr, const or_num* nm, const double* U_in,
+            double* U_out, double dt, double* src)
+{
+    return or_step_at(g, gr, nm, U_in, U_out, 0.0, dt, src);
+}
+
 /*
  * Advance U in place by up to nsteps steps, each with dt from eq. (16) on the
  * current state, stopping at t_end (dt is shortened to land on it) when
@@ -521,7 +575,7 @@ int or_run(const or_gas* g, const or_grid* gr, const or_num* nm, double* U, int6
         double dt = or_dt(g, gr, nm, U);
         if (t_end > 0.0 && *t + dt > t_end) dt = t_end - *t;
         double src[2];
-        st = or_step(g, gr, nm, U, V, dt, src);
+        st = or_step_at(g, gr, nm, U, V, *t, dt, src);
         if (st != OR_OK) break;
         memcpy(U, V, (size_t)(5 * n) * sizeof(double));
         *t += dt;

@@ -105,3 +105,37 @@ def S1(gas):
     Ck = gas["Cv"] / gas["R"]
     gm1 = gas["gamma"] - 1.0
     return -gm1 * Ck / (gas["tau_rho"] + gm1 * gas["tau_T"])
+
+
+def spatial_mode(gas, omega, direction=+1):
+    """Signalling problem: the complex wavenumber k of a wave of real
+    frequency omega, exp(-i omega t + i k x), travelling in the given
+    direction (sign of Re k), and its eigenvector over (rho', u', p', E_nu')
+    scaled to rho' = 1.  M(k) is affine in k, M = M0 + k M1, so k is a finite
+    generalised eigenvalue of (-i omega I - M0) X = k M1 X; the amplitude then
+    varies along x as exp(-Im k x)."""
+    import scipy.linalg as sl
+    M0 = matrix(gas, 0.0)
+    M1 = matrix(gas, 1.0) - M0
+    A = -1j * omega * np.eye(4) - M0
+    ks, V = sl.eig(A, M1)
+    idx = [i for i in range(len(ks)) if np.isfinite(ks[i]) and np.sign(ks[i].real) == direction]
+    assert len(idx) == 1, ks
+    i = idx[0]
+    return complex(ks[i]), V[:, i] / V[0, i]
+
+
+def spatial_k(gas, omega, direction=+1):
+    return spatial_mode(gas, omega, direction)[0]
+
+
+def source_transmission(gas, omega):
+    """Complex amplitude (density, relative to the source's) of the
+    right-going wave that a frozen plane sound wave imposed at x = 0 sets up in
+    the medium: the wave entering through x = 0 carries the incoming frozen
+    characteristic p' + rho0 c u' of the imposed state (2 c^2 per unit
+    density amplitude), and the medium's mode must carry the same."""
+    rho0, p0, _, _ = background(gas)
+    c = np.sqrt(gas["gamma"] * p0 / rho0)
+    _, X = spatial_mode(gas, omega)
+    return 2.0 * c * c / (X[2] + rho0 * c * X[1])

@@ -1,5 +1,6 @@
 /* Drives the oracle through its entry points on small grids (1D and 2D;
- * periodic, wall and outflow ends; both fluxes; the stiff branch) so that a
+ * periodic, wall, outflow and forced-source ends; both fluxes; the stiff
+ * branch) so that a
  * build with AddressSanitizer and UndefinedBehaviorSanitizer can check every
  * ghost-cell index and array access.  Exit status 0 when every run returns
  * OR_OK; the sanitizers abort on any invalid access. */
@@ -13,7 +14,7 @@
 static int run_case(int64_t nx, int64_t ny, const int32_t bc[4], int riemann, double tau0)
 {
     or_gas g = {1.4, 1.0, 1.0, 1.0, 1.0, tau0, -1.0, -1.0, 0.1, 0.5, 2.0, 0.1, 1.0, 2.0, 0.0, 0.0};
-    or_grid gr = {nx, ny, 1.0 / (double)nx, {bc[0], bc[1], bc[2], bc[3]}};
+    or_grid gr = {nx, ny, 1.0 / (double)nx, {bc[0], bc[1], bc[2], bc[3]}, 0.01, 0.1};
     or_num nm = {0.4, riemann, 0.5};
     const int64_t n = nx * ny;
     double* W = malloc(sizeof(double) * 5 * n);
@@ -43,11 +44,12 @@ static int run_case(int64_t nx, int64_t ny, const int32_t bc[4], int riemann, do
 
 int main(void)
 {
-    const int32_t kinds[3][4] = {{OR_BC_PERIODIC, OR_BC_PERIODIC, OR_BC_PERIODIC, OR_BC_PERIODIC},
+    const int32_t kinds[4][4] = {{OR_BC_PERIODIC, OR_BC_PERIODIC, OR_BC_PERIODIC, OR_BC_PERIODIC},
                                  {OR_BC_WALL, OR_BC_WALL, OR_BC_OUTFLOW, OR_BC_OUTFLOW},
-                                 {OR_BC_OUTFLOW, OR_BC_WALL, OR_BC_WALL, OR_BC_OUTFLOW}};
+                                 {OR_BC_OUTFLOW, OR_BC_WALL, OR_BC_WALL, OR_BC_OUTFLOW},
+                                 {OR_BC_SOURCE, OR_BC_OUTFLOW, OR_BC_WALL, OR_BC_PERIODIC}};
     int bad = 0;
-    for (int b = 0; b < 3; b++)
+    for (int b = 0; b < 4; b++)
         for (int riemann = 0; riemann < 2; riemann++) {
             bad += run_case(37, 1, kinds[b], riemann, 0.05);
             bad += run_case(4, 1, kinds[b], riemann, 0.05);

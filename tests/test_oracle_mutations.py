@@ -65,8 +65,14 @@ MUTATIONS = {
     "wall_keeps_normal_momentum": [("            if (fx_) Uc[1] = -Uc[1];\n", "")],
     "wall_mirror_off_by_one": [("return j < 0 ? -1 - j : 2 * n - 1 - j;",
                                 "return j < 0 ? -j : 2 * n - 2 - j;")],
-    "outflow_copies_wrong_cell": [("if (bc == OR_BC_OUTFLOW) return j < 0 ? 0 : n - 1;",
-                                   "if (bc == OR_BC_OUTFLOW) return j < 0 ? 1 : n - 2;")],
+    "outflow_copies_wrong_cell": [
+        ("if (bc == OR_BC_OUTFLOW || bc == OR_BC_SOURCE) return j < 0 ? 0 : n - 1;",
+         "if (bc == OR_BC_OUTFLOW || bc == OR_BC_SOURCE) return j < 0 ? 1 : n - 2;")],
+    "source_wave_runs_backwards": [("W[1] = (c / rho_b) * s;", "W[1] = -(c / rho_b) * s;")],
+    "source_pressure_not_isentropic": [("W[3] = p_b + (c * c) * s;", "W[3] = p_b + c * s;")],
+    "source_ignores_time": [("sin(omega * t - k * x)", "sin(-k * x)")],
+    "source_ghost_one_cell_off": [("double x = ((double)j + 0.5) * gr->h;",
+                                   "double x = ((double)j + 1.5) * gr->h;")],
 }
 
 

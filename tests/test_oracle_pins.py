@@ -373,6 +373,24 @@ def test_linear_rates_match_dispersion(oracle_lib, case):
     assert freq == pytest.approx(om.real, rel=2e-3), (om, freq)
 
 
+def test_signalling_roots_solve_paper_eq8():
+    """The spatial roots k(omega) used for the forced source are roots of the
+    printed eq. (8), and for small growth agree with the temporal root at
+    Re k: Im k = -Im omega / group velocity."""
+    for gas in (RESULTS_UNSTABLE, dict(wl.BASE_GAS)):
+        om = 70.0
+        k = D.spatial_k(gas, om)
+        assert abs(D.paper_residual(gas, om, k)) < 1e-12
+        kl = D.spatial_k(gas, om, -1)
+        assert abs(D.paper_residual(gas, om, kl)) < 1e-12
+        assert kl.real < 0
+        w0, _ = D.acoustic_mode(gas, k.real, +1)
+        dk = 1e-4 * k.real
+        vg = (D.acoustic_mode(gas, k.real + dk, +1)[0].real
+              - D.acoustic_mode(gas, k.real - dk, +1)[0].real) / (2 * dk)
+        assert k.imag == pytest.approx(-w0.imag / vg, rel=0.05)
+
+
 def test_paper_results_set_is_acoustically_unstable():
     gas = dict(gamma=1.4, R=1.0, Cv=0.1, rho0=1.0, T0=1.0, tau0=0.05, tau_rho=-1.0,
                tau_T=-1.5, Q0=10.0, Q_rho=0.0, Q_T=0.0, I0=10.0, I_rho=0.0, I_T=0.0,
@@ -658,3 +676,123 @@ def test_boundary_ghosts_embed_bitwise(oracle_lib, kind, twod):
     assert a["t"] == c["t"]
     inner = c["U"][:, 2:ny + 2, 2:nx + 2] if twod else c["U"][:, :, 2:nx + 2]
     assert np.array_equal(a["U"], inner)
+
+
+# ------------------------------------------------ forced source (section 3)
+
+RESULTS_UNSTABLE = dict(gamma=1.4, R=1.0, Cv=0.1, rho0=1.0, T0=1.0, tau0=0.05, tau_rho=-1.0,
+                        tau_T=-1.5, Q0=10.0, Q_rho=0.0, Q_T=0.0, I0=10.0, I_rho=0.0, I_T=0.0,
+                        fx=0.0, fy=0.0)
+
+
+def _forced_wave(oracle_lib, gas, n, lam=0.1, amp=1e-4, t_end=0.85):
+    """Run a forced source at x = 0 (outflow at x = 1) from the uniform
+    background until the front is near x = 1; return the measured spatial
+    growth rate of the envelope, its value at x = 0 over the source amplitude,
+    the wavenumber and the phase offset phi of sin(omega t - Re k x + phi) from
+    the zero crossings, all over 0.1 < x < 0.7."""
+    P = oracle_lib.Problem(gas, n, 1, bc=(oracle_lib.BC_SOURCE, oracle_lib.BC_OUTFLOW, 0, 0),
+                           source=(amp, lam))
+    r = P.run(P.prim_to_cons(wl.uniform_state(gas, n)), 10 ** 7, t_end=t_end)
+    assert r["status"] == 0 and r["t"] == t_end
+    d = r["U"][0, 0] - gas["rho0"]
+    x = (np.arange(n) + 0.5) / n
+    m = int(round(lam * n))
+    cs, amps = [], []
+    for i0 in range(0, n - m, m // 2):
+        seg = d[i0:i0 + m]
+        cs.append(x[i0:i0 + m].mean())
+        amps.append(0.5 * (seg.max() - seg.min()))
+    cs, amps = np.array(cs), np.array(amps)
+    sel = (cs > 0.1) & (cs < 0.7)
+    rate, icpt = np.polyfit(cs[sel], np.log(amps[sel]), 1)
+    zc = [x[i] + (x[i + 1] - x[i]) * d[i] / (d[i] - d[i + 1])
+          for i in range(int(0.1 * n), int(0.7 * n)) if d[i] * d[i + 1] < 0]
+    zc = np.array(zc)
+    kre = math.pi / np.polyfit(np.arange(len(zc)), zc, 1)[0]
+    c = math.sqrt(gas["gamma"] * gas["R"] * gas["T0"])
+    om = c * 2 * math.pi / lam
+    k = D.spatial_k(gas, om)
+    ph = np.mod(k.real * zc - om * t_end, math.pi)
+    phi = float(np.angle(np.mean(np.exp(2j * ph))) / 2)
+    return rate, math.exp(icpt) / amp, kre, phi
+
+
+@pytest.mark.parametrize("case", ["unstable", "damped"])
+def test_forced_source_matches_signalling_dispersion(oracle_lib, case):
+    """A source of real frequency omega = c k0 (k0 = 2 pi / lambda, lambda =
+    0.1) launches a wave whose envelope grows or decays along x at -Im k and
+    whose wavenumber is Re k, k the right-going root of eq. (8) at that omega
+    (the paper's growth law exp(-Im k x)); its amplitude and phase at x = 0
+    are those the source's incoming characteristic transmits.  The error
+    shrinks with the grid."""
+    gas = RESULTS_UNSTABLE if case == "unstable" else dict(wl.BASE_GAS)
+    c = math.sqrt(gas["gamma"] * gas["R"] * gas["T0"])
+    om = c * 2 * math.pi / 0.1
+    k = D.spatial_k(gas, om)
+    T = D.source_transmission(gas, om)
+    assert (k.imag < 0) == (case == "unstable")
+    errs = []
+    for n in (1000, 2000):
+        rate, a0, kre, phi = _forced_wave(oracle_lib, gas, n)
+        errs.append(abs(rate + k.imag))
+    assert rate == pytest.approx(-k.imag, abs=0.06), (rate, k)
+    assert kre == pytest.approx(k.real, rel=3e-4), (kre, k)
+    assert a0 == pytest.approx(abs(T), abs=0.02), (a0, T)
+    # a ghost one cell off shifts phi by 2 pi / 200 = 0.031
+    assert phi == pytest.approx(-np.angle(T), abs=0.008), (phi, T)
+    assert errs[1] < errs[0]
+
+
+def test_forced_source_at_zero_amplitude_is_a_steady_inflow(oracle_lib):
+    """With zero amplitude the source's ghosts are the background itself: a
+    uniform background stays bitwise uniform (1D and planar 2D)."""
+    gas = RESULTS_UNSTABLE
+    for ny in (1, 6):
+        P = oracle_lib.Problem(gas, 64, ny, bc=(oracle_lib.BC_SOURCE, oracle_lib.BC_OUTFLOW,
+                                                 0, 0), source=(0.0, 0.1))
+        U0 = P.prim_to_cons(wl.uniform_state(gas, 64, ny))
+        r = P.run(U0, 40)
+        assert r["status"] == 0
+        assert np.array_equal(r["U"], U0)
+
+
+def test_forced_source_planar_in_two_d(oracle_lib):
+    """A planar source on a 2D grid periodic in y gives every row the 1D
+    solution bit for bit, and no transverse momentum."""
+    gas = RESULTS_UNSTABLE
+    n, ny = 200, 4
+    src = (1e-3, 0.1)
+    bc = (oracle_lib.BC_SOURCE, oracle_lib.BC_OUTFLOW, 0, 0)
+    P1 = oracle_lib.Problem(gas, n, 1, bc=bc, source=src)
+    P2 = oracle_lib.Problem(gas, n, ny, h=1.0 / n, bc=bc, source=src)
+    r1 = P1.run(P1.prim_to_cons(wl.uniform_state(gas, n)), 150)
+    r2 = P2.run(P2.prim_to_cons(wl.uniform_state(gas, n, ny)), 150)
+    assert r1["status"] == 0 and r2["status"] == 0 and r1["t"] == r2["t"]
+    for kk in range(ny):
+        for c, c1 in ((0, 0), (1, 1), (3, 3), (4, 4)):
+            assert np.array_equal(r2["U"][c, kk], r1["U"][c1, 0])
+    assert not np.any(r2["U"][2])
+
+
+def test_forced_source_phase_follows_time(oracle_lib):
+    """The source is a function of the time of the state each step starts
+    from: stepping a state stored at time t with the time passed equals the
+    same steps taken from t through or_run, and differs from taking them as
+    if the state were at t = 0."""
+    gas = RESULTS_UNSTABLE
+    n = 200
+    P = oracle_lib.Problem(gas, n, 1, bc=(oracle_lib.BC_SOURCE, oracle_lib.BC_OUTFLOW, 0, 0),
+                           source=(1e-3, 0.1))
+    U0 = P.prim_to_cons(wl.uniform_state(gas, n))
+    a = P.run(U0, 30)
+    b = P.run(a["U"], 10, t0=a["t"])
+    U, t = a["U"], a["t"]
+    for _ in range(10):
+        dt = P.dt(U)
+        st, U, _ = P.step(U, dt, t)
+        assert st == 0
+        t += dt
+    assert np.array_equal(U, b["U"]) and t == b["t"]
+    st, V, _ = P.step(a["U"], P.dt(a["U"]), 0.0)
+    assert not np.array_equal(V, P.step(a["U"], P.dt(a["U"]), a["t"])[1])
