@@ -56,6 +56,9 @@ extern "C" {
 #define NG_BC_WALL 1     /* reflecting wall: mirrored ghosts, normal momentum
                             negated (the solid walls of section 2.4)          */
 #define NG_BC_OUTFLOW 2  /* free outflow: ghosts copy the edge cell           */
+#define NG_BC_SOURCE 3   /* x-low end only: forced oscillations from a source
+                            (the 1D runs of section 3): the ghosts carry the
+                            plane sound wave of ng_grid.src_amp/src_lambda   */
 #define NG_HLLC 0        /* three-wave HLLC flux (contact resolved)            */
 #define NG_HLL 1         /* two-wave HLL flux, eq. (13)                         */
 #define NG_MINMOD 0      /* minmod-limited slopes in eq. (14)                   */
@@ -86,13 +89,25 @@ typedef struct {
 /* Uniform grid of square cells of size h (section 2.3): ndim = 1 (ny = 1) or
  * 2; bc[4] = (x-low, x-high, y-low, y-high) boundary kinds NG_BC_* (y ends
  * ignored in 1D).  Planes are addressed with 32-bit byte offsets: at most
- * 2^30 cells in FP32 and 2^29 in FP64 and NG_MIXED. */
+ * 2^30 cells in FP32 and 2^29 in FP64 and NG_MIXED.
+ *
+ * NG_BC_SOURCE (bc[0] only; bc[1] then must not be periodic): the two ghost
+ * cells x = -h/2, -3h/2 hold, at the time t of the state a step starts from,
+ * s = src_amp sin(omega t - k x) with k = 2 pi / src_lambda, omega = c k,
+ *   rho = rho_b + s, u = (c / rho_b) s, v = 0, p = p_b + c^2 s,
+ *   E_nu = E_nu,b + (E_nu,b / rho_b) s,
+ * about the steady background at the reference point of eq. (6) (rho_b =
+ * rho0, p_b = R rho0 T0, E_nu,b = rho0 Cv T0 + rho0 tau0 Q0, c = the frozen
+ * sound speed sqrt(gamma p_b / rho_b)): a sound wave of wavelength
+ * src_lambda entering the domain.  Requires src_lambda > 0 and |src_amp| <
+ * rho_b / 2; both are ignored for other kinds. */
 typedef struct {
     int32_t ndim;
     int32_t reserved;
     int64_t nx, ny;
     double h;
     int32_t bc[4];
+    double src_amp, src_lambda;
 } ng_grid;
 
 /* cfl multiplies the bound of eq. (16); stiff_z is the dt/tau above which the

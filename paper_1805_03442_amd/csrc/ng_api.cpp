@@ -136,10 +136,16 @@ int validate(const ng_gas* gas, const ng_grid* grid, const ng_numerics* num, std
     if (!finite_pos(grid->h)) { err = "h must be positive"; return NG_EINVAL; }
     for (int i = 0; i < (grid->ndim == 2 ? 4 : 2); i++)
         if (grid->bc[i] != NG_BC_PERIODIC && grid->bc[i] != NG_BC_WALL &&
-            grid->bc[i] != NG_BC_OUTFLOW) {
-            err = "unknown boundary kind";
+            grid->bc[i] != NG_BC_OUTFLOW && !(i == 0 && grid->bc[i] == NG_BC_SOURCE)) {
+            err = "unknown boundary kind (a source is allowed at the x-low end only)";
             return NG_EINVAL;
         }
+    if (grid->bc[0] == NG_BC_SOURCE &&
+        (!finite_pos(grid->src_lambda) || !isfinite(grid->src_amp) ||
+         !(fabs(grid->src_amp) < 0.5 * gas->rho0))) {
+        err = "source needs src_lambda > 0 and |src_amp| < rho0 / 2";
+        return NG_EINVAL;
+    }
     for (int a = 0; a < 2; a++)
         if ((grid->bc[2 * a] == NG_BC_PERIODIC) != (grid->bc[2 * a + 1] == NG_BC_PERIODIC) &&
             (a == 0 || grid->ndim == 2)) {
@@ -278,7 +284,7 @@ struct ng_solver {
 };
 
 static_assert(NG_BC_PERIODIC == ng::kBcPeriodic && NG_BC_WALL == ng::kBcWall &&
-                  NG_BC_OUTFLOW == ng::kBcOutflow,
+                  NG_BC_OUTFLOW == ng::kBcOutflow && NG_BC_SOURCE == ng::kBcSource,
               "boundary kinds of the ABI and the kernels");
 
 namespace {
@@ -687,6 +693,24 @@ void fill_desc(InstDesc& d, const ng_gas* gas, const ng_grid* grid, const ng_num
         if (d.bc[i] != NG_BC_PERIODIC) d.any_bc = 1;
     }
     d.h = grid->h;
+    if (d.bc[0] == NG_BC_SOURCE) {
+        // the forced wave's constants (the device evaluates the sine at each
+        // accepted time)
+        const double pi = 3.141592653589793;
+        const double rho_b = gas->rho0;
+        const double p_b = gas->R * gas->rho0 * gas->T0;
+        const double ev_b = gas->rho0 * gas->Cv * gas->T0 + gas->rho0 * gas->tau0 * gas->Q0;
+        const double c = sqrt(gas->gamma * p_b / rho_b);
+        d.src_amp = grid->src_amp;
+        d.src_k = 2.0 * pi / grid->src_lambda;
+        d.src_omega = c * d.src_k;
+        d.src_rho = rho_b;
+        d.src_p = p_b;
+        d.src_ev = ev_b;
+        d.src_uc = c / rho_b;
+        d.src_c2 = c * c;
+        d.src_er = ev_b / rho_b;
+    }
     d.cfl = num->cfl;
     d.stiff_z = num->stiff_z;
     d.gamma = gas->gamma;

@@ -24,6 +24,7 @@ constexpr int kMaxWaves = 8;       // waves per workgroup, upper bound
 constexpr int kBcPeriodic = 0;
 constexpr int kBcWall = 1;
 constexpr int kBcOutflow = 2;
+constexpr int kBcSource = 3;   // x-low only: forced sound wave in the ghosts
 
 // Run-constant description of one solve.
 struct InstDesc {
@@ -50,6 +51,11 @@ struct InstDesc {
     // reference state of the FP32 deviation storage (zero for FP64)
     double uref[5];           // (rho_r, 0, 0, E_r, Ev_r)
     double p_r, H_r, D_r;     // p_r, E_r + p_r, Cv/R p_r - Ev_r
+    // forced source at the x-low end: s = amp sin(omega t - k x) about the
+    // background (rho_b, 0, 0, p_b, E_nu,b); uc = c / rho_b, c2 = c^2,
+    // er = E_nu,b / rho_b
+    double src_amp, src_k, src_omega;
+    double src_rho, src_p, src_ev, src_uc, src_c2, src_er;
 };
 
 // Mutable per-solve state, advanced by the finalize kernel.
@@ -69,6 +75,8 @@ struct InstCtrl {
     double rho_min, p_min, smax;
     uint32_t arrive;          // workgroups of the current step that have finished
     uint32_t pad;
+    double src_ghost[2][5];   // forced source: full conserved state of the ghosts
+                              // x = -h/2, -3h/2 at time t (set with t)
 };
 
 // One workgroup's reduction record of a step (or of the priming pass).

@@ -95,7 +95,7 @@ __device__ __forceinline__ int64_t axis_cell(int64_t j, int64_t n, int lo, int h
     if (j >= 0 && j < n) return j;
     const int bc = j < 0 ? lo : hi;
     if (bc == kBcPeriodic) return wrap_axis(j, n);
-    if (bc == kBcOutflow) return j < 0 ? 0 : n - 1;
+    if (bc == kBcOutflow || bc == kBcSource) return j < 0 ? 0 : n - 1;
     flip = true;
     const int64_t m = j < 0 ? -1 - j : 2 * n - 1 - j;
     return m < 0 ? 0 : (m >= n ? n - 1 : m);
@@ -389,6 +389,7 @@ struct StepCtl {
     double dt;
     int cur;
     bool active;
+    const double* gsrc;   // forced source: ghost states at the step's start time
 };
 
 __device__ __forceinline__ StepCtl read_ctl(const InstCtrl& c)
@@ -400,7 +401,19 @@ __device__ __forceinline__ StepCtl read_ctl(const InstCtrl& c)
     if (t + dt > t_end) dt = t_end - t;
     s.dt = dt;
     s.cur = c.cur;
+    s.gsrc = &c.src_ghost[0][0];
     return s;
+}
+
+// A forced-source ghost in the stored form: the full FP64 conserved state
+// (5 components; the 1D planes skip rho v) minus the reference (zero in FP64).
+template <class St, int NC>
+__device__ __forceinline__ void source_cell(const InstDesc& d, const double* g, St* U)
+{
+    for (int c = 0; c < NC; c++) {
+        const int q = NC == 5 ? c : (c < 2 ? c : c + 1);
+        U[c] = (St)(g[q] - d.uref[q]);
+    }
 }
 
 template <class R, int NC>
@@ -422,6 +435,28 @@ __device__ __forceinline__ void load_cell_cached(const R* __restrict__ base, int
 // flags to a solve: reject (sticky NG_EPHYS, buffers not swapped) or accept
 // (swap buffers, advance t, next dt from eq. (16)).  mode 1: priming (no step
 // taken, only the totals and the first dt).
+// Ghost states of a forced source at the x-low end for the time c.t: the
+// plane sound wave s = a sin(omega t - k x) at x = -h/2 and -3h/2 about the
+// background (section 3's forced oscillations), as conserved FP64 values
+// (eq. (5)).
+__device__ __noinline__ void source_ghosts(const InstDesc& d, InstCtrl& c)
+{
+    for (int g = 0; g < 2; g++) {
+        const double x = ((double)(-1 - g) + 0.5) * d.h;
+        const double s = d.src_amp * sin(d.src_omega * c.t - d.src_k * x);
+        const double rho = d.src_rho + s;
+        const double u = d.src_uc * s;
+        const double v = 0.0;
+        const double p = d.src_p + d.src_c2 * s;
+        const double e = d.src_ev + d.src_er * s;
+        c.src_ghost[g][0] = rho;
+        c.src_ghost[g][1] = rho * u;
+        c.src_ghost[g][2] = rho * v;
+        c.src_ghost[g][3] = p / d.gm1 + 0.5 * rho * (u * u + v * v) + e;
+        c.src_ghost[g][4] = e;
+    }
+}
+
 __device__ void accept_step(const InstDesc& d, InstCtrl& c, const StepCtl& sc, const double* v,
                             uint32_t flags, int mode)
 {
@@ -446,6 +481,7 @@ __device__ void accept_step(const InstDesc& d, InstCtrl& c, const StepCtl& sc, c
     c.p_min = v[9];
     c.dt_cfl = d.cfl * d.h / v[7];
     c.flags = 0u;
+    if (d.bc[0] == kBcSource) source_ghosts(d, c);
 }
 
 // ================================================================ finalize
@@ -601,7 +637,8 @@ __device__ __forceinline__ void flux_y(const typename P::K& k, const typename P:
 // One work item of the 2D step: strip (60 columns + halo) x chunk of rows.
 template <class P, int RS, bool BC>
 __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& k, int cur,
-                                        int64_t item, int lane, Acc<typename P::R>& acc)
+                                        const double* gsrc, int64_t item, int lane,
+                                        Acc<typename P::R>& acc)
 {
     using R = typename P::R;
     constexpr int NC = 5;
@@ -628,12 +665,17 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
         }
         return (uint32_t)((rr * nx + x) * (int64_t)sizeof(St));
     };
-    // a loaded row r as ghost values: wall ghosts carry the mirrored normal
-    // momentum (x ends: rho u, y ends: rho v)
+    // a loaded row r as ghost values: the lanes before a forced source take
+    // its wave, wall ghosts carry the mirrored normal momentum (x ends: rho u,
+    // y ends: rho v)
+    const int64_t xr = x0 - kHalo + lane;
+    const bool srcx = BC && d.bc[0] == kBcSource && xr < 0;
+    const double* gs = gsrc + (xr == -1 ? 0 : 5);
     auto ghost = [&](int64_t r, St* U) {
         if (BC) {
             bool fy;
             (void)axis_cell(r, ny, d.bc[2], d.bc[3], fy);
+            if (srcx) source_cell<St, NC>(d, gs, U);
             if (flipx) U[1] = -U[1];
             if (fy) U[2] = -U[2];
         }
@@ -789,12 +831,13 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
 // outflow end the ghost mapping (a uniform choice per solve)
 template <class P, int RS>
 __device__ __forceinline__ void march2d_bc(const InstDesc& d, const typename P::K& k, int cur,
-                                           int64_t item, int lane, Acc<typename P::R>& acc)
+                                           const double* gsrc, int64_t item, int lane,
+                                           Acc<typename P::R>& acc)
 {
     if (d.any_bc)
-        march2d<P, RS, true>(d, k, cur, item, lane, acc);
+        march2d<P, RS, true>(d, k, cur, gsrc, item, lane, acc);
     else
-        march2d<P, RS, false>(d, k, cur, item, lane, acc);
+        march2d<P, RS, false>(d, k, cur, gsrc, item, lane, acc);
 }
 
 template <class P>
@@ -818,9 +861,9 @@ __global__ void __launch_bounds__(256, P::kMinWaves) step2d_kernel(const InstDes
     const int64_t item = (int64_t)br.local * nwaves + wave;
     if (item < d.nitems) {
         if (d.riemann == 1)
-            march2d_bc<P, 1>(d, k, sc.cur, item, lane, acc);
+            march2d_bc<P, 1>(d, k, sc.cur, sc.gsrc, item, lane, acc);
         else
-            march2d_bc<P, 0>(d, k, sc.cur, item, lane, acc);
+            march2d_bc<P, 0>(d, k, sc.cur, sc.gsrc, item, lane, acc);
     }
     Partial* parts = (Partial*)d.partials;
     block_reduce_store(acc, parts + br.local, wave, lane, nwaves);
@@ -832,7 +875,8 @@ __global__ void __launch_bounds__(256, P::kMinWaves) step2d_kernel(const InstDes
 // One work item of the 1D step: a group of consecutive 60-cell segments.
 template <class P, int RS, bool BC>
 __device__ __forceinline__ void march1d(const InstDesc& d, const typename P::K& k, int cur,
-                                        int64_t item, int lane, Acc<typename P::R>& acc)
+                                        const double* gsrc, int64_t item, int lane,
+                                        Acc<typename P::R>& acc)
 {
     using R = typename P::R;
     constexpr int NC = 4;
@@ -855,9 +899,12 @@ __device__ __forceinline__ void march1d(const InstDesc& d, const typename P::K& 
         const uint32_t o = boff(sg);
         if (sg + 1 < s1) src.load(boff(sg + 1), Ux);
         if (BC) {
-            // wall ghosts carry the mirrored momentum
+            // the lanes before a forced source take its wave; wall ghosts
+            // carry the mirrored momentum
             bool f;
-            (void)axis_cell(sg * kInterior - kHalo + lane, n, d.bc[0], d.bc[1], f);
+            const int64_t xr = sg * kInterior - kHalo + lane;
+            (void)axis_cell(xr, n, d.bc[0], d.bc[1], f);
+            if (d.bc[0] == kBcSource && xr < 0) source_cell<St, NC>(d, gsrc + (xr == -1 ? 0 : 5), Uc);
             if (f) Uc[1] = -Uc[1];
         }
         P::prim(k, Uc, W);
@@ -901,12 +948,13 @@ __device__ __forceinline__ void march1d(const InstDesc& d, const typename P::K& 
 
 template <class P, int RS>
 __device__ __forceinline__ void march1d_bc(const InstDesc& d, const typename P::K& k, int cur,
+                                           const double* gsrc,
                                            int64_t item, int lane, Acc<typename P::R>& acc)
 {
     if (d.any_bc)
-        march1d<P, RS, true>(d, k, cur, item, lane, acc);
+        march1d<P, RS, true>(d, k, cur, gsrc, item, lane, acc);
     else
-        march1d<P, RS, false>(d, k, cur, item, lane, acc);
+        march1d<P, RS, false>(d, k, cur, gsrc, item, lane, acc);
 }
 
 template <class P>
@@ -930,9 +978,9 @@ __global__ void __launch_bounds__(256) step1d_kernel(const InstDesc* __restrict_
     const int64_t item = (int64_t)br.local * nwaves + wave;
     if (item < d.nitems) {
         if (d.riemann == 1)
-            march1d_bc<P, 1>(d, k, sc.cur, item, lane, acc);
+            march1d_bc<P, 1>(d, k, sc.cur, sc.gsrc, item, lane, acc);
         else
-            march1d_bc<P, 0>(d, k, sc.cur, item, lane, acc);
+            march1d_bc<P, 0>(d, k, sc.cur, sc.gsrc, item, lane, acc);
     }
     Partial* parts = (Partial*)d.partials;
     block_reduce_store(acc, parts + br.local, wave, lane, nwaves);
@@ -1040,14 +1088,14 @@ __global__ void __launch_bounds__(512) run_small_kernel(const InstDesc* __restri
         for (int64_t item = wave; item < d.nitems; item += nw) {
             if constexpr (NC == 5) {
                 if (d.riemann == 1)
-                    march2d_bc<P, 1>(d, k, sc.cur, item, lane, acc);
+                    march2d_bc<P, 1>(d, k, sc.cur, sc.gsrc, item, lane, acc);
                 else
-                    march2d_bc<P, 0>(d, k, sc.cur, item, lane, acc);
+                    march2d_bc<P, 0>(d, k, sc.cur, sc.gsrc, item, lane, acc);
             } else {
                 if (d.riemann == 1)
-                    march1d_bc<P, 1>(d, k, sc.cur, item, lane, acc);
+                    march1d_bc<P, 1>(d, k, sc.cur, sc.gsrc, item, lane, acc);
                 else
-                    march1d_bc<P, 0>(d, k, sc.cur, item, lane, acc);
+                    march1d_bc<P, 0>(d, k, sc.cur, sc.gsrc, item, lane, acc);
             }
         }
         uint32_t flags = acc_flags(acc);

@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "libng.so")
 
 NG_OK, NG_EINVAL, NG_ENOMEM, NG_EPHYS, NG_EDEVICE, NG_EFULL = 0, -1, -2, -3, -4, -5
-NG_BC_PERIODIC, NG_BC_WALL, NG_BC_OUTFLOW = 0, 1, 2
+NG_BC_PERIODIC, NG_BC_WALL, NG_BC_OUTFLOW, NG_BC_SOURCE = 0, 1, 2, 3
 NG_HLLC, NG_HLL = 0, 1
 NG_MINMOD = 0
 NG_FP64, NG_FP32, NG_MIXED = 0, 1, 2
@@ -45,7 +45,8 @@ class NgGas(C.Structure):
 
 class NgGrid(C.Structure):
     _fields_ = [("ndim", C.c_int32), ("reserved", C.c_int32), ("nx", C.c_int64),
-                ("ny", C.c_int64), ("h", C.c_double), ("bc", C.c_int32 * 4)]
+                ("ny", C.c_int64), ("h", C.c_double), ("bc", C.c_int32 * 4),
+                ("src_amp", C.c_double), ("src_lambda", C.c_double)]
 
 
 class NgNumerics(C.Structure):
@@ -136,11 +137,14 @@ def make_gas(g: dict) -> NgGas:
     return NgGas(*[float(g.get(f, 0.0)) for f in GAS_FIELDS])
 
 
-def make_grid(nx: int, ny: int = 1, h: float | None = None, bc=(NG_BC_PERIODIC,) * 4) -> NgGrid:
-    """bc = (x-low, x-high, y-low, y-high) boundary kinds."""
+def make_grid(nx: int, ny: int = 1, h: float | None = None, bc=(NG_BC_PERIODIC,) * 4,
+              source=(0.0, 0.0)) -> NgGrid:
+    """bc = (x-low, x-high, y-low, y-high) boundary kinds; source = (amplitude,
+    wavelength) of the forced wave of an NG_BC_SOURCE x-low end."""
     ndim = 1 if ny == 1 else 2
     h = float(h) if h is not None else 1.0 / nx
-    return NgGrid(ndim, 0, int(nx), int(ny), h, (C.c_int32 * 4)(*[int(b) for b in bc]))
+    return NgGrid(ndim, 0, int(nx), int(ny), h, (C.c_int32 * 4)(*[int(b) for b in bc]),
+                  float(source[0]), float(source[1]))
 
 
 def make_numerics(cfl=0.4, riemann=NG_HLLC, precision=NG_FP64, stiff_z=0.5) -> NgNumerics:
@@ -197,11 +201,11 @@ class Solver:
 
     def __init__(self, gas: dict, nx: int, ny: int = 1, W=None, U=None, h=None, cfl=0.4,
                  riemann=NG_HLLC, precision=NG_FP64, stiff_z=0.5, t0=0.0, stream=None,
-                 bc=(NG_BC_PERIODIC,) * 4):
+                 bc=(NG_BC_PERIODIC,) * 4, source=(0.0, 0.0)):
         L = lib()
         self.nx, self.ny = int(nx), int(ny)
         self.gas = make_gas(gas)
-        self.grid = make_grid(nx, ny, h, bc)
+        self.grid = make_grid(nx, ny, h, bc, source)
         self.num = make_numerics(cfl, riemann, precision, stiff_z)
         nbytes = C.c_size_t(0)
         check(L.ng_state_bytes(C.byref(self.grid), C.byref(self.num), C.byref(nbytes)),
@@ -316,9 +320,10 @@ class Batch:
         return bool(f.value)
 
     def add(self, gas: dict, nx: int, ny: int, W, t_end: float, max_steps: int = 2**62,
-            h=None, cfl=0.4, riemann=NG_HLLC, stiff_z=0.5, t0=0.0, bc=(NG_BC_PERIODIC,) * 4):
+            h=None, cfl=0.4, riemann=NG_HLLC, stiff_z=0.5, t0=0.0, bc=(NG_BC_PERIODIC,) * 4,
+            source=(0.0, 0.0)):
         """Returns the slot, or None when the batch is full (NG_EFULL)."""
-        g, gr = make_gas(gas), make_grid(nx, ny, h, bc)
+        g, gr = make_gas(gas), make_grid(nx, ny, h, bc, source)
         nm = make_numerics(cfl, riemann, self.precision, stiff_z)
         arr = _planes(W, ny)
         slot = C.c_int32(-1)

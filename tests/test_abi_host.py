@@ -40,7 +40,7 @@ def test_struct_sizes_match_header(ng):
     # the ctypes mirrors must have the C layout (checked through the sizes the
     # library itself reports for a known grid)
     assert C.sizeof(ng.NgGas) == 16 * 8
-    assert C.sizeof(ng.NgGrid) == 4 + 4 + 8 + 8 + 8 + 16
+    assert C.sizeof(ng.NgGrid) == 4 + 4 + 8 + 8 + 8 + 16 + 16
     assert C.sizeof(ng.NgNumerics) == 8 + 4 * 4 + 8
 
 
@@ -59,8 +59,10 @@ def test_state_bytes(ng):
 
 @pytest.mark.parametrize("field,value", [("gamma", 1.0), ("tau0", 0.0), ("R", -1.0),
                                          ("cfl", 1.5), ("nx", 3), ("riemann", 7),
-                                         ("fy_1d", 0.1), ("precision", 5), ("bc", (3, 3)),
-                                         ("bc", (0, 1)), ("huge", 1 << 30)])
+                                         ("fy_1d", 0.1), ("precision", 5), ("bc", (4, 2)),
+                                         ("bc", (0, 1)), ("bc", (2, 3)), ("bc", (3, 0)),
+                                         ("source", (0.0, 0.1)), ("source", (0.6, 0.1)),
+                                         ("huge", 1 << 30)])
 def test_invalid_arguments_rejected_before_device_use(ng, field, value):
     import numpy as np
     from paper_1805_03442_amd import workloads as wl
@@ -81,9 +83,14 @@ def test_invalid_arguments_rejected_before_device_use(ng, field, value):
     elif field == "precision":
         prec = value
     bc = (0, 0, 0, 0)
+    source = (0.0, 0.0)
     if field == "bc":
         bc = tuple(value) + (0, 0)
-    grid = ng.make_grid(nx, ny, bc=bc)
+    if field == "source":
+        # a source end with a zero wavelength, or an amplitude of rho0 / 2 or more
+        bc = (3, 2, 0, 0)
+        source = (value[1], value[0]) if value[0] == 0.0 else value
+    grid = ng.make_grid(nx, ny, bc=bc, source=source)
     if field == "huge":
         # 2^30 cells of FP64: byte offsets beyond 32 bits (the state is never read)
         grid = ng.make_grid(value, 1)

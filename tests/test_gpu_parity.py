@@ -58,15 +58,15 @@ def comps(ny):
 
 
 def run_both(ng, gas, W, nx, ny, steps, precision, riemann=0, stiff_z=0.5, launch=None,
-             t_end=None, small_limit=None, bc=(0, 0, 0, 0)):
+             t_end=None, small_limit=None, bc=(0, 0, 0, 0), source=(0.0, 0.0)):
     import oracle
     oracle.build()
-    P = oracle.Problem(gas, nx, ny, riemann=riemann, stiff_z=stiff_z, bc=bc)
+    P = oracle.Problem(gas, nx, ny, riemann=riemann, stiff_z=stiff_z, bc=bc, source=source)
     U0 = P.prim_to_cons(W)
     say(f"case nx={nx} ny={ny} steps={steps} prec={precision} riemann={riemann} launch={launch} "
-        f"bc={bc} small_limit={small_limit}")
+        f"bc={bc} source={source} small_limit={small_limit}")
     s = ng.Solver(gas, nx, ny, U=U0, precision=precision, riemann=riemann, stiff_z=stiff_z,
-                  bc=bc)
+                  bc=bc, source=source)
     if small_limit is not None:
         s.set_small_limit(small_limit)
     if launch:
@@ -509,4 +509,89 @@ def test_unphysical_initial_state_rejected(ng, bad):
         b.add(gas, 128, 1, W, t_end=0.1)
     assert err.value.code == ng.NG_EINVAL
     assert b.fits(128, 1)       # the refused solve left nothing behind
+    b.close()
+
+
+# ------------------------------------------- forced source end (section 3)
+
+SRC_GAS = dict(gamma=1.4, R=1.0, Cv=0.1, rho0=1.0, T0=1.0, tau0=0.05, tau_rho=-1.0,
+               tau_T=-1.5, Q0=10.0, Q_rho=0.0, Q_T=0.0, I0=10.0, I_rho=0.0, I_T=0.0,
+               fx=0.0, fy=0.0)
+
+
+@pytest.mark.parametrize("path", ["persistent", "per_step"])
+def test_forced_source_1d(ng, path):
+    """The acoustically unstable set driven by a source at x = 0 (outflow at
+    x = 1), on the persistent small-solve kernel and on the per-step kernels.
+    FP64 within 1e-12 of the oracle (the device sine of the source may differ
+    from libm's in the last bit); FP32 and mixed within 1e-5 relative L1."""
+    n, steps = 500, 400
+    W = wl.uniform_state(SRC_GAS, n)
+    small = None if path == "persistent" else 0
+    for prec in (ng.NG_FP64, ng.NG_FP32, ng.NG_MIXED):
+        for riemann in ((0, 1) if prec == ng.NG_FP64 else (0,)):
+            U, ref, d, U0 = run_both(ng, SRC_GAS, W, n, 1, steps, prec, riemann,
+                                     small_limit=small, bc=(3, 2, 0, 0), source=(1e-3, 0.1))
+            assert d["status"] == 0 and d["steps"] == steps
+            c = comps(1)
+            if prec == ng.NG_FP64:
+                e = rel_linf(U[c], ref["U"][c])
+                say(f"source 1d {path} fp64 riemann={riemann} rel_linf {e}")
+                assert np.all(e <= FP64_TOL), e
+                assert d["t"] == pytest.approx(ref["t"], rel=1e-13)
+            else:
+                e = rel_l1(U[c], ref["U"][c])
+                ep = rel_l1(U[c] - U0[c], ref["U"][c] - U0[c])
+                say(f"source 1d {path} prec={prec} rel_l1 {e} perturbation {ep}")
+                assert np.all(e <= FP32_TOL), e
+    # the wave has entered: the density perturbation reaches about c t
+    dr = ref["U"][0, 0] - SRC_GAS["rho0"]
+    front = np.nonzero(np.abs(dr) > 1e-5)[0].max() / n
+    assert 0.25 < front < 0.4, front
+
+
+@pytest.mark.parametrize("bc", [(3, 2, 0, 0), (3, 1, 1, 2)])
+def test_forced_source_2d(ng, bc):
+    """A planar source on a ragged 2D grid (periodic, or wall and outflow in
+    y) with a perturbed interior, against the oracle."""
+    nx, ny = 130, 70
+    r = np.random.Generator(np.random.PCG64(21))
+    W = wl.random_field_2d(SRC_GAS, 130, r, kmax=6, rms=1e-3)[:, :ny, :nx].copy()
+    for prec in (ng.NG_FP64, ng.NG_FP32):
+        U, ref, d, U0 = run_both(ng, SRC_GAS, W, nx, ny, 120, prec, bc=bc, source=(2e-3, 0.1),
+                                 small_limit=0)
+        assert d["status"] == 0
+        if prec == ng.NG_FP64:
+            e = rel_linf(U, ref["U"])
+            say(f"source 2d {bc} fp64 rel_linf {e}")
+            assert np.all(e <= FP64_TOL), e
+        else:
+            e = rel_l1(U, ref["U"])
+            say(f"source 2d {bc} fp32 rel_l1 {e}")
+            assert np.all(e <= FP32_TOL), e
+
+
+def test_forced_source_in_a_batch_equals_alone(ng):
+    """A source solve advanced in a batch beside periodic solves gives the same
+    bits as alone."""
+    n = 300
+    W = wl.uniform_state(SRC_GAS, n)
+    src = (1e-3, 0.1)
+    alone = ng.Solver(SRC_GAS, n, 1, W=W, precision=ng.NG_FP32, bc=(3, 2, 0, 0), source=src)
+    alone.set_small_limit(0)
+    alone.step(150)
+    Ua = alone.conserved()
+    alone.close()
+    w = wl.workload_1d_acoustic()
+    b = ng.Batch(4, 64 << 20, precision=ng.NG_FP32)
+    b.set_small_limit(0)
+    sl = [b.add(w["gas"], 1024, 1, w["W"], t_end=1e30, max_steps=150),
+          b.add(SRC_GAS, n, 1, W, t_end=1e30, max_steps=150, bc=(3, 2, 0, 0), source=src),
+          b.add(w["gas"], 1024, 1, w["W"], t_end=1e30, max_steps=150)]
+    for _ in range(20):
+        b.run(50)
+        if b.active() == 0:
+            break
+    assert b.active() == 0
+    assert np.array_equal(b.conserved(sl[1]), Ua)
     b.close()
