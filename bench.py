@@ -32,6 +32,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -126,6 +127,8 @@ def main():
     ap.add_argument("--accuracy-steps", type=int, default=100)
     ap.add_argument("--bounded-steps", type=int, default=200)
     ap.add_argument("--steps-1d", type=int, default=20000)
+    ap.add_argument("--no-source-runs", action="store_true",
+                    help="skip the forced-source runs of section 3")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain device copy of known size (for counter scaling)")
     args = ap.parse_args()
@@ -264,6 +267,47 @@ def main():
                                "unit": "cell-updates/s", "step_kernel_ms": rb["step_ms"],
                                "hbm_frac": BYTES_PER_CELL_FP32 * cells / (rb["step_ms"] * 1e-3)
                                / 1e9 / HBM_PEAK_GBS}
+
+    if not args.no_source_runs:
+        # section 3's 1D runs: sound from a source at x = 0 into the unstable
+        # medium to t = 0.8 (linear stage S = 0.5, N = 800; shock train S = 1,
+        # N = 1600), each precision to the end, and the FP32 / mixed error of
+        # the final perturbation against FP64
+        res = {}
+        for stage in ("linear", "nonlinear"):
+            ws = wl.workload_forced_source(stage)
+            fin, rec = {}, {}
+            for name, prec in (("fp64", ng.NG_FP64), ("fp32", ng.NG_FP32),
+                               ("mixed", ng.NG_MIXED)):
+                s = ng.Solver(ws["gas"], ws["nx"], 1, W=ws["W"], precision=prec, bc=ws["bc"],
+                              source=ws["source"])
+                if prec == ng.NG_FP64:
+                    Ub = s.conserved()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                taken = s.run_to_time(ws["t_end"])
+                el = time.perf_counter() - t0
+                fin[name] = s.conserved()
+                d = s.diagnostics()
+                s.close()
+                assert d["status"] == 0
+                rec[name] = {"steps": taken, "wall_ms": 1e3 * el,
+                             "cell_updates_per_s": ws["nx"] * taken / el}
+            W64 = fin["fp64"]
+            rho = W64[0, 0]
+            u = W64[1, 0] / rho
+            jumps = np.abs(np.diff(rho))
+            amp = ws["source"][0]
+            smooth = amp * 2 * math.pi / ws["source"][1] / ws["nx"]
+            for name in ("fp32", "mixed"):
+                rec[name]["rel_l1_of_perturbation_vs_fp64"] = max(
+                    float(np.abs(fin[name][c] - W64[c]).sum() / np.abs(W64[c] - Ub[c]).sum())
+                    for c in (0, 1, 3, 4))
+            res[stage] = dict(rec, workload=ws["name"], t_end=ws["t_end"],
+                              max_abs_u=float(np.abs(u).max()),
+                              shock_faces=int((jumps > 5 * smooth).sum()))
+            log(f"[bench] forced source {stage}: {res[stage]}")
+        out["forced_source_1d"] = res
 
     if not args.no_fp64:
         # error of the FP32 result against the FP64 path after the same steps

@@ -168,6 +168,17 @@ def blast_waves_1d(n: int) -> np.ndarray:
     return W
 
 
+def results_gas(S: float, tau0: float = 1.0) -> dict:
+    """Gas of the runs of section 3: gamma = 1.4, C_k = Cv / R = 0.1, tau_rho
+    = -1, tau_T = -1.5, Q and I exponents 0, rho0 = p0 = 1 and tau0 = 1 (the
+    units), and the degree of non-equilibrium S = tau0 Q0 / (R T0) through
+    Q0 = I0 = S R T0 / tau0 (pump and sink balance on the background)."""
+    q = S / tau0
+    return dict(gamma=1.4, R=1.0, Cv=0.1, rho0=1.0, T0=1.0, tau0=tau0, tau_rho=-1.0,
+                tau_T=-1.5, Q0=q, Q_rho=0.0, Q_T=0.0, I0=q, I_rho=0.0, I_T=0.0,
+                fx=0.0, fy=0.0)
+
+
 # ------------------------------------------------------------------ workloads
 
 def workload_1d_acoustic():
@@ -195,6 +206,22 @@ def workload_2d_random(n: int = 4096):
     W = random_field_2d(gas, n, rng(3))
     return dict(name=f"2d_random_{n}x{n}", gas=gas, W=W, nx=n, ny=n, steps=5000,
                 precision="fp32")
+
+
+def workload_forced_source(stage: str = "nonlinear"):
+    """The 1D runs of section 3: a source at x = 0 emits sound of wavelength
+    0.1 into the uniform background (free outflow at x = 1), t = 0.8.  Linear
+    stage: S = 0.5, N = 800; nonlinear stage: S = 1, N = 1600.  The paper
+    states no source amplitude; the readings are 1e-3 (linear) and 3e-2
+    (nonlinear: a simple wave of that amplitude steepens into shocks within
+    about 0.4 of travel, so the domain holds a shock train by t = 0.8)."""
+    if stage == "linear":
+        S, n, amp = 0.5, 800, 1e-3
+    else:
+        S, n, amp = 1.0, 1600, 3e-2
+    gas = results_gas(S)
+    return dict(name=f"forced_source_{stage}_S{S:g}_n{n}", gas=gas, W=uniform_state(gas, n),
+                nx=n, ny=1, bc=(3, 2, 0, 0), source=(amp, 0.1), t_end=0.8)
 
 
 def batch_1d_instances(count: int = 512, nmin_log2: float = 10.0, nmax_log2: float = 16.0,
