@@ -209,11 +209,13 @@ int ng_set_small_limit(ng_solver* s, int64_t max_cells);
 int ng_set_fused_accept(ng_solver* s, int32_t on);
 
 /* Kernel timing: ng_enable_timing(s, nsteps) with nsteps > 0 makes later
- * ng_step calls launch each step directly with HIP events on the solver's
- * stream around the step and finalize kernels (events for nsteps steps are
- * created here, outside any timed region); 0 turns it off.  ng_kernel_time
- * returns the mean durations in milliseconds over the last timed ng_step call
- * and the number of step launches timed. */
+ * ng_step calls launch each step directly (no graph), each step and finalize
+ * kernel recording its own start and end in HIP events (the launch carries
+ * the events, so no event packets sit between the kernels); the events for
+ * nsteps steps are created here, outside any timed region; 0 turns it off.
+ * ng_kernel_time returns the mean kernel durations in milliseconds over the
+ * last timed ng_step call (finalize_ms 0 when the step kernel accepted its own
+ * steps) and the number of step launches timed. */
 int ng_enable_timing(ng_solver* s, int32_t nsteps);
 int ng_kernel_time(ng_solver* s, double* step_ms, double* finalize_ms, int64_t* launches);
 

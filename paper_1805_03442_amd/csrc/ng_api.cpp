@@ -480,8 +480,9 @@ int enqueue_small(ng_batch* b, int64_t nsteps, hipStream_t st)
 bool any_big(const ng_batch* b) { return b->ninst[1] + b->ninst[2] > 0; }
 bool any_small(const ng_batch* b) { return b->nsmall[1] + b->nsmall[2] > 0; }
 
-// Timed variant: events around each step and finalize kernel (big solves), or
-// around the persistent launch (small solves; reported per step).
+// Timed variant: each step and finalize kernel (big solves) records its own
+// start and end in events of the pool (no event packets between launches), or
+// events around the persistent launch (small solves; reported per step).
 int enqueue_timed(ng_batch* b, int64_t nsteps)
 {
     size_t ne = 0;
@@ -503,20 +504,19 @@ int enqueue_timed(ng_batch* b, int64_t nsteps)
     for (int64_t i = 0; i < nsteps && any_big(b); i++) {
         for (int dim = 1; dim <= 2; dim++) {
             if (!b->ninst[dim]) continue;
-            hipEvent_t e0 = get_event(b, ne), e1 = get_event(b, ne + 1), e2 = get_event(b, ne + 2);
-            if (!e0 || !e1 || !e2) return dev_err(b, hipErrorOutOfMemory, "hipEventCreate");
-            CK(b, hipEventRecord(e0, b->stream));
+            hipEvent_t e0 = get_event(b, ne), e1 = get_event(b, ne + 1), e2 = get_event(b, ne + 2),
+                       e3 = get_event(b, ne + 3);
+            if (!e0 || !e1 || !e2 || !e3) return dev_err(b, hipErrorOutOfMemory, "hipEventCreate");
             CK(b, launch_step(dim, kind_of(b->prec), b->d_descs(), b->d_ctrls(),
                               b->d_blocks(dim), b->nblocks[dim], b->waves[dim], b->remap,
-                              b->fused, b->stream));
-            CK(b, hipEventRecord(e1, b->stream));
-            if (b->nsep[dim])
-                CK(b, launch_finalize(b->d_descs(), b->d_ctrls(), b->d_insts(dim), b->ninst[dim],
-                                      0, b->stream));
-            CK(b, hipEventRecord(e2, b->stream));
+                              b->fused, b->stream, e0, e1));
             step_pairs.push_back({ne, ne + 1});
-            fin_pairs.push_back({ne + 1, ne + 2});
-            ne += 3;
+            if (b->nsep[dim]) {
+                CK(b, launch_finalize(b->d_descs(), b->d_ctrls(), b->d_insts(dim), b->ninst[dim],
+                                      0, b->stream, e2, e3));
+                fin_pairs.push_back({ne + 2, ne + 3});
+            }
+            ne += 4;
         }
     }
     CK(b, hipStreamSynchronize(b->stream));
@@ -533,7 +533,7 @@ int enqueue_timed(ng_batch* b, int64_t nsteps)
     }
     if (!step_pairs.empty()) {
         b->t_step_ms = ts / step_pairs.size();
-        b->t_fin_ms = tf / fin_pairs.size();
+        b->t_fin_ms = fin_pairs.empty() ? 0.0 : tf / fin_pairs.size();
         b->t_launches = (int64_t)step_pairs.size();
     } else {
         b->t_step_ms = nsteps > 0 ? small_ms / nsteps : 0.0;
@@ -1206,7 +1206,7 @@ int ng_enable_timing(ng_solver* s, int32_t nsteps)
 {
     if (!s || nsteps < 0) return NG_EINVAL;
     s->b->timing = nsteps != 0;
-    size_t need = (size_t)nsteps * 3 * 2;
+    size_t need = (size_t)nsteps * 4 * 2;   // 4 per step and dimension
     if (need && !get_event(s->b, need - 1)) return solver_rc(s, dev_err(s->b, hipErrorOutOfMemory, "hipEventCreate"));
     return NG_OK;
 }

@@ -22,6 +22,7 @@
 // The finalize kernel (one workgroup per solve) folds those records in a fixed
 // order, accepts or rejects the step, advances t and computes the next dt.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <math.h>
 #include <stdint.h>
 
@@ -1137,26 +1138,40 @@ __global__ void __launch_bounds__(512) run_small_kernel(const InstDesc* __restri
 
 static inline bool grid_ok(int64_t nblocks) { return nblocks > 0 && nblocks < (1LL << 31); }
 
+// Launch on s; with events, through the AMD extension that records the
+// kernel's own start and end in them (no separate event packets on the
+// stream, so timing adds no gaps between launches).  Untimed launches use the
+// plain form, which stream capture records as a kernel node.
+template <class... A>
+static void launch(void (*kernel)(A...), dim3 g, dim3 b, hipStream_t s, hipEvent_t e0,
+                   hipEvent_t e1, A... a)
+{
+    if (e0 || e1)
+        hipExtLaunchKernelGGL(kernel, g, b, 0, s, e0, e1, 0, a...);
+    else
+        hipLaunchKernelGGL(kernel, g, b, 0, s, a...);
+}
+
 hipError_t launch_step(int dim, int prec, const InstDesc* descs, InstCtrl* ctrls,
                        const BlockRef* blocks, int64_t nblocks, int waves, int remap, int fused,
-                       hipStream_t s)
+                       hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     if (!grid_ok(nblocks) || waves < 1 || waves > 4) return hipErrorInvalidValue;
     dim3 g((unsigned)nblocks), b((unsigned)(64 * waves));
     if (dim == 2) {
         if (prec == 0)
-            hipLaunchKernelGGL(step2d_kernel<Plain64<5>>, g, b, 0, s, descs, ctrls, blocks, remap, fused);
+            launch(step2d_kernel<Plain64<5>>, g, b, s, e0, e1, descs, ctrls, blocks, remap, fused);
         else if (prec == 1)
-            hipLaunchKernelGGL(step2d_kernel<Dev32<5>>, g, b, 0, s, descs, ctrls, blocks, remap, fused);
+            launch(step2d_kernel<Dev32<5>>, g, b, s, e0, e1, descs, ctrls, blocks, remap, fused);
         else
-            hipLaunchKernelGGL(step2d_kernel<Mix32<5>>, g, b, 0, s, descs, ctrls, blocks, remap, fused);
+            launch(step2d_kernel<Mix32<5>>, g, b, s, e0, e1, descs, ctrls, blocks, remap, fused);
     } else {
         if (prec == 0)
-            hipLaunchKernelGGL(step1d_kernel<Plain64<4>>, g, b, 0, s, descs, ctrls, blocks, remap, fused);
+            launch(step1d_kernel<Plain64<4>>, g, b, s, e0, e1, descs, ctrls, blocks, remap, fused);
         else if (prec == 1)
-            hipLaunchKernelGGL(step1d_kernel<Dev32<4>>, g, b, 0, s, descs, ctrls, blocks, remap, fused);
+            launch(step1d_kernel<Dev32<4>>, g, b, s, e0, e1, descs, ctrls, blocks, remap, fused);
         else
-            hipLaunchKernelGGL(step1d_kernel<Mix32<4>>, g, b, 0, s, descs, ctrls, blocks, remap, fused);
+            launch(step1d_kernel<Mix32<4>>, g, b, s, e0, e1, descs, ctrls, blocks, remap, fused);
     }
     return hipGetLastError();
 }
@@ -1186,11 +1201,10 @@ hipError_t launch_prime(int dim, int prec, const InstDesc* descs, InstCtrl* ctrl
 }
 
 hipError_t launch_finalize(const InstDesc* descs, InstCtrl* ctrls, const int32_t* insts, int n,
-                           int mode, hipStream_t s)
+                           int mode, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)n), dim3(1024), 0, s, descs, ctrls, insts,
-                       mode);
+    launch(finalize_kernel, dim3((unsigned)n), dim3(1024), s, e0, e1, descs, ctrls, insts, mode);
     return hipGetLastError();
 }
 

@@ -1,5 +1,7 @@
 // ng_launch.hpp -- host-callable launchers of the HIP kernels (ng_kernels.hip).
-// dim: 1 or 2; prec: 0 = FP64, 1 = FP32.  All launches are asynchronous on s.
+// dim: 1 or 2; prec: 0 = FP64, 1 = FP32, 2 = mixed.  All launches are
+// asynchronous on s.  Optional events e0 / e1 receive the kernel's own start
+// and end (timed launches; never under stream capture).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -11,14 +13,15 @@ namespace ng {
 
 hipError_t launch_step(int dim, int prec, const InstDesc* descs, InstCtrl* ctrls,
                        const BlockRef* blocks, int64_t nblocks, int waves, int remap, int fused,
-                       hipStream_t s);
+                       hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // Priming pass: totals, checks and signal speed of the current state.  With
 // blocks == nullptr the launch covers solve `inst`'s own workgroups 0..nblocks-1.
 hipError_t launch_prime(int dim, int prec, const InstDesc* descs, InstCtrl* ctrls,
                         const BlockRef* blocks, int inst, int64_t nblocks, int waves,
                         hipStream_t s);
 hipError_t launch_finalize(const InstDesc* descs, InstCtrl* ctrls, const int32_t* insts, int n,
-                           int mode, hipStream_t s);
+                           int mode, hipStream_t s, hipEvent_t e0 = nullptr,
+                           hipEvent_t e1 = nullptr);
 hipError_t launch_small(int dim, int prec, const InstDesc* descs, InstCtrl* ctrls,
                         const int32_t* insts, int n, int waves, int64_t nsteps, hipStream_t s);
 hipError_t launch_set_limits(InstCtrl* ctrls, const int32_t* insts, int n, double t_end,

@@ -37,7 +37,7 @@ def kernel_hash(root: str = ROOT) -> str:
     return h.hexdigest()[:16]
 
 
-def stats_markdown(path: str, command: str, top: int = 12) -> str:
+def stats_markdown(path: str, command: str, top: int = 12, bench_json: str | None = None) -> str:
     rows = list(csv.DictReader(open(path)))
     out = [f"Command: `{command}`", "",
            "| kernel | calls | mean us | min us | max us | share |",
@@ -49,6 +49,17 @@ def stats_markdown(path: str, command: str, top: int = 12) -> str:
         out.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
                    f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
                    f"{float(r['Percentage']):.1f}% |")
+    if bench_json:
+        # the benchmark's own line from the same run: its HIP-event kernel
+        # duration is the figure the profiler's mean above should match
+        with open(bench_json) as f:
+            line = [ln for ln in f if ln.startswith("{")][-1]
+        b = json.loads(line)
+        r = b["roofline"]
+        out += ["", f"Same run, bench.py's own measurement: `{r['kernel']}` mean "
+                f"{1e3 * r['kernel_ms']:.1f} us over the timed launches (HIP events carried by "
+                f"each launch), {b['ms_per_step'] * 1e3:.1f} us per step, value "
+                f"{b['value']:.3e} {b['unit']}."]
     return "\n".join(out) + "\n"
 
 
@@ -109,6 +120,8 @@ def main(argv=None):
     a.add_argument("csv")
     a.add_argument("--command", required=True)
     a.add_argument("--out", required=True)
+    a.add_argument("--bench-json", default=None,
+                   help="stdout of the profiled bench.py run (its JSON line)")
     b = sub.add_parser("traffic")
     b.add_argument("fetch_csv")
     b.add_argument("write_csv")
@@ -138,7 +151,7 @@ def main(argv=None):
         print(md)
         return
     if args.cmd == "stats":
-        md = stats_markdown(args.csv, args.command)
+        md = stats_markdown(args.csv, args.command, bench_json=args.bench_json)
         with open(args.out, "w") as f:
             f.write(md)
         print(md)
