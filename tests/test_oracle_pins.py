@@ -391,6 +391,25 @@ def test_signalling_roots_solve_paper_eq8():
         assert k.imag == pytest.approx(-w0.imag / vg, rel=0.05)
 
 
+@pytest.mark.parametrize("S", [0.5, 1.0])
+def test_signalling_roots_high_frequency_limit(S):
+    """Closed form for the spatial increment at omega tau0 >> 1 (Q and I
+    exponents 0): Im k -> gamma_1 (X - Y/gamma) / (2 sqrt(gamma) tau0) with
+    X = C_k + S tau_T, Y = C_k + S (tau_T - tau_rho).  The section 3 set
+    (tau0 = 1, lambda = 0.1: omega tau0 = 74) is already in that limit."""
+    g = wl.results_gas(S)
+    gam, g1, Ck = g["gamma"], g["gamma"] - 1.0, g["Cv"] / g["R"]
+    X = Ck + S * g["tau_T"]
+    Y = Ck + S * (g["tau_T"] - g["tau_rho"])
+    lim = g1 * (X - Y / gam) / (2.0 * math.sqrt(gam) * g["tau0"])
+    c = math.sqrt(gam * g["R"] * g["T0"])
+    k_far = D.spatial_k(g, 1e5)
+    assert k_far.imag == pytest.approx(lim, rel=1e-4)
+    k_run = D.spatial_k(g, c * 2 * math.pi / 0.1)
+    assert k_run.imag == pytest.approx(lim, rel=2e-3)
+    assert (lim < 0) and abs(lim) < 0.2
+
+
 def test_paper_results_set_is_acoustically_unstable():
     gas = dict(gamma=1.4, R=1.0, Cv=0.1, rho0=1.0, T0=1.0, tau0=0.05, tau_rho=-1.0,
                tau_T=-1.5, Q0=10.0, Q_rho=0.0, Q_T=0.0, I0=10.0, I_rho=0.0, I_T=0.0,
