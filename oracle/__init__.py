@@ -37,7 +37,9 @@ class OrGas(C.Structure):
 
 class OrGrid(C.Structure):
     _fields_ = [("nx", C.c_int64), ("ny", C.c_int64), ("h", C.c_double),
-                ("bc", C.c_int32 * 4), ("src_amp", C.c_double), ("src_lambda", C.c_double)]
+                ("bc", C.c_int32 * 4), ("src_amp", C.c_double), ("src_lambda", C.c_double),
+                ("src_yc", C.c_double), ("src_hw", C.c_double), ("wedge_x0", C.c_double),
+                ("wedge_y0", C.c_double), ("wedge_tan", C.c_double)]
 
 
 class OrNum(C.Structure):
@@ -90,9 +92,11 @@ def _gas(g: dict) -> OrGas:
     return OrGas(*[float(g.get(f, 0.0)) for f in GAS_FIELDS])
 
 
-def _grid(nx: int, ny: int, h: float, bc=(0, 0, 0, 0), source=(0.0, 0.0)) -> OrGrid:
-    return OrGrid(int(nx), int(ny), float(h), (C.c_int32 * 4)(*bc), float(source[0]),
-                  float(source[1]))
+def _grid(nx: int, ny: int, h: float, bc=(0, 0, 0, 0), source=(0.0, 0.0),
+          wedge=(0.0, 0.0, 0.0)) -> OrGrid:
+    src = tuple(source) + (0.0, 0.0)[len(source) - 2:]
+    return OrGrid(int(nx), int(ny), float(h), (C.c_int32 * 4)(*bc), *[float(v) for v in src[:4]],
+                  *[float(v) for v in wedge])
 
 
 def _num(cfl: float, riemann: int = HLLC, stiff_z: float = 0.5) -> OrNum:
@@ -109,17 +113,20 @@ class Problem:
 
     def __init__(self, gas: dict, nx: int, ny: int = 1, h: float | None = None,
                  cfl: float = 0.4, riemann: int = HLLC, stiff_z: float = 0.5,
-                 bc=(BC_PERIODIC,) * 4, source=(0.0, 0.0)):
-        """``source = (amplitude, wavelength)`` of the forced wave of a
-        ``BC_SOURCE`` x-low end."""
+                 bc=(BC_PERIODIC,) * 4, source=(0.0, 0.0), wedge=(0.0, 0.0, 0.0)):
+        """``source = (amplitude, wavelength[, y_centre, half_width])`` of the
+        forced wave of a ``BC_SOURCE`` x-low end (half_width <= 0: the whole
+        edge); ``wedge = (x0, y0, tan)``: pump and sink only inside the wedge
+        x >= x0, |y - y0| <= (x - x0) tan (tan <= 0: everywhere)."""
         self.gas = dict(gas)
         self.nx, self.ny = int(nx), int(ny)
         self.h = float(h) if h is not None else 1.0 / self.nx
         self.cfl, self.riemann, self.stiff_z = float(cfl), int(riemann), float(stiff_z)
         self.bc = tuple(int(b) for b in bc)
-        self.source = (float(source[0]), float(source[1]))
+        self.source = tuple(float(v) for v in source)
+        self.wedge = tuple(float(v) for v in wedge)
         self._g = _gas(self.gas)
-        self._gr = _grid(self.nx, self.ny, self.h, self.bc, self.source)
+        self._gr = _grid(self.nx, self.ny, self.h, self.bc, self.source, self.wedge)
         self._nm = _num(self.cfl, self.riemann, self.stiff_z)
 
     @property

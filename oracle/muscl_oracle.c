@@ -33,8 +33,11 @@
  *                factor and a repeated rho f_x -- both read as misprints).
  *   time step    eq. (16) times a CFL number.
  *   boundaries  periodic, reflecting wall or free outflow ends (sections 2.4
- *                and 3), and the forced source of the 1D runs of section 3 at
- *                the x-low end (or_source_ghost).
+ *                and 3), and the forced source of the runs of section 3 at
+ *                the x-low end (or_source_ghost), on the whole edge or a
+ *                segment of it.
+ *   medium      active everywhere, or (2D sector run of section 3) only in a
+ *                wedge (or_active).
  *   stiff branch when dt/tau exceeds a threshold, the relaxation part of the
  *                E_nu update is integrated exactly with E_nue and tau frozen
  *                (our addition; the paper's runs never reach it).
@@ -71,8 +74,11 @@ typedef struct {
     double h;                      /* cell size                                */
     int32_t bc[4];                 /* x-low, x-high, y-low, y-high             */
     double src_amp;                /* OR_BC_SOURCE (x-low only): density       */
-    double src_lambda;             /*   amplitude and wavelength of the wave   */
-} or_grid;
+    double src_lambda;             /*   amplitude and wavelength of the wave,  */
+    double src_yc, src_hw;         /*   on |y - yc| <= hw (hw <= 0: whole edge) */
+    double wedge_x0, wedge_y0;     /* 2D: pump and sink only in the wedge      */
+    double wedge_tan;              /*   x >= x0, |y - y0| <= (x - x0) tan      */
+} or_grid;                         /*   (wedge_tan <= 0: everywhere)           */
 
 typedef struct {
     double cfl;                    /* multiplies the bound of eq. (16)         */
@@ -273,19 +279,23 @@ static int64_t or_ghost(int64_t j, int64_t n, int bc_lo, int bc_hi, int* flip)
  *
  * about the steady background at the reference point of eq. (6): rho_b =
  * rho0, p_b = R rho0 T0, E_nu,b = rho0 Cv T0 + rho0 tau0 Q0 (relaxation
- * balancing the pump in eq. (4)), c = sqrt(gamma p_b / rho_b).  The paper
+ * balancing the pump in eq. (4); without the last term where the ghost lies
+ * outside an active wedge, or_active), c = sqrt(gamma p_b / rho_b).  The paper
  * gives the wavelength but neither the amplitude nor the source's form; the
  * frozen-sound plane wave with unchanged specific vibrational energy is our
  * reading.  The E_nu part enters the domain only with the flow's own velocity,
  * i.e. at second order in the amplitude, so no linear check pins it.  t is the
  * time of the state the step starts from.
  */
-static void or_source_ghost(const or_gas* g, const or_grid* gr, double t, int64_t j, double U[5])
+static double or_active(const or_grid* gr, int64_t j, int64_t k);
+
+static void or_source_ghost(const or_gas* g, const or_grid* gr, double t, int64_t j, int64_t row,
+                            double U[5])
 {
     const double pi = 3.141592653589793;
     double rho_b = g->rho0;
     double p_b = g->R * g->rho0 * g->T0;
-    double ev_b = g->rho0 * g->Cv * g->T0 + g->rho0 * g->tau0 * g->Q0;
+    double ev_b = g->rho0 * g->Cv * g->T0 + or_active(gr, j, row) * (g->rho0 * g->tau0 * g->Q0);
     double c = sqrt(g->gamma * p_b / rho_b);
     double k = 2.0 * pi / gr->src_lambda;
     double omega = c * k;
@@ -298,6 +308,31 @@ static void or_source_ghost(const or_gas* g, const or_grid* gr, double t, int64_
     W[3] = p_b + (c * c) * s;
     W[4] = ev_b + (ev_b / rho_b) * s;
     or_cons(g, W, U);
+}
+
+/*
+ * The 2D sector run of section 3: the medium is active (pump Q and sink I of
+ * eq. (6)) only inside a wedge with apex (x0, y0) opening towards +x with
+ * half-angle atan(wedge_tan); elsewhere Q0 = I0 = 0 and only the relaxation
+ * acts.  Evaluated at the centre of cell (j, k), also for ghost cells.  The
+ * paper shows the geometry only in a figure; the wedge's placement is our
+ * reading.
+ */
+static double or_active(const or_grid* gr, int64_t j, int64_t k)
+{
+    if (!(gr->wedge_tan > 0.0)) return 1.0;
+    double x = ((double)j + 0.5) * gr->h;
+    double y = ((double)k + 0.5) * gr->h;
+    double dx = x - gr->wedge_x0;
+    return (dx >= 0.0 && fabs(y - gr->wedge_y0) <= dx * gr->wedge_tan) ? 1.0 : 0.0;
+}
+
+/* A source end drives the ghosts of row k only on its segment. */
+static int or_source_row(const or_grid* gr, int64_t k)
+{
+    if (!(gr->src_hw > 0.0)) return 1;
+    double y = ((double)k + 0.5) * gr->h;
+    return fabs(y - gr->src_yc) <= gr->src_hw;
 }
 
 /* ------------------------------------------------------------------- step */
@@ -359,7 +394,8 @@ int or_step_at(const or_gas* g, const or_grid* gr, const or_num* nm, const doubl
             int64_t s = ks * nx + js;
             double Uc[5] = {U_in[s], U_in[n + s], U_in[2 * n + s], U_in[3 * n + s],
                             U_in[4 * n + s]};
-            if (j < 0 && gr->bc[0] == OR_BC_SOURCE) or_source_ghost(g, gr, t, j, Uc);
+            if (j < 0 && gr->bc[0] == OR_BC_SOURCE && or_source_row(gr, k))
+                or_source_ghost(g, gr, t, j, k, Uc);
             if (fx_) Uc[1] = -Uc[1];
             if (fy_) Uc[2] = -Uc[2];
             double Wc[5];
@@ -407,9 +443,10 @@ int or_step_at(const or_gas* g, const or_grid* gr, const or_num* nm, const doubl
             }
             /* sources at t^n: eq. (6), E_nue = rho Cv T, T from eq. (7) */
             double T = p / (g->R * rho);
+            double act = or_active(gr, j, k);
             double tau = or_tau(g, rho, T);
-            double Q = or_Q(g, rho, T);
-            double I = or_I(g, rho, T);
+            double Q = act * or_Q(g, rho, T);
+            double I = act * or_I(g, rho, T);
             double Ee = rho * g->Cv * T;
             /* E_nu gained by relaxation over dt/2 */
             double dEr;
@@ -485,9 +522,10 @@ int or_step_at(const or_gas* g, const or_grid* gr, const or_num* nm, const doubl
             double rho = Wh[m], u = Wh[ne + m], v = Wh[2 * ne + m], p = Wh[3 * ne + m],
                    ev = Wh[4 * ne + m];
             double T = p / (g->R * rho);
+            double act = or_active(gr, j, k);
             double tau = or_tau(g, rho, T);
-            double Q = or_Q(g, rho, T);
-            double I = or_I(g, rho, T);
+            double Q = act * or_Q(g, rho, T);
+            double I = act * or_I(g, rho, T);
             double Ee = rho * g->Cv * T;
             double Y[5];
             Y[0] = 0.0;

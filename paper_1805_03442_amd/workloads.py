@@ -224,6 +224,42 @@ def workload_forced_source(stage: str = "nonlinear"):
                 nx=n, ny=1, bc=(3, 2, 0, 0), source=(amp, 0.1), t_end=0.8)
 
 
+def sector_active(n: int, L: float, x0: float, y0: float, tan: float) -> np.ndarray:
+    """Cells (ny, nx) of an n x n grid of side L whose centre lies in the wedge
+    x >= x0, |y - y0| <= (x - x0) tan (the active medium of the sector run)."""
+    h = L / n
+    x = (np.arange(n) + 0.5) * h
+    y = (np.arange(n) + 0.5) * h
+    dx = x[None, :] - x0
+    return (dx >= 0.0) & (np.abs(y[:, None] - y0) <= dx * tan)
+
+
+def workload_sector_2d(n: int = 600, S: float = 1.0, tau0: float = 1.0, amp: float = 1e-2,
+                       L: float = 1.2, t_end: float = 1.0):
+    """The 2D run of section 3: the active medium fills a sector of opening
+    angle 30 degrees whose apex is the source, the rest of the gas is passive
+    (no pump or sink); a wall G1 and free flow G2-G4.  The geometry is shown
+    only in a figure; the readings: square domain of side L = 1.2 (so the
+    wave meets G1 at t ~ 1, as the paper states), source on the x-low edge at
+    y = L/2 over one wavelength (|y - L/2| <= 0.05), the rest of that edge and
+    both y edges free outflow (G2-G4), the x-high edge a wall (G1), the sector
+    symmetric about y = L/2 with its apex at the source.  The initial state is
+    the steady background of each medium (E_nu carries rho tau0 Q0 only in
+    the active part)."""
+    gas = results_gas(S, tau0)
+    lam = 0.1
+    x0, y0, tan = 0.0, 0.5 * L, math.tan(math.radians(15.0))
+    act = sector_active(n, L, x0, y0, tan)
+    b = background(gas)
+    W = np.zeros((5, n, n))
+    W[0] = b["rho"]
+    W[3] = b["p"]
+    W[4] = gas["rho0"] * gas["Cv"] * gas["T0"] + np.where(act, gas["rho0"] * gas["tau0"] * gas["Q0"], 0.0)
+    return dict(name=f"sector_2d_S{S:g}_n{n}", gas=gas, W=W, nx=n, ny=n, h=L / n,
+                bc=(3, 1, 2, 2), source=(amp, lam, 0.5 * L, 0.5 * lam),
+                wedge=(x0, y0, tan), t_end=t_end, active=act)
+
+
 def batch_1d_instances(count: int = 512, nmin_log2: float = 10.0, nmax_log2: float = 16.0,
                        steps: int = 10000):
     """Batch of uneven 1D periodic instances: n log-uniform in [2^10, 2^16],

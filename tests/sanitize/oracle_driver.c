@@ -14,7 +14,9 @@
 static int run_case(int64_t nx, int64_t ny, const int32_t bc[4], int riemann, double tau0)
 {
     or_gas g = {1.4, 1.0, 1.0, 1.0, 1.0, tau0, -1.0, -1.0, 0.1, 0.5, 2.0, 0.1, 1.0, 2.0, 0.0, 0.0};
-    or_grid gr = {nx, ny, 1.0 / (double)nx, {bc[0], bc[1], bc[2], bc[3]}, 0.01, 0.1};
+    /* a source segment and an active wedge whenever the x-low end is a source */
+    or_grid gr = {nx, ny, 1.0 / (double)nx, {bc[0], bc[1], bc[2], bc[3]}, 0.01, 0.1,
+                  0.5, 0.2, 0.0, 0.5, bc[0] == OR_BC_SOURCE && ny > 1 ? 0.3 : 0.0};
     or_num nm = {0.4, riemann, 0.5};
     const int64_t n = nx * ny;
     double* W = malloc(sizeof(double) * 5 * n);

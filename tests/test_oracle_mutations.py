@@ -71,8 +71,15 @@ MUTATIONS = {
     "source_wave_runs_backwards": [("W[1] = (c / rho_b) * s;", "W[1] = -(c / rho_b) * s;")],
     "source_pressure_not_isentropic": [("W[3] = p_b + (c * c) * s;", "W[3] = p_b + c * s;")],
     "source_ignores_time": [("sin(omega * t - k * x)", "sin(-k * x)")],
-    "source_ghost_one_cell_off": [("double x = ((double)j + 0.5) * gr->h;",
-                                   "double x = ((double)j + 1.5) * gr->h;")],
+    "source_ghost_one_cell_off": [("double x = ((double)j + 0.5) * gr->h;\n    double s =",
+                                   "double x = ((double)j + 1.5) * gr->h;\n    double s =")],
+    "wedge_inverted": [("return (dx >= 0.0 && fabs(y - gr->wedge_y0) <= dx * gr->wedge_tan) ? 1.0 : 0.0;",
+                        "return (dx >= 0.0 && fabs(y - gr->wedge_y0) <= dx * gr->wedge_tan) ? 0.0 : 1.0;")],
+    "wedge_leaves_sink_on": [("            double I = act * or_I(g, rho, T);\n            double Ee",
+                              "            double I = or_I(g, rho, T);\n            double Ee")],
+    "source_segment_ignored": [("    if (!(gr->src_hw > 0.0)) return 1;", "    return 1;")],
+    "source_segment_off_by_one_row": [("    double y = ((double)k + 0.5) * gr->h;\n    return fabs",
+                                       "    double y = ((double)k + 1.5) * gr->h;\n    return fabs")],
 }
 
 

@@ -815,3 +815,124 @@ def test_forced_source_phase_follows_time(oracle_lib):
     assert np.array_equal(U, b["U"]) and t == b["t"]
     st, V, _ = P.step(a["U"], P.dt(a["U"]), 0.0)
     assert not np.array_equal(V, P.step(a["U"], P.dt(a["U"]), a["t"])[1])
+
+
+# ---------------------------------------------- 2D sector run (section 3)
+
+def _sector_problem(oracle_lib, n, L, S=0.5, tau0=0.05, amp=1e-3, wedge=None, source=None,
+                    gas=None):
+    w = wl.workload_sector_2d(n=n, S=S, tau0=tau0, amp=amp, L=L)
+    g = gas or w["gas"]
+    P = oracle_lib.Problem(g, n, n, h=w["h"], bc=w["bc"],
+                           source=source or w["source"], wedge=wedge or w["wedge"])
+    return P, w
+
+
+def test_sector_wedge_everywhere_or_nowhere(oracle_lib):
+    """A wedge that covers the whole grid is the uniform active medium, and one
+    that covers no cell is the passive gas (Q0 = I0 = 0), bit for bit, source
+    included."""
+    n, L = 40, 0.4
+    P, w = _sector_problem(oracle_lib, n, L)
+    U0 = P.prim_to_cons(wl.uniform_state(w["gas"], n, n))
+    everywhere = oracle_lib.Problem(w["gas"], n, n, h=w["h"], bc=w["bc"], source=w["source"],
+                                    wedge=(-100.0, 0.5 * L, 1e3))
+    uniform = oracle_lib.Problem(w["gas"], n, n, h=w["h"], bc=w["bc"], source=w["source"])
+    a = everywhere.run(U0, 30)
+    b = uniform.run(U0, 30)
+    assert a["status"] == 0 and np.array_equal(a["U"], b["U"])
+    passive = dict(w["gas"], Q0=0.0, I0=0.0)
+    Wp = wl.uniform_state(passive, n, n)
+    Pp = oracle_lib.Problem(passive, n, n, h=w["h"], bc=w["bc"], source=w["source"])
+    nowhere = oracle_lib.Problem(w["gas"], n, n, h=w["h"], bc=w["bc"], source=w["source"],
+                                 wedge=(100.0, 0.5 * L, 0.5))
+    U0p = Pp.prim_to_cons(Wp)
+    c = nowhere.run(U0p, 30)
+    d = Pp.run(U0p, 30)
+    assert c["status"] == 0 and np.array_equal(c["U"], d["U"])
+
+
+def test_sector_source_segment_and_steady_media(oracle_lib):
+    """A source segment longer than the edge is the whole-edge source (bitwise);
+    at zero amplitude the two steady media of the sector stay bitwise steady;
+    the sector run is mirror-symmetric about the source's y."""
+    n, L = 40, 0.4
+    P, w = _sector_problem(oracle_lib, n, L)
+    U0 = P.prim_to_cons(w["W"])
+    amp, lam = w["source"][:2]
+    long_seg = oracle_lib.Problem(w["gas"], n, n, h=w["h"], bc=w["bc"],
+                                  source=(amp, lam, 0.5 * L, 10.0), wedge=w["wedge"])
+    whole = oracle_lib.Problem(w["gas"], n, n, h=w["h"], bc=w["bc"], source=(amp, lam),
+                               wedge=w["wedge"])
+    a = long_seg.run(U0, 25)
+    b = whole.run(U0, 25)
+    assert a["status"] == 0 and np.array_equal(a["U"], b["U"])
+    quiet = oracle_lib.Problem(w["gas"], n, n, h=w["h"], bc=w["bc"],
+                               source=(0.0, lam, 0.5 * L, 0.5 * lam), wedge=w["wedge"])
+    q = quiet.run(U0, 25)
+    assert np.array_equal(q["U"], U0)
+    r = P.run(U0, 60)
+    U = r["U"]
+    M = U[:, ::-1, :].copy()
+    M[2] = -M[2]
+    # rounding-level asymmetry only (the sums are not evaluated mirror-wise),
+    # measured against the state's scale: momentum is a 1e-3 perturbation
+    assert np.abs(U - M).max() <= 1e-13 * np.abs(U).max()
+    assert np.abs(U[2]).max() > 1e-6
+
+
+def test_sector_wave_grows_only_in_the_active_wedge(oracle_lib):
+    """40 cells per wavelength, unstable set: along the axis of the wedge the
+    wave is weaker than in an all-active medium and stronger than in an
+    all-passive one, and its lead over the passive medium widens with
+    distance; far off the axis (outside the wedge) the sector run and the
+    passive run agree within 10 %."""
+    n, L, t_end = 180, 0.45, 0.3
+    w = wl.workload_sector_2d(n=n, S=0.5, tau0=0.05, amp=1e-3, L=L, t_end=t_end)
+    passive = dict(w["gas"], Q0=0.0, I0=0.0)
+    runs = {}
+    for name, g, wedge, W in (("sector", w["gas"], w["wedge"], w["W"]),
+                              ("active", w["gas"], (0.0, 0.0, 0.0),
+                               wl.uniform_state(w["gas"], n, n)),
+                              ("passive", passive, (0.0, 0.0, 0.0),
+                               wl.uniform_state(passive, n, n))):
+        P = oracle_lib.Problem(g, n, n, h=w["h"], bc=w["bc"], source=w["source"], wedge=wedge)
+        r = P.run(P.prim_to_cons(W), 10 ** 6, t_end=t_end)
+        assert r["status"] == 0
+        runs[name] = r["U"][0] - g["rho0"]
+    h = w["h"]
+    axis = slice(n // 2 - 4, n // 2 + 4)
+
+    def env(d, x0, x1, rows):
+        return np.abs(d[rows, int(x0 / h):int(x1 / h)]).max()
+
+    near = [env(runs[k], 0.07, 0.12, axis) for k in ("sector", "active", "passive")]
+    far = [env(runs[k], 0.22, 0.27, axis) for k in ("sector", "active", "passive")]
+    assert far[2] < far[0] < far[1], far
+    assert far[0] / far[2] > 1.1 * (near[0] / near[2]), (near, far)
+    off = slice(int(0.9 * n) - 4, int(0.9 * n) + 4)
+    a, b = env(runs["sector"], 0.1, 0.25, off), env(runs["passive"], 0.1, 0.25, off)
+    assert a == pytest.approx(b, rel=0.1), (a, b)
+
+
+def test_sector_source_segment_reaches_only_its_rows(oracle_lib):
+    """One step from the steady passive background: the source's ghosts drive
+    exactly the rows of its segment (|y - yc| <= hw), so only cells within two
+    rows and two columns of them change (the step's stencil)."""
+    n, L = 40, 0.4
+    gas = dict(wl.results_gas(0.5, 0.05), Q0=0.0, I0=0.0)
+    h = L / n
+    yc, hw = 0.2, 0.05
+    P = oracle_lib.Problem(gas, n, n, h=h, bc=(oracle_lib.BC_SOURCE, 1, 2, 2),
+                           source=(1e-3, 0.1, yc, hw))
+    U0 = P.prim_to_cons(wl.uniform_state(gas, n, n))
+    st, V, _ = P.step(U0, P.dt(U0), 0.0)
+    assert st == 0
+    changed = np.any(V != U0, axis=0)
+    y = (np.arange(n) + 0.5) * h
+    seg = np.abs(y - yc) <= hw
+    rows = np.nonzero(seg)[0]
+    box = np.zeros((n, n), dtype=bool)
+    box[rows.min() - 2:rows.max() + 3, 0:2] = True
+    assert not np.any(changed & ~box)
+    assert np.all(changed[rows, 0])
