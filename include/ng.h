@@ -100,7 +100,16 @@ typedef struct {
  * rho0, p_b = R rho0 T0, E_nu,b = rho0 Cv T0 + rho0 tau0 Q0, c = the frozen
  * sound speed sqrt(gamma p_b / rho_b)): a sound wave of wavelength
  * src_lambda entering the domain.  Requires src_lambda > 0 and |src_amp| <
- * rho_b / 2; both are ignored for other kinds. */
+ * rho_b / 2; both are ignored for other kinds.  In 2D, src_hw > 0 limits the
+ * source to the ghost rows whose centre y has |y - src_yc| <= src_hw (the
+ * other rows of that edge are free outflow); src_hw <= 0: the whole edge.
+ *
+ * Active wedge (2D sector run of section 3): wedge_tan > 0 confines the pump
+ * and sink of eq. (6) (Q0, I0) to the cells whose centre has x >= wedge_x0
+ * and |y - wedge_y0| <= (x - wedge_x0) wedge_tan; elsewhere the gas is
+ * passive (Q = I = 0, relaxation only), and a source's background E_nu is the
+ * passive one.  Requires a 2D grid and wedge_x0 >= 0.  wedge_tan <= 0: active
+ * everywhere (the fields are ignored). */
 typedef struct {
     int32_t ndim;
     int32_t reserved;
@@ -108,6 +117,8 @@ typedef struct {
     double h;
     int32_t bc[4];
     double src_amp, src_lambda;
+    double src_yc, src_hw;
+    double wedge_x0, wedge_y0, wedge_tan;
 } ng_grid;
 
 /* cfl multiplies the bound of eq. (16); stiff_z is the dt/tau above which the

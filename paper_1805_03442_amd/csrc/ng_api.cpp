@@ -146,6 +146,17 @@ int validate(const ng_gas* gas, const ng_grid* grid, const ng_numerics* num, std
         err = "source needs src_lambda > 0 and |src_amp| < rho0 / 2";
         return NG_EINVAL;
     }
+    if (grid->bc[0] == NG_BC_SOURCE && grid->src_hw > 0.0 &&
+        (grid->ndim != 2 || !isfinite(grid->src_yc) || !isfinite(grid->src_hw))) {
+        err = "a source segment needs a 2D grid and finite src_yc, src_hw";
+        return NG_EINVAL;
+    }
+    if (!isfinite(grid->wedge_tan) ||
+        (grid->wedge_tan > 0.0 && (grid->ndim != 2 || !(grid->wedge_x0 >= 0.0) ||
+                                   !isfinite(grid->wedge_x0) || !isfinite(grid->wedge_y0)))) {
+        err = "an active wedge needs a 2D grid, finite wedge_y0 and 0 <= wedge_x0 < inf";
+        return NG_EINVAL;
+    }
     for (int a = 0; a < 2; a++)
         if ((grid->bc[2 * a] == NG_BC_PERIODIC) != (grid->bc[2 * a + 1] == NG_BC_PERIODIC) &&
             (a == 0 || grid->ndim == 2)) {
@@ -693,13 +704,23 @@ void fill_desc(InstDesc& d, const ng_gas* gas, const ng_grid* grid, const ng_num
         if (d.bc[i] != NG_BC_PERIODIC) d.any_bc = 1;
     }
     d.h = grid->h;
+    // an active wedge takes the boundary instantiation of the kernels
+    d.wedge_tan = grid->wedge_tan > 0.0 ? grid->wedge_tan : 0.0;
+    d.wedge_x0 = grid->wedge_x0;
+    d.wedge_y0 = grid->wedge_y0;
+    if (d.wedge_tan > 0.0) d.any_bc = 1;
+    d.src_yc = grid->src_yc;
+    d.src_hw = d.bc[0] == NG_BC_SOURCE && grid->src_hw > 0.0 ? grid->src_hw : 0.0;
     if (d.bc[0] == NG_BC_SOURCE) {
         // the forced wave's constants (the device evaluates the sine at each
         // accepted time)
         const double pi = 3.141592653589793;
         const double rho_b = gas->rho0;
         const double p_b = gas->R * gas->rho0 * gas->T0;
-        const double ev_b = gas->rho0 * gas->Cv * gas->T0 + gas->rho0 * gas->tau0 * gas->Q0;
+        // the ghosts lie before x = 0, outside any wedge (wedge_x0 >= 0): the
+        // background there is the passive one when the grid has a wedge
+        const double act = d.wedge_tan > 0.0 ? 0.0 : 1.0;
+        const double ev_b = gas->rho0 * gas->Cv * gas->T0 + act * (gas->rho0 * gas->tau0 * gas->Q0);
         const double c = sqrt(gas->gamma * p_b / rho_b);
         d.src_amp = grid->src_amp;
         d.src_k = 2.0 * pi / grid->src_lambda;

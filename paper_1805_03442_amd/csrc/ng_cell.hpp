@@ -63,7 +63,8 @@ __device__ __forceinline__ double powr64(double x, double a)
     return pow(x, a);
 }
 
-// closures of eq. (6) at (rho, T)
+// closures of eq. (6) at (rho, T); the predictor and corrector scale Q and I
+// by act, 0 outside an active wedge (the 2D sector run of section 3)
 __device__ __forceinline__ void closures64(const K64& k, double rho, double T, double& tau,
                                            double& Q, double& I)
 {
@@ -118,7 +119,7 @@ __device__ __forceinline__ double speed64(const K64& k, const double* W)
 // W = (rho, u, v, p, E_nu) (2D) or (rho, u, p, E_nu) (1D); sx, sy limited slopes.
 template <int NC>
 __device__ __forceinline__ void predict64(const K64& k, const double* W, const double* sx,
-                                          const double* sy, double* Wh)
+                                          const double* sy, double* Wh, double act = 1.0)
 {
     const double gam = k.gam, gm1 = k.gm1, hdtdx = k.hdtdx, hdt = k.hdt;
     if (NC == 5) {
@@ -138,6 +139,8 @@ __device__ __forceinline__ void predict64(const K64& k, const double* W, const d
         double T = p / (k.R * rho);
         double tau, Q, I;
         closures64(k, rho, T, tau, Q, I);
+        Q = act * Q;
+        I = act * I;
         double Ee = rho * k.Cv * T;
         double dEr;
         double zh = hdt / tau;
@@ -160,6 +163,8 @@ __device__ __forceinline__ void predict64(const K64& k, const double* W, const d
         double T = p / (k.R * rho);
         double tau, Q, I;
         closures64(k, rho, T, tau, Q, I);
+        Q = act * Q;
+        I = act * I;
         double Ee = rho * k.Cv * T;
         double dEr;
         double zh = hdt / tau;
@@ -274,7 +279,7 @@ __device__ __forceinline__ void flux64(const K64& k, const double* WL, const dou
 template <int NC>
 __device__ __forceinline__ void update64(const K64& k, const double* Un, const double* dF,
                                          const double* dG, const double* Wh, double* Unew,
-                                         double& srcE, double& srcV)
+                                         double& srcE, double& srcV, double act = 1.0)
 {
     const double dt = k.dt, dtdx = k.dtdx;
     double rho = Wh[0], u = Wh[1];
@@ -290,6 +295,8 @@ __device__ __forceinline__ void update64(const K64& k, const double* Un, const d
     double T = p / (k.R * rho);
     double tau, Q, I;
     closures64(k, rho, T, tau, Q, I);
+    Q = act * Q;
+    I = act * I;
     double Ee = rho * k.Cv * T;
     double Y[5];
     const int iE = NC == 5 ? 3 : 2, iV = NC == 5 ? 4 : 3;
@@ -405,7 +412,7 @@ __device__ __forceinline__ float speed32(const K32& k, const float* W)
 // density, pressure and E_nu rows
 template <int NC>
 __device__ __forceinline__ void predict32(const K32& k, const float* W, const float* sx,
-                                          const float* sy, float* Wh)
+                                          const float* sy, float* Wh, float act = 1.0f)
 {
     const float hdtdx = k.hdtdx, hdt = k.hdt;
     constexpr int iP = NC == 5 ? 3 : 2, iV = NC == 5 ? 4 : 3;
@@ -433,6 +440,8 @@ __device__ __forceinline__ void predict32(const K32& k, const float* W, const fl
     }
     float itau, Q, I;
     closures32(k, rho, p, irho, itau, Q, I);
+    Q = act * Q;
+    I = act * I;
     float relax_num = fmaf(k.CvR, dp, k.D_r - de);   // E_nue - E_nu
     // (dt/2)/tau against half the threshold: the same decision as dt/tau
     // against the threshold (both sides scaled by exactly 1/2)
@@ -542,7 +551,7 @@ __device__ __forceinline__ void flux32(const K32& k, const float* WL, const floa
 template <int NC>
 __device__ __forceinline__ void update32(const K32& k, const float* Un, const float* dF,
                                          const float* dG, const float* Wh, float* Unew,
-                                         float& srcE, float& srcV)
+                                         float& srcE, float& srcV, float act = 1.0f)
 {
     constexpr int iP = NC == 5 ? 3 : 2, iV = NC == 5 ? 4 : 3;
     const float dt = k.dt, dtdx = k.dtdx;
@@ -552,6 +561,8 @@ __device__ __forceinline__ void update32(const K32& k, const float* Un, const fl
     float irho = rcp32(rho);
     float itau, Q, I;
     closures32(k, rho, p, irho, itau, Q, I);
+    Q = act * Q;
+    I = act * I;
     float yE = rho * (Q - I);
     float relax_num = fmaf(k.CvR, dp, k.D_r - de);
     float yV = fmaf(relax_num, itau, rho * Q);
@@ -584,7 +595,7 @@ __device__ __forceinline__ void update32(const K32& k, const float* Un, const fl
 template <int NC>
 __device__ __forceinline__ void increment32(const K32& k, float ev_n, const float* dF,
                                             const float* dG, const float* Wh, float* dU,
-                                            float& srcE, float& srcV)
+                                            float& srcE, float& srcV, float act = 1.0f)
 {
     constexpr int iP = NC == 5 ? 3 : 2, iV = NC == 5 ? 4 : 3;
     const float dt = k.dt, dtdx = k.dtdx;
@@ -594,6 +605,8 @@ __device__ __forceinline__ void increment32(const K32& k, float ev_n, const floa
     float irho = rcp32(rho);
     float itau, Q, I;
     closures32(k, rho, p, irho, itau, Q, I);
+    Q = act * Q;
+    I = act * I;
     float yE = rho * (Q - I);
     float relax_num = fmaf(k.CvR, dp, k.D_r - de);
     float yV = fmaf(relax_num, itau, rho * Q);

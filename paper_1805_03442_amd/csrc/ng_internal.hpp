@@ -56,6 +56,9 @@ struct InstDesc {
     // er = E_nu,b / rho_b
     double src_amp, src_k, src_omega;
     double src_rho, src_p, src_ev, src_uc, src_c2, src_er;
+    double src_yc, src_hw;    // 2D: the source drives rows with |y - yc| <= hw
+    // 2D sector run: pump and sink only for x >= x0, |y - y0| <= (x - x0) tan
+    double wedge_x0, wedge_y0, wedge_tan;   // tan <= 0: everywhere
 };
 
 // Mutable per-solve state, advanced by the finalize kernel.

@@ -154,9 +154,10 @@ struct Plain64 {
     }
     static __device__ void prim(const K& k, const R* U, R* W) { prim64<NC>(k, U, W); }
     static __device__ R speed(const K& k, const R* W) { return speed64<NC>(k, W); }
-    static __device__ void predict(const K& k, const R* W, const R* sx, const R* sy, R* Wh)
+    static __device__ void predict(const K& k, const R* W, const R* sx, const R* sy, R* Wh,
+                                   R act = 1)
     {
-        predict64<NC>(k, W, sx, sy, Wh);
+        predict64<NC>(k, W, sx, sy, Wh, act);
     }
     template <int RS>
     static __device__ void flux(const K& k, const R* L, const R* Rr, R* F)
@@ -164,9 +165,9 @@ struct Plain64 {
         flux64<NC, RS>(k, L, Rr, F);
     }
     static __device__ void update(const K& k, const R* Un, const R* dF, const R* dG, const R* Wh,
-                                  R* Unew, R& sE, R& sV)
+                                  R* Unew, R& sE, R& sV, R act = 1)
     {
-        update64<NC>(k, Un, dF, dG, Wh, Unew, sE, sV);
+        update64<NC>(k, Un, dF, dG, Wh, Unew, sE, sV, act);
     }
     static __device__ R full_rho(const K&, R r) { return r; }
     static __device__ R full_p(const K&, R p) { return p; }
@@ -221,9 +222,10 @@ struct Dev32 {
     }
     static __device__ void prim(const K& k, const R* U, R* W) { prim32<NC>(k, U, W); }
     static __device__ R speed(const K& k, const R* W) { return speed32<NC>(k, W); }
-    static __device__ void predict(const K& k, const R* W, const R* sx, const R* sy, R* Wh)
+    static __device__ void predict(const K& k, const R* W, const R* sx, const R* sy, R* Wh,
+                                   R act = 1)
     {
-        predict32<NC>(k, W, sx, sy, Wh);
+        predict32<NC>(k, W, sx, sy, Wh, act);
     }
     template <int RS>
     static __device__ void flux(const K& k, const R* L, const R* Rr, R* F)
@@ -231,9 +233,9 @@ struct Dev32 {
         flux32<NC, RS>(k, L, Rr, F);
     }
     static __device__ void update(const K& k, const R* Un, const R* dF, const R* dG, const R* Wh,
-                                  R* Unew, R& sE, R& sV)
+                                  R* Unew, R& sE, R& sV, R act = 1)
     {
-        update32<NC>(k, Un, dF, dG, Wh, Unew, sE, sV);
+        update32<NC>(k, Un, dF, dG, Wh, Unew, sE, sV, act);
     }
     static __device__ R full_rho(const K& k, R r) { return k.rho_r + r; }
     static __device__ R full_p(const K& k, R p) { return k.p_r + p; }
@@ -258,9 +260,10 @@ struct Mix32 {
         prim32<NC>(k, D, W);
     }
     static __device__ R speed(const K& k, const R* W) { return speed32<NC>(k, W); }
-    static __device__ void predict(const K& k, const R* W, const R* sx, const R* sy, R* Wh)
+    static __device__ void predict(const K& k, const R* W, const R* sx, const R* sy, R* Wh,
+                                   R act = 1)
     {
-        predict32<NC>(k, W, sx, sy, Wh);
+        predict32<NC>(k, W, sx, sy, Wh, act);
     }
     template <int RS>
     static __device__ void flux(const K& k, const R* L, const R* Rr, R* F)
@@ -268,10 +271,10 @@ struct Mix32 {
         flux32<NC, RS>(k, L, Rr, F);
     }
     static __device__ void update(const K& k, const St* Un, const R* dF, const R* dG, const R* Wh,
-                                  St* Unew, R& sE, R& sV)
+                                  St* Unew, R& sE, R& sV, R act = 1)
     {
         R dU[NC];
-        increment32<NC>(k, (R)Un[NC == 5 ? 4 : 3], dF, dG, Wh, dU, sE, sV);
+        increment32<NC>(k, (R)Un[NC == 5 ? 4 : 3], dF, dG, Wh, dU, sE, sV, act);
         for (int c = 0; c < NC; c++) Unew[c] = Un[c] + (St)dU[c];
     }
     static __device__ R full_rho(const K& k, R r) { return k.rho_r + r; }
@@ -672,14 +675,31 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
     const int64_t xr = x0 - kHalo + lane;
     const bool srcx = BC && d.bc[0] == kBcSource && xr < 0;
     const double* gs = gsrc + (xr == -1 ? 0 : 5);
+    // the source drives the ghosts of the rows of its segment (all rows when
+    // the segment's half-width is not positive)
+    auto src_row = [&](int64_t r) -> bool {
+        if (!(d.src_hw > 0.0)) return true;
+        const double y = ((double)r + 0.5) * d.h;
+        return fabs(y - d.src_yc) <= d.src_hw;
+    };
     auto ghost = [&](int64_t r, St* U) {
         if (BC) {
             bool fy;
             (void)axis_cell(r, ny, d.bc[2], d.bc[3], fy);
-            if (srcx) source_cell<St, NC>(d, gs, U);
+            if (srcx && src_row(r)) source_cell<St, NC>(d, gs, U);
             if (flipx) U[1] = -U[1];
             if (fy) U[2] = -U[2];
         }
+    };
+    // pump and sink only inside an active wedge (the 2D sector run of section
+    // 3): 1 or 0 for this lane's cell centre in row r, ghost cells included
+    const bool wedge = BC && d.wedge_tan > 0.0;
+    const double xc = ((double)xr + 0.5) * d.h;
+    auto active = [&](int64_t r) -> R {
+        if (!wedge) return (R)1;
+        const double y = ((double)r + 0.5) * d.h;
+        const double dx = xc - d.wedge_x0;
+        return (dx >= 0.0 && fabs(y - d.wedge_y0) <= dx * d.wedge_tan) ? (R)1 : (R)0;
     };
     auto slopes_x = [&](const R* W, R* sx) {
         for (int c = 0; c < NC; c++) {
@@ -727,7 +747,7 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
         // row r0-1: its north face state
         slopes_x(Wb, sx);
         for (int c = 0; c < NC; c++) sy[c] = minmod(Wb[c] - Wa[c], Wc[c] - Wb[c]);
-        P::predict(k, Wb, sx, sy, hb);
+        P::predict(k, Wb, sx, sy, hb, active(r0 - 1));
         for (int c = 0; c < NC; c++) hb[c] = face(hb[c], sy[c]);
         // row r0
         slopes_x(Wc, XA);
@@ -736,7 +756,7 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
             DA[c] = WA[c] - Wc[c];
             sy[c] = minmod(dp, DA[c]);
         }
-        P::predict(k, Wc, XA, sy, HA);
+        P::predict(k, Wc, XA, sy, HA, active(r0));
         for (int c = 0; c < NC; c++) {
             S[c] = face(HA[c], -sy[c]);
             NA[c] = face(HA[c], sy[c]);
@@ -767,7 +787,7 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
             Dn[c] = We[c] - Wd[c];
             sy[c] = minmod(Dp[c], Dn[c]);
         }
-        P::predict(k, Wd, x1s, sy, h1);
+        P::predict(k, Wd, x1s, sy, h1, active(i + 1));
         // y-face i+1/2 between the north state of row i and the south state
         // of row i+1
         {
@@ -799,7 +819,7 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
         R Wn[NC], sE, sV;
         const uint32_t o = boff(i);
         if (reread && !early) src.load(o, Ul);
-        P::update(k, Un, dF, dG, h0, Uo, sE, sV);
+        P::update(k, Un, dF, dG, h0, Uo, sE, sV, active(i));
         P::prim(k, Uo, Wn);
         R s = P::speed(k, Wn);
         if (inner) {

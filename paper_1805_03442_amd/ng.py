@@ -46,7 +46,9 @@ class NgGas(C.Structure):
 class NgGrid(C.Structure):
     _fields_ = [("ndim", C.c_int32), ("reserved", C.c_int32), ("nx", C.c_int64),
                 ("ny", C.c_int64), ("h", C.c_double), ("bc", C.c_int32 * 4),
-                ("src_amp", C.c_double), ("src_lambda", C.c_double)]
+                ("src_amp", C.c_double), ("src_lambda", C.c_double),
+                ("src_yc", C.c_double), ("src_hw", C.c_double), ("wedge_x0", C.c_double),
+                ("wedge_y0", C.c_double), ("wedge_tan", C.c_double)]
 
 
 class NgNumerics(C.Structure):
@@ -138,13 +140,15 @@ def make_gas(g: dict) -> NgGas:
 
 
 def make_grid(nx: int, ny: int = 1, h: float | None = None, bc=(NG_BC_PERIODIC,) * 4,
-              source=(0.0, 0.0)) -> NgGrid:
+              source=(0.0, 0.0), wedge=(0.0, 0.0, 0.0)) -> NgGrid:
     """bc = (x-low, x-high, y-low, y-high) boundary kinds; source = (amplitude,
-    wavelength) of the forced wave of an NG_BC_SOURCE x-low end."""
+    wavelength[, y_centre, half_width]) of the forced wave of an NG_BC_SOURCE
+    x-low end; wedge = (x0, y0, tan) of an active wedge (tan <= 0: none)."""
     ndim = 1 if ny == 1 else 2
     h = float(h) if h is not None else 1.0 / nx
+    src = tuple(float(v) for v in source) + (0.0, 0.0)[len(source) - 2:]
     return NgGrid(ndim, 0, int(nx), int(ny), h, (C.c_int32 * 4)(*[int(b) for b in bc]),
-                  float(source[0]), float(source[1]))
+                  *src[:4], *[float(v) for v in wedge])
 
 
 def make_numerics(cfl=0.4, riemann=NG_HLLC, precision=NG_FP64, stiff_z=0.5) -> NgNumerics:
@@ -201,11 +205,11 @@ class Solver:
 
     def __init__(self, gas: dict, nx: int, ny: int = 1, W=None, U=None, h=None, cfl=0.4,
                  riemann=NG_HLLC, precision=NG_FP64, stiff_z=0.5, t0=0.0, stream=None,
-                 bc=(NG_BC_PERIODIC,) * 4, source=(0.0, 0.0)):
+                 bc=(NG_BC_PERIODIC,) * 4, source=(0.0, 0.0), wedge=(0.0, 0.0, 0.0)):
         L = lib()
         self.nx, self.ny = int(nx), int(ny)
         self.gas = make_gas(gas)
-        self.grid = make_grid(nx, ny, h, bc, source)
+        self.grid = make_grid(nx, ny, h, bc, source, wedge)
         self.num = make_numerics(cfl, riemann, precision, stiff_z)
         nbytes = C.c_size_t(0)
         check(L.ng_state_bytes(C.byref(self.grid), C.byref(self.num), C.byref(nbytes)),
@@ -321,9 +325,9 @@ class Batch:
 
     def add(self, gas: dict, nx: int, ny: int, W, t_end: float, max_steps: int = 2**62,
             h=None, cfl=0.4, riemann=NG_HLLC, stiff_z=0.5, t0=0.0, bc=(NG_BC_PERIODIC,) * 4,
-            source=(0.0, 0.0)):
+            source=(0.0, 0.0), wedge=(0.0, 0.0, 0.0)):
         """Returns the slot, or None when the batch is full (NG_EFULL)."""
-        g, gr = make_gas(gas), make_grid(nx, ny, h, bc, source)
+        g, gr = make_gas(gas), make_grid(nx, ny, h, bc, source, wedge)
         nm = make_numerics(cfl, riemann, self.precision, stiff_z)
         arr = _planes(W, ny)
         slot = C.c_int32(-1)

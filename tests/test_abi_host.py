@@ -40,7 +40,7 @@ def test_struct_sizes_match_header(ng):
     # the ctypes mirrors must have the C layout (checked through the sizes the
     # library itself reports for a known grid)
     assert C.sizeof(ng.NgGas) == 16 * 8
-    assert C.sizeof(ng.NgGrid) == 4 + 4 + 8 + 8 + 8 + 16 + 16
+    assert C.sizeof(ng.NgGrid) == 4 + 4 + 8 + 8 + 8 + 16 + 16 + 16 + 24
     assert C.sizeof(ng.NgNumerics) == 8 + 4 * 4 + 8
 
 
@@ -62,7 +62,8 @@ def test_state_bytes(ng):
                                          ("fy_1d", 0.1), ("precision", 5), ("bc", (4, 2)),
                                          ("bc", (0, 1)), ("bc", (2, 3)), ("bc", (3, 0)),
                                          ("source", (0.0, 0.1)), ("source", (0.6, 0.1)),
-                                         ("huge", 1 << 30)])
+                                         ("segment_1d", 0.1), ("wedge_1d", 0.3),
+                                         ("wedge_x0", -0.1), ("huge", 1 << 30)])
 def test_invalid_arguments_rejected_before_device_use(ng, field, value):
     import numpy as np
     from paper_1805_03442_amd import workloads as wl
@@ -90,7 +91,17 @@ def test_invalid_arguments_rejected_before_device_use(ng, field, value):
         # a source end with a zero wavelength, or an amplitude of rho0 / 2 or more
         bc = (3, 2, 0, 0)
         source = (value[1], value[0]) if value[0] == 0.0 else value
-    grid = ng.make_grid(nx, ny, bc=bc, source=source)
+    wedge = (0.0, 0.0, 0.0)
+    if field == "segment_1d":
+        # a source segment needs a 2D grid
+        bc, source = (3, 2, 0, 0), (1e-3, 0.1, 0.5, value)
+    elif field == "wedge_1d":
+        wedge = (0.0, 0.5, value)
+    elif field == "wedge_x0":
+        # the wedge's apex must not lie before x = 0
+        ny = 64
+        wedge = (value, 0.5, 0.3)
+    grid = ng.make_grid(nx, ny, bc=bc, source=source, wedge=wedge)
     if field == "huge":
         # 2^30 cells of FP64: byte offsets beyond 32 bits (the state is never read)
         grid = ng.make_grid(value, 1)

@@ -58,15 +58,17 @@ def comps(ny):
 
 
 def run_both(ng, gas, W, nx, ny, steps, precision, riemann=0, stiff_z=0.5, launch=None,
-             t_end=None, small_limit=None, bc=(0, 0, 0, 0), source=(0.0, 0.0)):
+             t_end=None, small_limit=None, bc=(0, 0, 0, 0), source=(0.0, 0.0), h=None,
+             wedge=(0.0, 0.0, 0.0)):
     import oracle
     oracle.build()
-    P = oracle.Problem(gas, nx, ny, riemann=riemann, stiff_z=stiff_z, bc=bc, source=source)
+    P = oracle.Problem(gas, nx, ny, h=h, riemann=riemann, stiff_z=stiff_z, bc=bc, source=source,
+                       wedge=wedge)
     U0 = P.prim_to_cons(W)
     say(f"case nx={nx} ny={ny} steps={steps} prec={precision} riemann={riemann} launch={launch} "
-        f"bc={bc} source={source} small_limit={small_limit}")
-    s = ng.Solver(gas, nx, ny, U=U0, precision=precision, riemann=riemann, stiff_z=stiff_z,
-                  bc=bc, source=source)
+        f"bc={bc} source={source} wedge={wedge} small_limit={small_limit}")
+    s = ng.Solver(gas, nx, ny, U=U0, h=h, precision=precision, riemann=riemann, stiff_z=stiff_z,
+                  bc=bc, source=source, wedge=wedge)
     if small_limit is not None:
         s.set_small_limit(small_limit)
     if launch:
@@ -640,3 +642,59 @@ def test_forced_source_paper_runs_to_t08(ng, stage):
             e = rel_l1(U[c], ref["U"][c])
             say(f"  fp32 rel_l1 {e}")
             assert np.all(e <= (FP32_TOL if stage == "linear" else 1e-3)), e
+
+
+# ------------------------------------------------ 2D sector run (section 3)
+
+@pytest.mark.parametrize("shape", [(100, 100, 0), (130, 70, 0), (40, 40, None)])
+def test_sector_2d(ng, shape):
+    """Active wedge, source segment, wall G1 and free outflow, on the per-step
+    kernels (square and ragged grids) and on the persistent small-solve path:
+    FP64 within 1e-12 of the state's scale (the device sine of the source;
+    each component within 1e-10 of its own maximum).  FP32: density and the
+    energies within 1e-5 relative L1; the momenta, pure perturbations of the
+    sound wave, within 1e-4.  The FP32 state holds deviations from one uniform
+    reference, the active background; in the passive part E_nu deviates from
+    it by rho0 tau0 Q0 = 0.5, and the pressure recovered from E - E_nu there
+    carries ~ulp(0.5) = 6e-8 of absolute error, ~5e-5 of the wave."""
+    nx, ny, small = shape
+    n = max(nx, ny)
+    L = 0.5 * n / 100.0
+    w = wl.workload_sector_2d(n=n, S=0.5, tau0=0.05, amp=1e-3, L=L)
+    W = w["W"][:, :ny, :nx].copy()
+    yc = 0.5 * ny * w["h"]
+    src = (1e-3, 0.1, yc, 0.05)
+    wedge = (0.0, yc, w["wedge"][2])
+    for prec in (ng.NG_FP64, ng.NG_FP32):
+        U, ref, d, U0 = run_both(ng, w["gas"], W, nx, ny, 120, prec, h=w["h"], bc=w["bc"],
+                                 source=src, wedge=wedge, small_limit=small)
+        assert d["status"] == 0 and d["steps"] == 120
+        if prec == ng.NG_FP64:
+            e = rel_linf(U, ref["U"])
+            es = state_linf(U, ref["U"])
+            say(f"sector {shape} fp64 rel_linf {e} state_linf {es:.3e}")
+            assert es <= FP64_TOL and np.all(e <= 1e-10), (e, es)
+        else:
+            e = rel_l1(U, ref["U"])
+            say(f"sector {shape} fp32 rel_l1 {e}")
+            assert np.all(e[[0, 3, 4]] <= FP32_TOL), e
+            assert np.all(e[[1, 2]] <= 1e-4), e
+    # the wedge matters: the same run with the medium active everywhere differs
+    U2, ref2, _, _ = run_both(ng, w["gas"], W, nx, ny, 120, ng.NG_FP64, h=w["h"], bc=w["bc"],
+                              source=src, small_limit=small)
+    assert not np.array_equal(U2, U)
+
+
+def test_sector_invalid_setups_refused(ng):
+    gas = wl.results_gas(0.5, 0.05)
+    W1 = wl.uniform_state(gas, 64)
+    with pytest.raises(ng.NgError):
+        ng.Solver(gas, 64, 1, W=W1, wedge=(0.0, 0.5, 0.3))
+    W2 = np.repeat(W1, 64, axis=1)
+    with pytest.raises(ng.NgError):
+        ng.Solver(gas, 64, 64, W=W2, wedge=(-0.1, 0.5, 0.3))
+    s = ng.Solver(gas, 64, 64, W=W2, wedge=(0.0, 0.5, 0.3), bc=(3, 1, 2, 2),
+                  source=(1e-3, 0.1, 0.5, 0.05))
+    s.step(5)
+    assert s.diagnostics()["status"] == 0
+    s.close()
