@@ -128,7 +128,7 @@ def main():
     ap.add_argument("--bounded-steps", type=int, default=200)
     ap.add_argument("--steps-1d", type=int, default=20000)
     ap.add_argument("--no-source-runs", action="store_true",
-                    help="skip the forced-source runs of section 3")
+                    help="skip the forced-source runs of section 3 (1D and the 2D sector)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain device copy of known size (for counter scaling)")
     args = ap.parse_args()
@@ -308,6 +308,39 @@ def main():
                               shock_faces=int((jumps > 5 * smooth).sum()))
             log(f"[bench] forced source {stage}: {res[stage]}")
         out["forced_source_1d"] = res
+
+        # the 2D sector run of section 3 (active 30-degree wedge from the
+        # source, wall G1, free flow G2-G4) to t = 1 in FP32 and FP64: the
+        # wave's amplitude inside and outside the wedge, the FP32 error
+        ws = wl.workload_sector_2d()
+        fin, rec = {}, {}
+        for name, prec in (("fp64", ng.NG_FP64), ("fp32", ng.NG_FP32)):
+            s = ng.Solver(ws["gas"], ws["nx"], ws["ny"], W=ws["W"], h=ws["h"], precision=prec,
+                          bc=ws["bc"], source=ws["source"], wedge=ws["wedge"])
+            from paper_1805_03442_amd import autotune
+            autotune.apply(s)
+            if prec == ng.NG_FP64:
+                Ub = s.conserved()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            taken = s.run_to_time(ws["t_end"])
+            el = time.perf_counter() - t0
+            fin[name] = s.conserved()
+            d = s.diagnostics()
+            s.close()
+            assert d["status"] == 0
+            rec[name] = {"steps": taken, "wall_ms": 1e3 * el,
+                         "cell_updates_per_s": ws["nx"] * ws["ny"] * taken / el}
+        rec["fp32"]["rel_l1_of_perturbation_vs_fp64"] = {
+            nm: float(np.abs(fin["fp32"][c] - fin["fp64"][c]).sum()
+                      / np.abs(fin["fp64"][c] - Ub[c]).sum())
+            for c, nm in enumerate(["rho", "rho_u", "rho_v", "E", "E_nu"])}
+        drho = np.abs(fin["fp64"][0] - Ub[0])
+        act = ws["active"]
+        out["sector_2d"] = dict(rec, workload=ws["name"], t_end=ws["t_end"],
+                                max_drho_in_wedge=float(drho[act].max()),
+                                max_drho_outside=float(drho[~act].max()))
+        log(f"[bench] sector: {out['sector_2d']}")
 
     if not args.no_fp64:
         # error of the FP32 result against the FP64 path after the same steps
