@@ -762,7 +762,8 @@ void fill_desc(InstDesc& d, const ng_gas* gas, const ng_grid* grid, const ng_num
         d.uref[3] = E_r;
         d.uref[4] = ev_r;
         d.p_r = p_r;
-        d.H_r = E_r + p_r;
+        d.e1_r = p_r / d.gm1;
+        d.H_r = d.e1_r + p_r;
         d.D_r = gas->Cv / gas->R * p_r - ev_r;
     }
 }
@@ -797,9 +798,11 @@ int ensure_stage(ng_batch* b, size_t bytes)
 // p > 0); on failure returns the reason.
 template <class R>
 const char* convert_cells(const double* data, int64_t n, int nc, double gm1, const double* ref,
-                          bool is_prim, int64_t i0, int64_t a, int64_t b, R* st, int64_t m)
+                          bool split, double e1_r, bool is_prim, int64_t i0, int64_t a, int64_t b,
+                          R* st, int64_t m)
 {
     double Wc[5], Uc[5];
+    const int iE = nc == 5 ? 3 : 2, iV = nc - 1;
     for (int64_t i = a; i < b; i++) {
         for (int c = 0; c < nc; c++) (is_prim ? Wc : Uc)[c] = data[c * n + i0 + i];
         if (is_prim)
@@ -810,6 +813,8 @@ const char* convert_cells(const double* data, int64_t n, int nc, double gm1, con
             if (!isfinite(Uc[c]) || !isfinite(Wc[c])) return "non-finite initial value";
             st[c * m + i] = (R)(Uc[c] - ref[c]);
         }
+        // deviation storage keeps E - E_nu in the energy slot
+        if (split) st[iE * m + i] = (R)((Uc[iE] - Uc[iV]) - e1_r);
         if (!(Wc[0] > 0.0) || !(Wc[nc == 5 ? 3 : 2] > 0.0))
             return "initial density and pressure must be positive";
     }
@@ -828,6 +833,7 @@ int upload_state(ng_batch* b, const Slot& s, const double* data, bool is_prim)
     const double ref5[5] = {s.d.uref[0], 0.0, 0.0, s.d.uref[3], s.d.uref[4]};
     const double ref4[4] = {s.d.uref[0], 0.0, s.d.uref[3], s.d.uref[4]};
     const double* ref = nc == 5 ? ref5 : ref4;
+    const bool split = b->prec != NG_FP64;
     int rc = ensure_stage(b, sizeof(R) * nc * (size_t)n);
     if (rc) return rc;
     const int64_t per = (int64_t)(b->stage_bytes / (sizeof(R) * nc));
@@ -843,13 +849,14 @@ int upload_state(ng_batch* b, const Slot& s, const double* data, bool is_prim)
         nt = nt < 1 ? 1 : (nt > max_threads ? max_threads : nt);
         std::vector<const char*> why(nt, nullptr);
         if (nt == 1) {
-            why[0] = convert_cells<R>(data, n, nc, gm1, ref, is_prim, i0, 0, m, st, m);
+            why[0] = convert_cells<R>(data, n, nc, gm1, ref, split, s.d.e1_r, is_prim, i0, 0, m, st,
+                                     m);
         } else {
             std::vector<std::thread> th;
             for (int t = 0; t < nt; t++)
                 th.emplace_back([&, t] {
-                    why[t] = convert_cells<R>(data, n, nc, gm1, ref, is_prim, i0, m * t / nt,
-                                              m * (t + 1) / nt, st, m);
+                    why[t] = convert_cells<R>(data, n, nc, gm1, ref, split, s.d.e1_r, is_prim,
+                                              i0, m * t / nt, m * (t + 1) / nt, st, m);
                 });
             for (auto& x : th) x.join();
         }
@@ -984,8 +991,8 @@ int read_conserved(ng_batch* b, int slot, double* out, bool prim)
         CK(b, hipMemcpy(U.data(), (void*)s.d.buf[cur], sizeof(double) * U.size(),
                         hipMemcpyDeviceToHost));
         if (b->prec == NG_MIXED) {
-            const double ref5[5] = {s.d.uref[0], 0.0, 0.0, s.d.uref[3], s.d.uref[4]};
-            const double ref4[4] = {s.d.uref[0], 0.0, s.d.uref[3], s.d.uref[4]};
+            const double ref5[5] = {s.d.uref[0], 0.0, 0.0, s.d.e1_r, s.d.uref[4]};
+            const double ref4[4] = {s.d.uref[0], 0.0, s.d.e1_r, s.d.uref[4]};
             const double* ref = nc == 5 ? ref5 : ref4;
             for (int c = 0; c < nc; c++)
                 for (int64_t i = 0; i < n; i++) U[c * n + i] += ref[c];
@@ -994,11 +1001,16 @@ int read_conserved(ng_batch* b, int slot, double* out, bool prim)
         std::vector<float> D((size_t)nc * n);
         CK(b, hipMemcpy(D.data(), (void*)s.d.buf[cur], sizeof(float) * D.size(),
                         hipMemcpyDeviceToHost));
-        const double ref5[5] = {s.d.uref[0], 0.0, 0.0, s.d.uref[3], s.d.uref[4]};
-        const double ref4[4] = {s.d.uref[0], 0.0, s.d.uref[3], s.d.uref[4]};
+        const double ref5[5] = {s.d.uref[0], 0.0, 0.0, s.d.e1_r, s.d.uref[4]};
+        const double ref4[4] = {s.d.uref[0], 0.0, s.d.e1_r, s.d.uref[4]};
         const double* ref = nc == 5 ? ref5 : ref4;
         for (int c = 0; c < nc; c++)
             for (int64_t i = 0; i < n; i++) U[c * n + i] = ref[c] + (double)D[c * n + i];
+    }
+    if (b->prec != NG_FP64) {
+        // the energy slot held E - E_nu
+        const int iE = nc == 5 ? 3 : 2, iV = nc - 1;
+        for (int64_t i = 0; i < n; i++) U[iE * n + i] += U[iV * n + i];
     }
     if (!prim) {
         memcpy(out, U.data(), sizeof(double) * U.size());

@@ -7,13 +7,21 @@
 // one fixed evaluation order; the library is built without multiply-add
 // contraction so that these are the IEEE results of that order.
 //
-// FP32 ("Dev32"): the state is stored as deviations dU = U - U_ref from a
-// uniform reference at rest (rho_r, 0, 0, E_r, Ev_r).  Every flux and source
-// is evaluated in a form in which the reference part cancels exactly:
-//   p - p_r       = (gamma - 1)(dE - rho|v|^2/2 - dEv)          (eq. (5))
-//   F - F(U_ref)  = (rho u, rho u^2 + dp, rho u v, u (H_r + dE + dp), u Ev)
+// FP32 ("Dev32"): the state is stored as deviations from a uniform reference
+// at rest, and the energy slot holds e = E - E_nu (the thermal and kinetic
+// part) instead of E: (d rho, rho u, rho v, de = e - e_r, dEv = E_nu - Ev_r)
+// with e_r = p_r/(gamma - 1).  Pressure then needs no difference of E and
+// E_nu (eq. (5): p = (gamma - 1)(e - rho|v|^2/2)), so a medium whose E_nu lies
+// far from the reference (the passive part of the sector run) keeps its
+// pressure accurate.  e obeys the energy equation minus the E_nu equation:
+// flux u (e + p), source rho (Q - I) + rho v.f minus the E_nu source.  Every
+// flux and source is evaluated in a form in which the reference part cancels
+// exactly:
+//   p - p_r       = (gamma - 1)(de - rho|v|^2/2)                 (eq. (5))
+//   F - F(U_ref)  = (rho u, rho u^2 + dp, rho u v, u (H_r + de + dp), u Ev),
+//                   H_r = e_r + p_r
 //   E_nue - E_nu  = (Cv/R) dp - dEv + (Cv/R p_r - Ev_r)          (eq. (7))
-//   U*_K - U_K    = q_K (rho, rho S_K, rho v, E + p + rho (S_K - u) S*, Ev)_K,
+//   U*_K - U_K    = q_K (rho, rho S_K, rho v, e + p + rho (S_K - u) S*, Ev)_K,
 //                   q_K = (S* - u_K)/(S_K - S*)                 (HLLC star jump)
 // so that the O(1) background never enters a difference of two fluxes.  FP32
 // rounding then acts on the perturbation, not on the background.
@@ -345,6 +353,7 @@ __device__ __noinline__ float relax_exact(float num, double z)
 struct K32 {
     float gam, gm1, igm1, CvR;
     float rho_r, p_r, ev_r, H_r, D_r;   // reference state and its cancelled constants
+                                        // (H_r = e_r + p_r, e = E - E_nu)
     float irho0, iRT0;                  // 1/rho0, 1/(R T0)
     float itau0, Q0, I0;                // closures of eq. (6) in log2/exp2 form
     float tr, tT, Qr, QT, Ir, IT;
@@ -384,10 +393,10 @@ __device__ __forceinline__ void prim32(const K32& k, const float* D, float* W)
         float v = D[2] * ir;
         float m2 = fmaf(D[1], u, D[2] * v);
         W[2] = v;
-        W[3] = k.gm1 * (fmaf(-0.5f, m2, D[3]) - D[4]);
+        W[3] = k.gm1 * fmaf(-0.5f, m2, D[3]);
         W[4] = D[4];
     } else {
-        W[2] = k.gm1 * (fmaf(-0.5f, D[1] * u, D[2]) - D[3]);
+        W[2] = k.gm1 * fmaf(-0.5f, D[1] * u, D[2]);
         W[3] = D[3];
     }
 }
@@ -489,8 +498,8 @@ __device__ __forceinline__ void flux32(const K32& k, const float* WL, const floa
         float deL = WL[iV], deR = WR[iV];
         float m2L = NC == 5 ? fmaf(mL, uL, (rL * vL) * vL) : mL * uL;
         float m2R = NC == 5 ? fmaf(mR, uR, (rR * vR) * vR) : mR * uR;
-        float dEL = fmaf(0.5f, m2L, fmaf(dpL, k.igm1, deL));
-        float dER = fmaf(0.5f, m2R, fmaf(dpR, k.igm1, deR));
+        float dEL = fmaf(0.5f, m2L, dpL * k.igm1);   // de = e - e_r
+        float dER = fmaf(0.5f, m2R, dpR * k.igm1);
         float HL = k.H_r + (dEL + dpL), HR = k.H_r + (dER + dpR);
         float UL[5], UR[5], FL[5], FR[5];
         UL[0] = WL[0];
@@ -532,8 +541,8 @@ __device__ __forceinline__ void flux32(const K32& k, const float* WL, const floa
     float vK = NC == 5 ? (left ? WL[2] : WR[2]) : 0.0f;
     float SK = left ? SL : SR, dK = left ? dL : dR, mK = left ? mL : mR;
     float m2K = NC == 5 ? fmaf(mK, uK, (rK * vK) * vK) : mK * uK;   // rho |v|^2
-    float dEK = fmaf(0.5f, m2K, fmaf(dpK, k.igm1, deK));
-    float HK = k.H_r + (dEK + dpK);   // E + p
+    float dEK = fmaf(0.5f, m2K, dpK * k.igm1);   // de = e - e_r
+    float HK = k.H_r + (dEK + dpK);   // e + p
     float evK = k.ev_r + deK;
     float q = (supL || supR) ? 0.0f : (Ss - uK) * rcp32(SK - Ss);
     float sq = SK * q, sqr = sq * rK;
@@ -574,7 +583,6 @@ __device__ __forceinline__ void update32(const K32& k, const float* Un, const fl
         if (NC == 5) Unew[2] = fmaf(dt, rho * k.fy, Unew[2]);
         yE = fmaf(rho, fmaf(u, k.fx, v * k.fy), yE);
     }
-    Unew[iP] = fmaf(dt, yE, Unew[iP]);
     float dv = dt * yV;
     if (k.dt * itau > k.stiff_z) {
         // exact relaxation from the start-of-step E_nu, FP64 factor
@@ -585,6 +593,8 @@ __device__ __forceinline__ void update32(const K32& k, const float* Un, const fl
     } else {
         Unew[iV] = fmaf(dt, yV, Unew[iV]);
     }
+    // e = E - E_nu gains the energy source less what E_nu gains
+    Unew[iP] = fmaf(dt, yE, Unew[iP]) - dv;
     srcE = dt * yE;
     srcV = dv;
 }
@@ -616,7 +626,6 @@ __device__ __forceinline__ void increment32(const K32& k, float ev_n, const floa
         if (NC == 5) dU[2] = fmaf(dt, rho * k.fy, dU[2]);
         yE = fmaf(rho, fmaf(u, k.fx, v * k.fy), yE);
     }
-    dU[iP] = fmaf(dt, yE, dU[iP]);
     float dv = dt * yV;
     if (k.dt * itau > k.stiff_z) {
         float num = fmaf(k.CvR, dp, k.D_r - ev_n);
@@ -626,6 +635,7 @@ __device__ __forceinline__ void increment32(const K32& k, float ev_n, const floa
     } else {
         dU[iV] = fmaf(dt, yV, dU[iV]);
     }
+    dU[iP] = fmaf(dt, yE, dU[iP]) - dv;
     srcE = dt * yE;
     srcV = dv;
 }

@@ -50,7 +50,9 @@ struct InstDesc {
     double fx, fy;
     // reference state of the FP32 deviation storage (zero for FP64)
     double uref[5];           // (rho_r, 0, 0, E_r, Ev_r)
-    double p_r, H_r, D_r;     // p_r, E_r + p_r, Cv/R p_r - Ev_r
+    // the FP32 and mixed states hold E - E_nu (not E) in the energy slot, as a
+    // deviation from e1_r = p_r / (gamma - 1); H_r = e1_r + p_r
+    double p_r, H_r, D_r, e1_r;   // ..., Cv/R p_r - Ev_r, p_r / (gamma - 1)
     // forced source at the x-low end: s = amp sin(omega t - k x) about the
     // background (rho_b, 0, 0, p_b, E_nu,b); uc = c / rho_b, c2 = c^2,
     // er = E_nu,b / rho_b

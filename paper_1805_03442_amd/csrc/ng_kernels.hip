@@ -122,6 +122,8 @@ struct Plain64 {
     static constexpr int kMinWaves = 2;
     // U^n of the updated row is re-read from cache (no registers to spare)
     static constexpr bool kKeepRows = false;
+    // the energy slot holds E itself
+    static constexpr bool kSplitE = false;
     using St = double;
     using K = K64;
     static __device__ K make(const InstDesc& d, double dt)
@@ -181,6 +183,8 @@ struct Dev32 {
     static constexpr int kMinWaves = 1;
     // the raw rows stay in registers until their update
     static constexpr bool kKeepRows = true;
+    // the energy slot holds e = E - E_nu (deviation from e_r)
+    static constexpr bool kSplitE = true;
     static __device__ K make(const InstDesc& d, double dt)
     {
         K k;
@@ -252,6 +256,7 @@ struct Mix32 {
     using K = K32;
     static constexpr int kMinWaves = 1;
     static constexpr bool kKeepRows = true;
+    static constexpr bool kSplitE = true;
     static __device__ K make(const InstDesc& d, double dt) { return Dev32<NC>::make(d, dt); }
     static __device__ void prim(const K& k, const St* U, R* W)
     {
@@ -309,15 +314,16 @@ __device__ __forceinline__ void acc_cell(Acc<typename P::R>& a, const typename P
                                          const typename P::St* U, const typename P::R* W,
                                          typename P::R s, typename P::R sE, typename P::R sV)
 {
-    // component slots (rho, m_x, m_y, E, E_nu)
-    if (NC == 5) {
-        for (int c = 0; c < 5; c++) a.tot[c] += (double)U[c];
-    } else {
-        a.tot[0] += (double)U[0];
-        a.tot[1] += (double)U[1];
-        a.tot[3] += (double)U[2];
-        a.tot[4] += (double)U[3];
-    }
+    // component slots (rho, m_x, m_y, E, E_nu); a split energy slot holds
+    // E - E_nu, whose deviation plus that of E_nu is the deviation of E
+    constexpr int iE = NC == 5 ? 3 : 2, iV = NC - 1;
+    const double ev = (double)U[iV];
+    const double e = P::kSplitE ? (double)U[iE] + ev : (double)U[iE];
+    a.tot[0] += (double)U[0];
+    a.tot[1] += (double)U[1];
+    if (NC == 5) a.tot[2] += (double)U[2];
+    a.tot[3] += e;
+    a.tot[4] += ev;
     a.src[0] += (double)sE;
     a.src[1] += (double)sV;
     a.smax = fmax(a.smax, s);
@@ -410,14 +416,16 @@ __device__ __forceinline__ StepCtl read_ctl(const InstCtrl& c)
 }
 
 // A forced-source ghost in the stored form: the full FP64 conserved state
-// (5 components; the 1D planes skip rho v) minus the reference (zero in FP64).
-template <class St, int NC>
+// (5 components; the 1D planes skip rho v) minus the reference (zero in FP64),
+// with E - E_nu in the energy slot of a split state.
+template <class St, int NC, bool Split>
 __device__ __forceinline__ void source_cell(const InstDesc& d, const double* g, St* U)
 {
     for (int c = 0; c < NC; c++) {
         const int q = NC == 5 ? c : (c < 2 ? c : c + 1);
         U[c] = (St)(g[q] - d.uref[q]);
     }
+    if (Split) U[NC == 5 ? 3 : 2] = (St)((g[3] - g[4]) - d.e1_r);
 }
 
 template <class R, int NC>
@@ -686,7 +694,7 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
         if (BC) {
             bool fy;
             (void)axis_cell(r, ny, d.bc[2], d.bc[3], fy);
-            if (srcx && src_row(r)) source_cell<St, NC>(d, gs, U);
+            if (srcx && src_row(r)) source_cell<St, NC, P::kSplitE>(d, gs, U);
             if (flipx) U[1] = -U[1];
             if (fy) U[2] = -U[2];
         }
@@ -925,7 +933,7 @@ __device__ __forceinline__ void march1d(const InstDesc& d, const typename P::K& 
             bool f;
             const int64_t xr = sg * kInterior - kHalo + lane;
             (void)axis_cell(xr, n, d.bc[0], d.bc[1], f);
-            if (d.bc[0] == kBcSource && xr < 0) source_cell<St, NC>(d, gsrc + (xr == -1 ? 0 : 5), Uc);
+            if (d.bc[0] == kBcSource && xr < 0) source_cell<St, NC, P::kSplitE>(d, gsrc + (xr == -1 ? 0 : 5), Uc);
             if (f) Uc[1] = -Uc[1];
         }
         P::prim(k, Uc, W);

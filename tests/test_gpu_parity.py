@@ -653,10 +653,10 @@ def test_sector_2d(ng, shape):
     FP64 within 1e-12 of the state's scale (the device sine of the source;
     each component within 1e-10 of its own maximum).  FP32: density and the
     energies within 1e-5 relative L1; the momenta, pure perturbations of the
-    sound wave, within 1e-4.  The FP32 state holds deviations from one uniform
-    reference, the active background; in the passive part E_nu deviates from
-    it by rho0 tau0 Q0 = 0.5, and the pressure recovered from E - E_nu there
-    carries ~ulp(0.5) = 6e-8 of absolute error, ~5e-5 of the wave."""
+    sound wave, within 1e-4 (measured 1.7e-5 to 3e-5).  The FP32 state holds
+    deviations from one uniform reference, the active background; in the
+    passive part the stored E_nu deviation is -rho0 tau0 Q0 = -0.5, whose
+    rounding (ulp(0.5) = 6e-8) enters the relaxation source every step."""
     nx, ny, small = shape
     n = max(nx, ny)
     L = 0.5 * n / 100.0
