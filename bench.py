@@ -196,6 +196,13 @@ def main():
         out["roofline"]["alu"] = {"achieved": ach, "peak": VALU_PEAK_TLANEOPS,
                                   "unit": "T lane-op/s", "frac": ach / VALU_PEAK_TLANEOPS,
                                   "valu_insts_per_launch": insts}
+        m = vr["mean_per_dispatch"]
+        if "SQ_ACTIVE_INST_VALU" in m and "GRBM_GUI_ACTIVE" in m:
+            # share of the kernel's cycles in which a SIMD issues VALU work:
+            # 4 cycles per wave64 instruction over 1024 SIMDs, against the
+            # GPU-busy cycles of one of the 8 XCDs
+            out["roofline"]["alu"]["valu_busy"] = (m["SQ_ACTIVE_INST_VALU"] * 4 / 1024
+                                                   / (m["GRBM_GUI_ACTIVE"] / 8))
 
     if not args.no_fp64:
         log(f"[bench] FP64: timing {args.fp64_steps} steps")
