@@ -155,3 +155,68 @@ def test_batch_512_instances_sampled_fp64(ng, oracle_mod):
         assert np.array_equal(U[[0, 1, 3, 4]], ref["U"][[0, 1, 3, 4]])
         assert b.diagnostics(slots[j])["t"] == ref["t"]
     b.close()
+
+
+@pytest.mark.parametrize("prec_name", ["fp64", "fp32"])
+def test_1d_at_the_32bit_offset_limit(ng, oracle_mod, prec_name):
+    """The largest grids the 32-bit plane offsets allow: 2^29 cells in FP64,
+    2^30 in FP32 (byte offsets up to 2^32 - 8 and 2^32 - 4).  One step from a
+    state perturbed near the start, the middle and the end; the first, middle
+    and last cells equal the oracle stepping 11-cell windows of the same state
+    with the GPU's dt: FP64 bit for bit; FP32 within 1e-4 of the step's own
+    change on the sampled cells (one step of the uniform-reference FP32 state
+    rounds each cell's change at ~1e-7 of it)."""
+    import ctypes as C
+    fp64 = prec_name == "fp64"
+    n = 1 << (29 if fp64 else 30)
+    gas = dict(wl.BASE_GAS)
+    b = wl.background(gas)
+    say(f"max-size 1D {prec_name}: building {n} cells")
+    U = np.empty((4, n))
+    U[0].fill(b["rho"])
+    U[1].fill(0.0)
+    U[2].fill(b["p"] / (gas["gamma"] - 1.0) + b["ev"])
+    U[3].fill(b["ev"])
+    m = 300
+    bump = 0.01 * np.sin(2.0 * np.pi * np.arange(m) / m)
+    spots = [0, n // 2 - m // 2, n - m]
+    for s0 in spots:
+        U[0, s0:s0 + m] += bump
+        U[1, s0:s0 + m] += 0.5 * bump
+        U[2, s0:s0 + m] += 3.0 * bump
+    s = ng.Solver(gas, n, 1, U=U, precision=ng.NG_FP64 if fp64 else ng.NG_FP32)
+    s.set_small_limit(0)
+    say(f"max-size 1D {prec_name}: one step")
+    s.step(1)
+    d = s.diagnostics()
+    assert d["status"] == 0 and d["steps"] == 1
+    dt = d["dt_last"]
+    V = np.empty(4 * n)
+    rc = ng.lib().ng_get_conserved(s.h, V.ctypes.data_as(C.POINTER(C.c_double)))
+    assert rc == 0
+    V = V.reshape(4, n)
+    s.close()
+    say(f"max-size 1D {prec_name}: oracle windows")
+    P = oracle_mod.Problem(gas, 2 * R + 1, 1, h=1.0 / n)
+    pts = [0, 1, 2, 150, n // 2 - 1, n // 2, n - 151, n - 3, n - 2, n - 1]
+    num, den = 0.0, 0.0
+    for j in pts:
+        cols = np.arange(j - R, j + R + 1) % n
+        win = np.zeros((5, 1, 2 * R + 1))
+        win[[0, 1, 3, 4], 0, :] = U[:, cols]
+        st, Vw, _ = P.step(win, dt)
+        assert st == 0
+        ref = Vw[[0, 1, 3, 4], 0, R]
+        if fp64:
+            assert np.array_equal(V[:, j], ref), j
+        # the FP32 state is compared on the change of the step
+        num += float(np.abs(V[:, j] - ref).sum())
+        den += float(np.abs(ref - U[:, j]).sum())
+    say(f"max-size 1D {prec_name}: sampled error over the step's change {num / den:.3e}")
+    if not fp64:
+        assert num / den <= 1e-4
+    # cells far from every bump keep the background (exactly in FP64)
+    if fp64:
+        assert np.array_equal(V[:, n // 4], U[:, n // 4])
+    else:
+        assert np.allclose(V[:, n // 4], U[:, n // 4], rtol=0, atol=1e-6)
