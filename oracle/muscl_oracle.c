@@ -20,8 +20,8 @@
  *   slopes       minmod-limited undivided differences of W (eq. (14) with xi = 0;
  *                the paper does not name its limiter: minmod is our reading).
  *   predictor    primitive (Hancock) half step with the quasi-linear form of
- *                eqs. (1)-(5) and the sources at t^n ("two-step predictor-corrector",
- *                section 2.3; the predictor's form is our reading).
+ *                eqs. (1)-(5) and the sources at t^n (section 2.3 names a
+ *                two-step predictor-corrector; the predictor's form is our reading).
  *   face states  W^L = W_j^{n+1/2} + sigma_j/2,  W^R = W_{j+1}^{n+1/2} - sigma_{j+1}/2
  *                (eq. (14), xi = 0).
  *   flux         HLL, eq. (13), with the Davis wave speeds printed below it, or
