@@ -219,15 +219,20 @@ int ng_set_small_limit(ng_solver* s, int64_t max_cells);
  * kernel (0); see ng_batch_set_fused_accept. */
 int ng_set_fused_accept(ng_solver* s, int32_t on);
 
-/* Kernel timing: ng_enable_timing(s, nsteps) with nsteps > 0 makes later
- * ng_step calls launch each step directly (no graph), each step and finalize
- * kernel recording its own start and end in HIP events (the launch carries
- * the events, so no event packets sit between the kernels); the events for
- * nsteps steps are created here, outside any timed region; 0 turns it off.
+/* Kernel timing: ng_enable_timing(s, nsteps, every) with nsteps > 0 makes
+ * later ng_step calls launch each step directly (no graph).  The step and
+ * finalize kernels of steps every-1, 2*every-1, ... and of the last step of
+ * each call (counting from 0) record their own start and end in HIP events
+ * (the launch carries the events, so no event packets sit between the
+ * kernels); the other steps launch without events.  every >= 1: 1 times every
+ * step, a larger stride keeps the cost of the timed launches (a few
+ * microseconds each) out of the run's total.  The events for nsteps steps are
+ * created here, outside any timed region; nsteps 0 turns timing off.  EINVAL
+ * for nsteps < 0 or every < 1.
  * ng_kernel_time returns the mean kernel durations in milliseconds over the
- * last timed ng_step call (finalize_ms 0 when the step kernel accepted its own
- * steps) and the number of step launches timed. */
-int ng_enable_timing(ng_solver* s, int32_t nsteps);
+ * timed launches of the last timed ng_step call (finalize_ms 0 when the step
+ * kernel accepted its own steps) and the number of step launches timed. */
+int ng_enable_timing(ng_solver* s, int32_t nsteps, int32_t every);
 int ng_kernel_time(ng_solver* s, double* step_ms, double* finalize_ms, int64_t* launches);
 
 const char* ng_last_error(const ng_solver* s);

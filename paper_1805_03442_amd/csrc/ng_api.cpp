@@ -275,6 +275,7 @@ struct ng_batch {
     std::vector<int32_t> h_insts;
     // timing
     bool timing = false;
+    int timing_every = 1;
     std::vector<hipEvent_t> ev_pool;
     double t_step_ms = 0.0, t_fin_ms = 0.0;
     int64_t t_launches = 0;
@@ -491,9 +492,11 @@ int enqueue_small(ng_batch* b, int64_t nsteps, hipStream_t st)
 bool any_big(const ng_batch* b) { return b->ninst[1] + b->ninst[2] > 0; }
 bool any_small(const ng_batch* b) { return b->nsmall[1] + b->nsmall[2] > 0; }
 
-// Timed variant: each step and finalize kernel (big solves) records its own
-// start and end in events of the pool (no event packets between launches), or
-// events around the persistent launch (small solves; reported per step).
+// Timed variant: the step and finalize kernels (big solves) of every
+// timing_every-th step and of the last step record their own start and end in
+// events of the pool (no event packets between launches), the other steps
+// launch as in enqueue_one;
+// small solves: events around the persistent launch (reported per step).
 int enqueue_timed(ng_batch* b, int64_t nsteps)
 {
     size_t ne = 0;
@@ -513,6 +516,13 @@ int enqueue_timed(ng_batch* b, int64_t nsteps)
         ne = 2;
     }
     for (int64_t i = 0; i < nsteps && any_big(b); i++) {
+        // time steps every-1, 2*every-1, ... and the last one: the first timed
+        // launch never follows an idle GPU
+        if ((i + 1) % b->timing_every && i != nsteps - 1) {
+            int rc = enqueue_one(b, b->stream);
+            if (rc) return rc;
+            continue;
+        }
         for (int dim = 1; dim <= 2; dim++) {
             if (!b->ninst[dim]) continue;
             hipEvent_t e0 = get_event(b, ne), e1 = get_event(b, ne + 1), e2 = get_event(b, ne + 2),
@@ -1235,11 +1245,13 @@ int ng_set_graph_steps(ng_solver* s, int32_t steps)
     return NG_OK;
 }
 
-int ng_enable_timing(ng_solver* s, int32_t nsteps)
+int ng_enable_timing(ng_solver* s, int32_t nsteps, int32_t every)
 {
-    if (!s || nsteps < 0) return NG_EINVAL;
+    if (!s || nsteps < 0 || every < 1) return NG_EINVAL;
     s->b->timing = nsteps != 0;
-    size_t need = (size_t)nsteps * 4 * 2;   // 4 per step and dimension
+    s->b->timing_every = every;
+    // 2 around a persistent launch, 4 per timed step and dimension
+    size_t need = nsteps ? 2 + ((size_t)nsteps + every - 1) / every * 4 * 2 : 0;
     if (need && !get_event(s->b, need - 1)) return solver_rc(s, dev_err(s->b, hipErrorOutOfMemory, "hipEventCreate"));
     return NG_OK;
 }

@@ -105,7 +105,7 @@ def lib():
             "ng_set_graph_steps": ([vp, i32], C.c_int),
             "ng_set_small_limit": ([vp, i64], C.c_int),
             "ng_set_fused_accept": ([vp, i32], C.c_int),
-            "ng_enable_timing": ([vp, i32], C.c_int),
+            "ng_enable_timing": ([vp, i32, i32], C.c_int),
             "ng_kernel_time": ([vp, dp, dp, C.POINTER(i64)], C.c_int),
             "ng_last_error": ([vp], C.c_char_p),
             "ng_destroy": ([vp], None),
@@ -272,8 +272,8 @@ class Solver:
     def set_graph_steps(self, k: int):
         check(lib().ng_set_graph_steps(self.h, int(k)), "ng_set_graph_steps", self._err())
 
-    def enable_timing(self, nsteps: int):
-        check(lib().ng_enable_timing(self.h, int(nsteps)), "ng_enable_timing")
+    def enable_timing(self, nsteps: int, every: int = 1):
+        check(lib().ng_enable_timing(self.h, int(nsteps), int(every)), "ng_enable_timing")
 
     def kernel_time(self):
         a, b, n = C.c_double(0), C.c_double(0), C.c_int64(0)

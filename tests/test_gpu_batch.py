@@ -149,5 +149,18 @@ def test_graph_replay_equals_direct_launches(ng):
         b.set_graph_steps(4096)
         b.step(80)              # direct launches (below the graph length)
         assert np.array_equal(a.conserved(), b.conserved())
+        # timed launches, one step in three carrying events
+        c = ng.Solver(gas, n, n, W=W, precision=prec)
+        c.set_small_limit(0)
+        c.enable_timing(40, 3)
+        c.step(40)
+        step_ms, fin_ms, launches = c.kernel_time()
+        assert launches == 14 and step_ms > 0.0
+        c.enable_timing(0)
+        c.step(40)
+        assert np.array_equal(a.conserved(), c.conserved())
+        with pytest.raises(ng.NgError):
+            c.enable_timing(8, 0)
         a.close()
         b.close()
+        c.close()
