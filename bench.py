@@ -24,7 +24,10 @@ Prints one JSON line:
               FP64 and mixed, with the FP32 / mixed error against FP64
   fp32_vs_fp64, mixed_vs_fp64  relative L1 differences after the same steps
   cpu_baseline  the serial FP64 oracle on whole steps of the same grid (about
-              10 s of one host core)
+              10 s of one host core), the host CPU model, and batch_fleet: the
+              512-instance 1D batch workload's sample on the oracle in one
+              process per host core (aggregate rate, solves/s extrapolated)
+  timing      one step in eight carries the HIP events of its kernels
 Input: seeded synthetic isotropic k^-2 density field (|k| <= 64, rms 1e-3),
 isentropic pressure, fluid at rest; gas of eqs. (1)-(7) with Q_T = 2.
 """
@@ -101,6 +104,20 @@ def timed_run(ng, torch, gas, W, n, steps, warmup, precision, bc=(0, 0, 0, 0)):
     return dict(total_ms=total_ms, step_ms=step_ms, fin_ms=fin_ms, launches=launches, diag=d)
 
 
+def host_cpu():
+    """Model name of the host CPU and the number of cores this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return dict(model=model, cores_available=len(os.sched_getaffinity(0)))
+
+
 def cpu_baseline(gas, W, n, min_seconds=10.0, max_steps=8):
     """The serial FP64 oracle on whole steps of the same grid (dt of eq. (16)
     and the update), repeated until about ``min_seconds`` of CPU work."""
@@ -118,7 +135,50 @@ def cpu_baseline(gas, W, n, min_seconds=10.0, max_steps=8):
         steps += 1
     return dict(value=steps * n * n / el, unit="cell-updates/s", cores=1, kind="oracle",
                 sample=f"{steps} full steps (dt from eq. (16) + the update) of the {n}x{n} "
-                       f"grid, serial FP64 C oracle on one host core, {el:.1f} s")
+                       f"grid, serial FP64 C oracle on one host core, {el:.1f} s",
+                host=host_cpu())
+
+
+def _oracle_instance(task):
+    """Worker of cpu_fleet: one batch instance on the serial FP64 oracle."""
+    import oracle
+    gas, nx, W, steps = task
+    P = oracle.Problem(gas, nx, 1)
+    U = P.prim_to_cons(W)
+    t0 = time.perf_counter()
+    r = P.run(U, steps)
+    el = time.perf_counter() - t0
+    assert r["status"] == 0 and r["steps"] == steps
+    return nx * steps, el
+
+
+def cpu_fleet(count=512, steps_each=10000, every=8, steps=400, max_workers=16):
+    """The batch workload (count uneven 1D instances, steps_each steps each) on
+    the serial FP64 oracle, one process per host core: every ``every``-th
+    instance for ``steps`` steps, the processes fed largest first; aggregate
+    cell-updates/s over the wall time, and the whole workload's solves/s
+    extrapolated from it.  Runs before anything touches the GPU (the worker
+    processes are forked)."""
+    import multiprocessing as mp
+    import oracle
+    from paper_1805_03442_amd import workloads as wl
+    oracle.build()
+    insts = wl.batch_1d_instances(count, steps=steps_each)
+    sample = sorted(insts[::every], key=lambda i: -i["nx"])
+    workers = max(1, min(max_workers, len(os.sched_getaffinity(0))))
+    tasks = [(i["gas"], i["nx"], i["W"], steps) for i in sample]
+    with mp.get_context("fork").Pool(workers) as pool:
+        t0 = time.perf_counter()
+        res = pool.map(_oracle_instance, tasks, chunksize=1)
+        wall = time.perf_counter() - t0
+    done = float(sum(r[0] for r in res))
+    rate = done / wall
+    total = float(sum(i["nx"] for i in insts)) * steps_each
+    return dict(value=rate, unit="cell-updates/s", cores=workers, kind="oracle",
+                solves_per_s_extrapolated=count / (total / rate),
+                sample=f"{len(sample)} of the {count} batch instances (every {every}th) x "
+                       f"{steps} steps, one serial FP64 oracle process per core, {wall:.1f} s "
+                       f"wall; solves/s extrapolated to {count} instances x {steps_each} steps")
 
 
 def main():
@@ -144,6 +204,13 @@ def main():
         print("bench.py measures one GPU: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+
+    fleet = None
+    if not args.no_cpu_baseline:
+        # before the GPU is touched: the oracle's worker processes are forked
+        log("[bench] CPU fleet: the batch instances on the oracle, one process per core")
+        fleet = cpu_fleet()
+        log(f"[bench] oracle fleet {fleet['value']:.3e} cell-updates/s on {fleet['cores']} cores")
 
     import numpy as np
     import torch
@@ -394,6 +461,7 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline: oracle steps of the full grid")
         out["cpu_baseline"] = cpu_baseline(gas, W, n)
+        out["cpu_baseline"]["batch_fleet"] = fleet
         log(f"[bench] oracle {out['cpu_baseline']['value']:.3e} cell-updates/s")
 
     print(json.dumps(out), flush=True)
