@@ -26,7 +26,9 @@ Prints one JSON line:
   cpu_baseline  the serial FP64 oracle on whole steps of the same grid (about
               10 s of one host core), the host CPU model, and batch_fleet: the
               512-instance 1D batch workload's sample on the oracle in one
-              process per host core (aggregate rate, solves/s extrapolated)
+              process per host core (aggregate rate, solves/s extrapolated),
+              and per_config_1d: the two 1D workloads on one core
+  acoustic_1d_1024  the 1024-cell FP64 acoustic run (2000 steps) on the GPU
   timing      one step in eight carries the HIP events of its kernels
 Input: seeded synthetic isotropic k^-2 density field (|k| <= 64, rms 1e-3),
 isentropic pressure, fluid at rest; gas of eqs. (1)-(7) with Q_T = 2.
@@ -137,6 +139,29 @@ def cpu_baseline(gas, W, n, min_seconds=10.0, max_steps=8):
                 sample=f"{steps} full steps (dt from eq. (16) + the update) of the {n}x{n} "
                        f"grid, serial FP64 C oracle on one host core, {el:.1f} s",
                 host=host_cpu())
+
+
+def oracle_1d_configs():
+    """The oracle on the two 1D workloads: the 1024-cell acoustic run whole
+    (2000 steps), the 2^20-cell multi-mode run for 10 steps (its rate, and the
+    20000-step run's time extrapolated from it)."""
+    import oracle
+    from paper_1805_03442_amd import workloads as wl
+    oracle.build()
+    res = {}
+    for w, steps in ((wl.workload_1d_acoustic(), None), (wl.workload_1d_multimode(), 10)):
+        k = w["steps"] if steps is None else steps
+        P = oracle.Problem(w["gas"], w["nx"], 1)
+        U = P.prim_to_cons(w["W"])
+        t0 = time.perf_counter()
+        r = P.run(U, k)
+        el = time.perf_counter() - t0
+        assert r["status"] == 0 and r["steps"] == k
+        rate = w["nx"] * k / el
+        res[w["name"]] = dict(value=rate, unit="cell-updates/s", cores=1, steps_timed=k,
+                              seconds=el, run_seconds_extrapolated=w["nx"] * w["steps"] / rate
+                              if steps is not None else None)
+    return res
 
 
 def _oracle_instance(task):
@@ -335,6 +360,28 @@ def main():
                       / np.abs(fin1["fp64"][c] - U0[c]).sum()) for c in (0, 1, 3, 4))
         out["periodic_1d_2e20"] = dict(res1, steps=k + 20, workload=w1["name"])
 
+    if args.steps_1d > 0:
+        # the 1024-cell acoustic mode in FP64, its whole run of 2000 steps (one
+        # persistent workgroup; a first run loads the kernel)
+        w0 = wl.workload_1d_acoustic()
+        for rep in range(2):
+            s = ng.Solver(w0["gas"], w0["nx"], 1, W=w0["W"], precision=ng.NG_FP64)
+            torch.cuda.synchronize()
+            st = torch.cuda.current_stream()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            s.step(w0["steps"])
+            e1.record(st)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            s.close()
+        out["acoustic_1d_1024"] = {"workload": w0["name"], "precision": "fp64",
+                                   "steps": w0["steps"], "run_ms": ms,
+                                   "value": w0["nx"] * w0["steps"] / (ms * 1e-3),
+                                   "unit": "cell-updates/s"}
+        log(f"[bench] 1D 1024 FP64 acoustic run: {ms:.2f} ms for {w0['steps']} steps")
+
     if args.bounded_steps > 0:
         # the same grid between reflecting walls (x) and outflow ends (y):
         # ghost cells from the boundary rules instead of wrap-around
@@ -462,6 +509,7 @@ def main():
         log("[bench] CPU baseline: oracle steps of the full grid")
         out["cpu_baseline"] = cpu_baseline(gas, W, n)
         out["cpu_baseline"]["batch_fleet"] = fleet
+        out["cpu_baseline"]["per_config_1d"] = oracle_1d_configs()
         log(f"[bench] oracle {out['cpu_baseline']['value']:.3e} cell-updates/s")
 
     print(json.dumps(out), flush=True)
