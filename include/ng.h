@@ -202,7 +202,14 @@ int ng_get_conserved(ng_solver* s, double* cons_out);
 /* Launch shape of the step kernel: rows per work item (2D) or 60-cell
  * segments per work item (1D), and waves per workgroup.  Results do not
  * depend on it (every cell's arithmetic is the same); only the order of the
- * FP64 total sums does.  0 keeps the current value. */
+ * FP64 total sums does.  0 keeps the current value; -1 (the default)
+ * chooses from the solves launched together (all big solves of the dim): 2D
+ * the largest of 32, 16, 8 and 4 rows at which their work items (one
+ * wavefront each) add up to at least 4096, else 4; 1D the largest of 4, 2
+ * and 1 segments reaching 1024 work items, else 1.  A lone grid smaller than
+ * 4096^2 so keeps the SIMDs busy; a batch with work enough keeps long
+ * chunks.  Waves per workgroup 1, 2 or 4 (default 4).  2D rows below 4 and
+ * other values: EINVAL. */
 int ng_set_launch(ng_solver* s, int32_t rows_per_item, int32_t waves_per_block);
 
 /* Steps per captured graph in ng_run_to_time (default 64). */

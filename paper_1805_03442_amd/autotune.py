@@ -22,7 +22,7 @@ from . import workloads as wl
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
 
 CANDIDATES = {
-    2: [(r, w) for r in (8, 16, 24, 32, 48, 64) for w in (1, 2, 4)],
+    2: [(r, w) for r in (4, 8, 16, 24, 32, 48, 64) for w in (1, 2, 4)],
     1: [(s, w) for s in (1, 2, 4, 8, 16, 32) for w in (1, 2, 4)],
 }
 
@@ -46,24 +46,14 @@ def load_cache(path: str = CACHE) -> dict:
 
 
 def lookup(nx: int, ny: int, precision: int, path: str = CACHE):
-    """(rows, waves) for this shape: the exact bucket, else the nearest bucket of
-    the same dimension and precision (by log distance of the cell count), else
-    None (library defaults)."""
+    """(rows, waves) tuned for this shape's bucket, else None: the library's
+    automatic per-solve shape (rows or segments per item chosen from the grid
+    size) then applies."""
     cache = load_cache(path)
-    k = key(nx, ny, precision)
-    if k in cache:
-        e = cache[k]
-        return e["rows"], e["waves"]
-    prefix = k.split("_")[0] + "_" + k.split("_")[1] + "_"
-    best, bd = None, None
-    for kk, e in cache.items():
-        if not kk.startswith(prefix):
-            continue
-        a, b = kk[len(prefix):].split("x")
-        dist = abs(math.log2(int(a) * int(b)) - math.log2(max(nx * ny, 1)))
-        if bd is None or dist < bd:
-            best, bd = (e["rows"], e["waves"]), dist
-    return best
+    e = cache.get(key(nx, ny, precision))
+    if e is None:
+        return None
+    return e["rows"], e["waves"]
 
 
 def apply(solver: "ng.Solver", path: str = CACHE) -> bool:
@@ -125,7 +115,7 @@ def main():
     ap = argparse.ArgumentParser(description="tune step-kernel launch shapes")
     ap.add_argument("--shapes", default="4096x4096:fp32,4096x4096:fp64,4096x4096:mixed,"
                                         "1048576x1:fp32,1048576x1:fp64,1048576x1:mixed,"
-                                        "1024x1:fp64,16384x1:fp32,256x256:fp32,"
+                                        "16384x1:fp32,256x256:fp32,"
                                         "1024x1024:fp32,2048x2048:fp32")
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--out", default=CACHE, help="tuning cache to update")

@@ -14,6 +14,7 @@
 #include <map>
 #include <string>
 #include <thread>
+#include <utility>
 #include <vector>
 
 #include "../../include/ng.h"
@@ -26,8 +27,20 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kMinRows2D = 4;        // smallest rows-per-item the partial space allows
-constexpr int kDefaultRows2D = 32;
-constexpr int kDefaultSegs1D = 8;
+// rows (2D) or segments (1D) per item -1: chosen from the grids (auto_rows),
+// the default
+constexpr int kAutoRows = -1;
+constexpr int kDefaultRows2D = kAutoRows;
+constexpr int kDefaultSegs1D = kAutoRows;
+// work items (one wavefront each) a solve's automatic shape aims for.  2D:
+// the 4096^2 grid has 8832 at 32 rows; smaller grids shorten their row chunks
+// rather than leave most SIMDs idle (256^2 FP32: 41 -> 15 us per step at 4
+// rows, 2048^2: 84 -> 74 us at 16).  1D: 2^20 cells take 4 segments per item
+// (4370 items), 2^17 two, 2^15 one (FP64 2^15: 36 -> 17 us per step against
+// 8 segments).
+constexpr int64_t kAutoItems2D = 4096;
+constexpr int64_t kAutoItems1D = 1024;
+constexpr int kMaxAutoSegs1D = 4;
 constexpr int kDefaultWaves = 4;
 constexpr int kDefaultGraphSteps = 64;
 // Solves up to this many cells run in the persistent one-workgroup kernel
@@ -245,6 +258,7 @@ struct ng_batch {
     std::vector<Slot> slots;
     std::map<size_t, size_t> free_list;  // offset -> size
     int rows[3] = {0, kDefaultSegs1D, kDefaultRows2D};
+    int auto_rows[3] = {0, 0, 0};   // automatic shape of the current big solves
     int waves[3] = {0, kDefaultWaves, kDefaultWaves};
     int remap = 1;
     int64_t small_limit = -1;  // cells; -1: by precision, 0: persistent path off
@@ -364,6 +378,31 @@ bool has_room(const ng_batch* b, size_t bytes)
     return false;
 }
 
+// Work items of a grid at r rows (2D) or r segments (1D) per item.
+int64_t items_at(int dim, int64_t nx, int64_t ny, int r)
+{
+    const int64_t strips = cdiv(nx, kInterior);
+    return dim == 2 ? strips * cdiv(ny, r) : cdiv(strips, r);
+}
+
+// Rows (2D) or 60-cell segments (1D) per work item under the automatic shape,
+// one value for all big solves of a dim launched together (grids given as
+// (nx, ny) pairs): 2D the largest of 32, 16, 8 and 4 rows at which their work
+// items add up to kAutoItems2D, else 4; 1D the largest of 4, 2 and 1 segments
+// reaching kAutoItems1D, else 1.  A batch with work enough for the whole GPU
+// keeps long chunks (fewer halo rows); a lone small grid gets short ones.
+int auto_rows(int dim, const std::vector<std::pair<int64_t, int64_t>>& grids)
+{
+    const int hi = dim == 2 ? 32 : kMaxAutoSegs1D, lo = dim == 2 ? kMinRows2D : 1;
+    const int64_t want = dim == 2 ? kAutoItems2D : kAutoItems1D;
+    for (int r = hi; r > lo; r >>= 1) {
+        int64_t n = 0;
+        for (const auto& g : grids) n += items_at(dim, g.first, g.second, r);
+        if (n >= want) return r;
+    }
+    return lo;
+}
+
 // Work decomposition of one solve for the current launch shape of its dim.
 // A solve accepts its own steps inside the step kernel only when it is the one
 // big solve of its dim: with several, each of their workgroups would pay the
@@ -373,7 +412,14 @@ void shape_solve(ng_batch* b, Slot& s, bool alone = true)
     InstDesc& d = s.d;
     int dim = s.dim;
     d.waves_per_block = s.small ? 1 : b->waves[dim];
-    d.rows_per_item = s.small ? (dim == 2 ? kSmallRows2D : kSmallSegs1D) : b->rows[dim];
+    if (s.small)
+        d.rows_per_item = dim == 2 ? kSmallRows2D : kSmallSegs1D;
+    else if (b->rows[dim] != kAutoRows)
+        d.rows_per_item = b->rows[dim];
+    else if (b->auto_rows[dim] > 0)
+        d.rows_per_item = b->auto_rows[dim];
+    else
+        d.rows_per_item = auto_rows(dim, {{d.nx, d.ny}});
     d.nstrips = (int32_t)cdiv(d.nx, kInterior);
     if (dim == 2)
         d.nchunks = (int32_t)cdiv(d.ny, d.rows_per_item);
@@ -401,11 +447,18 @@ int rebuild(ng_batch* b)
     const int64_t lim = b->small_limit >= 0 ? b->small_limit
                                             : (b->prec != NG_FP64 ? kSmallCells32 : kSmallCells64);
     int nbig[3] = {0, 0, 0};
+    std::vector<std::pair<int64_t, int64_t>> grids[3];
     for (int i = 0; i < b->capacity; i++)
         if (b->slots[i].live) {
-            b->slots[i].small = b->slots[i].d.ncell <= lim;
-            if (!b->slots[i].small) nbig[b->slots[i].dim]++;
+            Slot& s = b->slots[i];
+            s.small = s.d.ncell <= lim;
+            if (!s.small) {
+                nbig[s.dim]++;
+                grids[s.dim].push_back({s.d.nx, s.d.ny});
+            }
         }
+    for (int dim = 1; dim <= 2; dim++)
+        b->auto_rows[dim] = grids[dim].empty() ? 0 : auto_rows(dim, grids[dim]);
     for (int pass = 0; pass < 2; pass++) {
         for (int i = 0; i < b->capacity; i++) {
             Slot& s = b->slots[i];
@@ -1402,10 +1455,10 @@ int ng_batch_remove(ng_batch* b, int32_t slot)
 int ng_batch_set_launch(ng_batch* b, int32_t dim, int32_t rows_per_item, int32_t waves_per_block)
 {
     if (!b || (dim != 1 && dim != 2)) return NG_EINVAL;
-    if (rows_per_item < 0 || waves_per_block < 0 || waves_per_block > 4 ||
-        (waves_per_block & (waves_per_block - 1)))
+    if (rows_per_item < kAutoRows || waves_per_block < 0 ||
+        waves_per_block > 4 || (waves_per_block & (waves_per_block - 1)))
         return NG_EINVAL;
-    if (dim == 2 && rows_per_item != 0 && rows_per_item < kMinRows2D) return NG_EINVAL;
+    if (dim == 2 && rows_per_item > 0 && rows_per_item < kMinRows2D) return NG_EINVAL;
     int old_r = b->rows[dim], old_w = b->waves[dim];
     if (rows_per_item) b->rows[dim] = rows_per_item;
     if (waves_per_block) b->waves[dim] = waves_per_block;

@@ -134,3 +134,18 @@ def test_strerror(ng):
     L = ng.lib()
     for code in (0, -1, -2, -3, -4, -5):
         assert len(L.ng_strerror(code)) > 0
+
+
+def test_autotune_uses_exact_buckets_only(tmp_path):
+    """A tuned launch shape applies only to its own size bucket; other sizes
+    keep the library's automatic shape (lookup gives None)."""
+    import json
+    from paper_1805_03442_amd import autotune
+    from paper_1805_03442_amd import ng as _ng
+    p = tmp_path / "tuning.json"
+    p.write_text(json.dumps({"2d_fp32_4096x4096": {"rows": 32, "waves": 4, "step_ms": 0.2}}))
+    assert autotune.lookup(4096, 4096, _ng.NG_FP32, str(p)) == (32, 4)
+    assert autotune.lookup(4000, 4200, _ng.NG_FP32, str(p)) == (32, 4)   # same bucket
+    assert autotune.lookup(2048, 2048, _ng.NG_FP32, str(p)) is None
+    assert autotune.lookup(4096, 4096, _ng.NG_FP64, str(p)) is None
+    assert autotune.lookup(4096, 1, _ng.NG_FP32, str(p)) is None
