@@ -204,8 +204,8 @@ int ng_get_conserved(ng_solver* s, double* cons_out);
  * depend on it (every cell's arithmetic is the same); only the order of the
  * FP64 total sums does.  0 keeps the current value; -1 (the default)
  * chooses from the solves launched together (all big solves of the dim): 2D
- * the largest of 32, 16, 8 and 4 rows at which their work items (one
- * wavefront each) add up to at least 4096, else 4; 1D 8 segments if they
+ * the largest of 32, 24, 16, 12, 8, 6 and 4 rows at which their work items
+ * (one wavefront each) add up to at least 2304, else 4; 1D 8 segments if they
  * give 8192 work items, else the largest of 4, 2 and 1 reaching 1024, else
  * 1.  A lone grid smaller than
  * 4096^2 so keeps the SIMDs busy; a batch with work enough keeps long

@@ -33,13 +33,15 @@ constexpr int kAutoRows = -1;
 constexpr int kDefaultRows2D = kAutoRows;
 constexpr int kDefaultSegs1D = kAutoRows;
 // work items (one wavefront each) a solve's automatic shape aims for.  2D:
-// the 4096^2 grid has 8832 at 32 rows; smaller grids shorten their row chunks
-// rather than leave most SIMDs idle (256^2 FP32: 41 -> 15 us per step at 4
-// rows, 2048^2: 84 -> 74 us at 16).  1D: a lone 2^20-cell grid is fastest at
+// about three quarters of the 3072 wavefronts the FP32 step kernel keeps
+// resident (3 per SIMD); the 4096^2 grid has 8832 at 32 rows, smaller grids
+// shorten their row chunks rather than leave SIMDs idle (256^2 FP32: 41 -> 15
+// us per step at 4 rows, 1024^2: 43 -> 29 at 8, 2048^2: 84 -> 64 at 24).  1D: a lone 2^20-cell grid is fastest at
 // 4 segments per item (4370 items), 2^17 at 2, 2^15 at 1 (FP64 2^15: 36 -> 17
 // us per step against 8); 8 segments only pay with far more work, as in the
 // 512-solve batch (16500 items: 4 segments cost it 9 %).
-constexpr int64_t kAutoItems2D = 4096;
+constexpr int64_t kAutoItems2D = 2304;
+constexpr int kAutoRows2D[] = {32, 24, 16, 12, 8, 6, 4};
 constexpr int64_t kAutoItems1D = 1024;
 constexpr int64_t kAutoItems1DWide = 8192;   // for 8 segments per item
 constexpr int kDefaultWaves = 4;
@@ -388,8 +390,8 @@ int64_t items_at(int dim, int64_t nx, int64_t ny, int r)
 
 // Rows (2D) or 60-cell segments (1D) per work item under the automatic shape,
 // one value for all big solves of a dim launched together (grids given as
-// (nx, ny) pairs): 2D the largest of 32, 16, 8 and 4 rows at which their work
-// items add up to kAutoItems2D, else 4; 1D 8 segments if they give
+// (nx, ny) pairs): 2D the largest of kAutoRows2D at which their work items
+// add up to kAutoItems2D, else 4; 1D 8 segments if they give
 // kAutoItems1DWide items, else the largest of 4, 2 and 1 reaching
 // kAutoItems1D, else 1.  A batch with work enough for the whole GPU
 // keeps long chunks (fewer halo rows); a lone small grid gets short ones.
@@ -400,12 +402,15 @@ int auto_rows(int dim, const std::vector<std::pair<int64_t, int64_t>>& grids)
         for (const auto& g : grids) n += items_at(dim, g.first, g.second, r);
         return n;
     };
-    if (dim == 1 && items(8) >= kAutoItems1DWide) return 8;
-    const int hi = dim == 2 ? 32 : 4, lo = dim == 2 ? kMinRows2D : 1;
-    const int64_t want = dim == 2 ? kAutoItems2D : kAutoItems1D;
-    for (int r = hi; r > lo; r >>= 1)
-        if (items(r) >= want) return r;
-    return lo;
+    if (dim == 2) {
+        for (int r : kAutoRows2D)
+            if (items(r) >= kAutoItems2D) return r;
+        return kMinRows2D;
+    }
+    if (items(8) >= kAutoItems1DWide) return 8;
+    for (int r = 4; r > 1; r >>= 1)
+        if (items(r) >= kAutoItems1D) return r;
+    return 1;
 }
 
 // Work decomposition of one solve for the current launch shape of its dim.
