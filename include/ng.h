@@ -203,14 +203,13 @@ int ng_get_conserved(ng_solver* s, double* cons_out);
  * segments per work item (1D), and waves per workgroup.  Results do not
  * depend on it (every cell's arithmetic is the same); only the order of the
  * FP64 total sums does.  0 keeps the current value; -1 (the default)
- * chooses from the solves launched together (all big solves of the dim): 2D
- * the largest of 32, 24, 16, 12, 8, 6 and 4 rows at which their work items
- * (one wavefront each) add up to at least 2304, else 4; 1D 8 segments if they
- * give 8192 work items, else the largest of 4, 2 and 1 reaching 1024, else
- * 1.  A lone grid smaller than
- * 4096^2 so keeps the SIMDs busy; a batch with work enough keeps long
- * chunks.  Waves per workgroup 1, 2 or 4 (default 4).  2D rows below 4 and
- * other values: EINVAL. */
+ * chooses from the solves launched together (all big solves of the dim):
+ * 2D the largest of 32, 24, 16, 12, 8, 6 and 4 rows at which their work
+ * items (one wavefront each) add up to at least 2304, else 4; 1D 8 segments
+ * if they give 8192 work items, else the largest of 4, 2 and 1 reaching
+ * 1024, else 1.  A lone grid smaller than 4096^2 so keeps the SIMDs busy; a
+ * batch with work enough keeps long chunks.  Waves per workgroup 1, 2 or 4
+ * (default 4).  2D rows below 4 and other values: EINVAL. */
 int ng_set_launch(ng_solver* s, int32_t rows_per_item, int32_t waves_per_block);
 
 /* Steps per captured graph in ng_run_to_time (default 64). */
