@@ -284,8 +284,9 @@ static int64_t or_ghost(int64_t j, int64_t n, int bc_lo, int bc_hi, int* flip)
  * gives the wavelength but neither the amplitude nor the source's form; the
  * frozen-sound plane wave with unchanged specific vibrational energy is our
  * reading.  The E_nu part enters the domain only with the flow's own velocity,
- * i.e. at second order in the amplitude, so no linear check pins it.  t is the
- * time of the state the step starts from.
+ * i.e. at second order in the amplitude; what pins it is that with frozen
+ * relaxation and no pump or sink E_nu / rho stays uniform.  t is the time of
+ * the state the step starts from.
  */
 static double or_active(const or_grid* gr, int64_t j, int64_t k);
 

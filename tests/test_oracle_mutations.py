@@ -71,6 +71,7 @@ MUTATIONS = {
     "source_wave_runs_backwards": [("W[1] = (c / rho_b) * s;", "W[1] = -(c / rho_b) * s;")],
     "source_pressure_not_isentropic": [("W[3] = p_b + (c * c) * s;", "W[3] = p_b + c * s;")],
     "source_ignores_time": [("sin(omega * t - k * x)", "sin(-k * x)")],
+    "source_vibrational_energy_fixed": [("W[4] = ev_b + (ev_b / rho_b) * s;", "W[4] = ev_b;")],
     "source_ghost_one_cell_off": [("double x = ((double)j + 0.5) * gr->h;\n    double s =",
                                    "double x = ((double)j + 1.5) * gr->h;\n    double s =")],
     "wedge_inverted": [("return (dx >= 0.0 && fabs(y - gr->wedge_y0) <= dx * gr->wedge_tan) ? 1.0 : 0.0;",

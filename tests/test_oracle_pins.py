@@ -817,6 +817,28 @@ def test_forced_source_phase_follows_time(oracle_lib):
     assert not np.array_equal(V, P.step(a["U"], P.dt(a["U"]), a["t"])[1])
 
 
+def test_forced_source_keeps_specific_vibrational_energy(oracle_lib):
+    """With relaxation frozen (tau0 huge) and no pump or sink, E_nu is a
+    passive density carried with the mass: HLLC and HLL give it the mass flux
+    times E_nu / rho wherever that ratio is uniform.  The source's ghosts
+    carry the background's E_nu / rho (reading of the source: E_nu scales
+    with the density of the wave), so the ratio stays uniform to rounding
+    while the wave fills the domain; a ghost with the background's E_nu
+    itself would shift it by about the wave's relative amplitude."""
+    gas = dict(wl.BASE_GAS, tau0=1e12, Q0=0.0, I0=0.0)
+    n = 400
+    for riemann in (oracle_lib.HLLC, oracle_lib.HLL):
+        P = oracle_lib.Problem(gas, n, 1, riemann=riemann,
+                               bc=(oracle_lib.BC_SOURCE, oracle_lib.BC_OUTFLOW, 0, 0),
+                               source=(1e-2, 0.1))
+        r = P.run(P.prim_to_cons(wl.uniform_state(gas, n)), 10 ** 6, t_end=0.5)
+        assert r["status"] == 0 and r["t"] == 0.5
+        U = r["U"][:, 0]
+        assert np.max(np.abs(U[0] - 1.0)) > 5e-3          # the wave is in
+        phi = U[4] / U[0]
+        assert np.max(np.abs(phi - gas["Cv"] * gas["T0"])) <= 1e-11
+
+
 # ---------------------------------------------- 2D sector run (section 3)
 
 def _sector_problem(oracle_lib, n, L, S=0.5, tau0=0.05, amp=1e-3, wedge=None, source=None,
