@@ -437,6 +437,45 @@ def test_fp32_woodward_colella(ng):
     assert np.all(e <= 1e-4), e
 
 
+def test_blast_waves_converge_to_the_fine_grid(ng):
+    """Section 2.4's verification at the paper's sizes: the blast-wave density
+    at t = 0.038 on 1000 ... 8000 cells approaches that of a 128000-cell run
+    (the paper compares with a 10^5-cell solution).  The L1 difference from
+    the fine run averaged onto each grid falls with every doubling and by at
+    least a factor 2 from 1000 to 8000 cells; mass stays at its initial total
+    between the walls."""
+    import time
+    gas = dict(wl.BASE_GAS, Cv=0.0, tau_rho=0.0, tau_T=0.0, Q0=0.0, Q_rho=0.0, Q_T=0.0,
+               I0=0.0, I_rho=0.0, I_T=0.0, tau0=1.0)
+    bc = (W_, W_, 0, 0)
+
+    def run(n):
+        s = ng.Solver(gas, n, 1, W=wl.blast_waves_1d(n), precision=ng.NG_FP64, bc=bc)
+        m0 = s.diagnostics()["total"][0]
+        t0 = time.perf_counter()
+        s.run_to_time(0.038, 10 ** 7)
+        el = time.perf_counter() - t0
+        d = s.diagnostics()
+        rho = s.conserved()[0, 0]
+        s.close()
+        assert d["status"] == 0 and d["t"] == 0.038
+        assert abs(d["total"][0] - m0) <= 1e-12 * m0
+        return rho, d["steps"], el
+
+    nf = 128000
+    say(f"blast waves: fine run n={nf}")
+    rf, steps, el = run(nf)
+    say(f"blast waves: n={nf} took {steps} steps in {el:.1f} s")
+    errs = []
+    for n in (1000, 2000, 4000, 8000):
+        rho, steps, _ = run(n)
+        avg = rf.reshape(n, nf // n).mean(axis=1)
+        errs.append(float(np.mean(np.abs(rho - avg))))
+        say(f"blast waves: n={n} steps {steps} L1 difference from the fine run {errs[-1]:.4f}")
+    assert all(b < a for a, b in zip(errs, errs[1:])), errs
+    assert errs[-1] < 0.5 * errs[0], errs
+
+
 @pytest.mark.parametrize("bc", [(W_, W_, O_, O_), (O_, O_, W_, W_)])
 def test_fp32_2d_boundaries(ng, bc):
     gas = dict(wl.BASE_GAS, Q_T=2.0)
