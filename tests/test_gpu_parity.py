@@ -476,6 +476,36 @@ def test_blast_waves_converge_to_the_fine_grid(ng):
     assert errs[-1] < 0.5 * errs[0], errs
 
 
+@pytest.mark.parametrize("stage", ["linear", "nonlinear"])
+def test_forced_source_runs_converge_to_the_fine_grid(ng, stage):
+    """Section 3's 1D runs at the paper's sizes (N = 200 ... 1600) against a
+    102400-cell run, as the paper compares with a 10^5-cell solution: the
+    density at t = 0.8, the fine run averaged onto each grid, differs less
+    with every doubling of N (the nonlinear stage through its shock train)."""
+    w = wl.workload_forced_source(stage)
+
+    def run(n):
+        s = ng.Solver(w["gas"], n, 1, W=wl.uniform_state(w["gas"], n), precision=ng.NG_FP64,
+                      bc=w["bc"], source=w["source"])
+        s.run_to_time(w["t_end"], 10 ** 7)
+        d = s.diagnostics()
+        rho = s.conserved()[0, 0]
+        s.close()
+        assert d["status"] == 0 and d["t"] == w["t_end"]
+        return rho, d["steps"]
+
+    nf = 102400
+    rf, steps = run(nf)
+    say(f"forced source {stage}: n={nf} took {steps} steps")
+    errs = []
+    for n in (200, 400, 800, 1600):
+        rho, _ = run(n)
+        avg = rf.reshape(n, nf // n).mean(axis=1)
+        errs.append(float(np.mean(np.abs(rho - avg))))
+        say(f"forced source {stage}: n={n} L1 difference from the fine run {errs[-1]:.3e}")
+    assert all(b < a for a, b in zip(errs, errs[1:])), errs
+
+
 @pytest.mark.parametrize("bc", [(W_, W_, O_, O_), (O_, O_, W_, W_)])
 def test_fp32_2d_boundaries(ng, bc):
     gas = dict(wl.BASE_GAS, Q_T=2.0)
