@@ -829,6 +829,38 @@ def test_sector_2d(ng, shape):
     assert not np.array_equal(U2, U)
 
 
+def test_sector_run_converges_to_the_fine_grid(ng):
+    """The 2D sector run of section 3 (S = 1, t = 1) on 150^2 ... 1200^2
+    cells against a 2400^2 run: the density, the fine run averaged onto each
+    grid, differs less with every doubling, inside and outside the wedge."""
+    def run(n):
+        w = wl.workload_sector_2d(n=n)
+        s = ng.Solver(w["gas"], n, n, W=w["W"], h=w["h"], precision=ng.NG_FP64, bc=w["bc"],
+                      source=w["source"], wedge=w["wedge"])
+        s.run_to_time(w["t_end"], 10 ** 7)
+        d = s.diagnostics()
+        rho = s.conserved()[0]
+        s.close()
+        assert d["status"] == 0 and d["t"] == w["t_end"]
+        return rho, d["steps"], w["active"]
+
+    nf = 2400
+    rf, steps, _ = run(nf)
+    say(f"sector: n={nf} took {steps} steps")
+    errs = []
+    for n in (150, 300, 600, 1200):
+        rho, _, act = run(n)
+        f = nf // n
+        avg = rf.reshape(n, f, n, f).mean(axis=(1, 3))
+        diff = np.abs(rho - avg)
+        errs.append((float(diff[act].mean()), float(diff[~act].mean())))
+        say(f"sector: n={n} L1 difference from the fine run, wedge {errs[-1][0]:.3e}, "
+            f"outside {errs[-1][1]:.3e}")
+    for side in (0, 1):
+        e = [x[side] for x in errs]
+        assert all(b < a for a, b in zip(e, e[1:])), errs
+
+
 def test_sector_invalid_setups_refused(ng):
     gas = wl.results_gas(0.5, 0.05)
     W1 = wl.uniform_state(gas, 64)
