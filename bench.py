@@ -29,6 +29,9 @@ Prints one JSON line:
               process per host core (aggregate rate, solves/s extrapolated),
               and per_config_1d: the two 1D workloads on one core
   acoustic_1d_1024  the 1024-cell FP64 acoustic run (2000 steps) on the GPU
+  forced_source_1d, sector_2d, blast_waves_1d  section 3's runs (1D also at
+              102400 cells) and section 2.4's blast waves at 128000 cells,
+              in FP32 and FP64 with the FP32 error against FP64
   timing      one step in eight carries the HIP events of its kernels
 Input: seeded synthetic isotropic k^-2 density field (|k| <= 64, rms 1e-3),
 isentropic pressure, fluid at rest; gas of eqs. (1)-(7) with Q_T = 2.
@@ -401,8 +404,14 @@ def main():
         # N = 1600), each precision to the end, and the FP32 / mixed error of
         # the final perturbation against FP64
         res = {}
-        for stage in ("linear", "nonlinear"):
+        for stage, nfine in (("linear", None), ("nonlinear", None), ("nonlinear", 102400)):
             ws = wl.workload_forced_source(stage)
+            key = stage
+            if nfine:
+                # the paper's 10^5-cell reference size
+                ws = dict(ws, nx=nfine, W=wl.uniform_state(ws["gas"], nfine),
+                          name=ws["name"].rsplit("_n", 1)[0] + f"_n{nfine}")
+                key = f"{stage}_n{nfine}"
             fin, rec = {}, {}
             for name, prec in (("fp64", ng.NG_FP64), ("fp32", ng.NG_FP32),
                                ("mixed", ng.NG_MIXED)):
@@ -430,11 +439,40 @@ def main():
                 rec[name]["rel_l1_of_perturbation_vs_fp64"] = max(
                     float(np.abs(fin[name][c] - W64[c]).sum() / np.abs(W64[c] - Ub[c]).sum())
                     for c in (0, 1, 3, 4))
-            res[stage] = dict(rec, workload=ws["name"], t_end=ws["t_end"],
-                              max_abs_u=float(np.abs(u).max()),
-                              shock_faces=int((jumps > 5 * smooth).sum()))
-            log(f"[bench] forced source {stage}: {res[stage]}")
+            steep = jumps > 5 * smooth
+            res[key] = dict(rec, workload=ws["name"], t_end=ws["t_end"],
+                            max_abs_u=float(np.abs(u).max()),
+                            shock_faces=int(steep.sum()),
+                            # runs of consecutive steep faces: one per shock
+                            shocks=int(steep[0] + (steep[1:] & ~steep[:-1]).sum()))
+            log(f"[bench] forced source {key}: {res[key]}")
         out["forced_source_1d"] = res
+
+        # section 2.4's blast waves between walls to t = 0.038 at the paper's
+        # reference size (128000 cells, ~514000 steps) in FP64 and FP32
+        gb = dict(wl.BASE_GAS, Cv=0.0, tau_rho=0.0, tau_T=0.0, Q0=0.0, Q_rho=0.0, Q_T=0.0,
+                  I0=0.0, I_rho=0.0, I_T=0.0, tau0=1.0)
+        nb = 128000
+        fin, rec = {}, {}
+        for name, prec in (("fp64", ng.NG_FP64), ("fp32", ng.NG_FP32)):
+            s = ng.Solver(gb, nb, 1, W=wl.blast_waves_1d(nb), precision=prec,
+                          bc=(ng.NG_BC_WALL, ng.NG_BC_WALL, 0, 0))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            taken = s.run_to_time(0.038)
+            el = time.perf_counter() - t0
+            fin[name] = s.conserved()
+            d = s.diagnostics()
+            s.close()
+            assert d["status"] == 0
+            rec[name] = {"steps": taken, "wall_ms": 1e3 * el,
+                         "cell_updates_per_s": nb * taken / el}
+        rec["fp32"]["rel_l1_vs_fp64"] = {
+            nm: float(np.abs(fin["fp32"][c] - fin["fp64"][c]).sum()
+                      / np.abs(fin["fp64"][c]).sum())
+            for c, nm in ((0, "rho"), (1, "rho_u"), (3, "E"))}
+        out["blast_waves_1d"] = dict(rec, workload=f"blast_waves_walls_n{nb}", t_end=0.038)
+        log(f"[bench] blast waves: {out['blast_waves_1d']}")
 
         # the 2D sector run of section 3 (active 30-degree wedge from the
         # source, wall G1, free flow G2-G4) to t = 1 in FP32 and FP64: the
