@@ -208,8 +208,9 @@ int ng_get_conserved(ng_solver* s, double* cons_out);
  * items (one wavefront each) add up to at least 2304, else 4; 1D 8 segments
  * if they give 8192 work items, else the largest of 4, 2 and 1 reaching
  * 1024, else 1.  A lone grid smaller than 4096^2 so keeps the SIMDs busy; a
- * batch with work enough keeps long chunks.  Waves per workgroup 1, 2 or 4
- * (default 4).  2D rows below 4 and other values: EINVAL. */
+ * batch with work enough keeps long chunks.  Waves per workgroup 1, 2 or 4,
+ * or -1: 4, except 2 for a 1D launch of fewer than 2048 work items (default
+ * -1 in 1D, 4 in 2D).  2D rows below 4 and other values: EINVAL. */
 int ng_set_launch(ng_solver* s, int32_t rows_per_item, int32_t waves_per_block);
 
 /* Steps per captured graph in ng_run_to_time (default 64). */

@@ -44,7 +44,11 @@ constexpr int64_t kAutoItems2D = 2304;
 constexpr int kAutoRows2D[] = {32, 24, 16, 12, 8, 6, 4};
 constexpr int64_t kAutoItems1D = 1024;
 constexpr int64_t kAutoItems1DWide = 8192;   // for 8 segments per item
-constexpr int kDefaultWaves = 4;
+// waves per workgroup -1: 4, except 2 for 1D launches of fewer than
+// kAutoItems1DWaves work items (FP64 2^15 cells: 17 -> 15 us per step)
+constexpr int kDefaultWaves2D = 4;
+constexpr int kDefaultWaves1D = kAutoRows;
+constexpr int64_t kAutoItems1DWaves = 2048;
 constexpr int kDefaultGraphSteps = 64;
 // Solves up to this many cells run in the persistent one-workgroup kernel
 // (many steps per launch); larger ones take one launch per step over the
@@ -262,7 +266,8 @@ struct ng_batch {
     std::map<size_t, size_t> free_list;  // offset -> size
     int rows[3] = {0, kDefaultSegs1D, kDefaultRows2D};
     int auto_rows[3] = {0, 0, 0};   // automatic shape of the current big solves
-    int waves[3] = {0, kDefaultWaves, kDefaultWaves};
+    int waves[3] = {0, kDefaultWaves1D, kDefaultWaves2D};
+    int auto_waves[3] = {0, 0, 0};  // automatic waves per workgroup of the big solves
     int remap = 1;
     int64_t small_limit = -1;  // cells; -1: by precision, 0: persistent path off
     int fused = 1;             // step kernels accept their own step (last workgroup)
@@ -413,6 +418,20 @@ int auto_rows(int dim, const std::vector<std::pair<int64_t, int64_t>>& grids)
     return 1;
 }
 
+// Waves per workgroup of a dim's big-solve launch: the set value, else the
+// automatic one of the current solves, else (a solve not yet in the tables)
+// that of the given grids alone.
+int waves_of(const ng_batch* b, int dim, const std::vector<std::pair<int64_t, int64_t>>& grids)
+{
+    if (b->waves[dim] > 0) return b->waves[dim];
+    if (b->auto_waves[dim] > 0) return b->auto_waves[dim];
+    if (dim == 2) return kDefaultWaves2D;
+    const int r = b->rows[1] > 0 ? b->rows[1] : auto_rows(1, grids);
+    int64_t n = 0;
+    for (const auto& g : grids) n += items_at(1, g.first, g.second, r);
+    return n < kAutoItems1DWaves ? 2 : 4;
+}
+
 // Work decomposition of one solve for the current launch shape of its dim.
 // A solve accepts its own steps inside the step kernel only when it is the one
 // big solve of its dim: with several, each of their workgroups would pay the
@@ -421,7 +440,7 @@ void shape_solve(ng_batch* b, Slot& s, bool alone = true)
 {
     InstDesc& d = s.d;
     int dim = s.dim;
-    d.waves_per_block = s.small ? 1 : b->waves[dim];
+    d.waves_per_block = s.small ? 1 : waves_of(b, dim, {{d.nx, d.ny}});
     if (s.small)
         d.rows_per_item = dim == 2 ? kSmallRows2D : kSmallSegs1D;
     else if (b->rows[dim] != kAutoRows)
@@ -467,8 +486,13 @@ int rebuild(ng_batch* b)
                 grids[s.dim].push_back({s.d.nx, s.d.ny});
             }
         }
-    for (int dim = 1; dim <= 2; dim++)
-        b->auto_rows[dim] = grids[dim].empty() ? 0 : auto_rows(dim, grids[dim]);
+    for (int dim = 1; dim <= 2; dim++) {
+        b->auto_rows[dim] = 0;
+        b->auto_waves[dim] = 0;
+        if (grids[dim].empty()) continue;
+        b->auto_rows[dim] = auto_rows(dim, grids[dim]);
+        b->auto_waves[dim] = waves_of(b, dim, grids[dim]);
+    }
     for (int pass = 0; pass < 2; pass++) {
         for (int i = 0; i < b->capacity; i++) {
             Slot& s = b->slots[i];
@@ -532,7 +556,7 @@ int enqueue_one(ng_batch* b, hipStream_t st)
     for (int dim = 1; dim <= 2; dim++) {
         if (!b->ninst[dim]) continue;
         CK(b, launch_step(dim, kind_of(b->prec), b->d_descs(), b->d_ctrls(),
-                          b->d_blocks(dim), b->nblocks[dim], b->waves[dim], b->remap, b->fused,
+                          b->d_blocks(dim), b->nblocks[dim], waves_of(b, dim, {}), b->remap, b->fused,
                           st));
         if (b->nsep[dim])
             CK(b, launch_finalize(b->d_descs(), b->d_ctrls(), b->d_insts(dim), b->ninst[dim], 0,
@@ -592,7 +616,7 @@ int enqueue_timed(ng_batch* b, int64_t nsteps)
                        e3 = get_event(b, ne + 3);
             if (!e0 || !e1 || !e2 || !e3) return dev_err(b, hipErrorOutOfMemory, "hipEventCreate");
             CK(b, launch_step(dim, kind_of(b->prec), b->d_descs(), b->d_ctrls(),
-                              b->d_blocks(dim), b->nblocks[dim], b->waves[dim], b->remap,
+                              b->d_blocks(dim), b->nblocks[dim], waves_of(b, dim, {}), b->remap,
                               b->fused, b->stream, e0, e1));
             step_pairs.push_back({ne, ne + 1});
             if (b->nsep[dim]) {
@@ -1465,8 +1489,8 @@ int ng_batch_remove(ng_batch* b, int32_t slot)
 int ng_batch_set_launch(ng_batch* b, int32_t dim, int32_t rows_per_item, int32_t waves_per_block)
 {
     if (!b || (dim != 1 && dim != 2)) return NG_EINVAL;
-    if (rows_per_item < kAutoRows || waves_per_block < 0 ||
-        waves_per_block > 4 || (waves_per_block & (waves_per_block - 1)))
+    if (rows_per_item < kAutoRows || waves_per_block < kAutoRows || waves_per_block > 4 ||
+        (waves_per_block > 0 && (waves_per_block & (waves_per_block - 1))))
         return NG_EINVAL;
     if (dim == 2 && rows_per_item > 0 && rows_per_item < kMinRows2D) return NG_EINVAL;
     int old_r = b->rows[dim], old_w = b->waves[dim];

@@ -269,7 +269,7 @@ def test_launch_shape_does_not_change_results(ng):
     # 1D segment groups
     w = wl.workload_1d_acoustic()
     res = []
-    for launch in ((1, 1), (8, 4), (3, 2), (-1, 4)):
+    for launch in ((1, 1), (8, 4), (3, 2), (-1, 4), (-1, -1)):
         U, ref, d, _ = run_both(ng, w["gas"], w["W"], 1024, 1, 50, ng.NG_FP32, launch=launch,
                                 small_limit=0)
         res.append(U)
