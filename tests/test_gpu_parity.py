@@ -529,6 +529,23 @@ def test_invalid_boundaries_rejected(ng):
         ng.Solver(gas, 64, 1, W=W, bc=(0, W_, 0, 0))
 
 
+def test_invalid_launch_shapes_rejected(ng):
+    """Rows or segments below -1, 2D rows from 1 to 3, waves other than -1,
+    0, 1, 2, 4: refused, and the solve keeps its shape and steps on."""
+    gas = dict(wl.BASE_GAS, Q_T=2.0)
+    for nx, ny in ((5000, 1), (300, 200)):
+        W = wl.uniform_state(gas, nx, ny)
+        s = ng.Solver(gas, nx, ny, W=W)
+        bad = [(-2, 0), (0, -2), (0, 3), (0, 8)] + ([(3, 0), (1, 0)] if ny > 1 else [])
+        for rows, waves in bad:
+            with pytest.raises(ng.NgError):
+                s.set_launch(rows, waves)
+        s.set_launch(-1, -1)
+        s.step(5)
+        assert s.diagnostics()["steps"] == 5
+        s.close()
+
+
 # --------------------------------------------------- rejected steps (NG_EPHYS)
 
 def _sink_case(ny):
