@@ -38,9 +38,10 @@
  *                segment of it.
  *   medium      active everywhere, or (2D sector run of section 3) only in a
  *                wedge (or_active).
- *   stiff branch when dt/tau exceeds a threshold, the relaxation part of the
- *                E_nu update is integrated exactly with E_nue and tau frozen
- *                (our addition; the paper's runs never reach it).
+ *   stiff branch when dt/tau exceeds a threshold, the E_nu equation (4)
+ *                (relaxation and pump) is integrated exactly over the (half)
+ *                step with E_nue, tau and Q frozen (our addition; the paper's
+ *                runs never reach it).
  *
  * Layout: U[c * ncell + k * nx + j], c = 0..4 -> (rho, rho u, rho v, E, E_nu),
  * cell (j, k) centred at ((j + 1/2) h, (k + 1/2) h).  A 1D problem is ny = 1 with
@@ -450,25 +451,37 @@ int or_step_at(const or_gas* g, const or_grid* gr, const or_num* nm, const doubl
             double I = act * or_I(g, rho, T);
             double Ee = rho * g->Cv * T;
             /* E_nu gained by relaxation over dt/2 */
-            double dEr;
-            double zh = hdt / tau;
-            if (dt / tau > nm->stiff_z)
-                dEr = (Ee - ev) * (-expm1(-zh));
-            else
-                dEr = hdt * ((Ee - ev) / tau);
+            double dEr = hdt * ((Ee - ev) / tau);
+            /* stiff: the E_nu equation (4), dE_nu/dt = (E_nue + tau rho Q -
+             * E_nu)/tau, solved exactly over dt/2 with E_nue, tau and Q frozen
+             * at t^n (relaxation and pump together); the pressure takes the
+             * total-energy source rho (Q - I) of eq. (3) less that gain */
+            const int stiff = dt / tau > nm->stiff_z;
+            double dEv = 0.0;
+            if (stiff) dEv = ((Ee + tau * (rho * Q)) - ev) * (-expm1(-(hdt / tau)));
             double r_h, u_h, v_h, p_h, e_h;
             if (twod) {
                 r_h = rho - hdtdx * (ax_r + ay_r);
                 u_h = u - hdtdx * (ax_u + ay_u) + hdt * g->fx;
                 v_h = v - hdtdx * (ax_v + ay_v) + hdt * g->fy;
-                p_h = p - hdtdx * (ax_p + ay_p) - gm1 * (dEr + hdt * (rho * I));
-                e_h = ev - hdtdx * (ax_e + ay_e) + (dEr + hdt * (rho * Q));
+                if (stiff) {
+                    p_h = p - hdtdx * (ax_p + ay_p) - gm1 * (dEv - hdt * (rho * (Q - I)));
+                    e_h = ev - hdtdx * (ax_e + ay_e) + dEv;
+                } else {
+                    p_h = p - hdtdx * (ax_p + ay_p) - gm1 * (dEr + hdt * (rho * I));
+                    e_h = ev - hdtdx * (ax_e + ay_e) + (dEr + hdt * (rho * Q));
+                }
             } else {
                 r_h = rho - hdtdx * ax_r;
                 u_h = u - hdtdx * ax_u + hdt * g->fx;
                 v_h = v - hdtdx * ax_v + hdt * g->fy;
-                p_h = p - hdtdx * ax_p - gm1 * (dEr + hdt * (rho * I));
-                e_h = ev - hdtdx * ax_e + (dEr + hdt * (rho * Q));
+                if (stiff) {
+                    p_h = p - hdtdx * ax_p - gm1 * (dEv - hdt * (rho * (Q - I)));
+                    e_h = ev - hdtdx * ax_e + dEv;
+                } else {
+                    p_h = p - hdtdx * ax_p - gm1 * (dEr + hdt * (rho * I));
+                    e_h = ev - hdtdx * ax_e + (dEr + hdt * (rho * Q));
+                }
             }
             Wh[m] = r_h;
             Wh[ne + m] = u_h;
@@ -549,10 +562,10 @@ int or_step_at(const or_gas* g, const or_grid* gr, const or_num* nm, const doubl
             double de = dt * Y[4];
             double z = dt / tau;
             if (z > nm->stiff_z) {
-                /* relaxation over the whole step integrated exactly from the
-                 * start-of-step E_nu, E_nue and tau frozen at t^{n+1/2} */
-                double dEr = (Ee - Un[4]) * (-expm1(-z));
-                de = dEr + dt * (rho * Q);
+                /* the E_nu equation (4) over the whole step, solved exactly
+                 * from the start-of-step E_nu with E_nue, tau and Q frozen at
+                 * t^{n+1/2}: relaxation toward E_nue + tau rho Q */
+                de = ((Ee + tau * (rho * Q)) - Un[4]) * (-expm1(-z));
                 if (twod) {
                     double dF = Fx[4 * ne + m] - Fx[4 * ne + m - 1];
                     double dG = Gy[4 * ne + m] - Gy[4 * ne + m - e.nxe];

@@ -58,7 +58,23 @@ MUTATIONS = {
     "eq16_drops_factor_two": [
         ("return fmax(vel + c, 2.0 * vel);", "return fmax(vel + c, vel);")],
     "stiff_branch_sign": [
-        ("double dEr = (Ee - Un[4]) * (-expm1(-z));", "double dEr = (Ee - Un[4]) * (expm1(-z));")],
+        ("de = ((Ee + tau * (rho * Q)) - Un[4]) * (-expm1(-z));",
+         "de = ((Ee + tau * (rho * Q)) - Un[4]) * (expm1(-z));")],
+    "stiff_predictor_relaxes_whole_step": [
+        ("(-expm1(-(hdt / tau)))", "(-expm1(-(dt / tau)))")],
+    "stiff_update_relaxes_from_midstep": [
+        ("de = ((Ee + tau * (rho * Q)) - Un[4]) * (-expm1(-z));",
+         "de = ((Ee + tau * (rho * Q)) - ev) * (-expm1(-z));")],
+    "stiff_update_drops_pump": [
+        ("de = ((Ee + tau * (rho * Q)) - Un[4]) * (-expm1(-z));",
+         "de = (Ee - Un[4]) * (-expm1(-z));")],
+    "stiff_predictor_drops_pump": [
+        ("dEv = ((Ee + tau * (rho * Q)) - ev)", "dEv = (Ee - ev)")],
+    "stiff_predictor_pressure_drops_sink": [
+        ("p_h = p - hdtdx * ax_p - gm1 * (dEv - hdt * (rho * (Q - I)));",
+         "p_h = p - hdtdx * ax_p - gm1 * (dEv - hdt * (rho * Q));"),
+        ("p_h = p - hdtdx * (ax_p + ay_p) - gm1 * (dEv - hdt * (rho * (Q - I)));",
+         "p_h = p - hdtdx * (ax_p + ay_p) - gm1 * (dEv - hdt * (rho * Q));")],
     "tau_wrong_exponent": [
         ("or_pow(T / g->T0, g->tau_T);", "or_pow(T / g->T0, g->tau_rho);")],
     "power_law_half_exponent": [("if (a == 0.5) return sqrt(x);", "if (a == 0.5) return x;")],

@@ -133,6 +133,80 @@ def test_stiff_equilibrium_limit_sod(oracle_lib):
     assert abs(st_f["rho_R"] - st["rho_R"]) > 2e-2
 
 
+def _uniform_gas_run(oracle_lib, gas, p, ev, dt, nsteps, stiff_z=0.5):
+    """A uniform 4-cell periodic gas at rest advanced by nsteps steps of a
+    fixed dt (no flux differences: the step is the source ODE alone)."""
+    W = wl.uniform_state(gas, 4)
+    W[3] = p
+    W[4] = ev
+    P = oracle_lib.Problem(gas, 4, h=1e3, stiff_z=stiff_z)
+    U = P.prim_to_cons(W)
+    for _ in range(nsteps):
+        st, U, _ = P.step(U, dt)
+        assert st == 0
+    return P.cons_to_prim(U)[:, 0, 0], U[:, 0, 0]
+
+
+@pytest.mark.parametrize("z", [0.6, 1.0, 2.0, 4.0])
+def test_stiff_branch_exact_with_frozen_coefficients(oracle_lib, z):
+    """With E_nue = 0 (Cv = 0), tau, Q and I constant (exponents 0) and Q = I,
+    eq. (4) for a gas at rest is dE_nu/dt = rho Q - E_nu/tau, solved by
+    E_nu(t) = tau rho Q + (E_nu(0) - tau rho Q) e^{-t/tau}, and eq. (3) keeps E
+    constant.  The coefficients are frozen whatever the mid-step state, so the
+    exponential branch (dt/tau = z above the threshold 0.5) must reproduce
+    that solution to rounding in one step; an explicit step, or one relaxing
+    from the mid-step E_nu or without the pump, is off by O(z^2) or more."""
+    gas = dict(EULER_GAS, tau0=0.05, Q0=0.2, I0=0.2)
+    dt = z * gas["tau0"]
+    ev0, rq = 0.7, gas["tau0"] * 1.0 * gas["Q0"]
+    W, U = _uniform_gas_run(oracle_lib, gas, 1.0, ev0, dt, 1)
+    exact = rq + (ev0 - rq) * math.exp(-z)
+    assert W[4] == pytest.approx(exact, rel=1e-14, abs=1e-16)
+    E0 = 1.0 / 0.4 + ev0
+    assert U[3] == pytest.approx(E0, rel=1e-15)
+    # two steps of dt/2 give the same E_nu (the frozen solution is a semigroup)
+    W2, _ = _uniform_gas_run(oracle_lib, gas, 1.0, ev0, dt / 2, 2, stiff_z=0.1)
+    assert W2[4] == pytest.approx(exact, rel=1e-14, abs=1e-16)
+
+
+@pytest.mark.parametrize("z", [0.6, 1.0, 2.0, 4.0])
+def test_stiff_branch_keeps_the_pumped_background_steady(oracle_lib, z):
+    """The steady background of reading 12, E_nu = E_nue + tau rho Q with Q = I
+    (eq. (4) with dE_nu/dt = 0), stays put to rounding when the exponential
+    branch runs in the predictor and the corrector at dt/tau = z (base gas:
+    Cv = 1, tau, Q and I depending on rho and T)."""
+    gas = dict(wl.BASE_GAS, Q_T=2.0, tau0=1e-3)
+    b = wl.background(gas)
+    W, _ = _uniform_gas_run(oracle_lib, gas, b["p"], b["ev"], z * gas["tau0"], 20)
+    assert abs(W[4] - b["ev"]) < 1e-14 and abs(W[3] - b["p"]) < 1e-14, (W, b)
+
+
+def test_stiff_branch_second_order_at_moderate_z(oracle_lib):
+    """Off equilibrium (p = 1, E_nu = 1.5 against 1.005), the base gas with
+    Q_T = 2 relaxes at tau0 = 0.01; with the threshold at 0.1 every predictor
+    and corrector takes the exponential branch at dt/tau0 = 0.8, 0.4, 0.2,
+    0.1.  The branch freezes E_nue, tau and Q at the predicted mid-step state
+    and integrates eq. (4) exactly, an exponential midpoint rule: local error
+    O(dt^3), so against the ODE of eqs. (3)-(4) solved to 1e-13 the error at
+    t = 0.04 falls by about 4 per halving of dt.  A predictor that relaxes over
+    the whole step, or a corrector that starts from the mid-step E_nu, makes
+    it first order or inconsistent."""
+    from scipy.integrate import solve_ivp
+    gas = dict(wl.BASE_GAS, Q_T=2.0, tau0=0.01)
+    y0 = [1.0, 1.5]
+    t_end = 0.04
+    ref = solve_ivp(_ode_rhs(gas), (0.0, t_end), y0, rtol=1e-13, atol=1e-15,
+                    method="DOP853").y[:, -1]
+    errs = []
+    for z in (0.8, 0.4, 0.2, 0.1):
+        nst = int(round(t_end / (z * gas["tau0"])))
+        W, _ = _uniform_gas_run(oracle_lib, gas, y0[0], y0[1], t_end / nst, nst, stiff_z=0.05)
+        errs.append(max(abs(W[3] - ref[0]), abs(W[4] - ref[1])))
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(3)]
+    assert errs[0] < 1e-4, errs
+    assert min(orders[1:]) > 1.8, (errs, orders)
+
+
 # ------------------------------------------ P3/P4: conservation and budgets
 
 def _random_2d(oracle_lib, n=48, amp=3e-2, seed=7, gas=None):
@@ -357,12 +431,24 @@ def _fit_rate(oracle_lib, gas, n, mode, t_end, nsamp=8, amp=1e-6):
     return om, rate, freq
 
 
-@pytest.mark.parametrize("case", ["base_k8pi", "qt2_k2pi", "unstable_S05_m4"])
+@pytest.mark.parametrize("case", ["base_k8pi", "qt2_k2pi", "unstable_S05_m4", "stiff_k2pi"])
 def test_linear_rates_match_dispersion(oracle_lib, case):
+    """Rate and frequency of a small sound wave against the acoustic root of
+    the linearised system.  stiff_k2pi: tau0 = 1e-4, so dt/tau is about 26
+    and both the predictor and the corrector take the exponential branch;
+    the wave must run at the equilibrium sound speed (4 % below the frozen
+    one) that the root gives."""
     if case == "base_k8pi":
         gas, mode, n, t_end = dict(wl.BASE_GAS), 4, 512, 0.3
     elif case == "qt2_k2pi":
         gas, mode, n, t_end = dict(wl.BASE_GAS, Q_T=2.0, tau0=0.2), 1, 128, 1.0
+    elif case == "stiff_k2pi":
+        gas, mode, n, t_end = dict(wl.BASE_GAS, tau0=1e-4), 1, 128, 1.0
+        P = oracle_lib.Problem(gas, n)
+        dt = P.dt(P.prim_to_cons(wl.uniform_state(gas, n)))
+        assert dt / gas["tau0"] > 20
+        frozen = math.sqrt(gas["gamma"]) * 2 * math.pi * mode
+        assert abs(D.acoustic_mode(gas, 2 * math.pi * mode, +1)[0].real / frozen - 1) > 0.03
     else:
         gas = dict(gamma=1.4, R=1.0, Cv=0.1, rho0=1.0, T0=1.0, tau0=0.05, tau_rho=-1.0,
                    tau_T=-1.5, Q0=10.0, Q_rho=0.0, Q_T=0.0, I0=10.0, I_rho=0.0, I_T=0.0,
