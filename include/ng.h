@@ -122,8 +122,9 @@ typedef struct {
 } ng_grid;
 
 /* cfl multiplies the bound of eq. (16); stiff_z is the dt/tau above which the
- * relaxation part of the E_nu update is integrated exactly (E_nue and tau
- * frozen over the (half) step). */
+ * E_nu equation (4), relaxation and pump together, is integrated exactly over
+ * the (half) step with E_nue, tau and Q frozen: E_nu relaxes toward
+ * E_nue + tau rho Q by the factor exp(-dt/tau). */
 typedef struct {
     double cfl;
     int32_t riemann;   /* NG_HLLC or NG_HLL */

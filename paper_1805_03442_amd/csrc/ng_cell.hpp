@@ -150,17 +150,19 @@ __device__ __forceinline__ void predict64(const K64& k, const double* W, const d
         Q = act * Q;
         I = act * I;
         double Ee = rho * k.Cv * T;
-        double dEr;
-        double zh = hdt / tau;
-        if (k.dt / tau > k.stiff_z)
-            dEr = (Ee - ev) * (-expm1(-zh));
-        else
-            dEr = hdt * ((Ee - ev) / tau);
         Wh[0] = rho - hdtdx * (ax_r + ay_r);
         Wh[1] = u - hdtdx * (ax_u + ay_u) + hdt * k.fx;
         Wh[2] = v - hdtdx * (ax_v + ay_v) + hdt * k.fy;
-        Wh[3] = p - hdtdx * (ax_p + ay_p) - gm1 * (dEr + hdt * (rho * I));
-        Wh[4] = ev - hdtdx * (ax_e + ay_e) + (dEr + hdt * (rho * Q));
+        if (k.dt / tau > k.stiff_z) {
+            // eq. (4) over dt/2 solved exactly with E_nue, tau, Q frozen
+            double dEv = ((Ee + tau * (rho * Q)) - ev) * (-expm1(-(hdt / tau)));
+            Wh[3] = p - hdtdx * (ax_p + ay_p) - gm1 * (dEv - hdt * (rho * (Q - I)));
+            Wh[4] = ev - hdtdx * (ax_e + ay_e) + dEv;
+        } else {
+            double dEr = hdt * ((Ee - ev) / tau);
+            Wh[3] = p - hdtdx * (ax_p + ay_p) - gm1 * (dEr + hdt * (rho * I));
+            Wh[4] = ev - hdtdx * (ax_e + ay_e) + (dEr + hdt * (rho * Q));
+        }
     } else {
         double rho = W[0], u = W[1], p = W[2], ev = W[3];
         double sr = sx[0], su = sx[1], sp = sx[2], se = sx[3];
@@ -174,16 +176,17 @@ __device__ __forceinline__ void predict64(const K64& k, const double* W, const d
         Q = act * Q;
         I = act * I;
         double Ee = rho * k.Cv * T;
-        double dEr;
-        double zh = hdt / tau;
-        if (k.dt / tau > k.stiff_z)
-            dEr = (Ee - ev) * (-expm1(-zh));
-        else
-            dEr = hdt * ((Ee - ev) / tau);
         Wh[0] = rho - hdtdx * ax_r;
         Wh[1] = u - hdtdx * ax_u + hdt * k.fx;
-        Wh[2] = p - hdtdx * ax_p - gm1 * (dEr + hdt * (rho * I));
-        Wh[3] = ev - hdtdx * ax_e + (dEr + hdt * (rho * Q));
+        if (k.dt / tau > k.stiff_z) {
+            double dEv = ((Ee + tau * (rho * Q)) - ev) * (-expm1(-(hdt / tau)));
+            Wh[2] = p - hdtdx * ax_p - gm1 * (dEv - hdt * (rho * (Q - I)));
+            Wh[3] = ev - hdtdx * ax_e + dEv;
+        } else {
+            double dEr = hdt * ((Ee - ev) / tau);
+            Wh[2] = p - hdtdx * ax_p - gm1 * (dEr + hdt * (rho * I));
+            Wh[3] = ev - hdtdx * ax_e + (dEr + hdt * (rho * Q));
+        }
     }
 }
 
@@ -326,10 +329,9 @@ __device__ __forceinline__ void update64(const K64& k, const double* Un, const d
     double de = dt * Y[iV];
     double z = dt / tau;
     if (z > k.stiff_z) {
-        // relaxation over the whole step integrated exactly from the
-        // start-of-step E_nu, with E_nue and tau frozen at t^{n+1/2}
-        double dEr = (Ee - Un[iV]) * (-expm1(-z));
-        de = dEr + dt * (rho * Q);
+        // eq. (4) over the whole step solved exactly from the start-of-step
+        // E_nu, with E_nue, tau and Q frozen at t^{n+1/2}
+        de = ((Ee + tau * (rho * Q)) - Un[iV]) * (-expm1(-z));
         if (NC == 5)
             Unew[iV] = Un[iV] - dtdx * (dF[iV] + dG[iV]) + de;
         else
@@ -343,11 +345,15 @@ __device__ __forceinline__ void update64(const K64& k, const double* Un, const d
 
 __device__ __forceinline__ float rcp32(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// E_nu change of an exact relaxation over a time z tau: num (1 - exp(-z)),
-// evaluated in FP64 (kept out of line: it runs only where dt/tau is large)
-__device__ __noinline__ float relax_exact(float num, double z)
+// Stiff branch: eq. (4) solved exactly over a time z tau with E_nue, tau and
+// Q frozen, E_nu(z tau) - E_nu = (num + tau rhoQ)(1 - exp(-z)), num = E_nue -
+// E_nu, evaluated in FP64 and returned less hq (the caller's explicit pump
+// term, which it adds back).  Kept out of line: it runs only where dt/tau is
+// large.
+__device__ __noinline__ float relax_exact(float num, float rhoQ, float itau, double z, float hq)
 {
-    return (float)((double)num * (-expm1(-z)));
+    const double a = ((double)num + (double)rhoQ / (double)itau) * (-expm1(-z));
+    return (float)(a - (double)hq);
 }
 
 struct K32 {
@@ -457,7 +463,7 @@ __device__ __forceinline__ void predict32(const K32& k, const float* W, const fl
     float z = hdt * itau;
     float dEr;
     if (z > k.hstiff_z)
-        dEr = relax_exact(relax_num, k.hdt64 * (double)itau);
+        dEr = relax_exact(relax_num, rho * Q, itau, k.hdt64 * (double)itau, hdt * (rho * Q));
     else
         dEr = relax_num * z;
     Wh[0] = fmaf(-hdtdx, a_r, dr);
@@ -585,9 +591,9 @@ __device__ __forceinline__ void update32(const K32& k, const float* Un, const fl
     }
     float dv = dt * yV;
     if (k.dt * itau > k.stiff_z) {
-        // exact relaxation from the start-of-step E_nu, FP64 factor
+        // eq. (4) solved exactly from the start-of-step E_nu, FP64 factor
         float num = fmaf(k.CvR, dp, k.D_r - Un[iV]);
-        float dEr = relax_exact(num, k.dt64 * (double)itau);
+        float dEr = relax_exact(num, rho * Q, itau, k.dt64 * (double)itau, dt * (rho * Q));
         dv = fmaf(dt, rho * Q, dEr);
         Unew[iV] = dv + Unew[iV];
     } else {
@@ -629,7 +635,7 @@ __device__ __forceinline__ void increment32(const K32& k, float ev_n, const floa
     float dv = dt * yV;
     if (k.dt * itau > k.stiff_z) {
         float num = fmaf(k.CvR, dp, k.D_r - ev_n);
-        float dEr = relax_exact(num, k.dt64 * (double)itau);
+        float dEr = relax_exact(num, rho * Q, itau, k.dt64 * (double)itau, dt * (rho * Q));
         dv = fmaf(dt, rho * Q, dEr);
         dU[iV] = dv + dU[iV];
     } else {
