@@ -274,6 +274,7 @@ struct ng_batch {
     int64_t nblocks[3] = {0, 0, 0};   // workgroups of the per-step launch (big solves)
     int ninst[3] = {0, 0, 0};         // big solves per dim
     int nsep[3] = {0, 0, 0};          // big solves accepted by the finalize kernel
+    int variant[3] = {0, 0, 0};       // step kernel variant of the per-step launch
     int nsmall[3] = {0, 0, 0};        // small solves per dim
     bool dirty = true;
     // captured step sequence
@@ -516,6 +517,18 @@ int rebuild(ng_batch* b)
             }
         }
     }
+    // the step kernel variant of each dim's launch: the periodic-HLLC kernel
+    // of a closure recipe when every big solve has that path, else the general
+    for (int dim = 1; dim <= 2; dim++) {
+        int v = -1;
+        for (int i = 0; i < b->capacity; i++) {
+            const Slot& s = b->slots[i];
+            if (!s.live || s.small || s.dim != dim) continue;
+            const int sv = (s.d.riemann == NG_HLLC && !s.d.any_bc) ? 1 + s.d.cl_recipe : 0;
+            v = (v < 0 || v == sv) ? sv : 0;
+        }
+        b->variant[dim] = v < 0 ? 0 : v;
+    }
     for (int dim = 1; dim <= 2; dim++) {
         if (b->h_blocks[dim].size() > b->tcap[dim]) {
             b->err = "workgroup table capacity exceeded";
@@ -555,7 +568,7 @@ int enqueue_one(ng_batch* b, hipStream_t st)
 {
     for (int dim = 1; dim <= 2; dim++) {
         if (!b->ninst[dim]) continue;
-        CK(b, launch_step(dim, kind_of(b->prec), b->d_descs(), b->d_ctrls(),
+        CK(b, launch_step(dim, kind_of(b->prec), b->variant[dim], b->d_descs(), b->d_ctrls(),
                           b->d_blocks(dim), b->nblocks[dim], waves_of(b, dim, {}), b->remap, b->fused,
                           st));
         if (b->nsep[dim])
@@ -615,7 +628,7 @@ int enqueue_timed(ng_batch* b, int64_t nsteps)
             hipEvent_t e0 = get_event(b, ne), e1 = get_event(b, ne + 1), e2 = get_event(b, ne + 2),
                        e3 = get_event(b, ne + 3);
             if (!e0 || !e1 || !e2 || !e3) return dev_err(b, hipErrorOutOfMemory, "hipEventCreate");
-            CK(b, launch_step(dim, kind_of(b->prec), b->d_descs(), b->d_ctrls(),
+            CK(b, launch_step(dim, kind_of(b->prec), b->variant[dim], b->d_descs(), b->d_ctrls(),
                               b->d_blocks(dim), b->nblocks[dim], waves_of(b, dim, {}), b->remap,
                               b->fused, b->stream, e0, e1));
             step_pairs.push_back({ne, ne + 1});
@@ -862,6 +875,30 @@ void fill_desc(InstDesc& d, const ng_gas* gas, const ng_grid* grid, const ng_num
         d.e1_r = p_r / d.gm1;
         d.H_r = d.e1_r + p_r;
         d.D_r = gas->Cv / gas->R * p_r - ev_r;
+    }
+    // eq. (6) with T = p / (R rho): (rho/rho0)^x (T/T0)^y =
+    // rho0^-x (R T0)^-y rho^(x - y) p^y; 1/tau takes the negated exponents
+    const double RT0 = gas->R * gas->T0;
+    const double xs[3] = {-gas->tau_rho, gas->Q_rho, gas->I_rho};
+    const double ys[3] = {-gas->tau_T, gas->Q_T, gas->I_T};
+    const double cs[3] = {1.0 / gas->tau0, gas->Q0, gas->I0};
+    int codes[6];
+    bool half = true;
+    for (int i = 0; i < 3; i++) {
+        d.cl_a[i] = xs[i] - ys[i];
+        d.cl_b[i] = ys[i];
+        d.cl_c[i] = cs[i] * pow(gas->rho0, -xs[i]) * pow(RT0, -ys[i]);
+        for (int j = 0; j < 2; j++) {
+            const double e2 = 2.0 * (j == 0 ? d.cl_a[i] : d.cl_b[i]);
+            if (e2 != nearbyint(e2) || fabs(e2) > 4.0) half = false;
+            else codes[2 * i + j] = (int)e2;
+        }
+    }
+    d.cl_recipe = 0;
+    for (int r = 1; half && r <= ng::kRecipes; r++) {
+        bool same = true;
+        for (int q = 0; q < 6; q++) same = same && codes[q] == ng::kRecipeCodes[r][q];
+        if (same) d.cl_recipe = r;
     }
 }
 

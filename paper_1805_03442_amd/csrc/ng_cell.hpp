@@ -31,6 +31,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include "ng_internal.hpp"
+
 namespace ng {
 
 // ------------------------------------------------------------- limiter
@@ -360,10 +362,9 @@ struct K32 {
     float gam, gm1, igm1, CvR;
     float rho_r, p_r, ev_r, H_r, D_r;   // reference state and its cancelled constants
                                         // (H_r = e_r + p_r, e = E - E_nu)
-    float irho0, iRT0;                  // 1/rho0, 1/(R T0)
-    float itau0, Q0, I0;                // closures of eq. (6) in log2/exp2 form
-    float tr, tT, Qr, QT, Ir, IT;
+    float cl_c[3], cl_a[3], cl_b[3];    // closures of eq. (6): c rho^a p^b
     float fx, fy;
+    float gp_r;                         // gamma p_r
     float stiff_z, hstiff_z;            // stiffness threshold on dt/tau, and half of it
     float dt, dtdx, hdtdx, hdt;
     float hdtfx, hdtfy;                 // (dt/2) f, the body force of the predictor
@@ -372,27 +373,65 @@ struct K32 {
     bool force;                         // f != 0
 };
 
-// 1/tau, Q and I of eq. (6) at full (rho, p) in FP32: with lr = log2(rho/rho0)
-// and lt = log2(T/T0), T/T0 = p/(R rho T0), each power law is one exp2 of a
-// linear form (no branch on the exponents).
+// x^(C/2) for a half-integer exponent code C in [-4, 4] known at compile
+// time, from x, 1/x and 1/sqrt(x)
+template <int C>
+__device__ __forceinline__ float pw_half(float x, float ix, float sx)
+{
+    static_assert(C >= -4 && C <= 4, "exponent code out of range");
+    if constexpr (C == 0) return 1.0f;
+    else if constexpr (C == 1) return x * sx;
+    else if constexpr (C == 2) return x;
+    else if constexpr (C == 3) return x * (x * sx);
+    else if constexpr (C == 4) return x * x;
+    else if constexpr (C == -1) return sx;
+    else if constexpr (C == -2) return ix;
+    else if constexpr (C == -3) return ix * sx;
+    else return ix * ix;
+}
+
+// 1/tau, Q and I of eq. (6) at full (rho, p) in FP32, each c rho^a p^b
+// (T = p / (R rho)).  Recipe CL > 0 (kRecipeCodes): the half-integer
+// exponents are compile-time constants, so each power is a product of rho,
+// p, 1/rho, 1/p and reciprocal square roots (at most one transcendental per
+// base).  CL = 0: one exp2 of a log2(rho) + b log2(p) per closure.  HaveIr:
+// irho is 1/rho; otherwise it is computed here when an exponent needs it.
+template <bool HaveIr, int CL>
 __device__ __forceinline__ void closures32(const K32& k, float rho, float p, float irho,
                                            float& itau, float& Q, float& I)
 {
-    float lr = __builtin_amdgcn_logf(rho * k.irho0);
-    float lt = __builtin_amdgcn_logf(p * k.iRT0 * irho);
-    itau = k.itau0 * __builtin_amdgcn_exp2f(-fmaf(k.tr, lr, k.tT * lt));
-    Q = k.Q0 * __builtin_amdgcn_exp2f(fmaf(k.Qr, lr, k.QT * lt));
-    I = k.I0 * __builtin_amdgcn_exp2f(fmaf(k.Ir, lr, k.IT * lt));
+    if constexpr (CL == 0) {
+        const float lr = __builtin_amdgcn_logf(rho), lp = __builtin_amdgcn_logf(p);
+        itau = k.cl_c[0] * __builtin_amdgcn_exp2f(fmaf(k.cl_a[0], lr, k.cl_b[0] * lp));
+        Q = k.cl_c[1] * __builtin_amdgcn_exp2f(fmaf(k.cl_a[1], lr, k.cl_b[1] * lp));
+        I = k.cl_c[2] * __builtin_amdgcn_exp2f(fmaf(k.cl_a[2], lr, k.cl_b[2] * lp));
+    } else {
+        constexpr int a0 = kRecipeCodes[CL][0], b0 = kRecipeCodes[CL][1];
+        constexpr int a1 = kRecipeCodes[CL][2], b1 = kRecipeCodes[CL][3];
+        constexpr int a2 = kRecipeCodes[CL][4], b2 = kRecipeCodes[CL][5];
+        constexpr bool odd_r = ((a0 | a1 | a2) & 1) != 0, neg_r = a0 < 0 || a1 < 0 || a2 < 0;
+        constexpr bool odd_p = ((b0 | b1 | b2) & 1) != 0, neg_p = b0 < -1 || b1 < -1 || b2 < -1;
+        float sr = 1.0f, ir = irho, ip = 1.0f, sp = 1.0f;
+        if constexpr (odd_r) sr = __builtin_amdgcn_rsqf(rho);
+        if constexpr (!HaveIr && neg_r) ir = odd_r ? sr * sr : rcp32(rho);
+        if constexpr (neg_p) ip = rcp32(p);
+        if constexpr (odd_p) sp = __builtin_amdgcn_rsqf(p);
+        itau = k.cl_c[0] * (pw_half<a0>(rho, ir, sr) * pw_half<b0>(p, ip, sp));
+        Q = k.cl_c[1] * (pw_half<a1>(rho, ir, sr) * pw_half<b1>(p, ip, sp));
+        I = k.cl_c[2] * (pw_half<a2>(rho, ir, sr) * pw_half<b2>(p, ip, sp));
+    }
 }
 
-// deviation primitives (d rho, u, [v], dp, dEv) from deviation conserved;
-// rho |v|^2 is formed as m.v, the momentum times the velocity
+// deviation primitives (d rho, u, [v], dp, dEv) from deviation conserved,
+// and 1/rho in W[NC] for the predictor and the signal speed; rho |v|^2 is
+// formed as m.v, the momentum times the velocity
 template <int NC>
 __device__ __forceinline__ void prim32(const K32& k, const float* D, float* W)
 {
     float rho = k.rho_r + D[0];
     float ir = rcp32(rho);
     float u = D[1] * ir;
+    W[NC] = ir;
     W[0] = D[0];
     W[1] = u;
     if (NC == 5) {
@@ -408,24 +447,25 @@ __device__ __forceinline__ void prim32(const K32& k, const float* D, float* W)
 }
 
 // signal speed of eq. (16) in FP32, max(|v| + c, 2|v|) = |v| + max(c, |v|)
-// (the same rounded value); c = sqrt(gamma p / rho) as gamma p rsqrt(gamma p rho);
-// |v| by the hardware square root (about 1 ulp; the speed only bounds dt)
+// (the same rounded value); c = sqrt(gamma p / rho) from the 1/rho that prim32
+// leaves in W[NC]; square roots by the hardware (about 1 ulp; the speed only
+// bounds dt)
 template <int NC>
 __device__ __forceinline__ float speed32(const K32& k, const float* W)
 {
-    float rho = k.rho_r + W[0];
     float u = W[1];
     float v2 = NC == 5 ? W[2] * W[2] : 0.0f;
-    float gp = k.gam * (k.p_r + W[NC == 5 ? 3 : 2]);
+    float gp = fmaf(k.gam, W[NC == 5 ? 3 : 2], k.gp_r);
     float vel = __builtin_amdgcn_sqrtf(fmaf(u, u, v2));
-    float c = gp * __builtin_amdgcn_rsqf(gp * rho);
+    float c = __builtin_amdgcn_sqrtf(gp * W[NC]);
     return vel + fmaxf(c, vel);
 }
 
 // half-step predictor in primitive form: W + (dt/2)(-A_x dW/dx - A_y dW/dy + S(W))
 // with undivided slopes sx, sy and the divergence su + tv shared by the
-// density, pressure and E_nu rows
-template <int NC>
+// density, pressure and E_nu rows.  FullRho: Wh[0] is the full density (the
+// HLLC flux and the corrector use only that), else its deviation.
+template <int NC, bool FullRho = false, int CL = 0>
 __device__ __forceinline__ void predict32(const K32& k, const float* W, const float* sx,
                                           const float* sy, float* Wh, float act = 1.0f)
 {
@@ -433,8 +473,8 @@ __device__ __forceinline__ void predict32(const K32& k, const float* W, const fl
     constexpr int iP = NC == 5 ? 3 : 2, iV = NC == 5 ? 4 : 3;
     float dr = W[0], u = W[1], dp = W[iP], de = W[iV];
     float rho = k.rho_r + dr, p = k.p_r + dp, ev = k.ev_r + de;
-    float irho = rcp32(rho);
-    float gp = k.gam * p;
+    float irho = W[NC];
+    float gp = fmaf(k.gam, dp, k.gp_r);
     float sr = sx[0], su = sx[1], sp = sx[iP], se = sx[iV];
     float a_r, a_u, a_v = 0.0f, a_p, a_e, v = 0.0f;
     if (NC == 5) {
@@ -454,7 +494,7 @@ __device__ __forceinline__ void predict32(const K32& k, const float* W, const fl
         a_e = fmaf(u, se, ev * su);
     }
     float itau, Q, I;
-    closures32(k, rho, p, irho, itau, Q, I);
+    closures32<true, CL>(k, rho, p, irho, itau, Q, I);
     Q = act * Q;
     I = act * I;
     float relax_num = fmaf(k.CvR, dp, k.D_r - de);   // E_nue - E_nu
@@ -466,7 +506,7 @@ __device__ __forceinline__ void predict32(const K32& k, const float* W, const fl
         dEr = relax_exact(relax_num, rho * Q, itau, k.hdt64 * (double)itau, hdt * (rho * Q));
     else
         dEr = relax_num * z;
-    Wh[0] = fmaf(-hdtdx, a_r, dr);
+    Wh[0] = fmaf(-hdtdx, a_r, FullRho ? rho : dr);
     Wh[1] = fmaf(-hdtdx, a_u, u);
     if (NC == 5) Wh[2] = fmaf(-hdtdx, a_v, v);
     if (k.force) {
@@ -484,15 +524,16 @@ __device__ __forceinline__ void predict32(const K32& k, const float* W, const fl
 // With sq = S_K q_K the components factor as
 //   rho (u + sq) = F_rho,  F_rho v,  (E + p)(u + sq) + sq rho (S_K - u) S*,
 //   E_nu (u + sq).
+// The HLLC flux takes face states with the full density in [0] (it uses the
+// density only in products), HLL the deviation (its jump U_R - U_L).
 template <int NC, int RS>
 __device__ __forceinline__ void flux32(const K32& k, const float* WL, const float* WR, float* F)
 {
     constexpr int iP = NC == 5 ? 3 : 2, iV = NC == 5 ? 4 : 3;
-    const float gam = k.gam;
-    float rL = k.rho_r + WL[0], rR = k.rho_r + WR[0];
+    float rL = RS == 1 ? k.rho_r + WL[0] : WL[0], rR = RS == 1 ? k.rho_r + WR[0] : WR[0];
     float uL = WL[1], uR = WR[1];
     float dpL = WL[iP], dpR = WR[iP];
-    float gpL = gam * (k.p_r + dpL), gpR = gam * (k.p_r + dpR);
+    float gpL = fmaf(k.gam, dpL, k.gp_r), gpR = fmaf(k.gam, dpR, k.gp_r);
     float cL = gpL * __builtin_amdgcn_rsqf(gpL * rL);
     float cR = gpR * __builtin_amdgcn_rsqf(gpR * rR);
     float SL = fminf(uL - cL, uR - cR);
@@ -540,8 +581,9 @@ __device__ __forceinline__ void flux32(const K32& k, const float* WL, const floa
     }
     float dL = SL - uL, dR = SR - uR;
     float Ss = fmaf(mL, dL, fmaf(-mR, dR, dpR - dpL)) * rcp32(fmaf(rL, dL, -(rR * dR)));
+    // bitwise on the comparison masks (no branch)
     const bool supL = 0.0f < SL, supR = SR < 0.0f;
-    const bool left = supL || (!supR && 0.0f < Ss);
+    const bool left = supL | (!supR & (0.0f < Ss));
     float rK = left ? rL : rR, uK = left ? uL : uR, dpK = left ? dpL : dpR;
     float deK = left ? WL[iV] : WR[iV];
     float vK = NC == 5 ? (left ? WL[2] : WR[2]) : 0.0f;
@@ -550,7 +592,7 @@ __device__ __forceinline__ void flux32(const K32& k, const float* WL, const floa
     float dEK = fmaf(0.5f, m2K, dpK * k.igm1);   // de = e - e_r
     float HK = k.H_r + (dEK + dpK);   // e + p
     float evK = k.ev_r + deK;
-    float q = (supL || supR) ? 0.0f : (Ss - uK) * rcp32(SK - Ss);
+    float q = (supL | supR) ? 0.0f : (Ss - uK) * rcp32(SK - Ss);
     float sq = SK * q, sqr = sq * rK;
     float us = uK + sq;
     float F0 = fmaf(sq, rK, mK);
@@ -563,19 +605,18 @@ __device__ __forceinline__ void flux32(const K32& k, const float* WL, const floa
 
 // corrector of eq. (15): U^n - dt/h (dF + dG) + dt Y(W^{n+1/2}); the source
 // rows without a body force reduce to rho (Q - I) and (E_nue - E_nu)/tau + rho Q
-template <int NC>
+template <int NC, bool FullRho = false, int CL = 0>
 __device__ __forceinline__ void update32(const K32& k, const float* Un, const float* dF,
                                          const float* dG, const float* Wh, float* Unew,
                                          float& srcE, float& srcV, float act = 1.0f)
 {
     constexpr int iP = NC == 5 ? 3 : 2, iV = NC == 5 ? 4 : 3;
     const float dt = k.dt, dtdx = k.dtdx;
-    float dr = Wh[0], u = Wh[1], dp = Wh[iP], de = Wh[iV];
+    float u = Wh[1], dp = Wh[iP], de = Wh[iV];
     float v = NC == 5 ? Wh[2] : 0.0f;
-    float rho = k.rho_r + dr, p = k.p_r + dp;
-    float irho = rcp32(rho);
+    float rho = FullRho ? Wh[0] : k.rho_r + Wh[0], p = k.p_r + dp;
     float itau, Q, I;
-    closures32(k, rho, p, irho, itau, Q, I);
+    closures32<false, CL>(k, rho, p, 0.0f, itau, Q, I);
     Q = act * Q;
     I = act * I;
     float yE = rho * (Q - I);
@@ -608,19 +649,18 @@ __device__ __forceinline__ void update32(const K32& k, const float* Un, const fl
 // The change of one step, -dt/h (dF + dG) + dt Y(W^{n+1/2}) (eq. (15)), for a
 // state kept in another precision: the same sources and stiff branch as
 // update32; ev_n is the start-of-step E_nu deviation the stiff branch relaxes.
-template <int NC>
+template <int NC, bool FullRho = false, int CL = 0>
 __device__ __forceinline__ void increment32(const K32& k, float ev_n, const float* dF,
                                             const float* dG, const float* Wh, float* dU,
                                             float& srcE, float& srcV, float act = 1.0f)
 {
     constexpr int iP = NC == 5 ? 3 : 2, iV = NC == 5 ? 4 : 3;
     const float dt = k.dt, dtdx = k.dtdx;
-    float dr = Wh[0], u = Wh[1], dp = Wh[iP], de = Wh[iV];
+    float u = Wh[1], dp = Wh[iP], de = Wh[iV];
     float v = NC == 5 ? Wh[2] : 0.0f;
-    float rho = k.rho_r + dr, p = k.p_r + dp;
-    float irho = rcp32(rho);
+    float rho = FullRho ? Wh[0] : k.rho_r + Wh[0], p = k.p_r + dp;
     float itau, Q, I;
-    closures32(k, rho, p, irho, itau, Q, I);
+    closures32<false, CL>(k, rho, p, 0.0f, itau, Q, I);
     Q = act * Q;
     I = act * I;
     float yE = rho * (Q - I);

@@ -26,6 +26,20 @@ constexpr int kBcWall = 1;
 constexpr int kBcOutflow = 2;
 constexpr int kBcSource = 3;   // x-low only: forced sound wave in the ghosts
 
+// Closure recipes of the FP32 arithmetic: the exponent codes (2a, 2b) of
+// 1/tau, Q and I of eq. (6), each written c rho^a p^b with T = p / (R rho),
+// compiled into kernels of their own so that the powers are products of rho,
+// p, 1/rho and one reciprocal square root instead of two log2 and three exp2.
+// The rows are the base gas of eq. (6) (tau ~ 1/(rho T), I ~ rho T^2,
+// Q ~ rho^1/2 T^Q_T) with Q_T = 2 and 1; a solve whose codes match a row runs
+// that recipe, any other the general form (row 0).
+constexpr int kRecipes = 2;
+constexpr int kRecipeCodes[kRecipes + 1][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {0, 2, -3, 4, -2, 4},
+    {0, 2, -1, 2, -2, 4},
+};
+
 // Run-constant description of one solve.
 struct InstDesc {
     int64_t nx, ny, ncell;
@@ -61,6 +75,11 @@ struct InstDesc {
     double src_yc, src_hw;    // 2D: the source drives rows with |y - yc| <= hw
     // 2D sector run: pump and sink only for x >= x0, |y - y0| <= (x - x0) tan
     double wedge_x0, wedge_y0, wedge_tan;   // tan <= 0: everywhere
+    // The closures of eq. (6) in terms of (rho, p) for the FP32 arithmetic:
+    // 1/tau, Q and I = cl_c rho^cl_a p^cl_b (with T = p / (R rho)); cl_recipe
+    // > 0 names the compiled recipe whose exponents they are (kRecipeCodes).
+    double cl_c[3], cl_a[3], cl_b[3];
+    int32_t cl_recipe, pad1;
 };
 
 // Mutable per-solve state, advanced by the finalize kernel.

@@ -124,6 +124,8 @@ struct Plain64 {
     static constexpr bool kKeepRows = false;
     // the energy slot holds E itself
     static constexpr bool kSplitE = false;
+    // the closure recipes are an FP32 fast path
+    static constexpr bool kRecipes = false;
     using St = double;
     using K = K64;
     static __device__ K make(const InstDesc& d, double dt)
@@ -156,6 +158,7 @@ struct Plain64 {
     }
     static __device__ void prim(const K& k, const R* U, R* W) { prim64<NC>(k, U, W); }
     static __device__ R speed(const K& k, const R* W) { return speed64<NC>(k, W); }
+    template <bool FR = false, int CL = 0>
     static __device__ void predict(const K& k, const R* W, const R* sx, const R* sy, R* Wh,
                                    R act = 1)
     {
@@ -166,6 +169,7 @@ struct Plain64 {
     {
         flux64<NC, RS>(k, L, Rr, F);
     }
+    template <bool FR = false, int CL = 0>
     static __device__ void update(const K& k, const R* Un, const R* dF, const R* dG, const R* Wh,
                                   R* Unew, R& sE, R& sV, R act = 1)
     {
@@ -185,6 +189,7 @@ struct Dev32 {
     static constexpr bool kKeepRows = true;
     // the energy slot holds e = E - E_nu (deviation from e_r)
     static constexpr bool kSplitE = true;
+    static constexpr bool kRecipes = true;
     static __device__ K make(const InstDesc& d, double dt)
     {
         K k;
@@ -197,17 +202,12 @@ struct Dev32 {
         k.ev_r = (float)d.uref[4];
         k.H_r = (float)d.H_r;
         k.D_r = (float)d.D_r;
-        k.irho0 = (float)(1.0 / d.rho0);
-        k.iRT0 = (float)(1.0 / (d.R * d.T0));
-        k.itau0 = (float)(1.0 / d.tau0);
-        k.Q0 = (float)d.Q0;
-        k.I0 = (float)d.I0;
-        k.tr = (float)d.tau_rho;
-        k.tT = (float)d.tau_T;
-        k.Qr = (float)d.Q_rho;
-        k.QT = (float)d.Q_T;
-        k.Ir = (float)d.I_rho;
-        k.IT = (float)d.I_T;
+        for (int i = 0; i < 3; i++) {
+            k.cl_c[i] = (float)d.cl_c[i];
+            k.cl_a[i] = (float)d.cl_a[i];
+            k.cl_b[i] = (float)d.cl_b[i];
+        }
+        k.gp_r = (float)(d.gamma * d.p_r);
         k.fx = (float)d.fx;
         k.fy = (float)d.fy;
         k.stiff_z = (float)d.stiff_z;
@@ -226,20 +226,24 @@ struct Dev32 {
     }
     static __device__ void prim(const K& k, const R* U, R* W) { prim32<NC>(k, U, W); }
     static __device__ R speed(const K& k, const R* W) { return speed32<NC>(k, W); }
+    // FR: the half-step state carries the full density (HLLC faces);
+    // CL: closure recipe
+    template <bool FR = false, int CL = 0>
     static __device__ void predict(const K& k, const R* W, const R* sx, const R* sy, R* Wh,
                                    R act = 1)
     {
-        predict32<NC>(k, W, sx, sy, Wh, act);
+        predict32<NC, FR, CL>(k, W, sx, sy, Wh, act);
     }
     template <int RS>
     static __device__ void flux(const K& k, const R* L, const R* Rr, R* F)
     {
         flux32<NC, RS>(k, L, Rr, F);
     }
+    template <bool FR = false, int CL = 0>
     static __device__ void update(const K& k, const R* Un, const R* dF, const R* dG, const R* Wh,
                                   R* Unew, R& sE, R& sV, R act = 1)
     {
-        update32<NC>(k, Un, dF, dG, Wh, Unew, sE, sV, act);
+        update32<NC, FR, CL>(k, Un, dF, dG, Wh, Unew, sE, sV, act);
     }
     static __device__ R full_rho(const K& k, R r) { return k.rho_r + r; }
     static __device__ R full_p(const K& k, R p) { return k.p_r + p; }
@@ -257,6 +261,7 @@ struct Mix32 {
     static constexpr int kMinWaves = 1;
     static constexpr bool kKeepRows = true;
     static constexpr bool kSplitE = true;
+    static constexpr bool kRecipes = true;
     static __device__ K make(const InstDesc& d, double dt) { return Dev32<NC>::make(d, dt); }
     static __device__ void prim(const K& k, const St* U, R* W)
     {
@@ -265,21 +270,25 @@ struct Mix32 {
         prim32<NC>(k, D, W);
     }
     static __device__ R speed(const K& k, const R* W) { return speed32<NC>(k, W); }
+    // FR: the half-step state carries the full density (HLLC faces);
+    // CL: closure recipe
+    template <bool FR = false, int CL = 0>
     static __device__ void predict(const K& k, const R* W, const R* sx, const R* sy, R* Wh,
                                    R act = 1)
     {
-        predict32<NC>(k, W, sx, sy, Wh, act);
+        predict32<NC, FR, CL>(k, W, sx, sy, Wh, act);
     }
     template <int RS>
     static __device__ void flux(const K& k, const R* L, const R* Rr, R* F)
     {
         flux32<NC, RS>(k, L, Rr, F);
     }
+    template <bool FR = false, int CL = 0>
     static __device__ void update(const K& k, const St* Un, const R* dF, const R* dG, const R* Wh,
                                   St* Unew, R& sE, R& sV, R act = 1)
     {
         R dU[NC];
-        increment32<NC>(k, (R)Un[NC == 5 ? 4 : 3], dF, dG, Wh, dU, sE, sV, act);
+        increment32<NC, FR, CL>(k, (R)Un[NC == 5 ? 4 : 3], dF, dG, Wh, dU, sE, sV, act);
         for (int c = 0; c < NC; c++) Unew[c] = Un[c] + (St)dU[c];
     }
     static __device__ R full_rho(const K& k, R r) { return k.rho_r + r; }
@@ -308,27 +317,37 @@ __device__ __forceinline__ void acc_init(Acc<R>& a)
 }
 
 // Record one updated cell: NC conserved values (as stored), its primitives
-// and signal speed, and its source increments.
+// and signal speed, and its source increments.  The minima of rho and p are
+// kept in the primitives' own form (deviations for FP32) and made full by
+// acc_finish: rounding is monotone, so the minimum of the full values is the
+// reference plus the minimum deviation.  A split energy slot holds E - E_nu;
+// its sum is made the sum of E by acc_finish.
 template <class P, int NC>
 __device__ __forceinline__ void acc_cell(Acc<typename P::R>& a, const typename P::K& k,
                                          const typename P::St* U, const typename P::R* W,
                                          typename P::R s, typename P::R sE, typename P::R sV)
 {
-    // component slots (rho, m_x, m_y, E, E_nu); a split energy slot holds
-    // E - E_nu, whose deviation plus that of E_nu is the deviation of E
     constexpr int iE = NC == 5 ? 3 : 2, iV = NC - 1;
-    const double ev = (double)U[iV];
-    const double e = P::kSplitE ? (double)U[iE] + ev : (double)U[iE];
     a.tot[0] += (double)U[0];
     a.tot[1] += (double)U[1];
     if (NC == 5) a.tot[2] += (double)U[2];
-    a.tot[3] += e;
-    a.tot[4] += ev;
+    a.tot[3] += (double)U[iE];
+    a.tot[4] += (double)U[iV];
     a.src[0] += (double)sE;
     a.src[1] += (double)sV;
     a.smax = fmax(a.smax, s);
-    a.rmin = fmin(a.rmin, P::full_rho(k, W[0]));
-    a.pmin = fmin(a.pmin, P::full_p(k, W[NC == 5 ? 3 : 2]));
+    a.rmin = fmin(a.rmin, W[0]);
+    a.pmin = fmin(a.pmin, W[NC == 5 ? 3 : 2]);
+}
+
+// Per-lane accumulators as the records expect them: the sum of E (a split
+// energy slot summed E - E_nu) and full minima of rho and p.
+template <class P>
+__device__ __forceinline__ void acc_finish(Acc<typename P::R>& a, const typename P::K& k)
+{
+    if (P::kSplitE) a.tot[3] += a.tot[4];
+    a.rmin = P::full_rho(k, a.rmin);
+    a.pmin = P::full_p(k, a.pmin);
 }
 
 // Failure flags of a lane: a non-finite value anywhere makes its sums
@@ -647,13 +666,16 @@ __device__ __forceinline__ void flux_y(const typename P::K& k, const typename P:
 }
 
 // One work item of the 2D step: strip (60 columns + halo) x chunk of rows.
-template <class P, int RS, bool BC>
+// CL: closure recipe of the FP32 arithmetic (0: general).
+template <class P, int RS, bool BC, int CL = 0>
 __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& k, int cur,
                                         const double* gsrc, int64_t item, int lane,
                                         Acc<typename P::R>& acc)
 {
     using R = typename P::R;
     constexpr int NC = 5;
+    // the HLLC flux takes the full density in its face states
+    constexpr bool FR = RS == 0;
     const int64_t nx = d.nx, ny = d.ny;
     const int64_t strip = item % d.nstrips, chunk = item / d.nstrips;
     const int64_t x0 = strip * kInterior;
@@ -661,21 +683,26 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
     const int64_t x = BC ? axis_cell(x0 - kHalo + lane, nx, d.bc[0], d.bc[1], flipx)
                          : wrap_axis(x0 - kHalo + lane, nx);
     const bool inner = lane >= kHalo && lane < kWave - kHalo && x0 + (lane - kHalo) < nx;
-    const int64_t r0 = chunk * d.rows_per_item;
-    const int64_t r1 = r0 + d.rows_per_item < ny ? r0 + d.rows_per_item : ny;
+    // rows in 32 bits (a grid has fewer than 2^30 cells): the row arithmetic
+    // is the same for every lane and stays on the scalar unit
+    const int nyi = (int)ny;
+    const int r0 = (int)(chunk * d.rows_per_item);
+    const int r1 = r0 + d.rows_per_item < nyi ? r0 + d.rows_per_item : nyi;
     using St = typename P::St;
     const Planes<St, NC> src(d.buf[cur], d.ncell);
     const Planes<St, NC> dst(d.buf[cur ^ 1], d.ncell);
+    const uint32_t rowb = (uint32_t)(nx * (int64_t)sizeof(St));
+    const uint32_t xb = (uint32_t)(x * (int64_t)sizeof(St));
     // byte offset of (row r, this lane's column); r within two rows of [0, ny)
-    auto boff = [&](int64_t r) -> uint32_t {
-        int64_t rr;
+    auto boff = [&](int r) -> uint32_t {
+        int rr;
         if (BC) {
             bool f;
-            rr = axis_cell(r, ny, d.bc[2], d.bc[3], f);
+            rr = (int)axis_cell(r, ny, d.bc[2], d.bc[3], f);
         } else {
-            rr = r < 0 ? r + ny : (r >= ny ? r - ny : r);
+            rr = r < 0 ? r + nyi : (r >= nyi ? r - nyi : r);
         }
-        return (uint32_t)((rr * nx + x) * (int64_t)sizeof(St));
+        return (uint32_t)rr * rowb + xb;
     };
     // a loaded row r as ghost values: the lanes before a forced source take
     // its wave, wall ghosts carry the mirrored normal momentum (x ends: rho u,
@@ -720,7 +747,7 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
     };
 
     // Rolling state, in two register sets that swap roles every row:
-    //   Wd/We  primitive state of rows i+1 / i+2
+    //   Wd/We  primitive state of rows i+1 / i+2 (and, FP32, 1/rho)
     //   Dp/Dn  y-differences W(i+1) - W(i) / W(i+2) - W(i+1)
     //   h0/h1  half-step state of rows i / i+1;  x0s/x1s their x-slopes
     //   Np/Nn  north face states of rows i / i+1
@@ -729,13 +756,13 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
     // Policies that keep the raw rows hold four of them (rows i .. i+3) in a
     // ring U0..U3, so U^n of row i is still in registers at its update;
     // the others re-read it and use U2/U3 only.
-    R WA[NC], WB[NC], DA[NC], DB[NC], HA[NC], HB[NC], XA[NC], XB[NC];
+    R WA[NC + 1], WB[NC + 1], DA[NC], DB[NC], HA[NC], HB[NC], XA[NC], XB[NC];
     R NA[NC], NB[NC], GA[NC], GB[NC];
     St U0[NC], U1[NC], U2[NC], U3[NC];
 
     // prologue: rows r0-2 .. r0+1
     {
-        R Wa[NC], Wb[NC], Wc[NC], sy[NC], sx[NC], hb[NC], S[NC];
+        R Wa[NC + 1], Wb[NC + 1], Wc[NC + 1], sy[NC], sx[NC], hb[NC], S[NC];
         St t[NC];
         St* t0 = P::kKeepRows ? U0 : t;
         St* t1 = P::kKeepRows ? U1 : t;
@@ -755,7 +782,7 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
         // row r0-1: its north face state
         slopes_x(Wb, sx);
         for (int c = 0; c < NC; c++) sy[c] = minmod(Wb[c] - Wa[c], Wc[c] - Wb[c]);
-        P::predict(k, Wb, sx, sy, hb, active(r0 - 1));
+        P::template predict<FR, CL>(k, Wb, sx, sy, hb, active(r0 - 1));
         for (int c = 0; c < NC; c++) hb[c] = face(hb[c], sy[c]);
         // row r0
         slopes_x(Wc, XA);
@@ -764,7 +791,7 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
             DA[c] = WA[c] - Wc[c];
             sy[c] = minmod(dp, DA[c]);
         }
-        P::predict(k, Wc, XA, sy, HA, active(r0));
+        P::template predict<FR, CL>(k, Wc, XA, sy, HA, active(r0));
         for (int c = 0; c < NC; c++) {
             S[c] = face(HA[c], -sy[c]);
             NA[c] = face(HA[c], sy[c]);
@@ -772,7 +799,7 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
         flux_y<P, RS>(k, hb, S, GA);
     }
 
-    auto row = [&](int64_t i, R* Wd, R* We, R* Dp, R* Dn, R* h0, R* h1, R* x0s, R* x1s,
+    auto row = [&](int i, R* Wd, R* We, R* Dp, R* Dn, R* h0, R* h1, R* x0s, R* x1s,
                    R* Np, R* Nn, R* Gp, R* Gn, St* Uk, St* Uc, St* Ux) {
         // U^n of row i: kept in the ring (Uk), or else re-read from cache
         // for the update (it was loaded two rows ago).  Loads complete in
@@ -784,10 +811,14 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
         St Ul[NC];
         St* Un = reread ? Ul : Uk;
         if (early) src.load(boff(i), Ul);
-        // row i+2 has arrived in Uc; put row i+3 in flight
+        // row i+2 has arrived in Uc; put row i+3 in flight.  The load is
+        // issued on every row (on the chunk's last row it fetches row i+2
+        // again, from cache, into the unused buffer): a load on one path only
+        // makes the compiler's wait counts assume the other path, so each row
+        // would wait for the loads it has just issued
         ghost(i + 2, Uc);
         P::prim(k, Uc, We);
-        if (i + 1 < r1) src.load(boff(i + 3), Ux);
+        src.load(boff(i + 1 < r1 ? i + 3 : i + 2), Ux);
         // predictor of row i+1
         R sy[NC];
         slopes_x(Wd, x1s);
@@ -795,7 +826,7 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
             Dn[c] = We[c] - Wd[c];
             sy[c] = minmod(Dp[c], Dn[c]);
         }
-        P::predict(k, Wd, x1s, sy, h1, active(i + 1));
+        P::template predict<FR, CL>(k, Wd, x1s, sy, h1, active(i + 1));
         // y-face i+1/2 between the north state of row i and the south state
         // of row i+1
         {
@@ -824,10 +855,10 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
         }
         // update of row i
         St Uo[NC];
-        R Wn[NC], sE, sV;
+        R Wn[NC + 1], sE, sV;
         const uint32_t o = boff(i);
         if (reread && !early) src.load(o, Ul);
-        P::update(k, Un, dF, dG, h0, Uo, sE, sV, active(i));
+        P::template update<FR, CL>(k, Un, dF, dG, h0, Uo, sE, sV, active(i));
         P::prim(k, Uo, Wn);
         R s = P::speed(k, Wn);
         if (inner) {
@@ -836,7 +867,7 @@ __device__ __forceinline__ void march2d(const InstDesc& d, const typename P::K& 
         }
     };
 
-    int64_t i = r0;
+    int i = r0;
     if constexpr (P::kKeepRows) {
         for (; i < r1; i += 4) {
             row(i, WA, WB, DA, DB, HA, HB, XA, XB, NA, NB, GA, GB, U0, U2, U3);
@@ -869,7 +900,47 @@ __device__ __forceinline__ void march2d_bc(const InstDesc& d, const typename P::
         march2d<P, RS, false>(d, k, cur, gsrc, item, lane, acc);
 }
 
-template <class P>
+// One HLLC work item: a periodic solve whose closures match a compiled recipe
+// (kRecipeCodes) takes that recipe's march, every other solve the general
+// one.  Every kernel that steps a solve applies this same rule, so a solve's
+// state is bitwise the same on every path.
+template <class P, int CL = kRecipes>
+__device__ __forceinline__ void march2d_hllc(const InstDesc& d, const typename P::K& k, int cur,
+                                             const double* gsrc, int64_t item, int lane,
+                                             Acc<typename P::R>& acc)
+{
+    if constexpr (P::kRecipes && CL > 0) {
+        if (!d.any_bc && d.cl_recipe == CL) {
+            march2d<P, 0, false, CL>(d, k, cur, gsrc, item, lane, acc);
+            return;
+        }
+        march2d_hllc<P, CL - 1>(d, k, cur, gsrc, item, lane, acc);
+    } else {
+        march2d_bc<P, 0>(d, k, cur, gsrc, item, lane, acc);
+    }
+}
+
+template <class P, int CL = kRecipes>
+__device__ __forceinline__ void march1d_hllc(const InstDesc& d, const typename P::K& k, int cur,
+                                             const double* gsrc, int64_t item, int lane,
+                                             Acc<typename P::R>& acc)
+{
+    if constexpr (P::kRecipes && CL > 0) {
+        if (!d.any_bc && d.cl_recipe == CL) {
+            march1d<P, 0, false, CL>(d, k, cur, gsrc, item, lane, acc);
+            return;
+        }
+        march1d_hllc<P, CL - 1>(d, k, cur, gsrc, item, lane, acc);
+    } else {
+        march1d_bc<P, 0>(d, k, cur, gsrc, item, lane, acc);
+    }
+}
+
+// V = 0: any solves (boundary kind, flux and closures per solve);
+// V = 1 + r: every solve of the launch is periodic with the HLLC flux and its
+// closures match recipe r (kRecipeCodes; r = 0: the general form) -- a kernel
+// with only that path, and so fewer registers.
+template <class P, int V>
 __global__ void __launch_bounds__(256, P::kMinWaves) step2d_kernel(const InstDesc* __restrict__ descs,
                                                      InstCtrl* __restrict__ ctrls,
                                                      const BlockRef* __restrict__ blocks,
@@ -889,11 +960,14 @@ __global__ void __launch_bounds__(256, P::kMinWaves) step2d_kernel(const InstDes
     acc_init(acc);
     const int64_t item = (int64_t)br.local * nwaves + wave;
     if (item < d.nitems) {
-        if (d.riemann == 1)
+        if constexpr (V > 0)
+            march2d<P, 0, false, V - 1>(d, k, sc.cur, sc.gsrc, item, lane, acc);
+        else if (d.riemann == 1)
             march2d_bc<P, 1>(d, k, sc.cur, sc.gsrc, item, lane, acc);
         else
-            march2d_bc<P, 0>(d, k, sc.cur, sc.gsrc, item, lane, acc);
+            march2d_hllc<P>(d, k, sc.cur, sc.gsrc, item, lane, acc);
     }
+    acc_finish<P>(acc, k);
     Partial* parts = (Partial*)d.partials;
     block_reduce_store(acc, parts + br.local, wave, lane, nwaves);
     if (fused && d.fused) last_block_accept(d, ctrls[br.inst], sc);
@@ -902,13 +976,14 @@ __global__ void __launch_bounds__(256, P::kMinWaves) step2d_kernel(const InstDes
 // ================================================================ 1D step
 
 // One work item of the 1D step: a group of consecutive 60-cell segments.
-template <class P, int RS, bool BC>
+template <class P, int RS, bool BC, int CL = 0>
 __device__ __forceinline__ void march1d(const InstDesc& d, const typename P::K& k, int cur,
                                         const double* gsrc, int64_t item, int lane,
                                         Acc<typename P::R>& acc)
 {
     using R = typename P::R;
     constexpr int NC = 4;
+    constexpr bool FR = RS == 0;
     const int64_t n = d.nx;
     using St = typename P::St;
     const Planes<St, NC> src(d.buf[cur], n);
@@ -924,9 +999,12 @@ __device__ __forceinline__ void march1d(const InstDesc& d, const typename P::K& 
     St UA[NC], UB[NC];
     src.load(boff(s0), UA);
     auto seg = [&](int64_t sg, St* Uc, St* Ux) {
-        R W[NC], sx[NC], h[NC];
+        R W[NC + 1], sx[NC], h[NC];
         const uint32_t o = boff(sg);
-        if (sg + 1 < s1) src.load(boff(sg + 1), Ux);
+        // issued on every segment (the last one fetches itself again, from
+        // cache, into the unused buffer), so that the compiler's wait counts
+        // let the load stay in flight
+        src.load(boff(sg + 1 < s1 ? sg + 1 : sg), Ux);
         if (BC) {
             // the lanes before a forced source take its wave; wall ghosts
             // carry the mirrored momentum
@@ -944,7 +1022,7 @@ __device__ __forceinline__ void march1d(const InstDesc& d, const typename P::K& 
             pin(b);
             sx[c] = minmod(a, b);
         }
-        P::predict(k, W, sx, sx, h);
+        P::template predict<FR, CL>(k, W, sx, sx, h);
         R E[NC], Wr[NC], Fx[NC], dF[NC];
         for (int c = 0; c < NC; c++) {
             E[c] = face(h[c], sx[c]);
@@ -956,8 +1034,8 @@ __device__ __forceinline__ void march1d(const InstDesc& d, const typename P::K& 
             pin(dF[c]);
         }
         St Uo[NC];
-        R Wn[NC], sE, sV;
-        P::update(k, Uc, dF, dF, h, Uo, sE, sV);
+        R Wn[NC + 1], sE, sV;
+        P::template update<FR, CL>(k, Uc, dF, dF, h, Uo, sE, sV);
         P::prim(k, Uo, Wn);
         R s = P::speed(k, Wn);
         const bool inner =
@@ -986,7 +1064,8 @@ __device__ __forceinline__ void march1d_bc(const InstDesc& d, const typename P::
         march1d<P, RS, false>(d, k, cur, gsrc, item, lane, acc);
 }
 
-template <class P>
+// V as for step2d_kernel
+template <class P, int V>
 __global__ void __launch_bounds__(256) step1d_kernel(const InstDesc* __restrict__ descs,
                                                      InstCtrl* __restrict__ ctrls,
                                                      const BlockRef* __restrict__ blocks,
@@ -1006,11 +1085,14 @@ __global__ void __launch_bounds__(256) step1d_kernel(const InstDesc* __restrict_
     acc_init(acc);
     const int64_t item = (int64_t)br.local * nwaves + wave;
     if (item < d.nitems) {
-        if (d.riemann == 1)
+        if constexpr (V > 0)
+            march1d<P, 0, false, V - 1>(d, k, sc.cur, sc.gsrc, item, lane, acc);
+        else if (d.riemann == 1)
             march1d_bc<P, 1>(d, k, sc.cur, sc.gsrc, item, lane, acc);
         else
-            march1d_bc<P, 0>(d, k, sc.cur, sc.gsrc, item, lane, acc);
+            march1d_hllc<P>(d, k, sc.cur, sc.gsrc, item, lane, acc);
     }
+    acc_finish<P>(acc, k);
     Partial* parts = (Partial*)d.partials;
     block_reduce_store(acc, parts + br.local, wave, lane, nwaves);
     if (fused && d.fused) last_block_accept(d, ctrls[br.inst], sc);
@@ -1063,7 +1145,7 @@ __global__ void __launch_bounds__(256) prime_kernel(const InstDesc* __restrict__
             if (!inner) continue;
             for (int64_t r = rows0; r < rows1; r++) {
                 St U[NC];
-                R W[NC];
+                R W[NC + 1];
                 load_cell_cached<St, NC>(src, ncell, r * nx + xo, U);
                 P::prim(k, U, W);
                 R s = P::speed(k, W);
@@ -1071,6 +1153,7 @@ __global__ void __launch_bounds__(256) prime_kernel(const InstDesc* __restrict__
             }
         }
     }
+    acc_finish<P>(acc, k);
     Partial* parts = (Partial*)d.partials;
     block_reduce_store(acc, parts + br.local, wave, lane, nwaves);
 }
@@ -1119,14 +1202,15 @@ __global__ void __launch_bounds__(512) run_small_kernel(const InstDesc* __restri
                 if (d.riemann == 1)
                     march2d_bc<P, 1>(d, k, sc.cur, sc.gsrc, item, lane, acc);
                 else
-                    march2d_bc<P, 0>(d, k, sc.cur, sc.gsrc, item, lane, acc);
+                    march2d_hllc<P>(d, k, sc.cur, sc.gsrc, item, lane, acc);
             } else {
                 if (d.riemann == 1)
                     march1d_bc<P, 1>(d, k, sc.cur, sc.gsrc, item, lane, acc);
                 else
-                    march1d_bc<P, 0>(d, k, sc.cur, sc.gsrc, item, lane, acc);
+                    march1d_hllc<P>(d, k, sc.cur, sc.gsrc, item, lane, acc);
             }
         }
+        acc_finish<P>(acc, k);
         uint32_t flags = acc_flags(acc);
         double smax = (double)acc.smax, rmin = (double)acc.rmin, pmin = (double)acc.pmin;
         for (int m = 32; m >= 1; m >>= 1) {
@@ -1180,26 +1264,55 @@ static void launch(void (*kernel)(A...), dim3 g, dim3 b, hipStream_t s, hipEvent
         hipLaunchKernelGGL(kernel, g, b, 0, s, a...);
 }
 
-hipError_t launch_step(int dim, int prec, const InstDesc* descs, InstCtrl* ctrls,
+// Step kernel of a policy for variant v (the FP64 arithmetic has no closure
+// recipes: its periodic-HLLC variant is 1 whatever the recipe).
+template <template <int> class Pol, int NC>
+static void launch_variant(int v, dim3 g, dim3 b, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                           const InstDesc* descs, InstCtrl* ctrls, const BlockRef* blocks,
+                           int remap, int fused)
+{
+    using P = Pol<NC>;
+    if constexpr (NC == 5) {
+        if (v == 0) launch(step2d_kernel<P, 0>, g, b, s, e0, e1, descs, ctrls, blocks, remap, fused);
+        else if (v == 1 || !P::kRecipes)
+            launch(step2d_kernel<P, 1>, g, b, s, e0, e1, descs, ctrls, blocks, remap, fused);
+        else if constexpr (P::kRecipes) {
+            if (v == 2) launch(step2d_kernel<P, 2>, g, b, s, e0, e1, descs, ctrls, blocks, remap, fused);
+            else launch(step2d_kernel<P, 3>, g, b, s, e0, e1, descs, ctrls, blocks, remap, fused);
+        }
+    } else {
+        if (v == 0) launch(step1d_kernel<P, 0>, g, b, s, e0, e1, descs, ctrls, blocks, remap, fused);
+        else if (v == 1 || !P::kRecipes)
+            launch(step1d_kernel<P, 1>, g, b, s, e0, e1, descs, ctrls, blocks, remap, fused);
+        else if constexpr (P::kRecipes) {
+            if (v == 2) launch(step1d_kernel<P, 2>, g, b, s, e0, e1, descs, ctrls, blocks, remap, fused);
+            else launch(step1d_kernel<P, 3>, g, b, s, e0, e1, descs, ctrls, blocks, remap, fused);
+        }
+    }
+}
+
+hipError_t launch_step(int dim, int prec, int variant, const InstDesc* descs, InstCtrl* ctrls,
                        const BlockRef* blocks, int64_t nblocks, int waves, int remap, int fused,
                        hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
+    static_assert(kRecipes == 2, "launch_variant instantiates variants 0..3");
     if (!grid_ok(nblocks) || waves < 1 || waves > 4) return hipErrorInvalidValue;
+    if (variant < 0 || variant > kRecipes + 1) return hipErrorInvalidValue;
     dim3 g((unsigned)nblocks), b((unsigned)(64 * waves));
     if (dim == 2) {
         if (prec == 0)
-            launch(step2d_kernel<Plain64<5>>, g, b, s, e0, e1, descs, ctrls, blocks, remap, fused);
+            launch_variant<Plain64, 5>(variant, g, b, s, e0, e1, descs, ctrls, blocks, remap, fused);
         else if (prec == 1)
-            launch(step2d_kernel<Dev32<5>>, g, b, s, e0, e1, descs, ctrls, blocks, remap, fused);
+            launch_variant<Dev32, 5>(variant, g, b, s, e0, e1, descs, ctrls, blocks, remap, fused);
         else
-            launch(step2d_kernel<Mix32<5>>, g, b, s, e0, e1, descs, ctrls, blocks, remap, fused);
+            launch_variant<Mix32, 5>(variant, g, b, s, e0, e1, descs, ctrls, blocks, remap, fused);
     } else {
         if (prec == 0)
-            launch(step1d_kernel<Plain64<4>>, g, b, s, e0, e1, descs, ctrls, blocks, remap, fused);
+            launch_variant<Plain64, 4>(variant, g, b, s, e0, e1, descs, ctrls, blocks, remap, fused);
         else if (prec == 1)
-            launch(step1d_kernel<Dev32<4>>, g, b, s, e0, e1, descs, ctrls, blocks, remap, fused);
+            launch_variant<Dev32, 4>(variant, g, b, s, e0, e1, descs, ctrls, blocks, remap, fused);
         else
-            launch(step1d_kernel<Mix32<4>>, g, b, s, e0, e1, descs, ctrls, blocks, remap, fused);
+            launch_variant<Mix32, 4>(variant, g, b, s, e0, e1, descs, ctrls, blocks, remap, fused);
     }
     return hipGetLastError();
 }
