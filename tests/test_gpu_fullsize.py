@@ -1,12 +1,21 @@
 """Parity at the benchmark's full sizes, in the launch shape the benchmark
 uses (the autotuned one), on sampled cells: the oracle cannot run a 4096^2
-grid quickly, but one step of a cell depends only on the 5 x 5 cells around it
-(two per side), so for each sampled cell the oracle steps an 11 x 11 window cut
-from the same initial state (periodic wrap) with the GPU's dt and its centre is
-compared with the GPU's cell.  Samples include the grid's corners and edges.
+grid quickly, but K steps of a cell depend only on the cells within 2K of it,
+so for each sampled cell the oracle steps a window of half-width 2K + 3 cut
+from the same initial state (periodic wrap; its edges go wrong and the error
+moves in 2 cells per step) K times with the GPU's dt sequence, and its centre
+is compared with the GPU's cell.  Samples include the grid's corners, strip
+edges and random cells.  K = 5.
 
-Bars as in test_gpu_parity: FP64 bit for bit; FP32 within 1e-5 relative L1
-over the samples.  The 1D 2^20-cell workload is checked the same way.
+Bars: FP64 bit for bit; FP32 within 1e-5 relative L1 of the full values over
+the samples, and, on the change over the K steps, within ten times what the
+FP32 storage of the deviation from the background explains: each step rounds
+the stored deviation dU by about 2^-24 of itself, so after K steps the change
+carries about sqrt(K) 2^-24 |dU| of error (relative L1 over the samples; at
+least 1e-4).  A kernel that left the state untouched is off by 1 there.  On
+the 4096^2 grid a step changes the perturbation by about 0.5 %, so the bar is
+the 1e-4 floor; on the 2^20-cell 1D grid by about 1e-4, and the bar is about
+3e-3.  The 1D 2^20-cell workload is checked the same way.
 """
 import numpy as np
 import pytest
@@ -15,7 +24,9 @@ from paper_1805_03442_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
 
-R = 5   # window half-width: the update reaches 2 cells, the window edges are wrong
+K = 5          # steps compared
+R = 2 * K + 3  # window half-width: each step reaches 2 cells, the window edges go wrong
+FP32_CHANGE_FLOOR = 1e-4
 
 
 def say(msg):
@@ -46,16 +57,58 @@ def samples_2d(n, count, seed):
     return pts
 
 
-def one_step_gpu(ng, gas, W, nx, ny, prec):
+def k_steps_gpu(ng, gas, W, nx, ny, prec):
+    """K steps on the GPU in the benchmark's launch shape: the state before
+    and after, and the dt of each step."""
     from paper_1805_03442_amd import autotune
     s = ng.Solver(gas, nx, ny, W=W, precision=prec)
     autotune.apply(s)
     U0 = s.conserved()
-    s.step(1)
+    dts = []
+    for _ in range(K):
+        s.step(1)
+        dts.append(s.diagnostics()["dt_last"])
     U1 = s.conserved()
-    dt = s.diagnostics()["dt_last"]
+    assert s.diagnostics()["status"] == 0
     s.close()
-    return U0, U1, dt
+    return U0, U1, dts
+
+
+def oracle_window(P, win, dts):
+    for dt in dts:
+        st, win, _ = P.step(win, dt)
+        assert st == 0
+    return win
+
+
+class Bars:
+    """Accumulated full-value and change errors over the sampled cells; bg is
+    the background conserved state the FP32 storage is a deviation from."""
+
+    def __init__(self, bg):
+        self.bg = np.asarray(bg)
+        self.num = self.den = self.cnum = self.cden = self.dev = 0.0
+
+    def add(self, a, b, a0):
+        self.num += float(np.abs(a - b).sum())
+        self.den += float(np.abs(b).sum())
+        self.cnum += float(np.abs((a - a0) - (b - a0)).sum())
+        self.cden += float(np.abs(b - a0).sum())
+        self.dev += float(np.abs(a0 - self.bg).sum())
+
+    def check(self, what):
+        full, change = self.num / self.den, self.cnum / self.cden
+        bar = max(FP32_CHANGE_FLOOR, 10.0 * np.sqrt(K) * 2.0 ** -24 * self.dev / self.cden)
+        say(f"{what}: sampled rel L1 {full:.3e}, of the {K}-step change {change:.3e} "
+            f"(bar {bar:.2e})")
+        assert full <= 1e-5
+        assert change <= bar
+
+
+def background_cons(gas, comps):
+    b = wl.background(gas)
+    U = np.array([b["rho"], 0.0, 0.0, b["p"] / (gas["gamma"] - 1.0) + b["ev"], b["ev"]])
+    return U[comps]
 
 
 @pytest.mark.parametrize("prec_name", ["fp64", "fp32"])
@@ -63,25 +116,21 @@ def test_2d_4096_sampled_cells(ng, oracle_mod, prec_name):
     prec = ng.NG_FP64 if prec_name == "fp64" else ng.NG_FP32
     w = wl.workload_2d_random(4096)
     n = 4096
-    say(f"full-size 2D {n}^2 {prec_name}: one GPU step")
-    U0, U1, dt = one_step_gpu(ng, w["gas"], w["W"], n, n, prec)
+    say(f"full-size 2D {n}^2 {prec_name}: {K} GPU steps")
+    U0, U1, dts = k_steps_gpu(ng, w["gas"], w["W"], n, n, prec)
     # the oracle steps windows of the state the GPU started from (as read back)
     P = oracle_mod.Problem(w["gas"], 2 * R + 1, 2 * R + 1, h=1.0 / n)
-    num, den, worst = 0.0, 0.0, 0.0
+    bars = Bars(background_cons(w["gas"], [0, 1, 2, 3, 4]))
     for (k, j) in samples_2d(n, 48, 5):
         rows = np.arange(k - R, k + R + 1) % n
         cols = np.arange(j - R, j + R + 1) % n
-        win = U0[:, rows][:, :, cols]
-        st, V, _ = P.step(win, dt)
-        assert st == 0
+        V = oracle_window(P, U0[:, rows][:, :, cols], dts)
         a, b = U1[:, k, j], V[:, R, R]
         if prec == ng.NG_FP64:
             assert np.array_equal(a, b), (k, j, a, b)
-        num += float(np.abs(a - b).sum())
-        den += float(np.abs(b).sum())
-        worst = max(worst, float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300))))
-    say(f"full-size 2D {prec_name}: sampled rel L1 {num / den:.3e}, worst cell {worst:.3e}")
-    assert num / den <= 1e-5
+        bars.add(a, b, U0[:, k, j])
+    if prec == ng.NG_FP32:
+        bars.check(f"full-size 2D {prec_name}")
 
 
 @pytest.mark.parametrize("prec_name", ["fp64", "fp32"])
@@ -89,23 +138,21 @@ def test_1d_2e20_sampled_cells(ng, oracle_mod, prec_name):
     prec = ng.NG_FP64 if prec_name == "fp64" else ng.NG_FP32
     w = wl.workload_1d_multimode()
     n = w["nx"]
-    say(f"full-size 1D {n} {prec_name}: one GPU step")
-    U0, U1, dt = one_step_gpu(ng, w["gas"], w["W"], n, 1, prec)
+    say(f"full-size 1D {n} {prec_name}: {K} GPU steps")
+    U0, U1, dts = k_steps_gpu(ng, w["gas"], w["W"], n, 1, prec)
     P = oracle_mod.Problem(w["gas"], 2 * R + 1, 1, h=1.0 / n)
     r = np.random.Generator(np.random.PCG64(6))
     pts = [0, 1, n - 1, n - 2, 59, 60, 61] + [int(v) for v in r.integers(0, n, size=64)]
-    num, den = 0.0, 0.0
+    bars = Bars(background_cons(w["gas"], [0, 1, 3, 4]))
     for j in pts:
         cols = np.arange(j - R, j + R + 1) % n
-        st, V, _ = P.step(U0[:, :, cols], dt)
-        assert st == 0
-        a, b = U1[:, 0, j], V[:, 0, R]
+        V = oracle_window(P, U0[:, :, cols], dts)
+        a, b = U1[[0, 1, 3, 4], 0, j], V[[0, 1, 3, 4], 0, R]
         if prec == ng.NG_FP64:
             assert np.array_equal(a, b), (j, a, b)
-        num += float(np.abs(a - b).sum())
-        den += float(np.abs(b).sum())
-    say(f"full-size 1D {prec_name}: sampled rel L1 {num / den:.3e}")
-    assert num / den <= 1e-5
+        bars.add(a, b, U0[[0, 1, 3, 4], 0, j])
+    if prec == ng.NG_FP32:
+        bars.check(f"full-size 1D {prec_name}")
 
 
 def test_2d_4096_totals_follow_the_source_budget(ng):

@@ -148,12 +148,17 @@ def test_fp64_run_to_time(ng):
     assert np.all(e <= FP64_TOL), e
 
 
+@pytest.mark.parametrize("length", ["long", "short"])
 @pytest.mark.parametrize("mode", ["fp32", "mixed"])
 @pytest.mark.parametrize("case", ["1d_acoustic", "1d_multimode_small", "2d_random_small"])
-def test_fp32_against_oracle(ng, case, mode):
-    """FP32 arithmetic on FP32 deviations (fp32) or on FP64 deviations (mixed):
-    both within the FP32 bar of the full field; the mixed state does not
-    accumulate the per-step FP32 rounding of the stored perturbation."""
+def test_fp32_against_oracle(ng, case, mode, length):
+    """FP32 arithmetic on FP32 deviations (fp32) or on FP64 deviations (mixed).
+    long runs (2000, 3000 and 300 steps): both within the FP32 bar of the full
+    field; the mixed state, which does not accumulate the per-step FP32
+    rounding of the stored perturbation, also within it on the change of the
+    state.  short runs (a tenth of the steps): both within the bar on the
+    change of the state, the stricter measure (the perturbation is about 1e-3
+    of the full values)."""
     if case == "1d_acoustic":
         w = wl.workload_1d_acoustic()
         gas, W, nx, ny, steps = w["gas"], w["W"], 1024, 1, 2000
@@ -166,15 +171,17 @@ def test_fp32_against_oracle(ng, case, mode):
         nx = ny = 256
         steps = 300
         W = wl.random_field_2d(gas, nx, wl.rng(3), kmax=64)
+    if length == "short":
+        steps //= 10
     prec = ng.NG_FP32 if mode == "fp32" else ng.NG_MIXED
     U, ref, d, U0 = run_both(ng, gas, W, nx, ny, steps, prec)
     cs = comps(ny)
     e = rel_l1(U[cs], ref["U"][cs])
-    # error on the perturbation itself (stricter, reported)
+    # error on the perturbation itself (stricter)
     ed = rel_l1((U - U0)[cs], (ref["U"] - U0)[cs])
-    say(f"{mode} {case} rel_l1 {e}  perturbation rel_l1 {ed}")
+    say(f"{mode} {case} {steps} steps: rel_l1 {e}  perturbation rel_l1 {ed}")
     assert np.all(e <= FP32_TOL), e
-    if mode == "mixed":
+    if mode == "mixed" or length == "short":
         assert np.all(ed <= FP32_TOL), ed
 
 
@@ -812,12 +819,14 @@ def test_sector_2d(ng, shape):
     """Active wedge, source segment, wall G1 and free outflow, on the per-step
     kernels (square and ragged grids) and on the persistent small-solve path:
     FP64 within 1e-12 of the state's scale (the device sine of the source;
-    each component within 1e-10 of its own maximum).  FP32: density and the
-    energies within 1e-5 relative L1; the momenta, pure perturbations of the
-    sound wave, within 1e-4 (measured 1.7e-5 to 3e-5).  The FP32 state holds
-    deviations from one uniform reference, the active background; in the
-    passive part the stored E_nu deviation is -rho0 tau0 Q0 = -0.5, whose
-    rounding (ulp(0.5) = 6e-8) enters the relaxation source every step."""
+    each component within 1e-10 of its own maximum).  Mixed (FP32
+    arithmetic, FP64 deviation state): every component within 1e-5 relative
+    L1.  FP32: density and the energies within 1e-5; the momenta, pure
+    perturbations of the sound wave, within the measured bound 5e-5
+    (1.7e-5 to 3e-5 measured), not 1e-5: the FP32 state holds deviations
+    from one uniform reference, the active background, so in the passive
+    part the stored E_nu deviation is -rho0 tau0 Q0 = -0.5, whose rounding
+    (ulp(0.5) = 6e-8) enters the relaxation source every step."""
     nx, ny, small = shape
     n = max(nx, ny)
     L = 0.5 * n / 100.0
@@ -826,7 +835,7 @@ def test_sector_2d(ng, shape):
     yc = 0.5 * ny * w["h"]
     src = (1e-3, 0.1, yc, 0.05)
     wedge = (0.0, yc, w["wedge"][2])
-    for prec in (ng.NG_FP64, ng.NG_FP32):
+    for prec in (ng.NG_FP64, ng.NG_FP32, ng.NG_MIXED):
         U, ref, d, U0 = run_both(ng, w["gas"], W, nx, ny, 120, prec, h=w["h"], bc=w["bc"],
                                  source=src, wedge=wedge, small_limit=small)
         assert d["status"] == 0 and d["steps"] == 120
@@ -835,11 +844,15 @@ def test_sector_2d(ng, shape):
             es = state_linf(U, ref["U"])
             say(f"sector {shape} fp64 rel_linf {e} state_linf {es:.3e}")
             assert es <= FP64_TOL and np.all(e <= 1e-10), (e, es)
+        elif prec == ng.NG_MIXED:
+            e = rel_l1(U, ref["U"])
+            say(f"sector {shape} mixed rel_l1 {e}")
+            assert np.all(e <= FP32_TOL), e
         else:
             e = rel_l1(U, ref["U"])
             say(f"sector {shape} fp32 rel_l1 {e}")
             assert np.all(e[[0, 3, 4]] <= FP32_TOL), e
-            assert np.all(e[[1, 2]] <= 1e-4), e
+            assert np.all(e[[1, 2]] <= 5e-5), e
     # the wedge matters: the same run with the medium active everywhere differs
     U2, ref2, _, _ = run_both(ng, w["gas"], W, nx, ny, 120, ng.NG_FP64, h=w["h"], bc=w["bc"],
                               source=src, small_limit=small)
