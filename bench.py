@@ -7,32 +7,43 @@ conservative update of eq. (15), the signal-speed maximum for the next dt of
 eq. (16), FP64 totals and source budgets, and the per-solve reduction that
 accepts the step and advances t.
 
+Timing: at least 0.3 s of warm-up steps (and at least --warmup steps), then
+five windows of --steps steps, each between HIP events on the solver's stream;
+``value`` and ``ms_per_step`` come from the median window.  One more window of
+max(--steps, 100) steps launches every step kernel with its own start and end
+events; their mean is the kernel duration of ``roofline``.
+
 Prints one JSON line:
-  value       cell-updates/s over the timed steps (state resident in HBM)
+  value       cell-updates/s of the median window (state resident in HBM)
   roofline    the step kernel's algorithmic bytes per launch (40 B per cell:
-              read 5 FP32 planes, write 5) over its mean launch time from HIP
-              events on its stream, against the 8 TB/s HBM peak; traffic from
-              the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary when it was
-              taken on the current kernel source, else null; "alu": vector
-              lane-operations per second (committed SQ_INSTS_VALU count x 64
-              over the same launch time) against the non-packed FP32 issue
-              peak, the limit this kernel actually runs into
-  fp64        the same workload through the FP64 path (comparison)
-  mixed       the same workload with FP32 arithmetic on an FP64 deviation state
+              read 5 FP32 planes, write 5) over its mean launch time, against
+              the 8 TB/s HBM peak; traffic from the committed rocprofv3
+              FETCH_SIZE/WRITE_SIZE summary when it was taken on the current
+              kernel source, else null; "alu": vector lane-operations per second
+              (committed SQ_INSTS_VALU count x 64 over the same launch time)
+              against the non-packed FP32 issue peak, the limit this kernel
+              actually runs into
+  config3_5000_steps  the workload's whole run (5000 steps) in FP32, FP64 and
+              mixed (FP32 arithmetic on an FP64 deviation state): wall time,
+              cell-updates/s, the step kernels' durations (one extra window),
+              and the FP32 and mixed errors against FP64 at the same end time
+  batch       512 uneven 1D instances: FP32, mixed and FP64 batches against one
+              solve at a time in FP64, equal accuracy checked on every instance
+  served      the served stream (continuous batching): scaled sizes to the end
+              (p50/p99 latency, solves/s) and the full sizes for a bounded
+              wall time (completed, backlog, offered load)
   bounded_ends  the FP32 step on the same grid with wall and outflow ends
   periodic_1d_2e20  the 1D 2^20-cell multi-mode run (20000 steps) in FP32,
               FP64 and mixed, with the FP32 / mixed error against FP64
-  fp32_vs_fp64, mixed_vs_fp64  relative L1 differences after the same steps
+  acoustic_1d_1024  the 1024-cell FP64 acoustic run (2000 steps) on the GPU
+  forced_source_1d, sector_2d, blast_waves_1d  section 3's runs (1D also at
+              102400 cells) and section 2.4's blast waves at 128000 cells,
+              in FP32 and FP64 with the FP32 error against FP64
   cpu_baseline  the serial FP64 oracle on whole steps of the same grid (about
               10 s of one host core), the host CPU model, and batch_fleet: the
               512-instance 1D batch workload's sample on the oracle in one
               process per host core (aggregate rate, solves/s extrapolated),
               and per_config_1d: the two 1D workloads on one core
-  acoustic_1d_1024  the 1024-cell FP64 acoustic run (2000 steps) on the GPU
-  forced_source_1d, sector_2d, blast_waves_1d  section 3's runs (1D also at
-              102400 cells) and section 2.4's blast waves at 128000 cells,
-              in FP32 and FP64 with the FP32 error against FP64
-  timing      one step in eight carries the HIP events of its kernels
 Input: seeded synthetic isotropic k^-2 density field (|k| <= 64, rms 1e-3),
 isentropic pressure, fluid at rest; gas of eqs. (1)-(7) with Q_T = 2.
 """
@@ -81,32 +92,95 @@ def traffic_record():
     return counter_record(TRAFFIC_FILE)
 
 
-# one step in TIMING_EVERY carries the start/end events of its kernels (their
-# mean is the kernel duration); the others launch without events, so the timed
-# launches' own cost stays out of the total
-TIMING_EVERY = 8
+WARMUP_SECONDS = 0.3
+REPS = 5
 
 
-def timed_run(ng, torch, gas, W, n, steps, warmup, precision, bc=(0, 0, 0, 0)):
+# steps per captured HIP graph (ng_set_graph_steps); --no-graphs makes it
+# larger than any run, so that every step is a direct launch (counter passes
+# of rocprofv3 run that way)
+GRAPH_STEPS = None
+
+
+def setup_solver(s):
     from paper_1805_03442_amd import autotune
-    s = ng.Solver(gas, n, n, W=W, precision=precision, bc=bc)
     autotune.apply(s)
-    s.step(warmup)
+    if GRAPH_STEPS is not None:
+        s.set_graph_steps(GRAPH_STEPS)
+
+
+def timed_run(ng, torch, gas, W, n, steps, warmup, precision, bc=(0, 0, 0, 0), reps=REPS):
+    """Warm-up (>= WARMUP_SECONDS and >= warmup steps), ``reps`` windows of
+    ``steps`` steps between HIP events on the solver's stream (median), then
+    one window of max(steps, 100) steps whose every step kernel carries its
+    own start/end events (mean kernel duration)."""
+    s = ng.Solver(gas, n, n, W=W, precision=precision, bc=bc)
+    setup_solver(s)
+    st = torch.cuda.current_stream()
+    s.step(max(warmup, 1))
     torch.cuda.synchronize()
-    s.enable_timing(steps, TIMING_EVERY)
+    t0 = time.perf_counter()
+    warm = max(warmup, 1)
+    while time.perf_counter() - t0 < WARMUP_SECONDS:
+        s.step(20)
+        torch.cuda.synchronize()
+        warm += 20
+    wins = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        s.step(steps)
+        e1.record(st)
+        torch.cuda.synchronize()
+        wins.append(e0.elapsed_time(e1))
+    kw = max(steps, 100)
+    s.enable_timing(kw, 1)
+    s.step(kw)
+    torch.cuda.synchronize()
+    step_ms, fin_ms, launches = s.kernel_time()
+    s.enable_timing(0, 1)
+    d = s.diagnostics()
+    s.close()
+    assert d["status"] == 0, d
+    med = sorted(wins)[len(wins) // 2]
+    return dict(total_ms=med, windows_ms=wins, warmup_steps=warm, step_ms=step_ms,
+                fin_ms=fin_ms, launches=launches, diag=d)
+
+
+def run_whole(ng, torch, gas, W, n, precision, steps=None, t_end=None):
+    """A whole run (steps, or to t_end) through ng_step / ng_run_to_time
+    between HIP events, then one window of 50 steps with every step kernel
+    timed; returns the state at the end of the run and the rates."""
+    s = ng.Solver(gas, n, n, W=W, precision=precision)
+    setup_solver(s)
+    s.step(1)
+    torch.cuda.synchronize()
+    d0 = s.diagnostics()
     st = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     e0.record(st)
-    s.step(steps)
+    if t_end is None:
+        s.step(steps - 1)
+    else:
+        s.run_to_time(t_end)
     e1.record(st)
     torch.cuda.synchronize()
-    total_ms = e0.elapsed_time(e1)
-    step_ms, fin_ms, launches = s.kernel_time()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
     d = s.diagnostics()
+    assert d["status"] == 0, d
+    U = s.conserved()
+    taken = d["steps"] - d0["steps"]
+    s.enable_timing(50, 1)
+    s.step(50)
+    torch.cuda.synchronize()
+    kms, _, _ = s.kernel_time()
     s.close()
-    return dict(total_ms=total_ms, step_ms=step_ms, fin_ms=fin_ms, launches=launches, diag=d)
+    return dict(U=U, t=d["t"], steps=d["steps"], run_ms=ms, wall_s=wall,
+                cell_updates_per_s=float(n) * n * taken / (ms * 1e-3), step_kernel_ms=kms)
 
 
 def host_cpu():
@@ -209,23 +283,41 @@ def cpu_fleet(count=512, steps_each=10000, every=8, steps=400, max_workers=16):
                        f"wall; solves/s extrapolated to {count} instances x {steps_each} steps")
 
 
+def error_vs(U, ref, U0, names):
+    """Relative L1 of the full field and of the change from U0, per component."""
+    import numpy as np
+    full, pert = {}, {}
+    for c, nm in names:
+        full[nm] = float(np.abs(U[c] - ref[c]).sum() / np.abs(ref[c]).sum())
+        den = float(np.abs(ref[c] - U0[c]).sum())
+        pert[nm] = float(np.abs(U[c] - ref[c]).sum() / den) if den > 0 else None
+    return {"rel_l1": full, "rel_l1_of_perturbation": pert}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=4096)
-    ap.add_argument("--fp64-steps", type=int, default=100)
+    ap.add_argument("--config3-steps", type=int, default=5000,
+                    help="length of the whole FP32/FP64/mixed run of the 2D workload (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--accuracy-steps", type=int, default=100)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-full-wall", type=float, default=12.0)
     ap.add_argument("--bounded-steps", type=int, default=200)
     ap.add_argument("--steps-1d", type=int, default=20000)
     ap.add_argument("--no-source-runs", action="store_true",
                     help="skip the forced-source runs of section 3 (1D and the 2D sector)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain device copy of known size (for counter scaling)")
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="launch every step directly (no captured graphs; for counter passes)")
     args = ap.parse_args()
+    if args.no_graphs:
+        global GRAPH_STEPS
+        GRAPH_STEPS = 1 << 30
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -252,14 +344,15 @@ def main():
     gas = dict(wl.BASE_GAS, Q_T=2.0)
     W = wl.random_field_2d(gas, n, wl.rng(3))
 
-    log(f"[bench] FP32: warmup {args.warmup}, timing {args.steps} steps")
+    log(f"[bench] FP32: warmup >= {args.warmup} steps and {WARMUP_SECONDS} s, "
+        f"{REPS} windows of {args.steps} steps")
     r32 = timed_run(ng, torch, gas, W, n, args.steps, args.warmup, ng.NG_FP32)
     cells = float(n) * n
     ms_per_step = r32["total_ms"] / args.steps
     value = cells * args.steps / (r32["total_ms"] * 1e-3)
     achieved = BYTES_PER_CELL_FP32 * cells / (r32["step_ms"] * 1e-3) / 1e9
-    log(f"[bench] FP32 {ms_per_step:.4f} ms/step, step kernel {r32['step_ms']:.4f} ms, "
-        f"finalize {r32['fin_ms']:.4f} ms, {value:.3e} cell-updates/s")
+    log(f"[bench] FP32 {ms_per_step:.4f} ms/step (windows {r32['windows_ms']}), step kernel "
+        f"{r32['step_ms']:.4f} ms, finalize {r32['fin_ms']:.4f} ms, {value:.3e} cell-updates/s")
 
     tr = traffic_record()
     traffic = None
@@ -267,7 +360,8 @@ def main():
         traffic = tr["bytes_per_launch"]
 
     out = {
-        "metric": "cell-updates/s (FP32 fused MUSCL step, 2D 4096^2) + %HBM roofline",
+        "metric": "cell-updates/s (FP32 fused MUSCL step, 2D 4096^2) + %HBM roofline; "
+                  "p50/p99 solve latency",
         "value": value,
         "unit": "cell-updates/s",
         "n_gpus": 1,
@@ -282,10 +376,14 @@ def main():
         "config": {"workload": f"2d_periodic_{n}x{n}_random_field_fp32", "nx": n, "ny": n,
                    "precision": "fp32 deviations, fp64 totals", "riemann": "hllc",
                    "cfl": 0.4, "Q_T": 2.0},
+        "timing": {"windows_ms": r32["windows_ms"], "statistic": "median of windows",
+                   "warmup_steps_run": r32["warmup_steps"],
+                   "warmup_seconds_min": WARMUP_SECONDS},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "step2d_kernel<Dev32<5>>",
                      "kernel_ms": r32["step_ms"], "launches_timed": r32["launches"],
+                     "finalize_ms": r32["fin_ms"],
                      "algorithmic_bytes_per_launch": BYTES_PER_CELL_FP32 * cells},
     }
     # the step is limited by vector ALU issue: lane-operations per second from
@@ -296,7 +394,8 @@ def main():
         ach = insts * 64 / (r32["step_ms"] * 1e-3) / 1e12
         out["roofline"]["alu"] = {"achieved": ach, "peak": VALU_PEAK_TLANEOPS,
                                   "unit": "T lane-op/s", "frac": ach / VALU_PEAK_TLANEOPS,
-                                  "valu_insts_per_launch": insts}
+                                  "valu_insts_per_launch": insts,
+                                  "lane_ops_per_cell_update": insts * 64 / cells}
         m = vr["mean_per_dispatch"]
         if "SQ_ACTIVE_INST_VALU" in m and "GRBM_GUI_ACTIVE" in m:
             # share of the kernel's cycles in which a SIMD issues VALU work:
@@ -305,27 +404,67 @@ def main():
             out["roofline"]["alu"]["valu_busy"] = (m["SQ_ACTIVE_INST_VALU"] * 4 / 1024
                                                    / (m["GRBM_GUI_ACTIVE"] / 8))
 
-    if not args.no_fp64:
-        log(f"[bench] FP64: timing {args.fp64_steps} steps")
-        r64 = timed_run(ng, torch, gas, W, n, args.fp64_steps, 5, ng.NG_FP64)
-        v64 = cells * args.fp64_steps / (r64["total_ms"] * 1e-3)
-        out["fp64"] = {"value": v64, "unit": "cell-updates/s",
-                       "ms_per_step": r64["total_ms"] / args.fp64_steps,
-                       "step_kernel_ms": r64["step_ms"],
-                       "hbm_frac": BYTES_PER_CELL_FP64 * cells / (r64["step_ms"] * 1e-3) / 1e9
-                       / HBM_PEAK_GBS,
-                       "steps": args.fp64_steps}
-        log(f"[bench] FP64 {v64:.3e} cell-updates/s")
+    if args.config3_steps > 0:
+        # the workload's whole run in each precision: FP32 takes the steps, FP64
+        # and mixed run to the FP32 end time (the same time within their own
+        # dt sequence), so the errors compare states at equal time
+        k = args.config3_steps
+        log(f"[bench] 2D {n}^2: the whole {k}-step run in FP32, FP64, mixed")
+        res = {}
+        runs = {}
+        runs["fp32"] = run_whole(ng, torch, gas, W, n, ng.NG_FP32, steps=k)
+        for name, prec in (("fp64", ng.NG_FP64), ("mixed", ng.NG_MIXED)):
+            runs[name] = run_whole(ng, torch, gas, W, n, prec, t_end=runs["fp32"]["t"])
+        s0 = ng.Solver(gas, n, n, W=W, precision=ng.NG_FP64)
+        U0 = s0.conserved()
+        s0.close()
+        names = list(enumerate(["rho", "rho_u", "rho_v", "E", "E_nu"]))
+        for name in ("fp32", "fp64", "mixed"):
+            r = runs[name]
+            bpc = BYTES_PER_CELL_FP32 if name == "fp32" else BYTES_PER_CELL_FP64
+            res[name] = {"steps": r["steps"], "t_end": r["t"], "run_ms": r["run_ms"],
+                         "cell_updates_per_s": r["cell_updates_per_s"],
+                         "step_kernel_ms": r["step_kernel_ms"],
+                         "hbm_frac": bpc * cells / (r["step_kernel_ms"] * 1e-3) / 1e9
+                         / HBM_PEAK_GBS}
+            if name != "fp64":
+                res[name]["vs_fp64"] = error_vs(r["U"], runs["fp64"]["U"], U0, names)
+            log(f"[bench] config 3 {name}: {res[name]}")
+        # the shock indicator of the parity definitions: smallest ratio of
+        # neighbouring pressures along x and y
+        Wf = runs["fp64"]["U"]
+        rho = Wf[0]
+        p = 0.4 * (Wf[3] - 0.5 * (Wf[1] ** 2 + Wf[2] ** 2) / rho - Wf[4])
+        rx = np.minimum(p / np.roll(p, -1, 1), np.roll(p, -1, 1) / p).min()
+        ry = np.minimum(p / np.roll(p, -1, 0), np.roll(p, -1, 0) / p).min()
+        res["min_neighbour_pressure_ratio"] = float(min(rx, ry))
+        out["config3_5000_steps"] = dict(res, workload=f"2d_random_{n}x{n}", steps=k)
+        del runs, Wf, rho, p
 
-    if not args.no_fp64:
-        # FP32 arithmetic on an FP64 deviation state: 80 B per cell of state traffic
-        k = args.fp64_steps
-        log(f"[bench] mixed (FP32 arithmetic, FP64 state): timing {k} steps")
-        rm = timed_run(ng, torch, gas, W, n, k, 5, ng.NG_MIXED)
-        out["mixed"] = {"value": cells * k / (rm["total_ms"] * 1e-3), "unit": "cell-updates/s",
-                        "ms_per_step": rm["total_ms"] / k, "step_kernel_ms": rm["step_ms"],
-                        "hbm_frac": BYTES_PER_CELL_FP64 * cells / (rm["step_ms"] * 1e-3) / 1e9
-                        / HBM_PEAK_GBS, "steps": k}
+    if not args.no_batch:
+        from paper_1805_03442_amd import bench_batch
+        log("[bench] batch of 512 uneven 1D instances")
+        out["batch"] = bench_batch.measure(torch)
+
+    if not args.no_serve:
+        from paper_1805_03442_amd import bench_serve
+        budget = 200 << 30
+        log("[bench] served stream, scaled sizes, to the end")
+        recs = wl.serve_trace(count=400, log2_1d=(10.0, 14.0), side_2d=(64.0, 256.0),
+                              t_end=(0.005, 0.02))
+        sc = bench_serve.run(recs, budget, 1024, 32, 120.0)
+        log(f"[bench] served scaled: {sc}")
+        log(f"[bench] served stream, full sizes, {args.serve_full_wall} s")
+        recs = wl.serve_trace(count=2000)
+        fu = bench_serve.run(recs, budget, 1024, 32, args.serve_full_wall)
+        log(f"[bench] served full: {fu}")
+        out["served"] = {
+            "budget_bytes": budget, "capacity": 1024, "tick_steps": 32,
+            "scaled": dict(sc, trace="400 requests, Poisson 200/s, 1D n 2^10..2^14, "
+                                     "2D 64^2..256^2, t_end 0.005..0.02, run to the end"),
+            "full": dict(fu, trace="2000 requests, Poisson 200/s, 1D n 2^12..2^20, "
+                                   "2D 256^2..2048^2, t_end 0.1..2, "
+                                   f"{args.serve_full_wall} s of wall time")}
 
     if args.steps_1d > 0:
         # 1D periodic 2^20 cells, 64 random modes, Q_T = 2: the whole run of
@@ -336,9 +475,8 @@ def main():
         n1 = w1["nx"]
         res1, fin1 = {}, {}
         for name, prec in (("fp32", ng.NG_FP32), ("fp64", ng.NG_FP64), ("mixed", ng.NG_MIXED)):
-            from paper_1805_03442_amd import autotune
             s = ng.Solver(w1["gas"], n1, 1, W=w1["W"], precision=prec)
-            autotune.apply(s)
+            setup_solver(s)
             s.step(20)
             torch.cuda.synchronize()
             st = torch.cuda.current_stream()
@@ -391,7 +529,8 @@ def main():
         k = args.bounded_steps
         log(f"[bench] FP32 with wall/outflow ends: timing {k} steps")
         rb = timed_run(ng, torch, gas, W, n, k, 5, ng.NG_FP32,
-                       bc=(ng.NG_BC_WALL, ng.NG_BC_WALL, ng.NG_BC_OUTFLOW, ng.NG_BC_OUTFLOW))
+                       bc=(ng.NG_BC_WALL, ng.NG_BC_WALL, ng.NG_BC_OUTFLOW, ng.NG_BC_OUTFLOW),
+                       reps=3)
         out["bounded_ends"] = {"bc": "x walls, y outflow", "steps": k,
                                "value": cells * k / (rb["total_ms"] * 1e-3),
                                "unit": "cell-updates/s", "step_kernel_ms": rb["step_ms"],
@@ -482,8 +621,7 @@ def main():
         for name, prec in (("fp64", ng.NG_FP64), ("fp32", ng.NG_FP32)):
             s = ng.Solver(ws["gas"], ws["nx"], ws["ny"], W=ws["W"], h=ws["h"], precision=prec,
                           bc=ws["bc"], source=ws["source"], wedge=ws["wedge"])
-            from paper_1805_03442_amd import autotune
-            autotune.apply(s)
+            setup_solver(s)
             if prec == ng.NG_FP64:
                 Ub = s.conserved()
             torch.cuda.synchronize()
@@ -506,33 +644,6 @@ def main():
                                 max_drho_in_wedge=float(drho[act].max()),
                                 max_drho_outside=float(drho[~act].max()))
         log(f"[bench] sector: {out['sector_2d']}")
-
-    if not args.no_fp64:
-        # error of the FP32 result against the FP64 path after the same steps
-        m = args.accuracy_steps
-        log(f"[bench] FP32 vs FP64 after {m} steps")
-        outs = []
-        for prec in (ng.NG_FP32, ng.NG_FP64, ng.NG_MIXED):
-            s = ng.Solver(gas, n, n, W=W, precision=prec)
-            s.step(m)
-            outs.append(s.conserved())
-            s.close()
-        U32, U64, Umx = outs
-        U0 = ng.Solver(gas, n, n, W=W, precision=ng.NG_FP64)
-        Ub = U0.conserved()
-        U0.close()
-        names = ["rho", "rho_u", "rho_v", "E", "E_nu"]
-        full = {nm: float(np.abs(U32[c] - U64[c]).sum() / np.abs(U64[c]).sum())
-                for c, nm in enumerate(names)}
-        pert = {nm: float(np.abs(U32[c] - U64[c]).sum() / np.abs(U64[c] - Ub[c]).sum())
-                for c, nm in enumerate(names)}
-        out["fp32_vs_fp64"] = {"steps": m, "rel_l1": full, "rel_l1_of_perturbation": pert}
-        out["mixed_vs_fp64"] = {
-            "steps": m,
-            "rel_l1_of_perturbation": {
-                nm: float(np.abs(Umx[c] - U64[c]).sum() / np.abs(U64[c] - Ub[c]).sum())
-                for c, nm in enumerate(names)}}
-        log(f"[bench] FP32 vs FP64 rel L1 {full}")
 
     if args.calibrate_copy:
         nbytes = 1 << 30
