@@ -246,6 +246,37 @@ int ng_kernel_time(ng_solver* s, double* step_ms, double* finalize_ms, int64_t* 
 
 const char* ng_last_error(const ng_solver* s);
 
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): one step of eq. (15)
+ * on an FP64 state in caller device memory, calling no hipMalloc, hipFree or
+ * other allocating routine.  Its scratch -- the solve's descriptor and control
+ * block, the workgroup table and the per-workgroup reduction records -- lives
+ * in a static device array of 2 MiB that each GPU the library runs on holds
+ * until the process ends; a grid whose launch needs more (about 20000
+ * workgroups, e.g. beyond 8192^2 cells in 2D) is refused with NG_ENOMEM.
+ *   gas, grid, num: as for ng_init_state; num->precision must be NG_FP64;
+ *   U_in:  device, FP64 conserved planes (rho, rho u, [rho v], E, E_nu) in the
+ *          layout of the host arrays, the state at time t (read only);
+ *   U_out: device, same size, distinct from U_in: receives the state after
+ *          the step (undefined if the call returns NG_EPHYS);
+ *   t, t_end: time of U_in and end time (the step is shortened to land on
+ *          t_end > t; t_end <= t: no end time); dt is that of eq. (16) on U_in;
+ *   hip_stream: the stream the kernels are enqueued on;
+ *   out:   NULL (the call only enqueues: asynchronous, usable under stream
+ *          capture) or a host ng_diag that receives t, dt_last, the totals of
+ *          U_out, ... (synchronises the stream; returns NG_EPHYS when the step
+ *          was rejected).
+ * The state is bitwise that of ng_init_conserved(U_in) + ng_step(1).  Every
+ * call on a GPU shares that GPU's scratch (each call writes all of it that it
+ * reads): calls that overlap on one GPU race, so enqueue them on one stream.
+ * Errors: NG_EINVAL (invalid arguments, as ng_init_state, or another
+ * precision), NG_ENOMEM (grid beyond the scratch), NG_EDEVICE; the text is
+ * returned by ng_static_last_error (per host thread). */
+int ng_step_static(const ng_gas* gas, const ng_grid* grid, const ng_numerics* num,
+                   const void* U_in, void* U_out, double t, double t_end, void* hip_stream,
+                   ng_diag* out);
+const char* ng_static_last_error(void);
+
 /* Free the host-side object.  Never frees dev_buf or the stream. */
 void ng_destroy(ng_solver* s);
 

@@ -1389,6 +1389,123 @@ int ng_kernel_time(ng_solver* s, double* step_ms, double* finalize_ms, int64_t* 
     return NG_OK;
 }
 
+// --------------------------------------------- one step without allocation
+
+// The entry point for callers that cannot allocate: one FP64 step from U_in to
+// U_out with the descriptor, control block, workgroup table and reduction
+// records in the library's static scratch (ng_kernels.hip).  The launch shape
+// is the automatic one of a lone solve, so the state equals ng_step's.
+static thread_local std::string g_static_err;
+
+int ng_step_static(const ng_gas* gas, const ng_grid* grid, const ng_numerics* num,
+                   const void* U_in, void* U_out, double t, double t_end, void* hip_stream,
+                   ng_diag* out)
+{
+    std::string err;
+    int rc = validate(gas, grid, num, err);
+    if (rc) {
+        g_static_err = err;
+        return rc;
+    }
+    if (num->precision != NG_FP64) {
+        g_static_err = "ng_step_static: the state must be FP64 (NG_FP64)";
+        return NG_EINVAL;
+    }
+    if (!U_in || !U_out || U_in == (const void*)U_out) {
+        g_static_err = "ng_step_static: U_in and U_out must be distinct device buffers";
+        return NG_EINVAL;
+    }
+    InstDesc d;
+    fill_desc(d, gas, grid, num, NG_FP64);
+    const int dim = grid->ndim;
+    d.rows_per_item = auto_rows(dim, {{d.nx, d.ny}});
+    d.nstrips = (int32_t)cdiv(d.nx, kInterior);
+    d.nchunks = (int32_t)(dim == 2 ? cdiv(d.ny, d.rows_per_item) : cdiv(d.nstrips, d.rows_per_item));
+    d.nitems = dim == 2 ? (int64_t)d.nstrips * d.nchunks : (int64_t)d.nchunks;
+    d.waves_per_block = dim == 2 ? kDefaultWaves2D : (d.nitems < kAutoItems1DWaves ? 2 : 4);
+    d.nblocks = cdiv(d.nitems, d.waves_per_block);
+    d.fused = d.nblocks <= kFusedMaxBlocks ? 1 : 0;
+    // scratch layout: descriptor, control block, finalize index list,
+    // workgroup table, per-workgroup records
+    const size_t o_ctrl = align_up(sizeof(InstDesc));
+    const size_t o_insts = o_ctrl + align_up(sizeof(InstCtrl));
+    const size_t o_blocks = o_insts + kAlign;
+    const size_t o_parts = o_blocks + align_up(sizeof(BlockRef) * (size_t)d.nblocks);
+    const size_t need = o_parts + sizeof(Partial) * (size_t)d.nblocks;
+    if (need > kStaticScratchBytes) {
+        g_static_err = "ng_step_static: the grid needs " + std::to_string(need) +
+                       " bytes of scratch (" + std::to_string(d.nblocks) +
+                       " workgroups), the static scratch holds " +
+                       std::to_string(kStaticScratchBytes);
+        return NG_ENOMEM;
+    }
+    void* base = nullptr;
+    hipError_t e = static_scratch(&base);
+    if (e != hipSuccess) {
+        g_static_err = std::string("hipGetSymbolAddress: ") + hipGetErrorString(e);
+        return NG_EDEVICE;
+    }
+    char* sc = (char*)base;
+    InstDesc* descs = (InstDesc*)sc;
+    InstCtrl* ctrls = (InstCtrl*)(sc + o_ctrl);
+    int32_t* insts = (int32_t*)(sc + o_insts);
+    BlockRef* blocks = (BlockRef*)(sc + o_blocks);
+    d.buf[0] = (uint64_t)(uintptr_t)U_in;
+    d.buf[1] = (uint64_t)(uintptr_t)U_out;
+    d.partials = (uint64_t)(uintptr_t)(sc + o_parts);
+    InstCtrl c;
+    memset(&c, 0, sizeof(c));
+    c.t = t;
+    c.t_end = t_end > t ? t_end : INFINITY;
+    c.max_steps = 1;
+    const int variant = (d.riemann == NG_HLLC && !d.any_bc) ? 1 : 0;
+    hipStream_t st = (hipStream_t)hip_stream;
+    e = launch_static_setup(d, c, descs, ctrls, insts, blocks, d.nblocks, st);
+    if (e == hipSuccess)
+        e = launch_prime(dim, kind_of(NG_FP64), descs, ctrls, nullptr, 0, d.nblocks,
+                         d.waves_per_block, st);
+    if (e == hipSuccess) e = launch_finalize(descs, ctrls, insts, 1, 1, st);
+    if (e == hipSuccess)
+        e = launch_step(dim, kind_of(NG_FP64), variant, descs, ctrls, blocks, d.nblocks,
+                        d.waves_per_block, 1, d.fused, st);
+    if (e == hipSuccess && !d.fused) e = launch_finalize(descs, ctrls, insts, 1, 0, st);
+    if (e != hipSuccess) {
+        g_static_err = std::string("kernel launch: ") + hipGetErrorString(e);
+        return NG_EDEVICE;
+    }
+    if (!out) return NG_OK;
+    InstCtrl h;
+    e = hipMemcpyAsync(&h, ctrls, sizeof(InstCtrl), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        g_static_err = std::string("read-back: ") + hipGetErrorString(e);
+        return NG_EDEVICE;
+    }
+    const double hd = dim == 2 ? d.h * d.h : d.h;
+    memset(out, 0, sizeof(*out));
+    out->t = h.t;
+    out->dt_last = h.dt_last;
+    double dt = h.dt_cfl;
+    if (h.t + dt > h.t_end) dt = h.t_end - h.t;
+    out->dt_next = dt;
+    out->steps = h.steps;
+    for (int q = 0; q < 5; q++) out->total[q] = h.total[q] * hd;
+    out->src_budget[0] = h.budget[0] * hd;
+    out->src_budget[1] = h.budget[1] * hd;
+    out->rho_min = h.rho_min;
+    out->p_min = h.p_min;
+    out->smax = h.smax;
+    out->status = h.status;
+    out->flags = h.flags;
+    if (h.status != 0) {
+        g_static_err = "ng_step_static: the step produced rho <= 0, p <= 0 or a non-finite value";
+        return NG_EPHYS;
+    }
+    return NG_OK;
+}
+
+const char* ng_static_last_error(void) { return g_static_err.c_str(); }
+
 const char* ng_last_error(const ng_solver* s)
 {
     if (!s) return "null solver";

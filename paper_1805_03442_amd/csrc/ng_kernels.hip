@@ -26,6 +26,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "ng_cell.hpp"
 #include "ng_internal.hpp"
 #include "ng_launch.hpp"
@@ -1244,6 +1246,61 @@ __global__ void __launch_bounds__(512) run_small_kernel(const InstDesc* __restri
         }
         __syncthreads();
     }
+}
+
+// ======================================================= static scratch
+
+// Device memory of the entry point for callers that cannot allocate
+// (ng_step_static): the solve's descriptor and control block, the index list
+// of the finalize kernel, the workgroup table and the per-workgroup reduction
+// records, in one file-scope array of kStaticScratchBytes that each GPU holds
+// until the process ends.  Host code never uses the array's name as an
+// address: static_scratch() takes each device's own address of it once.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+hipError_t static_scratch(void** ptr)
+{
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
+}
+
+// Fill the static scratch for one solve: descriptor, control block and index
+// list from the arguments (no host staging), and the workgroup table
+// (workgroup j of the launch is workgroup j of solve 0).
+__global__ void static_setup_kernel(InstDesc d, InstCtrl c, InstDesc* __restrict__ descs,
+                                    InstCtrl* __restrict__ ctrls, int32_t* __restrict__ insts,
+                                    BlockRef* __restrict__ blocks, int64_t nblocks)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        descs[0] = d;
+        ctrls[0] = c;
+        insts[0] = 0;
+    }
+    for (; i < nblocks; i += (int64_t)gridDim.x * blockDim.x) blocks[i] = BlockRef{0, (int32_t)i};
+}
+
+hipError_t launch_static_setup(const InstDesc& d, const InstCtrl& c, InstDesc* descs,
+                               InstCtrl* ctrls, int32_t* insts, BlockRef* blocks,
+                               int64_t nblocks, hipStream_t s)
+{
+    const int64_t g = nblocks < 256 * 64 ? (nblocks + 255) / 256 : 64;
+    hipLaunchKernelGGL(static_setup_kernel, dim3((unsigned)(g > 0 ? g : 1)), dim3(256), 0, s, d,
+                       c, descs, ctrls, insts, blocks, nblocks);
+    return hipGetLastError();
 }
 
 // ================================================================ launchers

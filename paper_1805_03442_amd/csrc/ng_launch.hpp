@@ -30,4 +30,15 @@ hipError_t launch_small(int dim, int prec, const InstDesc* descs, InstCtrl* ctrl
 hipError_t launch_set_limits(InstCtrl* ctrls, const int32_t* insts, int n, double t_end,
                              int64_t max_steps_from_now, hipStream_t s);
 
+// Static scratch of the entry point that allocates nothing: its device
+// address on the current device (looked up once per device), and the kernel
+// that writes one solve's descriptor, control block, finalize index list and
+// workgroup table into it.
+constexpr size_t kStaticScratchBytes = size_t(2) << 20;
+constexpr int kMaxDevices = 64;
+hipError_t static_scratch(void** ptr);
+hipError_t launch_static_setup(const InstDesc& d, const InstCtrl& c, InstDesc* descs,
+                               InstCtrl* ctrls, int32_t* insts, BlockRef* blocks,
+                               int64_t nblocks, hipStream_t s);
+
 }  // namespace ng

@@ -35,7 +35,7 @@ EXPORTED = (
     "ng_batch_active", "ng_batch_diagnostics", "ng_batch_get_state", "ng_batch_get_conserved",
     "ng_batch_remove", "ng_batch_set_launch", "ng_batch_set_small_limit",
     "ng_batch_set_fused_accept", "ng_batch_last_error",
-    "ng_batch_destroy",
+    "ng_batch_destroy", "ng_step_static", "ng_static_last_error",
 )
 
 
@@ -118,6 +118,9 @@ def lib():
             "ng_batch_poll": ([vp, C.POINTER(i32), i32, C.POINTER(i32)], C.c_int),
             "ng_batch_active": ([vp, C.POINTER(i32)], C.c_int),
             "ng_batch_diagnostics": ([vp, i32, C.POINTER(NgDiag)], C.c_int),
+            "ng_step_static": ([C.POINTER(NgGas), C.POINTER(NgGrid), C.POINTER(NgNumerics), vp,
+                                vp, C.c_double, C.c_double, vp, C.POINTER(NgDiag)], C.c_int),
+            "ng_static_last_error": ([], C.c_char_p),
             "ng_batch_get_state": ([vp, i32, dp], C.c_int),
             "ng_batch_get_conserved": ([vp, i32, dp], C.c_int),
             "ng_batch_remove": ([vp, i32], C.c_int),
@@ -290,6 +293,25 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def step_static(gas: dict, nx: int, ny: int, U_in, U_out, t: float = 0.0, t_end: float = 0.0,
+                h=None, cfl=0.4, riemann=NG_HLLC, stiff_z=0.5, bc=(NG_BC_PERIODIC,) * 4,
+                source=(0.0, 0.0), wedge=(0.0, 0.0, 0.0), stream=None, diag: bool = True):
+    """One FP64 step (``ng_step_static``) from the device buffer U_in to U_out
+    (torch CUDA tensors or device addresses: FP64 conserved planes in the ABI
+    layout), with the library's static scratch; returns the diagnostics dict
+    (diag=True, synchronising) or None (asynchronous)."""
+    def addr(x):
+        return int(x.data_ptr()) if hasattr(x, "data_ptr") else int(x)
+    d = NgDiag()
+    rc = lib().ng_step_static(C.byref(make_gas(gas)), C.byref(make_grid(nx, ny, h, bc, source, wedge)),
+                              C.byref(make_numerics(cfl, riemann, NG_FP64, stiff_z)),
+                              C.c_void_p(addr(U_in)), C.c_void_p(addr(U_out)), float(t),
+                              float(t_end), C.c_void_p(stream_handle(stream)),
+                              C.byref(d) if diag else None)
+    check(rc, "ng_step_static", lib().ng_static_last_error().decode())
+    return d.as_dict() if diag else None
 
 
 class Batch:

@@ -149,3 +149,28 @@ def test_autotune_uses_exact_buckets_only(tmp_path):
     assert autotune.lookup(2048, 2048, _ng.NG_FP32, str(p)) is None
     assert autotune.lookup(4096, 4096, _ng.NG_FP64, str(p)) is None
     assert autotune.lookup(4096, 1, _ng.NG_FP32, str(p)) is None
+
+
+def test_static_step_refuses_before_device_use(ng):
+    """The entry point that allocates nothing refuses another precision, equal
+    input and output buffers, and a grid beyond its static scratch, before any
+    device call (the placeholder addresses are never touched)."""
+    L = ng.lib()
+    gas = ng.make_gas(dict(gamma=1.4, R=1.0, Cv=1.0, rho0=1.0, T0=1.0, tau0=0.05,
+                           tau_rho=-1.0, tau_T=-1.0, Q0=0.1, Q_rho=0.5, Q_T=1.0,
+                           I0=0.1, I_rho=1.0, I_T=2.0))
+    a, b = C.c_void_p(0x1000), C.c_void_p(0x2000)
+    cases = [
+        (ng.make_grid(64, 64), ng.make_numerics(precision=ng.NG_FP32), a, b, ng.NG_EINVAL,
+         b"FP64"),
+        (ng.make_grid(64, 64), ng.make_numerics(precision=ng.NG_FP64), a, a, ng.NG_EINVAL,
+         b"distinct"),
+        (ng.make_grid(16384, 16384), ng.make_numerics(precision=ng.NG_FP64), a, b,
+         ng.NG_ENOMEM, b"static scratch"),
+        (ng.make_grid(2, 1), ng.make_numerics(precision=ng.NG_FP64), a, b, ng.NG_EINVAL, b""),
+    ]
+    for grid, num, u_in, u_out, code, text in cases:
+        rc = L.ng_step_static(C.byref(gas), C.byref(grid), C.byref(num), u_in, u_out, 0.0, 0.0,
+                              None, None)
+        assert rc == code, (rc, code)
+        assert text in L.ng_static_last_error()
