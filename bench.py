@@ -34,8 +34,10 @@ Prints one JSON line:
               wall time (completed, backlog, offered load)
   bounded_ends  the FP32 step on the same grid with wall and outflow ends
   periodic_1d_2e20  the 1D 2^20-cell multi-mode run (20000 steps) in FP32,
-              FP64 and mixed, with the FP32 / mixed error against FP64
-  acoustic_1d_1024  the 1024-cell FP64 acoustic run (2000 steps) on the GPU
+              FP64 and mixed on the cooperative path (FP32 also with one
+              launch per step), with the FP32 / mixed error against FP64
+  acoustic_1d_1024  the 1024-cell FP64 acoustic run (2000 steps) on the GPU,
+              cooperative and in the one-workgroup persistent kernel
   forced_source_1d, sector_2d, blast_waves_1d  section 3's runs (1D also at
               102400 cells) and section 2.4's blast waves at 128000 cells,
               in FP32 and FP64 with the FP32 error against FP64
@@ -468,15 +470,20 @@ def main():
 
     if args.steps_1d > 0:
         # 1D periodic 2^20 cells, 64 random modes, Q_T = 2: the whole run of
-        # steps_1d steps in each precision (graph-launched, no per-launch
-        # events), and the FP32 / mixed error against FP64 at the end
+        # steps_1d steps in each precision (the library's path for a lone 1D
+        # solve: one cooperative launch with a grid barrier per step; FP32
+        # also with one graph-launched kernel per step, for comparison), and
+        # the FP32 / mixed error against FP64 at the end
         k = args.steps_1d
         w1 = wl.workload_1d_multimode()
         n1 = w1["nx"]
         res1, fin1 = {}, {}
-        for name, prec in (("fp32", ng.NG_FP32), ("fp64", ng.NG_FP64), ("mixed", ng.NG_MIXED)):
+
+        def run_1d(prec, coop):
             s = ng.Solver(w1["gas"], n1, 1, W=w1["W"], precision=prec)
             setup_solver(s)
+            if not coop:
+                s.set_coop(0)
             s.step(20)
             torch.cuda.synchronize()
             st = torch.cuda.current_stream()
@@ -486,12 +493,18 @@ def main():
             s.step(k)
             e1.record(st)
             torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1)
-            res1[name] = {"value": n1 * k / (ms * 1e-3), "unit": "cell-updates/s",
-                          "us_per_step": 1e3 * ms / k}
-            fin1[name] = s.conserved()
+            U = s.conserved()
             s.close()
+            return e0.elapsed_time(e1), U
+
+        for name, prec in (("fp32", ng.NG_FP32), ("fp64", ng.NG_FP64), ("mixed", ng.NG_MIXED)):
+            ms, fin1[name] = run_1d(prec, True)
+            res1[name] = {"value": n1 * k / (ms * 1e-3), "unit": "cell-updates/s",
+                          "us_per_step": 1e3 * ms / k, "path": "cooperative"}
             log(f"[bench] 1D 2^20 {name}: {res1[name]['value']:.3e} cell-updates/s")
+        ms, U = run_1d(ng.NG_FP32, False)
+        assert np.array_equal(U, fin1["fp32"])
+        res1["fp32"]["us_per_step_one_launch_per_step"] = 1e3 * ms / k
         s0 = ng.Solver(w1["gas"], n1, 1, W=w1["W"], precision=ng.NG_FP64)
         U0 = s0.conserved()
         s0.close()
@@ -503,10 +516,14 @@ def main():
 
     if args.steps_1d > 0:
         # the 1024-cell acoustic mode in FP64, its whole run of 2000 steps (one
-        # persistent workgroup; a first run loads the kernel)
+        # cooperative launch over 5 CUs; a first run loads the kernel), and
+        # the same run in the persistent one-workgroup kernel
         w0 = wl.workload_1d_acoustic()
-        for rep in range(2):
+        for rep in range(3):
             s = ng.Solver(w0["gas"], w0["nx"], 1, W=w0["W"], precision=ng.NG_FP64)
+            if rep == 2:
+                s.set_coop(0)
+                ms_coop = ms
             torch.cuda.synchronize()
             st = torch.cuda.current_stream()
             e0 = torch.cuda.Event(enable_timing=True)
@@ -518,10 +535,13 @@ def main():
             ms = e0.elapsed_time(e1)
             s.close()
         out["acoustic_1d_1024"] = {"workload": w0["name"], "precision": "fp64",
-                                   "steps": w0["steps"], "run_ms": ms,
-                                   "value": w0["nx"] * w0["steps"] / (ms * 1e-3),
-                                   "unit": "cell-updates/s"}
-        log(f"[bench] 1D 1024 FP64 acoustic run: {ms:.2f} ms for {w0['steps']} steps")
+                                   "steps": w0["steps"], "run_ms": ms_coop,
+                                   "us_per_step": 1e3 * ms_coop / w0["steps"],
+                                   "value": w0["nx"] * w0["steps"] / (ms_coop * 1e-3),
+                                   "unit": "cell-updates/s", "path": "cooperative",
+                                   "us_per_step_one_workgroup": 1e3 * ms / w0["steps"]}
+        log(f"[bench] 1D 1024 FP64 acoustic run: {ms_coop:.2f} ms for {w0['steps']} steps "
+            f"(one workgroup: {ms:.2f} ms)")
 
     if args.bounded_steps > 0:
         # the same grid between reflecting walls (x) and outflow ends (y):

@@ -50,6 +50,9 @@ extern "C" {
 #define NG_EPHYS (-3)   /* a step produced rho <= 0, p <= 0 or a non-finite value */
 #define NG_EDEVICE (-4) /* a HIP runtime call failed                           */
 #define NG_EFULL (-5)   /* batch: no free slot or no room in the arena         */
+#define NG_ESTALL (-6)  /* a cooperative launch's grid-barrier wait ran out of
+                           polls (see ng_set_coop); the solve keeps its last
+                           accepted step and stops, like NG_EPHYS              */
 
 /* ------------------------------------------------------- enumerated options */
 #define NG_BC_PERIODIC 0 /* wrap-around ghost cells                             */
@@ -224,6 +227,25 @@ int ng_set_graph_steps(ng_solver* s, int32_t steps);
  * persistent path off.  Both paths give bitwise the same state. */
 int ng_set_small_limit(ng_solver* s, int64_t max_cells);
 
+/* Cooperative path (the time loop of eq. (15) with the dt of eq. (16) chosen
+ * after every step).  A solve that is alone in its object, 1D, without a
+ * forced source and of at most max_cells cells is advanced by one
+ * cooperative launch per call (up to 65536 steps each): every step, its
+ * workgroups -- all resident together -- update their segments, meet at a
+ * grid barrier in device memory, and the last to arrive folds the step's
+ * records, accepts the step and sends the next dt to the others.  No launch
+ * or host round trip per step; the state, t and dt are bitwise those of one
+ * launch per step (only the summation order of the FP64 totals differs).
+ * max_cells: -1 restores the default (4194304), 0 turns the path off (the
+ * persistent one-workgroup path or one launch per step take over).
+ * spin_limit: polls of memory (about a microsecond each) a workgroup spends
+ * in one barrier wait before it gives up (-1: the default, 1048576); a wait
+ * that runs out ends the launch early with every kernel exiting, and the
+ * next synchronising call reports NG_ESTALL.  Cooperative launches must be
+ * supported by the device (else the other paths run).  Synchronising;
+ * NG_EINVAL for values below -1. */
+int ng_set_coop(ng_solver* s, int64_t max_cells, int32_t spin_limit);
+
 /* Step acceptance inside the step kernel (1, default) or by a separate
  * kernel (0); see ng_batch_set_fused_accept. */
 int ng_set_fused_accept(ng_solver* s, int32_t on);
@@ -345,6 +367,10 @@ int ng_batch_set_fused_accept(ng_batch* b, int32_t on);
 
 /* Persistent-path size limit of a batch (see ng_set_small_limit). */
 int ng_batch_set_small_limit(ng_batch* b, int64_t max_cells);
+
+/* Cooperative path of a batch (see ng_set_coop): taken only while the batch
+ * holds exactly one live solve that qualifies. */
+int ng_batch_set_coop(ng_batch* b, int64_t max_cells, int32_t spin_limit);
 
 /* Launch shape of the batched step kernels (see ng_set_launch). */
 int ng_batch_set_launch(ng_batch* b, int32_t dim, int32_t rows_per_item,

@@ -62,6 +62,17 @@ constexpr int kSmallWaves = 8;
 // step kernel (last workgroup); beyond it the per-workgroup release fence costs
 // more than the separate finalize launch.
 constexpr int64_t kFusedMaxBlocks = 256;
+// A batch's only solve, when it is 1D with at most this many cells and no
+// forced source, runs in the cooperative kernel: many steps per launch over
+// many workgroups, with a grid barrier per step instead of two launches.
+constexpr int64_t kCoopCells = int64_t(1) << 22;
+// polls of a grid-barrier wait before it gives up (each a memory round trip
+// of about a microsecond and a short sleep: about a second)
+constexpr int32_t kCoopSpin = 1 << 20;
+// a cooperative launch gives each work item a wave of its own, four waves
+// per workgroup (one per SIMD of a CU), while the items fit in that many
+// workgroups; more items take the kernel's largest workgroups
+constexpr int kCoopSmallWaves = 4;
 // Pinned staging buffers of the initial-state upload (two, used in turn).
 constexpr size_t kStageBytes = size_t(16) << 20;
 // Host threads converting one staging chunk, and the cells each takes at least.
@@ -99,7 +110,7 @@ size_t solve_bytes(const ng_grid* g, int prec)
 }
 
 struct Layout {
-    size_t descs, ctrls, insts, iota, blocks1, blocks2, heap;
+    size_t descs, ctrls, insts, iota, coop, blocks1, blocks2, heap;
 };
 
 Layout header_layout(int capacity, size_t tcap1, size_t tcap2)
@@ -114,6 +125,8 @@ Layout header_layout(int capacity, size_t tcap1, size_t tcap2)
     o += align_up(sizeof(int32_t) * 5 * capacity);
     L.iota = o;
     o += align_up(sizeof(int32_t) * capacity);
+    L.coop = o;
+    o += align_up(sizeof(CoopSync));
     L.blocks1 = o;
     o += align_up(sizeof(BlockRef) * tcap1);
     L.blocks2 = o;
@@ -248,6 +261,7 @@ struct Slot {
     int64_t block_off = 0;  // first entry in the dim's block table
     int pos = 0;            // index in the dim's instance list (big or small)
     bool small = false;     // advanced by the persistent one-workgroup kernel
+    bool coop = false;      // advanced by the cooperative kernel
     bool reported = false;
 };
 
@@ -270,6 +284,12 @@ struct ng_batch {
     int auto_waves[3] = {0, 0, 0};  // automatic waves per workgroup of the big solves
     int remap = 1;
     int64_t small_limit = -1;  // cells; -1: by precision, 0: persistent path off
+    int64_t coop_limit = -1;   // cells; -1: kCoopCells, 0: cooperative path off
+    int32_t coop_spin = kCoopSpin;
+    int coop_slot = -1;        // the solve the cooperative kernel advances, or -1
+    int coop_grid = 0, coop_waves = 0, coop_rows = 1, coop_variant = 0;
+    int dev_coop = -1;         // cooperative launch supported (-1: not asked yet)
+    int dev_cus = 0;
     int fused = 1;             // step kernels accept their own step (last workgroup)
     int64_t nblocks[3] = {0, 0, 0};   // workgroups of the per-step launch (big solves)
     int ninst[3] = {0, 0, 0};         // big solves per dim
@@ -309,6 +329,7 @@ struct ng_batch {
     int32_t* d_insts(int dim) { return (int32_t*)(arena + L.insts) + dim * capacity; }
     int32_t* d_small(int dim) { return (int32_t*)(arena + L.insts) + (2 + dim) * capacity; }
     int32_t* d_iota() { return (int32_t*)(arena + L.iota); }
+    CoopSync* d_coop() { return (CoopSync*)(arena + L.coop); }
     BlockRef* d_blocks(int dim) { return (BlockRef*)(arena + (dim == 1 ? L.blocks1 : L.blocks2)); }
 };
 
@@ -318,6 +339,7 @@ struct ng_solver {
     std::string err;
 };
 
+static_assert(NG_ESTALL == ng::kStatusStall, "status of a stalled cooperative launch");
 static_assert(NG_BC_PERIODIC == ng::kBcPeriodic && NG_BC_WALL == ng::kBcWall &&
                   NG_BC_OUTFLOW == ng::kBcOutflow && NG_BC_SOURCE == ng::kBcSource,
               "boundary kinds of the ABI and the kernels");
@@ -441,9 +463,11 @@ void shape_solve(ng_batch* b, Slot& s, bool alone = true)
 {
     InstDesc& d = s.d;
     int dim = s.dim;
-    d.waves_per_block = s.small ? 1 : waves_of(b, dim, {{d.nx, d.ny}});
+    d.waves_per_block = s.small ? 1 : (s.coop ? kCoopSmallWaves : waves_of(b, dim, {{d.nx, d.ny}}));
     if (s.small)
         d.rows_per_item = dim == 2 ? kSmallRows2D : kSmallSegs1D;
+    else if (s.coop)
+        d.rows_per_item = b->coop_rows;
     else if (b->rows[dim] != kAutoRows)
         d.rows_per_item = b->rows[dim];
     else if (b->auto_rows[dim] > 0)
@@ -458,6 +482,78 @@ void shape_solve(ng_batch* b, Slot& s, bool alone = true)
     d.nitems = dim == 2 ? (int64_t)d.nstrips * d.nchunks : (int64_t)d.nchunks;
     d.nblocks = cdiv(d.nitems, d.waves_per_block);
     d.fused = (b->fused && alone && !s.small && d.nblocks <= kFusedMaxBlocks) ? 1 : 0;
+}
+
+// The cooperative path: a batch whose only live solve is 1D, has no forced
+// source and at most coop_limit cells, on a device that supports cooperative
+// launches.  Marks that solve (Slot::coop), sets coop_slot (else -1) and the
+// launch shape: while the 60-cell segments fit one per wave in workgroups of
+// kCoopSmallWaves waves (one per SIMD) with at most one workgroup per CU,
+// that; else workgroups of the kernel's largest size, as many as stay
+// resident together, each wave taking an equal run of consecutive segments
+// (so that the march's prefetch of the next segment covers the run).
+int choose_coop(ng_batch* b)
+{
+    b->coop_slot = -1;
+    int live = 0, cand = -1;
+    for (int i = 0; i < b->capacity; i++) {
+        Slot& s = b->slots[i];
+        s.coop = false;
+        if (!s.live) continue;
+        live++;
+        cand = i;
+    }
+    const int64_t lim = b->coop_limit >= 0 ? b->coop_limit : kCoopCells;
+    if (live != 1 || lim == 0) return NG_OK;
+    Slot& s = b->slots[cand];
+    if (s.dim != 1 || s.d.bc[0] == kBcSource || s.d.ncell > lim) return NG_OK;
+    if (b->dev_coop < 0) {
+        int dev = 0, coop = 0, cus = 0;
+        CK(b, hipGetDevice(&dev));
+        CK(b, hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+        CK(b, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        b->dev_coop = coop ? 1 : 0;
+        b->dev_cus = cus;
+    }
+    if (!b->dev_coop || b->dev_cus < 1) return NG_OK;
+    const int kind = kind_of(b->prec);
+    const int v = (s.d.riemann == NG_HLLC && !s.d.any_bc) ? 1 + s.d.cl_recipe : 0;
+    const int64_t segs = cdiv(s.d.nx, kInterior);
+    int per_cu = 0, maxw = 0;
+    CK(b, coop_capacity(kind, v, kCoopSmallWaves, &per_cu, &maxw));
+    int waves = kCoopSmallWaves;
+    int64_t rows = 1;
+    if (segs > (int64_t)kCoopSmallWaves * b->dev_cus) {
+        waves = maxw;
+        CK(b, coop_capacity(kind, v, waves, &per_cu, &maxw));
+        rows = cdiv(segs, (int64_t)per_cu * b->dev_cus * waves);
+    }
+    const int64_t resident = (int64_t)per_cu * b->dev_cus;
+    const int64_t items = cdiv(segs, rows);
+    const int64_t grid = std::min<int64_t>(cdiv(items, waves), resident);
+    if (grid < 1 || coop_space((uint64_t)grid) > (uint64_t)s.partial_cap * sizeof(Partial))
+        return NG_OK;
+    s.coop = true;
+    b->coop_slot = cand;
+    b->coop_grid = (int)grid;
+    b->coop_waves = waves;
+    b->coop_rows = (int)rows;
+    b->coop_variant = v;
+    return NG_OK;
+}
+
+// Launch the cooperative kernel for nsteps steps (in launches of at most
+// kCoopMaxSteps steps).
+int enqueue_coop(ng_batch* b, int64_t nsteps)
+{
+    for (int64_t left = nsteps; left > 0;) {
+        const int64_t n = std::min<int64_t>(left, kCoopMaxSteps);
+        CK(b, launch_coop(kind_of(b->prec), b->coop_variant, b->d_descs(), b->d_ctrls(),
+                          b->coop_slot, b->d_coop(), b->coop_grid, b->coop_waves, n,
+                          b->coop_spin, b->stream));
+        left -= n;
+    }
+    return NG_OK;
 }
 
 // Rebuild the device tables (descriptors, per-dim solve lists and workgroup
@@ -476,12 +572,14 @@ int rebuild(ng_batch* b)
     // exactly those), then those of small solves (used by the priming pass only)
     const int64_t lim = b->small_limit >= 0 ? b->small_limit
                                             : (b->prec != NG_FP64 ? kSmallCells32 : kSmallCells64);
+    int rc = choose_coop(b);
+    if (rc) return rc;
     int nbig[3] = {0, 0, 0};
     std::vector<std::pair<int64_t, int64_t>> grids[3];
     for (int i = 0; i < b->capacity; i++)
         if (b->slots[i].live) {
             Slot& s = b->slots[i];
-            s.small = s.d.ncell <= lim;
+            s.small = !s.coop && s.d.ncell <= lim;
             if (!s.small) {
                 nbig[s.dim]++;
                 grids[s.dim].push_back({s.d.nx, s.d.ny});
@@ -602,6 +700,21 @@ int enqueue_timed(ng_batch* b, int64_t nsteps)
     size_t ne = 0;
     std::vector<std::pair<size_t, size_t>> step_pairs, fin_pairs;
     double small_ms = 0.0;
+    if (b->coop_slot >= 0) {
+        hipEvent_t e0 = get_event(b, 0), e1 = get_event(b, 1);
+        if (!e0 || !e1) return dev_err(b, hipErrorOutOfMemory, "hipEventCreate");
+        CK(b, hipEventRecord(e0, b->stream));
+        int rc = enqueue_coop(b, nsteps);
+        if (rc) return rc;
+        CK(b, hipEventRecord(e1, b->stream));
+        CK(b, hipStreamSynchronize(b->stream));
+        float ms = 0.f;
+        CK(b, hipEventElapsedTime(&ms, e0, e1));
+        b->t_step_ms = nsteps > 0 ? ms / nsteps : 0.0;
+        b->t_fin_ms = 0.0;
+        b->t_launches = cdiv(nsteps, kCoopMaxSteps);
+        return NG_OK;
+    }
     if (any_small(b)) {
         hipEvent_t e0 = get_event(b, 0), e1 = get_event(b, 1);
         if (!e0 || !e1) return dev_err(b, hipErrorOutOfMemory, "hipEventCreate");
@@ -689,13 +802,15 @@ int ensure_graph(ng_batch* b)
     return NG_OK;
 }
 
-// Enqueue nsteps steps: the small solves in one persistent launch, the big
-// ones as whole captured graphs, then single launches for the rest.
+// Enqueue nsteps steps: the cooperative solve in cooperative launches; else
+// the small solves in one persistent launch, the big ones as whole captured
+// graphs, then single launches for the rest.
 int enqueue_steps(ng_batch* b, int64_t nsteps)
 {
     int rc = rebuild(b);
     if (rc) return rc;
     if (b->timing) return enqueue_timed(b, nsteps);
+    if (b->coop_slot >= 0) return enqueue_coop(b, nsteps);
     rc = enqueue_small(b, nsteps, b->stream);
     if (rc || !any_big(b)) return rc;
     int64_t left = nsteps;
@@ -1204,6 +1319,7 @@ const char* ng_strerror(int code)
     case NG_EPHYS: return "non-physical state (rho <= 0, p <= 0 or non-finite)";
     case NG_EDEVICE: return "HIP runtime error";
     case NG_EFULL: return "batch full";
+    case NG_ESTALL: return "cooperative launch stalled (grid-barrier wait ran out of polls)";
     default: return "unknown error";
     }
 }
@@ -1300,6 +1416,10 @@ int ng_run_to_time(ng_solver* s, double t_end, int64_t max_steps, int64_t* steps
         const InstCtrl& c = b->h_ctrls[s->slot];
         if (c.status != 0) {
             if (steps_taken) *steps_taken = c.steps - steps0;
+            if (c.status == kStatusStall) {
+                s->err = "cooperative launch: a grid-barrier wait ran out of polls";
+                return NG_ESTALL;
+            }
             s->err = "step rejected: non-physical state";
             return NG_EPHYS;
         }
@@ -1359,6 +1479,12 @@ int ng_set_small_limit(ng_solver* s, int64_t max_cells)
 {
     if (!s) return NG_EINVAL;
     return solver_rc(s, ng_batch_set_small_limit(s->b, max_cells));
+}
+
+int ng_set_coop(ng_solver* s, int64_t max_cells, int32_t spin_limit)
+{
+    if (!s) return NG_EINVAL;
+    return solver_rc(s, ng_batch_set_coop(s->b, max_cells, spin_limit));
 }
 
 int ng_set_graph_steps(ng_solver* s, int32_t steps)
@@ -1666,6 +1792,15 @@ int ng_batch_set_small_limit(ng_batch* b, int64_t max_cells)
 {
     if (!b || max_cells < -1) return NG_EINVAL;
     b->small_limit = max_cells;
+    b->dirty = true;
+    return rebuild(b);
+}
+
+int ng_batch_set_coop(ng_batch* b, int64_t max_cells, int32_t spin_limit)
+{
+    if (!b || max_cells < -1 || spin_limit < -1) return NG_EINVAL;
+    b->coop_limit = max_cells;
+    b->coop_spin = spin_limit < 0 ? kCoopSpin : spin_limit;
     b->dirty = true;
     return rebuild(b);
 }

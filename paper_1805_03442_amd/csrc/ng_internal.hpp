@@ -103,6 +103,58 @@ struct InstCtrl {
                               // x = -h/2, -3h/2 at time t (set with t)
 };
 
+// Grid barrier of a cooperative launch (one solve advanced many steps per
+// launch by workgroups that stay resident together), zeroed before each
+// launch.  Workgroup b arrives at the counter of group b % groups (one group
+// up to kCoopFlat workgroups, else kCoopGroups); the last arrival of a group
+// arrives at top; the last arrival at top decides the step and writes the
+// outcome to every group's line: three 8-byte words, each (step number << 32
+// | 32 bits of payload) -- the low and high halves of the next CFL step and
+// (accepted | failure flags << 1) -- so that a reader which sees the step
+// number in all three words holds one whole message.  Each counter and line
+// sits in a 128-byte cache line of its own.
+constexpr int kCoopGroups = 16;
+constexpr int kCoopFlat = 32;
+constexpr int kCoopMaxWaves = 16;   // waves per workgroup of a cooperative launch
+struct CoopSync {
+    uint32_t grp[kCoopGroups][32];
+    uint32_t top[32];
+    uint64_t line[kCoopGroups][16];
+    uint32_t stall[32];            // [0]: set by a workgroup whose wait ran out
+};
+
+// Per-workgroup data of a cooperative launch, in the solve's reduction space:
+// records of the workgroup's last two steps (by step parity), the step's
+// signal speed and flags for the barrier, and the workgroup's view of the
+// solve's control when it left.
+struct CoopRec {
+    double tot[5];      // sums of U^{n+1} over the workgroup's cells
+    double src[2];      // sums of the step's source increments
+    double bud[2];      // sums of the source increments of the launch's earlier accepted steps
+    double smax, rho_min, p_min;
+    uint32_t flags, step;
+};
+struct CoopSlot {
+    double smax;
+    uint32_t flags, pad;
+};
+struct CoopView {
+    double t, dt_cfl, dt_last;
+    int64_t steps, nacc;   // steps of the solve; steps this launch accepted
+    int32_t cur, status;
+    uint32_t flags, pad;
+};
+// bytes of reduction space a cooperative launch of G workgroups uses
+constexpr uint64_t coop_space(uint64_t G)
+{
+    return G * (2 * sizeof(CoopRec) + sizeof(CoopSlot) + sizeof(CoopView));
+}
+
+// Status of a solve whose cooperative launch ended at a wait that ran out of
+// polls (the value of NG_ESTALL); like NG_EPHYS it stops the solve, which keeps
+// its last accepted step.
+constexpr int32_t kStatusStall = -6;
+
 // One workgroup's reduction record of a step (or of the priming pass).
 struct Partial {
     double tot[5];

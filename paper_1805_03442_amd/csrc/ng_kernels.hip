@@ -122,6 +122,8 @@ struct Plain64 {
     // the FP64 step needs more than 128 registers; asking for two waves per
     // SIMD trades a few spills for latency hiding (13 % faster at 4096^2)
     static constexpr int kMinWaves = 2;
+    // largest workgroup of a cooperative launch (eight waves: two per SIMD)
+    static constexpr int kCoopThreads = 512;
     // U^n of the updated row is re-read from cache (no registers to spare)
     static constexpr bool kKeepRows = false;
     // the energy slot holds E itself
@@ -187,6 +189,10 @@ struct Dev32 {
     using St = float;   // stored state: FP32 deviations
     using K = K32;
     static constexpr int kMinWaves = 1;
+    // eight waves, as in FP64: two such workgroups share a CU when the kernel
+    // fits 128 registers (sixteen-wave workgroups, which force 128, spill and
+    // were slower: 2^20 cells 17.6 against 14.6 us per step)
+    static constexpr int kCoopThreads = 512;
     // the raw rows stay in registers until their update
     static constexpr bool kKeepRows = true;
     // the energy slot holds e = E - E_nu (deviation from e_r)
@@ -261,6 +267,7 @@ struct Mix32 {
     using St = double;
     using K = K32;
     static constexpr int kMinWaves = 1;
+    static constexpr int kCoopThreads = 512;
     static constexpr bool kKeepRows = true;
     static constexpr bool kSplitE = true;
     static constexpr bool kRecipes = true;
@@ -366,12 +373,13 @@ __device__ __forceinline__ uint32_t acc_flags(const Acc<R>& a)
 }
 
 // Fold the lanes of each wave (lane 0 keeps a fixed-order result), then the
-// waves of the workgroup in wave order, and store the workgroup's record.
-template <class R>
+// waves of the workgroup in wave order, and store the workgroup's record
+// (WT: with agent-scope stores, which write through to memory).
+template <class R, int MaxW = kMaxWaves, bool WT = false>
 __device__ void block_reduce_store(Acc<R>& a, Partial* out, int wave, int lane, int nwaves)
 {
-    __shared__ double sh[kMaxWaves][11];
-    __shared__ uint32_t shf[kMaxWaves];
+    __shared__ double sh[MaxW][11];
+    __shared__ uint32_t shf[MaxW];
     uint32_t flags = acc_flags(a);
     double smax = (double)a.smax, rmin = (double)a.rmin, pmin = (double)a.pmin;
     for (int m = 32; m >= 1; m >>= 1) {
@@ -411,7 +419,20 @@ __device__ void block_reduce_store(Acc<R>& a, Partial* out, int wave, int lane, 
             r.p_min = fmin(r.p_min, sh[w][9]);
             r.flags |= shf[w];
         }
-        *out = r;
+        if constexpr (WT) {
+            auto put = [](double* p, double x) {
+                __hip_atomic_store(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            };
+            for (int c = 0; c < 5; c++) put(&out->tot[c], r.tot[c]);
+            put(&out->src[0], r.src[0]);
+            put(&out->src[1], r.src[1]);
+            put(&out->smax, r.smax);
+            put(&out->rho_min, r.rho_min);
+            put(&out->p_min, r.p_min);
+            __hip_atomic_store(&out->flags, r.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            *out = r;
+        }
     }
 }
 
@@ -526,12 +547,11 @@ __device__ void accept_step(const InstDesc& d, InstCtrl& c, const StepCtl& sc, c
 // calling workgroup (up to 16 waves): strided per-thread sums, then lanes
 // (butterfly; lane 0's order is fixed), then waves in order.  The result is in
 // out[10] / *oflags, valid in thread 0 after the call.
-__device__ void fold_partials(const InstDesc& d, double* out, uint32_t* oflags)
+__device__ void fold_partials(const InstDesc& d, int64_t nb, double* out, uint32_t* oflags)
 {
     __shared__ double sh[16][10];
     __shared__ uint32_t shf[16];
     const Partial* parts = (const Partial*)d.partials;
-    const int64_t nb = d.nblocks;
     double tot[5] = {0, 0, 0, 0, 0}, src0 = 0.0, src1 = 0.0, smax = 0.0, rmin = INFINITY,
            pmin = INFINITY;
     uint32_t flags = 0;
@@ -594,7 +614,7 @@ __global__ void __launch_bounds__(256) finalize_kernel(const InstDesc* __restric
     if (mode == 1 && c.status != 0) return;
     double v[10];
     uint32_t flags;
-    fold_partials(d, v, &flags);
+    fold_partials(d, d.nblocks, v, &flags);
     if (threadIdx.x == 0) accept_step(d, c, sc, v, flags, mode);
 }
 
@@ -618,7 +638,7 @@ __device__ void last_block_accept(const InstDesc& d, InstCtrl& c, const StepCtl&
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     double v[10];
     uint32_t flags;
-    fold_partials(d, v, &flags);
+    fold_partials(d, d.nblocks, v, &flags);
     if (threadIdx.x == 0) {
         accept_step(d, c, sc, v, flags, 0);
         c.arrive = 0u;
@@ -628,10 +648,13 @@ __device__ void last_block_accept(const InstDesc& d, InstCtrl& c, const StepCtl&
 // ================================================================ 2D step
 
 // The NC conserved planes of one state buffer: uniform base addresses and a
-// 32-bit byte offset per cell (planes are < 4 GiB).
+// 32-bit byte offset per cell (planes are < 4 GiB).  Coh: agent-scope loads
+// and stores (the cooperative launch, where the next step's loads must see
+// what workgroups on other XCDs stored: the stores write through to memory
+// and the loads never take a stale line from this XCD's L2).
 typedef __attribute__((address_space(1))) char gchar;
 
-template <class R, int NC>
+template <class R, int NC, bool Coh = false>
 struct Planes {
     typedef __attribute__((address_space(1))) R gR;
     gchar* base[NC];
@@ -641,11 +664,23 @@ struct Planes {
     }
     __device__ __forceinline__ void load(uint32_t boff, R* U) const
     {
-        for (int c = 0; c < NC; c++) U[c] = *(const gR*)(base[c] + (uint64_t)boff);
+        for (int c = 0; c < NC; c++) {
+            if constexpr (Coh)
+                U[c] = __hip_atomic_load((gR*)(base[c] + (uint64_t)boff), __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+            else
+                U[c] = *(const gR*)(base[c] + (uint64_t)boff);
+        }
     }
     __device__ __forceinline__ void store(uint32_t boff, const R* U) const
     {
-        for (int c = 0; c < NC; c++) __builtin_nontemporal_store(U[c], (gR*)(base[c] + (uint64_t)boff));
+        for (int c = 0; c < NC; c++) {
+            if constexpr (Coh)
+                __hip_atomic_store((gR*)(base[c] + (uint64_t)boff), U[c], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            else
+                __builtin_nontemporal_store(U[c], (gR*)(base[c] + (uint64_t)boff));
+        }
     }
 };
 
@@ -922,22 +957,6 @@ __device__ __forceinline__ void march2d_hllc(const InstDesc& d, const typename P
     }
 }
 
-template <class P, int CL = kRecipes>
-__device__ __forceinline__ void march1d_hllc(const InstDesc& d, const typename P::K& k, int cur,
-                                             const double* gsrc, int64_t item, int lane,
-                                             Acc<typename P::R>& acc)
-{
-    if constexpr (P::kRecipes && CL > 0) {
-        if (!d.any_bc && d.cl_recipe == CL) {
-            march1d<P, 0, false, CL>(d, k, cur, gsrc, item, lane, acc);
-            return;
-        }
-        march1d_hllc<P, CL - 1>(d, k, cur, gsrc, item, lane, acc);
-    } else {
-        march1d_bc<P, 0>(d, k, cur, gsrc, item, lane, acc);
-    }
-}
-
 // V = 0: any solves (boundary kind, flux and closures per solve);
 // V = 1 + r: every solve of the launch is periodic with the HLLC flux and its
 // closures match recipe r (kRecipeCodes; r = 0: the general form) -- a kernel
@@ -978,7 +997,8 @@ __global__ void __launch_bounds__(256, P::kMinWaves) step2d_kernel(const InstDes
 // ================================================================ 1D step
 
 // One work item of the 1D step: a group of consecutive 60-cell segments.
-template <class P, int RS, bool BC, int CL = 0>
+// Coh: agent-scope state loads and stores (Planes).
+template <class P, int RS, bool BC, int CL = 0, bool Coh = false>
 __device__ __forceinline__ void march1d(const InstDesc& d, const typename P::K& k, int cur,
                                         const double* gsrc, int64_t item, int lane,
                                         Acc<typename P::R>& acc)
@@ -988,8 +1008,8 @@ __device__ __forceinline__ void march1d(const InstDesc& d, const typename P::K& 
     constexpr bool FR = RS == 0;
     const int64_t n = d.nx;
     using St = typename P::St;
-    const Planes<St, NC> src(d.buf[cur], n);
-    const Planes<St, NC> dst(d.buf[cur ^ 1], n);
+    const Planes<St, NC, Coh> src(d.buf[cur], n);
+    const Planes<St, NC, Coh> dst(d.buf[cur ^ 1], n);
     const int64_t s0 = item * d.rows_per_item;
     const int64_t s1 = s0 + d.rows_per_item < d.nstrips ? s0 + d.rows_per_item : d.nstrips;
     auto boff = [&](int64_t sg) -> uint32_t {
@@ -1055,15 +1075,32 @@ __device__ __forceinline__ void march1d(const InstDesc& d, const typename P::K& 
     if (sg < s1) seg(sg, UA, UB);
 }
 
-template <class P, int RS>
+template <class P, int RS, bool Coh = false>
 __device__ __forceinline__ void march1d_bc(const InstDesc& d, const typename P::K& k, int cur,
                                            const double* gsrc,
                                            int64_t item, int lane, Acc<typename P::R>& acc)
 {
     if (d.any_bc)
-        march1d<P, RS, true>(d, k, cur, gsrc, item, lane, acc);
+        march1d<P, RS, true, 0, Coh>(d, k, cur, gsrc, item, lane, acc);
     else
-        march1d<P, RS, false>(d, k, cur, gsrc, item, lane, acc);
+        march1d<P, RS, false, 0, Coh>(d, k, cur, gsrc, item, lane, acc);
+}
+
+// the 1D counterpart of march2d_hllc
+template <class P, int CL = kRecipes, bool Coh = false>
+__device__ __forceinline__ void march1d_hllc(const InstDesc& d, const typename P::K& k, int cur,
+                                             const double* gsrc, int64_t item, int lane,
+                                             Acc<typename P::R>& acc)
+{
+    if constexpr (P::kRecipes && CL > 0) {
+        if (!d.any_bc && d.cl_recipe == CL) {
+            march1d<P, 0, false, CL, Coh>(d, k, cur, gsrc, item, lane, acc);
+            return;
+        }
+        march1d_hllc<P, CL - 1, Coh>(d, k, cur, gsrc, item, lane, acc);
+    } else {
+        march1d_bc<P, 0, Coh>(d, k, cur, gsrc, item, lane, acc);
+    }
 }
 
 // V as for step2d_kernel
@@ -1245,6 +1282,354 @@ __global__ void __launch_bounds__(512) run_small_kernel(const InstDesc* __restri
             accept_step(d, c, sc, sh[0], shf[0], 0);
         }
         __syncthreads();
+    }
+}
+
+// ================================================== cooperative solves
+
+// this wave's memory operations have completed: vmcnt(0) lgkmcnt(0) (flat
+// stores count in both)
+__device__ __forceinline__ void wait_mem() { __builtin_amdgcn_s_waitcnt(0x0070); }
+
+// One 1D solve advanced through up to nsteps steps by one cooperative launch
+// of G workgroups that stay resident together (no launch per step).  Every
+// workgroup tracks the solve's control (t, steps, buffer, CFL step) itself,
+// alike.  Each step it marches its share of the 60-cell segments with
+// agent-scope state loads and stores (the stores write through to memory and
+// the loads never take a stale line of its own XCD's L2), reduces its signal
+// speed and failure flags, stores them to its slot, waits for the stores and
+// arrives at the two-level counter of the CoopSync block.  The last arrival
+// reads the G slots, decides the step (eq. (16)'s next CFL step, or
+// rejection) and writes the outcome to every group's line; the others poll
+// their group's line.  The FP64 sums of the step (totals, source budgets,
+// extrema) never cross the barrier: each workgroup folds its own into a
+// record while it waits, and a kernel after the launch (coop_after_kernel)
+// folds the records of the last accepted step into the control block.  Per-
+// cell arithmetic, t and dt follow the step kernels and the finalize kernel
+// operation for operation, so the state, t and dt are bitwise those of one
+// launch per step; only the summation order of the FP64 totals differs.
+// Every wait is bounded by spin_limit polls: a workgroup whose wait runs out
+// sets the stall word and leaves, the others leave when their own next wait
+// runs out, and the solve keeps the last step a barrier accepted.  Solves
+// with a forced source are not run here (their ghosts follow t through the
+// control block).
+template <class P, int V>
+__global__ void __launch_bounds__(P::kCoopThreads) run_coop1d_kernel(
+    const InstDesc* __restrict__ descs, const InstCtrl* __restrict__ ctrls, int inst,
+    CoopSync* __restrict__ cs, int64_t nsteps, int32_t spin_limit)
+{
+    using R = typename P::R;
+    const InstDesc& d = descs[inst];
+    const InstCtrl& c = ctrls[inst];
+    const uint32_t G = gridDim.x, b = blockIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int nw = blockDim.x >> 6;
+    const uint32_t ng = G <= (uint32_t)kCoopFlat ? 1u : (uint32_t)kCoopGroups;
+    const uint32_t grp = b % ng;
+    const uint32_t gsize = (G - 1u - grp) / ng + 1u;   // workgroups b' < G with b' % ng == grp
+    CoopRec* recs = (CoopRec*)d.partials;                // [parity][G]
+    CoopSlot* slots = (CoopSlot*)(recs + 2 * (size_t)G);
+    CoopView* views = (CoopView*)(slots + G);
+    __shared__ CoopRec s_rec[2];
+    __shared__ double s_bud[2];
+    __shared__ double s_sum[kCoopMaxWaves][9];
+    __shared__ double s_sm[kCoopMaxWaves];
+    __shared__ uint32_t s_fl[kCoopMaxWaves];
+    __shared__ int s_role;   // 0: waits, 1: decides the step, 2: its wait ran out
+    __shared__ uint64_t s_msg[3];
+    // the solve's control, as every workgroup tracks it
+    const double t_end = c.t_end;
+    const int64_t max_steps = c.max_steps;
+    double t = c.t, dt_cfl = c.dt_cfl, dt_last = c.dt_last;
+    int64_t steps = c.steps, nacc = 0;
+    int cur = c.cur, status = c.status;
+    uint32_t bad = 0;
+    bool active = status == 0 && t < t_end && steps < max_steps;
+    if (threadIdx.x == 0) {
+        s_bud[0] = s_bud[1] = 0.0;
+        s_rec[0].step = s_rec[1].step = 0xffffffffu;
+    }
+    __syncthreads();
+    for (int64_t st = 0; st < nsteps && active; st++) {
+        const uint32_t gen = (uint32_t)(st + 1);
+        double dt = dt_cfl;
+        if (t + dt > t_end) dt = t_end - t;
+        const typename P::K k = P::make(d, dt);
+        Acc<R> acc;
+        acc_init(acc);
+        for (int64_t item = (int64_t)b * nw + wave; item < d.nitems; item += (int64_t)G * nw) {
+            if constexpr (V > 0)
+                march1d<P, 0, false, V - 1, true>(d, k, cur, nullptr, item, lane, acc);
+            else if (d.riemann == 1)
+                march1d_bc<P, 1, true>(d, k, cur, nullptr, item, lane, acc);
+            else
+                march1d_hllc<P, kRecipes, true>(d, k, cur, nullptr, item, lane, acc);
+        }
+        acc_finish<P>(acc, k);
+        // the barrier needs only the signal speed and the failure flags
+        uint32_t fl = acc_flags(acc);
+        double sm = (double)acc.smax;
+        for (int m = 32; m >= 1; m >>= 1) {
+            sm = fmax(sm, lane_xor(sm, lane, m));
+            fl |= (uint32_t)__builtin_amdgcn_ds_bpermute(((lane ^ m) & 63) << 2, (int)fl);
+        }
+        if (lane == 0) {
+            s_sm[wave] = sm;
+            s_fl[wave] = fl;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double m = 0.0;
+            uint32_t f = 0;
+            for (int w = 0; w < nw; w++) {
+                m = fmax(m, s_sm[w]);
+                f |= s_fl[w];
+            }
+            __hip_atomic_store(&slots[b].smax, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&slots[b].flags, f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            wait_mem();
+            int role = 0;
+            const uint32_t pg = __hip_atomic_fetch_add(&cs->grp[grp][0], 1u, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+            if (pg == gen * gsize - 1u) {
+                if (ng == 1u) {
+                    role = 1;
+                } else {
+                    const uint32_t pt = __hip_atomic_fetch_add(&cs->top[0], 1u, __ATOMIC_RELAXED,
+                                                               __HIP_MEMORY_SCOPE_AGENT);
+                    role = pt == gen * ng - 1u ? 1 : 0;
+                }
+            }
+            s_role = role;
+            s_rec[st & 1].smax = m;
+            s_rec[st & 1].flags = f;
+        }
+        // this workgroup's FP64 sums of the step (lanes, then waves in order),
+        // while the last arrivals are on their way
+        {
+            double v[9];
+            for (int q = 0; q < 5; q++) v[q] = acc.tot[q];
+            v[5] = acc.src[0];
+            v[6] = acc.src[1];
+            v[7] = (double)acc.rmin;
+            v[8] = (double)acc.pmin;
+            for (int m = 32; m >= 1; m >>= 1) {
+                for (int q = 0; q < 7; q++) v[q] += lane_xor(v[q], lane, m);
+                v[7] = fmin(v[7], lane_xor(v[7], lane, m));
+                v[8] = fmin(v[8], lane_xor(v[8], lane, m));
+            }
+            if (lane == 0)
+                for (int q = 0; q < 9; q++) s_sum[wave][q] = v[q];
+        }
+        __syncthreads();
+        // thread 0: the waves' sums into the step's record (waves in order)
+        auto fold_rec = [&]() {
+            CoopRec& r = s_rec[st & 1];
+            double v[9];
+            for (int q = 0; q < 7; q++) v[q] = 0.0;
+            v[7] = v[8] = INFINITY;
+            for (int w = 0; w < nw; w++) {
+                for (int q = 0; q < 7; q++) v[q] += s_sum[w][q];
+                v[7] = fmin(v[7], s_sum[w][7]);
+                v[8] = fmin(v[8], s_sum[w][8]);
+            }
+            for (int q = 0; q < 5; q++) r.tot[q] = v[q];
+            r.src[0] = v[5];
+            r.src[1] = v[6];
+            r.bud[0] = s_bud[0];
+            r.bud[1] = s_bud[1];
+            r.rho_min = v[7];
+            r.p_min = v[8];
+            r.step = (uint32_t)st;
+        };
+        if (s_role == 1) {
+            // the step over all workgroups: the largest signal speed and the
+            // union of the failure flags
+            double m = 0.0;
+            uint32_t f = 0;
+            for (uint32_t j = threadIdx.x; j < G; j += blockDim.x) {
+                m = fmax(m, __hip_atomic_load(&slots[j].smax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                f |= __hip_atomic_load(&slots[j].flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            for (int mm = 32; mm >= 1; mm >>= 1) {
+                m = fmax(m, lane_xor(m, lane, mm));
+                f |= (uint32_t)__builtin_amdgcn_ds_bpermute(((lane ^ mm) & 63) << 2, (int)f);
+            }
+            // (thread 0 read the arrival's s_sm / s_fl before the last barrier)
+            if (lane == 0) {
+                s_sm[wave] = m;
+                s_fl[wave] = f;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                for (int w = 1; w < nw; w++) {
+                    m = fmax(m, s_sm[w]);
+                    f |= s_fl[w];
+                }
+                const uint32_t fb = f & 7u;
+                // eq. (16) for the new state, as the finalize kernel computes it
+                const double dtc = fb ? dt_cfl : d.cfl * d.h / m;
+                const uint64_t db = (uint64_t)__double_as_longlong(dtc);
+                const uint64_t tag = (uint64_t)gen << 32;
+                s_msg[0] = tag | (db & 0xffffffffull);
+                s_msg[1] = tag | (db >> 32);
+                s_msg[2] = tag | (uint64_t)(fb ? fb << 1 : 1u);
+            }
+            __syncthreads();
+            if (threadIdx.x < ng)
+                for (int w = 0; w < 3; w++)
+                    __hip_atomic_store(&cs->line[threadIdx.x][w], s_msg[w], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+            if (threadIdx.x == 0) fold_rec();
+        } else if (threadIdx.x == 0) {
+            fold_rec();
+            int32_t n = 0;
+            for (;;) {
+                uint64_t mw[3];
+                for (int w = 0; w < 3; w++)
+                    mw[w] = __hip_atomic_load(&cs->line[grp][w], __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+                if ((uint32_t)(mw[0] >> 32) == gen && (uint32_t)(mw[1] >> 32) == gen &&
+                    (uint32_t)(mw[2] >> 32) == gen) {
+                    for (int w = 0; w < 3; w++) s_msg[w] = mw[w];
+                    break;
+                }
+                if (++n > spin_limit) {
+                    __hip_atomic_fetch_or(&cs->stall[0], 1u, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+                    s_role = 2;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        __syncthreads();
+        if (s_role == 2) break;
+        const uint32_t out = (uint32_t)s_msg[2];
+        if (out & 1u) {
+            // accepted: as accept_step advances the control block
+            t = t + dt;
+            steps = steps + 1;
+            cur ^= 1;
+            dt_last = dt;
+            dt_cfl = __longlong_as_double(
+                (long long)((s_msg[0] & 0xffffffffull) | (s_msg[1] << 32)));
+            nacc++;
+            active = t < t_end && steps < max_steps;
+            if (threadIdx.x == 0) {
+                s_bud[0] += s_rec[st & 1].src[0];
+                s_bud[1] += s_rec[st & 1].src[1];
+            }
+        } else {
+            status = -3;   // NG_EPHYS
+            bad = out >> 1;
+            active = false;
+        }
+        __syncthreads();   // s_msg, s_role and s_bud are rewritten in the next step
+    }
+    // leave the workgroup's last two records and its view of the control
+    if (threadIdx.x == 0) {
+        recs[b] = s_rec[0];
+        recs[G + b] = s_rec[1];
+        CoopView w;
+        w.t = t;
+        w.dt_cfl = dt_cfl;
+        w.dt_last = dt_last;
+        w.steps = steps;
+        w.nacc = nacc;
+        w.cur = cur;
+        w.status = status;
+        w.flags = bad;
+        w.pad = 0u;
+        views[b] = w;
+    }
+}
+
+// After a cooperative launch of G workgroups (one workgroup): the most
+// advanced view of the control (most steps accepted; a rejection over a
+// wait that ran out at the same step) becomes the solve's control, with the
+// FP64 totals and extrema of the last accepted step and the source budgets of
+// every accepted step folded from the records in workgroup order.  A launch
+// whose wait ran out leaves the solve stopped with kStatusStall.
+__global__ void __launch_bounds__(256) coop_after_kernel(const InstDesc* __restrict__ descs,
+                                                         InstCtrl* __restrict__ ctrls, int inst,
+                                                         const CoopSync* __restrict__ cs, int G)
+{
+    const InstDesc& d = descs[inst];
+    InstCtrl& c = ctrls[inst];
+    const CoopRec* recs = (const CoopRec*)d.partials;
+    const CoopView* views = (const CoopView*)((const CoopSlot*)(recs + 2 * (size_t)G) + G);
+    __shared__ uint64_t s_key[4];
+    __shared__ double sh[4][10];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    // key of a view: steps accepted, then rejection, then the lowest index
+    uint64_t key = 0;
+    for (int j = t; j < G; j += blockDim.x) {
+        const CoopView& a = views[j];
+        const uint64_t kj = ((uint64_t)a.nacc << 33) | ((uint64_t)(a.status != 0) << 32) |
+                            (uint64_t)(0xffffffffu - (uint32_t)j);
+        key = kj > key ? kj : key;
+    }
+    for (int m = 32; m >= 1; m >>= 1) {
+        const int src = ((lane ^ m) & 63) << 2;
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)(uint32_t)key);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)(uint32_t)(key >> 32));
+        const uint64_t o = ((uint64_t)hi << 32) | lo;
+        key = o > key ? o : key;
+    }
+    if (lane == 0) s_key[wave] = key;
+    __syncthreads();
+    for (int x = 0; x < (int)(blockDim.x >> 6); x++) key = s_key[x] > key ? s_key[x] : key;
+    const CoopView w = views[0xffffffffu - (uint32_t)key];
+    const int p = (int)((w.nacc - 1) & 1);
+    double v[10] = {0, 0, 0, 0, 0, 0, 0, 0, INFINITY, INFINITY};
+    if (w.nacc > 0) {
+        for (int j = t; j < G; j += blockDim.x) {
+            const CoopRec& r = recs[(size_t)p * G + j];
+            for (int q = 0; q < 5; q++) v[q] += r.tot[q];
+            v[5] += r.bud[0] + r.src[0];
+            v[6] += r.bud[1] + r.src[1];
+            v[7] = fmax(v[7], r.smax);
+            v[8] = fmin(v[8], r.rho_min);
+            v[9] = fmin(v[9], r.p_min);
+        }
+        for (int m = 32; m >= 1; m >>= 1) {
+            for (int q = 0; q < 7; q++) v[q] += lane_xor(v[q], lane, m);
+            v[7] = fmax(v[7], lane_xor(v[7], lane, m));
+            v[8] = fmin(v[8], lane_xor(v[8], lane, m));
+            v[9] = fmin(v[9], lane_xor(v[9], lane, m));
+        }
+        if (lane == 0)
+            for (int q = 0; q < 10; q++) sh[wave][q] = v[q];
+    }
+    __syncthreads();
+    if (t != 0) return;
+    if (w.nacc > 0) {
+        for (int x = 1; x < (int)(blockDim.x >> 6); x++) {
+            for (int q = 0; q < 7; q++) v[q] += sh[x][q];
+            v[7] = fmax(v[7], sh[x][7]);
+            v[8] = fmin(v[8], sh[x][8]);
+            v[9] = fmin(v[9], sh[x][9]);
+        }
+        const double n = (double)d.ncell;
+        for (int q = 0; q < 5; q++) c.total[q] = v[q] + n * d.uref[q];
+        c.budget[0] += v[5];
+        c.budget[1] += v[6];
+        c.smax = v[7];
+        c.rho_min = v[8];
+        c.p_min = v[9];
+        c.t = w.t;
+        c.steps = w.steps;
+        c.cur = w.cur;
+        c.dt_cfl = w.dt_cfl;
+        c.dt_last = w.dt_last;
+        c.flags = 0u;
+    }
+    if (w.status != 0) {
+        c.status = w.status;
+        c.flags = w.flags;
+    } else if (cs->stall[0] != 0u && c.status == 0) {
+        c.status = kStatusStall;
     }
 }
 
@@ -1431,6 +1816,65 @@ hipError_t launch_small(int dim, int prec, const InstDesc* descs, InstCtrl* ctrl
         else
             hipLaunchKernelGGL((run_small_kernel<Mix32<4>, 4>), g, b, 0, s, descs, ctrls, insts, nsteps);
     }
+    return hipGetLastError();
+}
+
+// The cooperative 1D kernel of a precision and variant (as launch_step).
+template <template <int> class Pol>
+static const void* coop_kernel_of(int v)
+{
+    using P = Pol<4>;
+    if (v == 0) return (const void*)run_coop1d_kernel<P, 0>;
+    if (v == 1 || !P::kRecipes) return (const void*)run_coop1d_kernel<P, 1>;
+    if constexpr (P::kRecipes) {
+        if (v == 2) return (const void*)run_coop1d_kernel<P, 2>;
+        return (const void*)run_coop1d_kernel<P, 3>;
+    }
+    return nullptr;
+}
+
+static const void* coop_kernel(int prec, int variant)
+{
+    if (variant < 0 || variant > kRecipes + 1) return nullptr;
+    if (prec == 0) return coop_kernel_of<Plain64>(variant);
+    if (prec == 1) return coop_kernel_of<Dev32>(variant);
+    if (prec == 2) return coop_kernel_of<Mix32>(variant);
+    return nullptr;
+}
+
+static int coop_max_threads(int prec)
+{
+    return prec == 0 ? Plain64<4>::kCoopThreads
+                     : (prec == 1 ? Dev32<4>::kCoopThreads : Mix32<4>::kCoopThreads);
+}
+
+hipError_t coop_capacity(int prec, int variant, int waves, int* blocks_per_cu, int* max_waves)
+{
+    const void* k = coop_kernel(prec, variant);
+    if (!k) return hipErrorInvalidValue;
+    *max_waves = coop_max_threads(prec) / kWave;
+    if (waves < 1 || waves > *max_waves) return hipErrorInvalidValue;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, waves * kWave, 0);
+}
+
+hipError_t launch_coop(int prec, int variant, const InstDesc* descs, InstCtrl* ctrls, int inst,
+                       CoopSync* cs, int grid, int waves, int64_t nsteps, int32_t spin_limit,
+                       hipStream_t s)
+{
+    const void* k = coop_kernel(prec, variant);
+    const int maxw = coop_max_threads(prec) / kWave;
+    if (!k || grid < 1 || waves < 1 || waves > maxw || nsteps < 1 || nsteps > kCoopMaxSteps ||
+        spin_limit < 0)
+        return hipErrorInvalidValue;
+    hipError_t e = hipMemsetAsync(cs, 0, sizeof(CoopSync), s);
+    if (e != hipSuccess) return e;
+    void* args[] = {(void*)&descs, (void*)&ctrls, (void*)&inst, (void*)&cs, (void*)&nsteps,
+                    (void*)&spin_limit};
+    e = hipLaunchCooperativeKernel(k, dim3((unsigned)grid), dim3((unsigned)(waves * kWave)), args,
+                                   0, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(coop_after_kernel, dim3(1), dim3(256), 0, s, descs, ctrls, inst,
+                       (const CoopSync*)cs, grid);
     return hipGetLastError();
 }
 

@@ -30,6 +30,18 @@ hipError_t launch_small(int dim, int prec, const InstDesc* descs, InstCtrl* ctrl
 hipError_t launch_set_limits(InstCtrl* ctrls, const int32_t* insts, int n, double t_end,
                              int64_t max_steps_from_now, hipStream_t s);
 
+// Cooperative launch of one 1D solve (solve `inst`, no forced source) for up
+// to nsteps <= kCoopMaxSteps steps: grid workgroups of `waves` waves, all
+// resident together (the runtime refuses a grid that does not fit); cs is the
+// batch's barrier block, cleared here first.  coop_capacity gives the
+// resident workgroups per CU of that kernel and the largest waves per
+// workgroup.  variant as for launch_step.
+constexpr int64_t kCoopMaxSteps = int64_t(1) << 16;
+hipError_t coop_capacity(int prec, int variant, int waves, int* blocks_per_cu, int* max_waves);
+hipError_t launch_coop(int prec, int variant, const InstDesc* descs, InstCtrl* ctrls, int inst,
+                       CoopSync* cs, int grid, int waves, int64_t nsteps, int32_t spin_limit,
+                       hipStream_t s);
+
 // Static scratch of the entry point that allocates nothing: its device
 // address on the current device (looked up once per device), and the kernel
 // that writes one solve's descriptor, control block, finalize index list and

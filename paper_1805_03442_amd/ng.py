@@ -17,7 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "libng.so")
 
-NG_OK, NG_EINVAL, NG_ENOMEM, NG_EPHYS, NG_EDEVICE, NG_EFULL = 0, -1, -2, -3, -4, -5
+NG_OK, NG_EINVAL, NG_ENOMEM, NG_EPHYS, NG_EDEVICE, NG_EFULL, NG_ESTALL = 0, -1, -2, -3, -4, -5, -6
 NG_BC_PERIODIC, NG_BC_WALL, NG_BC_OUTFLOW, NG_BC_SOURCE = 0, 1, 2, 3
 NG_HLLC, NG_HLL = 0, 1
 NG_MINMOD = 0
@@ -30,10 +30,10 @@ GAS_FIELDS = ("gamma", "R", "Cv", "rho0", "T0", "tau0", "tau_rho", "tau_T",
 EXPORTED = (
     "ng_strerror", "ng_state_bytes", "ng_init_state", "ng_init_conserved", "ng_step",
     "ng_run_to_time", "ng_diagnostics", "ng_get_state", "ng_get_conserved", "ng_set_launch",
-    "ng_set_graph_steps", "ng_set_small_limit", "ng_set_fused_accept", "ng_enable_timing", "ng_kernel_time", "ng_last_error", "ng_destroy",
+    "ng_set_graph_steps", "ng_set_small_limit", "ng_set_coop", "ng_set_fused_accept", "ng_enable_timing", "ng_kernel_time", "ng_last_error", "ng_destroy",
     "ng_batch_create", "ng_batch_solve_bytes", "ng_batch_fits", "ng_batch_add", "ng_batch_run", "ng_batch_poll",
     "ng_batch_active", "ng_batch_diagnostics", "ng_batch_get_state", "ng_batch_get_conserved",
-    "ng_batch_remove", "ng_batch_set_launch", "ng_batch_set_small_limit",
+    "ng_batch_remove", "ng_batch_set_launch", "ng_batch_set_small_limit", "ng_batch_set_coop",
     "ng_batch_set_fused_accept", "ng_batch_last_error",
     "ng_batch_destroy", "ng_step_static", "ng_static_last_error",
 )
@@ -104,6 +104,7 @@ def lib():
             "ng_set_launch": ([vp, i32, i32], C.c_int),
             "ng_set_graph_steps": ([vp, i32], C.c_int),
             "ng_set_small_limit": ([vp, i64], C.c_int),
+            "ng_set_coop": ([vp, i64, i32], C.c_int),
             "ng_set_fused_accept": ([vp, i32], C.c_int),
             "ng_enable_timing": ([vp, i32, i32], C.c_int),
             "ng_kernel_time": ([vp, dp, dp, C.POINTER(i64)], C.c_int),
@@ -126,6 +127,7 @@ def lib():
             "ng_batch_remove": ([vp, i32], C.c_int),
             "ng_batch_set_launch": ([vp, i32, i32, i32], C.c_int),
             "ng_batch_set_small_limit": ([vp, i64], C.c_int),
+            "ng_batch_set_coop": ([vp, i64, i32], C.c_int),
             "ng_batch_set_fused_accept": ([vp, i32], C.c_int),
             "ng_batch_last_error": ([vp], C.c_char_p),
             "ng_batch_destroy": ([vp], None),
@@ -269,6 +271,10 @@ class Solver:
     def set_small_limit(self, max_cells: int):
         check(lib().ng_set_small_limit(self.h, int(max_cells)), "ng_set_small_limit", self._err())
 
+    def set_coop(self, max_cells: int = -1, spin_limit: int = -1):
+        check(lib().ng_set_coop(self.h, int(max_cells), int(spin_limit)), "ng_set_coop",
+              self._err())
+
     def set_fused_accept(self, on: bool):
         check(lib().ng_set_fused_accept(self.h, 1 if on else 0), "ng_set_fused_accept")
 
@@ -407,6 +413,10 @@ class Batch:
 
     def set_small_limit(self, max_cells: int):
         check(lib().ng_batch_set_small_limit(self.h, int(max_cells)), "ng_batch_set_small_limit",
+              self._err())
+
+    def set_coop(self, max_cells: int = -1, spin_limit: int = -1):
+        check(lib().ng_batch_set_coop(self.h, int(max_cells), int(spin_limit)), "ng_batch_set_coop",
               self._err())
 
     def set_fused_accept(self, on: bool):

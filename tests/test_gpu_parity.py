@@ -59,16 +59,24 @@ def comps(ny):
 
 def run_both(ng, gas, W, nx, ny, steps, precision, riemann=0, stiff_z=0.5, launch=None,
              t_end=None, small_limit=None, bc=(0, 0, 0, 0), source=(0.0, 0.0), h=None,
-             wedge=(0.0, 0.0, 0.0)):
+             wedge=(0.0, 0.0, 0.0), coop=None):
+    """The solve on the GPU and in the oracle.  Path of a lone 1D solve: the
+    library's default (the cooperative kernel) when small_limit and coop are
+    None; a given small_limit turns the cooperative path off unless coop says
+    otherwise (-1: the persistent one-workgroup path, 0: one launch per step)."""
     import oracle
     oracle.build()
     P = oracle.Problem(gas, nx, ny, h=h, riemann=riemann, stiff_z=stiff_z, bc=bc, source=source,
                        wedge=wedge)
     U0 = P.prim_to_cons(W)
     say(f"case nx={nx} ny={ny} steps={steps} prec={precision} riemann={riemann} launch={launch} "
-        f"bc={bc} source={source} wedge={wedge} small_limit={small_limit}")
+        f"bc={bc} source={source} wedge={wedge} small_limit={small_limit} coop={coop}")
     s = ng.Solver(gas, nx, ny, U=U0, h=h, precision=precision, riemann=riemann, stiff_z=stiff_z,
                   bc=bc, source=source, wedge=wedge)
+    if coop is None and small_limit is not None:
+        coop = 0
+    if coop is not None:
+        s.set_coop(coop)
     if small_limit is not None:
         s.set_small_limit(small_limit)
     if launch:
@@ -204,7 +212,7 @@ def _smooth_state(gas, nx, ny):
 def test_smallest_and_narrow_grids(ng, shape):
     """The smallest grids the library accepts (4 cells per axis) and axes
     narrower than one 60-cell strip, on the persistent and the per-step
-    paths, periodic and with wall/outflow ends: FP64 and FP32 within the
+    paths (and the cooperative one in 1D), periodic and with wall/outflow ends: FP64 and FP32 within the
     parity bars.  The momenta decay to ~1e-4 of their start on the 4-cell
     axes (dt/tau > 1 there: the stiff branch, whose expm1 may differ from
     libm's in the last bit), so they are measured against the larger of their
@@ -214,7 +222,7 @@ def test_smallest_and_narrow_grids(ng, shape):
     W = _smooth_state(gas, nx, ny)
     bcs = [(0, 0, 0, 0), (W_, O_, 0, 0) if ny == 1 else (W_, O_, O_, W_)]
     for bc in bcs:
-        for limit in (-1, 0):
+        for limit in ((None, -1, 0) if ny == 1 else (-1, 0)):
             U, ref, d, U0 = run_both(ng, gas, W, nx, ny, 60, ng.NG_FP64, small_limit=limit,
                                      bc=bc)
             assert d["steps"] == 60 and d["status"] == 0
@@ -303,8 +311,9 @@ def test_translation_invariance_on_gpu(ng):
 @pytest.mark.parametrize("case", ["1d_fp64", "1d_fp32", "2d_fp32", "2d_fp64_hll", "1d_mixed",
                                   "2d_mixed"])
 def test_persistent_small_path_equals_per_step_path(ng, case):
-    """Small solves run many steps per launch in one workgroup; the state is
-    bitwise that of one launch per step, and both match the oracle."""
+    """Small solves run many steps per launch in one workgroup (and a lone 1D
+    solve in the cooperative kernel); the state is bitwise that of one launch
+    per step, and all match the oracle."""
     gas = dict(wl.BASE_GAS, Q_T=2.0)
     riemann = 1 if case.endswith("hll") else 0
     prec = ng.NG_FP64 if "fp64" in case else (ng.NG_MIXED if "mixed" in case else ng.NG_FP32)
@@ -316,15 +325,16 @@ def test_persistent_small_path_equals_per_step_path(ng, case):
         W = wl.random_field_2d(gas, 64, np.random.Generator(np.random.PCG64(21)), kmax=6,
                                rms=2e-2)[:, :ny, :nx].copy()
     outs = []
-    for limit in (-1, 0):
+    for limit in ((-1, 0, None) if ny == 1 else (-1, 0)):
         U, ref, d, _ = run_both(ng, gas, W, nx, ny, 300, prec, riemann=riemann,
                                 small_limit=limit)
         outs.append((U, d))
         if prec == ng.NG_FP64:
             e = rel_linf(U[comps(ny)], ref["U"][comps(ny)])
             assert np.all(e <= FP64_TOL), e
-    assert np.array_equal(outs[0][0], outs[1][0])
-    assert outs[0][1]["t"] == outs[1][1]["t"] and outs[0][1]["steps"] == 300
+    for o in outs[1:]:
+        assert np.array_equal(outs[0][0], o[0])
+        assert outs[0][1]["t"] == o[1]["t"] and o[1]["steps"] == 300
     # run_to_time on the persistent path lands on t_end
     s = ng.Solver(gas, nx, ny, W=W, precision=prec, riemann=riemann)
     s.run_to_time(0.01)
@@ -347,6 +357,7 @@ def test_fused_accept_equals_separate_finalize(ng):
             res = []
             for fused in (True, False):
                 s = ng.Solver(gas, nx, ny, W=W, precision=prec)
+                s.set_coop(0)
                 s.set_small_limit(0)
                 s.set_fused_accept(fused)
                 s.step(40)
@@ -382,7 +393,7 @@ def _moving_state(gas, nx, ny, seed):
 
 
 @pytest.mark.parametrize("bc", BC_CASES_1D)
-@pytest.mark.parametrize("small_limit", [None, 0])
+@pytest.mark.parametrize("small_limit", [None, -1, 0])
 def test_fp64_1d_boundaries_bitwise(ng, bc, small_limit):
     gas = dict(wl.BASE_GAS, Q_T=2.0)
     n = 1500
@@ -415,7 +426,7 @@ def test_fp64_2d_boundaries_small_path_bitwise(ng):
     assert np.array_equal(U, ref["U"]), rel_linf(U, ref["U"])
 
 
-@pytest.mark.parametrize("small_limit", [None, 0])
+@pytest.mark.parametrize("small_limit", [None, -1, 0])
 def test_fp64_woodward_colella_bitwise(ng, small_limit):
     """Section 2.4's interacting blast waves between walls (Euler limit,
     n = 1000) to t = 0.038, about 3900 steps through strong shocks."""
@@ -566,7 +577,7 @@ def _sink_case(ny):
 
 
 @pytest.mark.parametrize("ny", [1, 40])
-@pytest.mark.parametrize("small_limit", [None, 0])
+@pytest.mark.parametrize("small_limit", [None, -1, 0])
 def test_fp64_rejected_step_keeps_last_good_state(ng, ny, small_limit):
     """The step that produces p <= 0 is rejected at the oracle's step; the
     solve keeps the oracle's last good state bit for bit and does not move on."""
@@ -580,6 +591,7 @@ def test_fp64_rejected_step_keeps_last_good_state(ng, ny, small_limit):
     say(f"sink case ny={ny} small_limit={small_limit}: oracle stops after {ref['steps']} steps")
     s = ng.Solver(gas, n, ny if ny > 1 else 1, U=U0, precision=ng.NG_FP64)
     if small_limit is not None:
+        s.set_coop(0)
         s.set_small_limit(small_limit)
     with pytest.raises(ng.NgError) as err:
         s.run_to_time(10.0, 2000)
