@@ -98,10 +98,12 @@ WARMUP_SECONDS = 0.3
 REPS = 5
 
 
-# steps per captured HIP graph (ng_set_graph_steps); --no-graphs makes it
-# larger than any run, so that every step is a direct launch (counter passes
-# of rocprofv3 run that way)
+# steps per captured HIP graph (ng_set_graph_steps); --no-graphs sets the
+# library's largest value, 4096, which no call of the timed legs reaches
+# (they issue at most a few hundred steps per call), so that every step is a
+# direct launch (counter passes of rocprofv3 run that way)
 GRAPH_STEPS = None
+NO_GRAPH_STEPS = 4096
 
 
 def setup_solver(s):
@@ -319,7 +321,7 @@ def main():
     args = ap.parse_args()
     if args.no_graphs:
         global GRAPH_STEPS
-        GRAPH_STEPS = 1 << 30
+        GRAPH_STEPS = NO_GRAPH_STEPS
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

@@ -217,7 +217,10 @@ int ng_get_conserved(ng_solver* s, double* cons_out);
  * -1 in 1D, 4 in 2D).  2D rows below 4 and other values: EINVAL. */
 int ng_set_launch(ng_solver* s, int32_t rows_per_item, int32_t waves_per_block);
 
-/* Steps per captured graph in ng_run_to_time (default 64). */
+/* Steps per captured graph (default 64, 1 to 4096): calls of ng_step and
+ * ng_run_to_time replay whole graphs of this many steps and launch the rest
+ * directly.  Waits for the steps in flight when a graph exists.  EINVAL
+ * outside 1..4096. */
 int ng_set_graph_steps(ng_solver* s, int32_t steps);
 
 /* Solves of at most max_cells cells are advanced by a persistent kernel in

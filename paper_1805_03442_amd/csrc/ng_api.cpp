@@ -287,7 +287,7 @@ struct ng_batch {
     int64_t coop_limit = -1;   // cells; -1: kCoopCells, 0: cooperative path off
     int32_t coop_spin = kCoopSpin;
     int coop_slot = -1;        // the solve the cooperative kernel advances, or -1
-    int coop_grid = 0, coop_waves = 0, coop_rows = 1, coop_variant = 0;
+    int coop_grid = 0, coop_waves = 0, coop_variant = 0;
     int dev_coop = -1;         // cooperative launch supported (-1: not asked yet)
     int dev_cus = 0;
     int fused = 1;             // step kernels accept their own step (last workgroup)
@@ -357,9 +357,13 @@ int dev_err(ng_batch* b, hipError_t e, const char* what)
         if (e_ != hipSuccess) return dev_err((b), e_, #call); \
     } while (0)
 
+// Destroy the captured step sequence; launches of it may still be in flight
+// on the batch stream (ng_set_graph_steps, a new length in ensure_graph), so
+// the stream is drained first.
 void drop_graph(ng_batch* b)
 {
     if (b->gexec) {
+        (void)hipStreamSynchronize(b->stream);
         (void)hipGraphExecDestroy(b->gexec);
         b->gexec = nullptr;
     }
@@ -467,7 +471,7 @@ void shape_solve(ng_batch* b, Slot& s, bool alone = true)
     if (s.small)
         d.rows_per_item = dim == 2 ? kSmallRows2D : kSmallSegs1D;
     else if (s.coop)
-        d.rows_per_item = b->coop_rows;
+        d.rows_per_item = 1;
     else if (b->rows[dim] != kAutoRows)
         d.rows_per_item = b->rows[dim];
     else if (b->auto_rows[dim] > 0)
@@ -490,8 +494,8 @@ void shape_solve(ng_batch* b, Slot& s, bool alone = true)
 // launch shape: while the 60-cell segments fit one per wave in workgroups of
 // kCoopSmallWaves waves (one per SIMD) with at most one workgroup per CU,
 // that; else workgroups of the kernel's largest size, as many as stay
-// resident together, each wave taking an equal run of consecutive segments
-// (so that the march's prefetch of the next segment covers the run).
+// resident together (and have a segment for every wave); the kernel deals
+// the segments to the waves in turn.
 int choose_coop(ng_batch* b)
 {
     b->coop_slot = -1;
@@ -522,22 +526,18 @@ int choose_coop(ng_batch* b)
     int per_cu = 0, maxw = 0;
     CK(b, coop_capacity(kind, v, kCoopSmallWaves, &per_cu, &maxw));
     int waves = kCoopSmallWaves;
-    int64_t rows = 1;
     if (segs > (int64_t)kCoopSmallWaves * b->dev_cus) {
         waves = maxw;
         CK(b, coop_capacity(kind, v, waves, &per_cu, &maxw));
-        rows = cdiv(segs, (int64_t)per_cu * b->dev_cus * waves);
     }
     const int64_t resident = (int64_t)per_cu * b->dev_cus;
-    const int64_t items = cdiv(segs, rows);
-    const int64_t grid = std::min<int64_t>(cdiv(items, waves), resident);
+    const int64_t grid = std::min<int64_t>(cdiv(segs, waves), resident);
     if (grid < 1 || coop_space((uint64_t)grid) > (uint64_t)s.partial_cap * sizeof(Partial))
         return NG_OK;
     s.coop = true;
     b->coop_slot = cand;
     b->coop_grid = (int)grid;
     b->coop_waves = waves;
-    b->coop_rows = (int)rows;
     b->coop_variant = v;
     return NG_OK;
 }

@@ -996,12 +996,15 @@ __global__ void __launch_bounds__(256, P::kMinWaves) step2d_kernel(const InstDes
 
 // ================================================================ 1D step
 
-// One work item of the 1D step: a group of consecutive 60-cell segments.
-// Coh: agent-scope state loads and stores (Planes).
+// One work item of the 1D step: a group of consecutive 60-cell segments, or
+// with first >= 0 the segments first .. end-1 (the cooperative kernel's share
+// of a wave).  The next segment's load is issued before the current one is
+// computed.  Coh: agent-scope state loads and stores (Planes).
 template <class P, int RS, bool BC, int CL = 0, bool Coh = false>
 __device__ __forceinline__ void march1d(const InstDesc& d, const typename P::K& k, int cur,
                                         const double* gsrc, int64_t item, int lane,
-                                        Acc<typename P::R>& acc)
+                                        Acc<typename P::R>& acc, int64_t first = -1,
+                                        int64_t end = -1)
 {
     using R = typename P::R;
     constexpr int NC = 4;
@@ -1010,8 +1013,10 @@ __device__ __forceinline__ void march1d(const InstDesc& d, const typename P::K& 
     using St = typename P::St;
     const Planes<St, NC, Coh> src(d.buf[cur], n);
     const Planes<St, NC, Coh> dst(d.buf[cur ^ 1], n);
-    const int64_t s0 = item * d.rows_per_item;
-    const int64_t s1 = s0 + d.rows_per_item < d.nstrips ? s0 + d.rows_per_item : d.nstrips;
+    const int64_t s0 = first >= 0 ? first : item * d.rows_per_item;
+    const int64_t s1 = first >= 0 ? end
+                                  : (s0 + d.rows_per_item < d.nstrips ? s0 + d.rows_per_item
+                                                                      : d.nstrips);
     auto boff = [&](int64_t sg) -> uint32_t {
         bool f;
         const int64_t x = BC ? axis_cell(sg * kInterior - kHalo + lane, n, d.bc[0], d.bc[1], f)
@@ -1078,28 +1083,30 @@ __device__ __forceinline__ void march1d(const InstDesc& d, const typename P::K& 
 template <class P, int RS, bool Coh = false>
 __device__ __forceinline__ void march1d_bc(const InstDesc& d, const typename P::K& k, int cur,
                                            const double* gsrc,
-                                           int64_t item, int lane, Acc<typename P::R>& acc)
+                                           int64_t item, int lane, Acc<typename P::R>& acc,
+                                           int64_t first = -1, int64_t end = -1)
 {
     if (d.any_bc)
-        march1d<P, RS, true, 0, Coh>(d, k, cur, gsrc, item, lane, acc);
+        march1d<P, RS, true, 0, Coh>(d, k, cur, gsrc, item, lane, acc, first, end);
     else
-        march1d<P, RS, false, 0, Coh>(d, k, cur, gsrc, item, lane, acc);
+        march1d<P, RS, false, 0, Coh>(d, k, cur, gsrc, item, lane, acc, first, end);
 }
 
 // the 1D counterpart of march2d_hllc
 template <class P, int CL = kRecipes, bool Coh = false>
 __device__ __forceinline__ void march1d_hllc(const InstDesc& d, const typename P::K& k, int cur,
                                              const double* gsrc, int64_t item, int lane,
-                                             Acc<typename P::R>& acc)
+                                             Acc<typename P::R>& acc, int64_t first = -1,
+                                             int64_t end = -1)
 {
     if constexpr (P::kRecipes && CL > 0) {
         if (!d.any_bc && d.cl_recipe == CL) {
-            march1d<P, 0, false, CL, Coh>(d, k, cur, gsrc, item, lane, acc);
+            march1d<P, 0, false, CL, Coh>(d, k, cur, gsrc, item, lane, acc, first, end);
             return;
         }
-        march1d_hllc<P, CL - 1, Coh>(d, k, cur, gsrc, item, lane, acc);
+        march1d_hllc<P, CL - 1, Coh>(d, k, cur, gsrc, item, lane, acc, first, end);
     } else {
-        march1d_bc<P, 0, Coh>(d, k, cur, gsrc, item, lane, acc);
+        march1d_bc<P, 0, Coh>(d, k, cur, gsrc, item, lane, acc, first, end);
     }
 }
 
@@ -1294,7 +1301,9 @@ __device__ __forceinline__ void wait_mem() { __builtin_amdgcn_s_waitcnt(0x0070);
 // One 1D solve advanced through up to nsteps steps by one cooperative launch
 // of G workgroups that stay resident together (no launch per step).  Every
 // workgroup tracks the solve's control (t, steps, buffer, CFL step) itself,
-// alike.  Each step it marches its share of the 60-cell segments with
+// alike.  Each step its waves march their segments (wave g of the W in the
+// launch takes the run [g S / W, (g + 1) S / W) of the S segments: equal
+// counts to within one, neighbours' halos in the same cache lines) with
 // agent-scope state loads and stores (the stores write through to memory and
 // the loads never take a stale line of its own XCD's L2), reduces its signal
 // speed and failure flags, stores them to its slot, waits for the stores and
@@ -1357,13 +1366,17 @@ __global__ void __launch_bounds__(P::kCoopThreads) run_coop1d_kernel(
         const typename P::K k = P::make(d, dt);
         Acc<R> acc;
         acc_init(acc);
-        for (int64_t item = (int64_t)b * nw + wave; item < d.nitems; item += (int64_t)G * nw) {
+        // this wave's run of consecutive segments: the equal share
+        // [g S / W, (g + 1) S / W) of the S segments over the launch's W waves
+        const int64_t W = (int64_t)G * nw, gw = (int64_t)b * nw + wave;
+        const int64_t f0 = gw * d.nstrips / W, f1 = (gw + 1) * d.nstrips / W;
+        if (f0 < f1) {
             if constexpr (V > 0)
-                march1d<P, 0, false, V - 1, true>(d, k, cur, nullptr, item, lane, acc);
+                march1d<P, 0, false, V - 1, true>(d, k, cur, nullptr, 0, lane, acc, f0, f1);
             else if (d.riemann == 1)
-                march1d_bc<P, 1, true>(d, k, cur, nullptr, item, lane, acc);
+                march1d_bc<P, 1, true>(d, k, cur, nullptr, 0, lane, acc, f0, f1);
             else
-                march1d_hllc<P, kRecipes, true>(d, k, cur, nullptr, item, lane, acc);
+                march1d_hllc<P, kRecipes, true>(d, k, cur, nullptr, 0, lane, acc, f0, f1);
         }
         acc_finish<P>(acc, k);
         // the barrier needs only the signal speed and the failure flags

@@ -22,3 +22,12 @@ def test_host_cpu_record():
     h = bench.host_cpu()
     assert h["cores_available"] >= 1
     assert h["model"] is None or isinstance(h["model"], str)
+
+
+def test_no_graphs_value_is_accepted_by_the_library():
+    """--no-graphs sets the library's largest graph length, which every timed
+    call stays below (so each step is a direct launch); ng_set_graph_steps
+    accepts 1..4096."""
+    sys.path.insert(0, ROOT)
+    import bench
+    assert 1 <= bench.NO_GRAPH_STEPS <= 4096
