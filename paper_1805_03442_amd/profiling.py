@@ -125,7 +125,7 @@ def main(argv=None):
     b = sub.add_parser("traffic")
     b.add_argument("fetch_csv")
     b.add_argument("write_csv")
-    b.add_argument("--kernel", default="step2d_kernel<ng::Dev32<5> >")
+    b.add_argument("--kernel", default="step2d_kernel<ng::Dev32<5>")
     b.add_argument("--copy-bytes", type=int, default=1 << 30)
     b.add_argument("--alg-bytes", type=float, default=40.0 * 4096 * 4096)
     b.add_argument("--command", required=True)
@@ -133,7 +133,7 @@ def main(argv=None):
     b.add_argument("--out-md", required=True)
     c = sub.add_parser("counters")
     c.add_argument("csv")
-    c.add_argument("--kernel", default="step2d_kernel<ng::Dev32<5> >")
+    c.add_argument("--kernel", default="step2d_kernel<ng::Dev32<5>")
     c.add_argument("--command", required=True)
     c.add_argument("--out", required=True)
     c.add_argument("--out-json", default=None)
