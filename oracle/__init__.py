@@ -4,9 +4,11 @@ TEST INFRASTRUCTURE.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
 ``cpu_baseline`` leg of ``bench.py`` may import this package.  The HIP library
 shares no code with it, and the product path never calls it.
 
-The arithmetic lives in ``muscl_oracle.c`` (plain C, FP64, built with
-``-ffp-contract=off``); this module only builds it and marshals arrays through
-ctypes.  Each function cites the passage of the paper it follows in the C file.
+The arithmetic lives in ``muscl_oracle.c`` (the MUSCL step, eq. (15)) and
+``csph_oracle.c`` (the CSPH-TVD step, eqs. (9)-(14), 1D), plain C in FP64
+built with ``-ffp-contract=off`` into one library; this module only builds it
+and marshals arrays through ctypes.  Each function cites the passage of the
+paper it follows in the C files.
 
 Arrays: a state is ``U[5, ny, nx]`` (rho, rho*u, rho*v, E, E_nu), FP64; a 1D
 problem is ``ny == 1`` with ``rho*v == 0``.
@@ -20,7 +22,8 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "muscl_oracle.c")
+_SRC = os.path.join(_HERE, "csph_oracle.c")      # includes muscl_oracle.c
+_SRCS = [_SRC, os.path.join(_HERE, "muscl_oracle.c")]
 _LIB = os.environ.get("NG_ORACLE_LIB") or os.path.join(_HERE, "_build", "liboracle.so")
 
 BC_PERIODIC, BC_WALL, BC_OUTFLOW, BC_SOURCE = 0, 1, 2, 3
@@ -49,10 +52,11 @@ class OrNum(C.Structure):
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (serial, -O2, no FMA contraction)."""
     os.makedirs(os.path.dirname(_LIB), exist_ok=True)
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if (force or not os.path.exists(_LIB)
+            or os.path.getmtime(_LIB) < max(os.path.getmtime(f) for f in _SRCS)):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-                               "-shared", "-o", tmp, _SRC, "-lm"])
+                               "-shared", "-I", _HERE, "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -84,6 +88,14 @@ def lib():
         L.or_cons_to_prim.argtypes = [C.POINTER(OrGas), C.c_int64, dp, dp]
         L.or_face_flux.argtypes = [C.POINTER(OrGas), C.c_int32, dp, dp, dp]
         L.or_source.argtypes = [C.POINTER(OrGas), dp, dp]
+        # the CSPH-TVD entry points (absent from a build of the MUSCL file alone,
+        # as the MUSCL mutation tests make)
+        if hasattr(L, "cs_step"):
+            L.cs_step.argtypes = [C.POINTER(OrGas), C.POINTER(OrGrid), C.POINTER(OrNum), dp,
+                                  dp, C.c_double, dp, dp]
+            L.cs_step.restype = C.c_int
+            L.cs_run.argtypes = L.or_run.argtypes
+            L.cs_run.restype = C.c_int
         _lib = L
     return _lib
 
@@ -176,6 +188,42 @@ class Problem:
         budget = np.zeros(2)
         dt_last = C.c_double(0.0)
         st = lib().or_run(C.byref(self._g), C.byref(self._gr), C.byref(self._nm), _p(U),
+                          int(nsteps), float(t_end), C.byref(t), C.byref(steps), _p(budget),
+                          C.byref(dt_last))
+        return dict(status=st, U=U, t=t.value, steps=steps.value, budget=budget,
+                    dt_last=dt_last.value)
+
+
+class CsphProblem(Problem):
+    """The CSPH-TVD scheme of section 2.3 (eqs. (9)-(14)) on a 1D grid with
+    periodic, wall or outflow ends: same gas, grid, time step (eq. (16)) and
+    state layout as ``Problem``; ``riemann`` and ``stiff_z`` are not used (HLL,
+    explicit sources)."""
+
+    def __init__(self, gas: dict, nx: int, h: float | None = None, cfl: float = 0.4,
+                 bc=(BC_PERIODIC,) * 4):
+        super().__init__(gas, nx, 1, h=h, cfl=cfl, riemann=HLL, bc=bc)
+
+    def step(self, U: np.ndarray, dt: float, t: float = 0.0, xi: bool = False):
+        """One step with a given dt.  Returns (status, U_new, src[2]), and with
+        ``xi`` also the particles' displacements at the end of the Lagrangian
+        stage (eq. (11)), one per cell."""
+        U = np.ascontiguousarray(U, dtype=np.float64).reshape(5, 1, self.nx)
+        V = np.empty_like(U)
+        src = np.zeros(2)
+        X = np.zeros(self.nx)
+        st = lib().cs_step(C.byref(self._g), C.byref(self._gr), C.byref(self._nm), _p(U),
+                           _p(V), float(dt), _p(src), _p(X) if xi else None)
+        return (st, V, src, X) if xi else (st, V, src)
+
+    def run(self, U: np.ndarray, nsteps: int, t0: float = 0.0, t_end: float = 0.0):
+        """As ``Problem.run`` with the CSPH-TVD step."""
+        U = np.array(U, dtype=np.float64, copy=True).reshape(5, 1, self.nx)
+        t = C.c_double(t0)
+        steps = C.c_int64(0)
+        budget = np.zeros(2)
+        dt_last = C.c_double(0.0)
+        st = lib().cs_run(C.byref(self._g), C.byref(self._gr), C.byref(self._nm), _p(U),
                           int(nsteps), float(t_end), C.byref(t), C.byref(steps), _p(budget),
                           C.byref(dt_last))
         return dict(status=st, U=U, t=t.value, steps=steps.value, budget=budget,

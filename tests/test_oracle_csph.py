@@ -1,0 +1,287 @@
+"""Pins of the CSPH-TVD oracle (section 2.3, eqs. (9)-(14), 1D) against what
+the paper and the mathematics fix: the exact Riemann solution (Sod), the
+roots of the linearised system (sound frequency and decay), exact
+conservation (the SPH pair terms are antisymmetric and the fluxes
+telescope), the discrete source budget, uniform steady states, mirror
+symmetry and walls, and the consistency of the SPH pressure force with
+-dp/dx.  Each is chosen so that a plausible slip in the scheme (a sign, the
+kernel's normalisation, the pair velocity, the averaging of the corrector,
+the displacement in the face values) fails at least one of them
+(tests/test_oracle_csph_mutations.py plants such slips).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from mathref import dispersion as D
+from mathref import exact_riemann as ER
+from paper_1805_03442_amd import workloads as wl
+
+EULER_GAS = dict(gamma=1.4, R=1.0, Cv=0.0, rho0=1.0, T0=1.0, tau0=1.0, tau_rho=0.0,
+                 tau_T=0.0, Q0=0.0, Q_rho=0.0, Q_T=0.0, I0=0.0, I_rho=0.0, I_T=0.0,
+                 fx=0.0, fy=0.0)
+
+
+def _run(oracle_lib, gas, W, nsteps=10 ** 7, t_end=0.0, bc=(0, 0, 0, 0), h=None):
+    n = W.shape[-1]
+    P = oracle_lib.CsphProblem(gas, n, h=h, bc=bc)
+    U0 = P.prim_to_cons(W)
+    r = P.run(U0, nsteps, t_end=t_end)
+    assert r["status"] == 0
+    return P, U0, r
+
+
+def test_sod_converges_to_the_exact_solution(oracle_lib):
+    """Periodic top hat: on [1/2, 1) the Sod problem about x = 3/4 until
+    t = 0.1.  L1 density error against the exact solution falls with every
+    doubling (shocks and the contact allow about first order); the plateaus
+    between the fan and the contact and between the contact and the shock
+    hold the exact star states; the other interface gives the mirror
+    image."""
+    left, right = (1.0, 0.0, 1.0), (0.125, 0.0, 0.1)
+    st = ER.star_state(left, right, 1.4)
+    errs = []
+    for n in (256, 512, 1024, 2048):
+        W = wl.riemann_tophat(EULER_GAS, n, left + (0.0,), right + (0.0,))
+        P, _, r = _run(oracle_lib, EULER_GAS, W, t_end=0.1)
+        assert r["t"] == pytest.approx(0.1, abs=1e-15)
+        Wf = P.cons_to_prim(r["U"])[:, 0, :]
+        x = wl.cell_centres(n)
+        sel = x >= 0.5
+        rho_ex, _, _ = ER.sample(left, right, 1.4, (x[sel] - 0.75) / 0.1)
+        errs.append(np.sum(np.abs(Wf[0, sel] - rho_ex)) / n)
+        if n == 2048:
+            t = 0.1
+            xc = 0.75 + st["u"] * t
+            x1 = 0.5 * ((0.75 + st["tail_L"] * t) + xc)
+            x2 = 0.5 * (xc + (0.75 + st["shock_R"] * t))
+            for xm, rho_ref in ((x1, st["rho_L"]), (x2, st["rho_R"])):
+                j = int(xm * n)
+                assert abs(Wf[0, j] - rho_ref) < 1e-3
+                assert abs(Wf[3, j] - st["p"]) < 1e-4
+                assert abs(Wf[1, j] - st["u"]) < 1e-4
+            Wm = Wf[:, ::-1]
+            assert np.max(np.abs(Wm[0] - Wf[0])) < 1e-12
+            assert np.max(np.abs(Wm[1] + Wf[1])) < 1e-12
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    assert min(orders) > 0.7, (errs, orders)
+
+
+def _random_state(gas, n, seed):
+    r = np.random.Generator(np.random.PCG64(seed))
+    x = wl.cell_centres(n)
+    W = wl.uniform_state(gas, n)
+    b = wl.background(gas)
+    W[0, 0] = b["rho"] * (1.0 + 0.2 * np.sin(2 * np.pi * x + r.uniform(0, 6))
+                          + 0.05 * r.standard_normal(n))
+    W[1, 0] = 0.2 * np.sin(4 * np.pi * x + r.uniform(0, 6))
+    W[3, 0] = b["p"] * (1.0 + 0.2 * np.cos(2 * np.pi * x) + 0.05 * r.standard_normal(n))
+    W[3, 0, n // 3:n // 2] *= 1.5       # a pressure jump
+    return W
+
+
+@pytest.mark.parametrize("gas_name", ["euler", "base_qt2"])
+def test_conservation_and_source_budget(oracle_lib, gas_name):
+    """Periodic, 60 steps: mass and momentum are conserved to rounding (the
+    SPH force's pair terms cancel, the fluxes telescope); the energy and E_nu
+    totals change by exactly the summed source increments of the steps
+    (zero for the Euler gas)."""
+    gas = EULER_GAS if gas_name == "euler" else dict(wl.BASE_GAS, Q_T=2.0)
+    n = 300
+    W = _random_state(gas, n, 3)
+    P, U0, r = _run(oracle_lib, gas, W, nsteps=60)
+    U1 = r["U"]
+    scale = np.abs(U0).sum(axis=(1, 2))
+    for c in (0, 1):
+        assert abs(U1[c].sum() - U0[c].sum()) <= 1e-13 * scale[c], c
+    dE = U1[3].sum() - U0[3].sum()
+    dV = U1[4].sum() - U0[4].sum()
+    assert abs(dE - r["budget"][0]) <= 1e-12 * scale[3]
+    assert abs(dV - r["budget"][1]) <= 1e-12 * scale[4]
+    if gas_name == "euler":
+        assert r["budget"][0] == 0.0
+        assert abs(dE) <= 1e-13 * scale[3]
+    else:
+        assert abs(dE) > 1e-6 * scale[3]    # the sources do act
+
+
+def test_uniform_states_stay_put(oracle_lib):
+    """The pumped steady background of the base gas (E_nu = E_nue + tau rho
+    Q, Q = I) at rest, and a uniform flow of the Euler gas, stay uniform and
+    unchanged to rounding."""
+    n = 90
+    gas = dict(wl.BASE_GAS)
+    W = wl.uniform_state(gas, n)
+    P, U0, r = _run(oracle_lib, gas, W, nsteps=30)
+    assert np.max(np.abs(r["U"] - U0)) <= 1e-13
+    W = wl.uniform_state(EULER_GAS, n)
+    W[1] = 0.3
+    P, U0, r = _run(oracle_lib, EULER_GAS, W, nsteps=30)
+    assert np.max(np.abs(r["U"] - U0)) <= 1e-13
+
+
+@pytest.mark.parametrize("u0,bc", [(0.4, (0, 0, 0, 0)), (0.0, (1, 1, 0, 0))],
+                         ids=["periodic_moving", "walls_at_rest"])
+def test_lagrangian_stage_is_exact_under_uniform_acceleration(oracle_lib, u0, bc):
+    """A uniform gas under a constant body force f: the pressure forces
+    cancel pair by pair, every particle accelerates at f, and the
+    predictor-corrector of eqs. (10)-(11) (positions advanced with the mean
+    of the end velocities, a trapezoidal rule) is exact for a velocity
+    linear in time: the displacement after one step is u0 dt + f dt^2 / 2
+    and the velocity u0 + f dt, with the density unchanged."""
+    n, f, dt = 40, 7.0, 0.01
+    gas = dict(EULER_GAS, fx=f)
+    W = wl.uniform_state(gas, n)
+    W[0] = 1.3
+    W[1] = u0
+    W[3] = 0.9
+    P = oracle_lib.CsphProblem(gas, n, bc=bc)
+    st, V, _, xi = P.step(P.prim_to_cons(W), dt, xi=True)
+    assert st == 0
+    x_ex = u0 * dt + 0.5 * f * dt * dt
+    assert np.max(np.abs(xi - x_ex)) <= 1e-15
+    Wf = P.cons_to_prim(V)[:, 0, :]
+    assert np.max(np.abs(Wf[0] - 1.3)) <= 1e-14
+    assert np.max(np.abs(Wf[1] - (u0 + f * dt))) <= 1e-14
+
+
+def _fit_rate(oracle_lib, gas, n, mode, t_end, nsamp=8, amp=1e-6):
+    k = 2 * math.pi * mode
+    om, vec = D.acoustic_mode(gas, k, +1)
+    W = wl.acoustic_mode_1d(gas, n, mode, amp, mode_vector=vec)
+    P = oracle_lib.CsphProblem(gas, n)
+    U = P.prim_to_cons(W)
+    x = wl.cell_centres(n)
+    b = wl.background(gas)
+    ts, amps, phs = [], [], []
+    t = 0.0
+    for i in range(nsamp + 1):
+        if i > 0:
+            r = P.run(U, 10 ** 7, t0=t, t_end=t_end * i / nsamp)
+            assert r["status"] == 0
+            U, t = r["U"], r["t"]
+        a = np.sum((U[0, 0] - b["rho"]) * np.exp(-1j * k * x)) * 2.0 / n
+        ts.append(t)
+        amps.append(abs(a))
+        phs.append(np.angle(a))
+    rate = np.polyfit(ts, np.log(amps), 1)[0]
+    freq = -np.polyfit(ts, np.unwrap(phs), 1)[0]
+    return om, rate, freq
+
+
+def test_sound_waves_against_the_linearised_system(oracle_lib):
+    """A small sound wave (base gas, k = 8 pi) runs at the frequency of the
+    acoustic root of the linearised system of eqs. (1)-(7) (within 5e-4 at
+    512 cells, converging) and decays at its rate plus the scheme's own
+    damping, which halves with every doubling of the resolution."""
+    gas = dict(wl.BASE_GAS)
+    res = {n: _fit_rate(oracle_lib, gas, n, 4, 0.3) for n in (256, 512)}
+    om = res[512][0]
+    assert abs(res[512][2] / om.real - 1.0) < 5e-4
+    assert abs(res[256][2] / om.real - 1.0) > abs(res[512][2] / om.real - 1.0)
+    e256 = res[256][1] - om.imag
+    e512 = res[512][1] - om.imag
+    assert e256 < 0 and e512 < 0                 # the scheme damps
+    assert 1.7 < e256 / e512 < 2.6, (e256, e512)  # first order
+    assert abs(e512) < 0.25 * abs(om.imag)
+
+
+def _self_convergence(oracle_lib, make, ns=(128, 256, 512), nref=2048, t_end=0.2):
+    def run(n):
+        gas, W = make(n)
+        _, _, r = _run(oracle_lib, gas, W, t_end=t_end)
+        return r["U"][:, 0, :]
+    ref = run(nref)
+    es = []
+    for n in ns:
+        U = run(n)
+        R = ref.reshape(5, n, nref // n).mean(axis=2)
+        es.append(np.abs(U[0] - R[0]).mean())
+    return [math.log2(es[i] / es[i + 1]) for i in range(len(es) - 1)]
+
+
+def test_advection_is_second_order_and_sound_first(oracle_lib):
+    """Smooth flows, self-convergence of the density.  Pure advection (uniform
+    pressure and velocity: only the Eulerian stage acts, through the
+    displaced linear profiles of eq. (14)) converges at second order.  A
+    sound wave converges at first order: the Lagrangian stage moves the
+    pressure with the density frozen (no mass row in eq. (12)), and the
+    Eulerian stage adds the advective part of the compression afterwards."""
+    def advect(n):
+        x = wl.cell_centres(n)
+        W = np.zeros((5, 1, n))
+        W[0, 0] = 1.0 + 0.2 * np.sin(2 * np.pi * x)
+        W[1, 0] = 0.5
+        W[3, 0] = 1.0
+        return EULER_GAS, W
+
+    def sound(n):
+        om, vec = D.acoustic_mode(EULER_GAS, 2 * math.pi, +1)
+        return EULER_GAS, wl.acoustic_mode_1d(EULER_GAS, n, 1, 1e-2, mode_vector=vec)
+
+    oa = _self_convergence(oracle_lib, advect)
+    assert min(oa) > 1.8, oa
+    os_ = _self_convergence(oracle_lib, sound)
+    assert 0.9 < min(os_) and max(os_) < 1.5, os_
+
+
+def test_first_step_matches_the_divergences(oracle_lib):
+    """One step with a vanishing dt: the momentum gained at rest is the SPH
+    pressure force, -dp/dx of the cell averages to second order (this fixes
+    the kernel's normalisation, the particle volume and the sign); with a
+    velocity field at uniform pressure, the mass and energy changes are
+    -d(rho u)/dx and -d(u (E + p))/dx (pressure work of the pairs plus the
+    advective flux), converging at least at first order at the extrema."""
+    errs = []
+    for n in (64, 128, 256):
+        x = wl.cell_centres(n)
+        h = 1.0 / n
+        P = oracle_lib.CsphProblem(EULER_GAS, n)
+        dt = 1e-9
+        W = np.zeros((5, 1, n))
+        W[0, 0] = 1.0 + 0.1 * np.sin(2 * np.pi * x)
+        W[3, 0] = 1.0 + 0.2 * np.cos(2 * np.pi * x)
+        st, V, _ = P.step(P.prim_to_cons(W), dt)
+        assert st == 0
+        pa = (0.2 * np.cos(2 * np.pi * (x + h / 2)) - 0.2 * np.cos(2 * np.pi * (x - h / 2))) / h
+        e1 = np.max(np.abs(V[1, 0] / dt + pa)) / np.max(np.abs(pa))
+        W2 = np.zeros((5, 1, n))
+        W2[0, 0] = 1.0
+        W2[1, 0] = 0.1 * np.sin(2 * np.pi * x)
+        W2[3, 0] = 1.0
+        U2 = P.prim_to_cons(W2)
+        st, V2, _ = P.step(U2, dt)
+
+        def fe(xx):
+            u = 0.1 * np.sin(2 * np.pi * xx)
+            return u * (1.0 / 0.4 + 0.5 * u * u + 1.0)
+        dE = -(fe(x + h / 2) - fe(x - h / 2)) / h
+        e2 = np.max(np.abs((V2[3, 0] - U2[3, 0]) / dt - dE)) / np.max(np.abs(dE))
+        dr = -(0.1 * np.sin(2 * np.pi * (x + h / 2)) - 0.1 * np.sin(2 * np.pi * (x - h / 2))) / h
+        e3 = np.max(np.abs((V2[0, 0] - U2[0, 0]) / dt - dr)) / np.max(np.abs(dr))
+        errs.append((e1, e2, e3))
+    for i in range(2):
+        assert errs[i][0] / errs[i + 1][0] > 3.5, errs
+        assert errs[i][1] / errs[i + 1][1] > 1.8, errs
+        assert errs[i][2] / errs[i + 1][2] > 1.8, errs
+    assert errs[-1][0] < 2e-4 and errs[-1][1] < 1e-2 and errs[-1][2] < 1e-2, errs
+
+
+def test_walls_equal_the_mirrored_periodic_domain(oracle_lib):
+    """A domain between two reflecting walls equals one half of the periodic
+    domain of twice the length holding the mirror image (u reversed)."""
+    m = 120
+    gas = dict(wl.BASE_GAS, Q_T=2.0)
+    Wh = _random_state(gas, m, 7)
+    Wp = np.concatenate([Wh, Wh[:, :, ::-1]], axis=2)
+    Wp[1, 0, m:] *= -1.0
+    _, _, rp = _run(oracle_lib, gas, Wp, nsteps=80)
+    # the periodic run takes dt from the whole domain, which holds the same
+    # speeds as the walled half, so both take the same steps
+    _, _, rw = _run(oracle_lib, gas, Wh, nsteps=80, bc=(1, 1, 0, 0), h=1.0 / (2 * m))
+    a, b = rw["U"][:, 0, :], rp["U"][:, 0, :m]
+    scale = np.max(np.abs(b), axis=1)
+    for c in (0, 1, 3, 4):
+        assert np.max(np.abs(a[c] - b[c])) <= 1e-12 * scale[c], c
+    assert rw["t"] == rp["t"]
