@@ -8,7 +8,10 @@
  * (continuity, momentum, total energy, vibrational energy) with the closures
  * (6) and the ideal-gas EOS (7); the step is the MUSCL predictor-corrector of
  * eq. (15) with the limited linear face states of eq. (14) (xi = 0), the HLL
- * flux of eq. (13) or the HLLC flux, and the time step of eq. (16).
+ * flux of eq. (13) or the HLLC flux, and the time step of eq. (16).  1D
+ * solves can take the paper's other step instead, CSPH-TVD (section 2.3,
+ * eqs. (9)-(14)): a Lagrangian SPH predictor-corrector followed by an
+ * Eulerian HLL remap of the displaced particles (ng_numerics.scheme).
  *
  * Conventions for every call:
  *   - return NG_OK (0) on success or a negative NG_E* code; the text of the
@@ -70,6 +73,20 @@ extern "C" {
                             FP64 totals and FP64 stiff relaxation factor      */
 #define NG_MIXED 2       /* as NG_FP32, but the deviations are stored in FP64
                             and each step's FP32 increment is added in FP64   */
+#define NG_MUSCL 0       /* the Eulerian MUSCL step of eq. (15)                 */
+#define NG_CSPH_TVD 1    /* the CSPH-TVD step of section 2.3 (1D, NG_FP64,
+                            NG_HLL, no forced source): particles at the cell
+                            centres move by the predictor (10) and corrector
+                            (11) under eq. (12) -- SPH pressure force and work
+                            over the two neighbours with the cubic-spline
+                            kernel W of smoothing length h and particle volume
+                            h, phi = sqrt(2 p); body force, pump, sink and
+                            relaxation as in eqs. (2)-(4) -- and are remapped
+                            by eq. (9) with the HLL flux (13) of u U between
+                            the displaced face values of eq. (14), U^{n+1/2} =
+                            (U^n + U~)/2, Theta the minmod slopes of U^n per
+                            unit length.  Sources are explicit (stiff_z is not
+                            used); the time step is that of eq. (16)          */
 
 /* status flags of ng_diag.flags */
 #define NG_FLAG_NONFINITE 1u
@@ -127,13 +144,15 @@ typedef struct {
 /* cfl multiplies the bound of eq. (16); stiff_z is the dt/tau above which the
  * E_nu equation (4), relaxation and pump together, is integrated exactly over
  * the (half) step with E_nue, tau and Q frozen: E_nu relaxes toward
- * E_nue + tau rho Q by the factor exp(-dt/tau). */
+ * E_nue + tau rho Q by the factor exp(-dt/tau).  scheme: NG_MUSCL, or
+ * NG_CSPH_TVD with a 1D grid, NG_FP64, NG_HLL and no forced source (any other
+ * combination, or another value, is NG_EINVAL). */
 typedef struct {
     double cfl;
     int32_t riemann;   /* NG_HLLC or NG_HLL */
     int32_t limiter;   /* NG_MINMOD         */
     int32_t precision; /* NG_FP64, NG_FP32 or NG_MIXED */
-    int32_t reserved;
+    int32_t scheme;    /* NG_MUSCL or NG_CSPH_TVD     */
     double stiff_z;
 } ng_numerics;
 
@@ -231,7 +250,7 @@ int ng_set_graph_steps(ng_solver* s, int32_t steps);
 int ng_set_small_limit(ng_solver* s, int64_t max_cells);
 
 /* Cooperative path (the time loop of eq. (15) with the dt of eq. (16) chosen
- * after every step).  A solve that is alone in its object, 1D, without a
+ * after every step).  A MUSCL solve that is alone in its object, 1D, without a
  * forced source and of at most max_cells cells is advanced by one
  * cooperative launch per call (up to 65536 steps each): every step, its
  * workgroups -- all resident together -- update their segments, meet at a
@@ -273,7 +292,8 @@ const char* ng_last_error(const ng_solver* s);
 
 /* For callers that cannot allocate memory (code under HIP graph capture,
  * tight serving loops, harnesses that forbid hipMalloc): one step of eq. (15)
- * on an FP64 state in caller device memory, calling no hipMalloc, hipFree or
+ * (or, with num->scheme = NG_CSPH_TVD, one CSPH-TVD step of section 2.3) on an
+ * FP64 state in caller device memory, calling no hipMalloc, hipFree or
  * other allocating routine.  Its scratch -- the solve's descriptor and control
  * block, the workgroup table and the per-workgroup reduction records -- lives
  * in a static device array of 2 MiB that each GPU the library runs on holds

@@ -89,7 +89,9 @@ bool prec_ok(int prec) { return prec == NG_FP32 || prec == NG_FP64 || prec == NG
 // arithmetic on FP64 deviations
 int kind_of(int prec) { return prec == NG_FP64 ? 0 : (prec == NG_FP32 ? 1 : 2); }
 
-int64_t strips_of(const ng_grid* g) { return cdiv(g->nx, kInterior); }
+// strips (2D) or segments (1D) of a grid; 1D counts the shorter segments of
+// the CSPH-TVD step, the most either scheme gives
+int64_t strips_of(const ng_grid* g) { return cdiv(g->nx, g->ndim == 2 ? kInterior : kCsphInterior); }
 
 // most workgroups any allowed launch shape gives this grid (1 wave per block,
 // smallest rows per item)
@@ -209,6 +211,13 @@ int validate(const ng_gas* gas, const ng_grid* grid, const ng_numerics* num, std
     if (num->limiter != NG_MINMOD) { err = "unknown limiter"; return NG_EINVAL; }
     if (!prec_ok(num->precision)) { err = "unknown precision"; return NG_EINVAL; }
     if (!(num->stiff_z >= 0.0)) { err = "stiff_z must be >= 0"; return NG_EINVAL; }
+    if (num->scheme != NG_MUSCL && num->scheme != NG_CSPH_TVD) { err = "unknown scheme"; return NG_EINVAL; }
+    if (num->scheme == NG_CSPH_TVD &&
+        (grid->ndim != 1 || num->precision != NG_FP64 || num->riemann != NG_HLL ||
+         grid->bc[0] == NG_BC_SOURCE)) {
+        err = "the CSPH-TVD step needs a 1D grid, NG_FP64, NG_HLL and no forced source";
+        return NG_EINVAL;
+    }
     return NG_OK;
 }
 
@@ -340,6 +349,8 @@ struct ng_solver {
 };
 
 static_assert(NG_ESTALL == ng::kStatusStall, "status of a stalled cooperative launch");
+static_assert(NG_MUSCL == ng::kSchemeMuscl && NG_CSPH_TVD == ng::kSchemeCsph,
+              "schemes of the ABI and the kernels");
 static_assert(NG_BC_PERIODIC == ng::kBcPeriodic && NG_BC_WALL == ng::kBcWall &&
                   NG_BC_OUTFLOW == ng::kBcOutflow && NG_BC_SOURCE == ng::kBcSource,
               "boundary kinds of the ABI and the kernels");
@@ -478,7 +489,7 @@ void shape_solve(ng_batch* b, Slot& s, bool alone = true)
         d.rows_per_item = b->auto_rows[dim];
     else
         d.rows_per_item = auto_rows(dim, {{d.nx, d.ny}});
-    d.nstrips = (int32_t)cdiv(d.nx, kInterior);
+    d.nstrips = (int32_t)cdiv(d.nx, dim == 2 ? kInterior : seg_cells(d.scheme));
     if (dim == 2)
         d.nchunks = (int32_t)cdiv(d.ny, d.rows_per_item);
     else
@@ -510,7 +521,8 @@ int choose_coop(ng_batch* b)
     const int64_t lim = b->coop_limit >= 0 ? b->coop_limit : kCoopCells;
     if (live != 1 || lim == 0) return NG_OK;
     Slot& s = b->slots[cand];
-    if (s.dim != 1 || s.d.bc[0] == kBcSource || s.d.ncell > lim) return NG_OK;
+    if (s.dim != 1 || s.d.bc[0] == kBcSource || s.d.scheme != kSchemeMuscl || s.d.ncell > lim)
+        return NG_OK;
     if (b->dev_coop < 0) {
         int dev = 0, coop = 0, cus = 0;
         CK(b, hipGetDevice(&dev));
@@ -923,6 +935,7 @@ void fill_desc(InstDesc& d, const ng_gas* gas, const ng_grid* grid, const ng_num
     d.ncell = d.nx * d.ny;
     d.ndim = grid->ndim;
     d.riemann = num->riemann;
+    d.scheme = num->scheme;
     d.any_bc = 0;
     for (int i = 0; i < 4; i++) {
         d.bc[i] = (i < 2 || grid->ndim == 2) ? grid->bc[i] : NG_BC_PERIODIC;
@@ -1545,7 +1558,7 @@ int ng_step_static(const ng_gas* gas, const ng_grid* grid, const ng_numerics* nu
     fill_desc(d, gas, grid, num, NG_FP64);
     const int dim = grid->ndim;
     d.rows_per_item = auto_rows(dim, {{d.nx, d.ny}});
-    d.nstrips = (int32_t)cdiv(d.nx, kInterior);
+    d.nstrips = (int32_t)cdiv(d.nx, dim == 2 ? kInterior : seg_cells(d.scheme));
     d.nchunks = (int32_t)(dim == 2 ? cdiv(d.ny, d.rows_per_item) : cdiv(d.nstrips, d.rows_per_item));
     d.nitems = dim == 2 ? (int64_t)d.nstrips * d.nchunks : (int64_t)d.nchunks;
     d.waves_per_block = dim == 2 ? kDefaultWaves2D : (d.nitems < kAutoItems1DWaves ? 2 : 4);

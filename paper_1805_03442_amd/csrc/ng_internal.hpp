@@ -18,6 +18,19 @@ constexpr int kHalo = 2;           // ghost cells per side of the stencil
 constexpr int kInterior = kWave - 2 * kHalo;  // cells a wave updates per row
 constexpr int kMaxWaves = 8;       // waves per workgroup, upper bound
 
+// Schemes of a 1D solve (the values of NG_MUSCL and NG_CSPH_TVD).  A CSPH-TVD
+// step reaches three cells to each side (predictor, corrector, face values),
+// so its wave segments keep three halo lanes per side.
+constexpr int kSchemeMuscl = 0;
+constexpr int kSchemeCsph = 1;
+constexpr int kCsphHalo = 3;
+constexpr int kCsphInterior = kWave - 2 * kCsphHalo;
+// cells a wave updates per 1D segment under a scheme
+constexpr int seg_cells(int scheme)
+{
+    return scheme == kSchemeCsph ? kCsphInterior : kInterior;
+}
+
 // Boundary kinds of an axis end (the values of NG_BC_*): ghost cells wrap
 // around, mirror the interior with the normal momentum negated, or copy the
 // edge cell.
@@ -45,13 +58,14 @@ struct InstDesc {
     int64_t nx, ny, ncell;
     int32_t ndim, riemann;
     int32_t nstrips;          // 2D: column strips of kInterior cells; 1D: segments
+                              // of seg_cells(scheme) cells
     int32_t rows_per_item;    // 2D: rows per work item; 1D: segments per work item
     int32_t nchunks;          // 2D: row chunks; 1D: segment groups
     int32_t waves_per_block;
     int32_t fused;            // the step kernel accepts the step (last workgroup)
     int32_t bc[4];            // boundary kinds: x-low, x-high, y-low, y-high
     int32_t any_bc;           // some end is not periodic
-    int32_t pad0;
+    int32_t scheme;           // kSchemeMuscl, or kSchemeCsph (1D, FP64)
     int64_t nitems;           // nstrips * nchunks (2D) or nchunks (1D)
     int64_t nblocks;          // workgroups of this solve's step launch
     uint64_t buf[2];          // device addresses of the two state buffers

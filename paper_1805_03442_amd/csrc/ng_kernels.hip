@@ -12,7 +12,9 @@
 //       updated, the north face state and the y-flux below it) in registers, so
 //       each y-face flux is computed once and each cell is loaded once (plus a
 //       2-row halo per chunk).
-//   1D: a work item is a group of consecutive 60-cell segments.
+//   1D: a work item is a group of consecutive 60-cell segments (58 cells and
+//       3 halo lanes per side for the CSPH-TVD step of section 2.3, whose
+//       particles reach three cells).
 // Each cell's arithmetic does not depend on where it sits in a strip or chunk,
 // so results are independent of the launch shape.
 //
@@ -27,8 +29,10 @@
 #include <stdint.h>
 
 #include <mutex>
+#include <type_traits>
 
 #include "ng_cell.hpp"
+#include "ng_csph.hpp"
 #include "ng_internal.hpp"
 #include "ng_launch.hpp"
 
@@ -76,7 +80,7 @@ __device__ __forceinline__ float lane_xor(float v, int lane, int m)
     return __int_as_float(__builtin_amdgcn_ds_bpermute(((lane ^ m) & 63) << 2, __float_as_int(v)));
 }
 
-// index of a cell coordinate in [-2, n + 62) on a periodic axis of n >= 4
+// index of a cell coordinate in [-3, n + 62) on a periodic axis of n >= 4
 // cells (one wrap suffices when n >= 64; short axes wrap several times)
 __device__ __forceinline__ int64_t wrap_axis(int64_t x, int64_t n)
 {
@@ -86,10 +90,10 @@ __device__ __forceinline__ int64_t wrap_axis(int64_t x, int64_t n)
     return x;
 }
 
-// Cell of coordinate j in [-2, n + 62) on an axis of n >= 4 cells whose ends
+// Cell of coordinate j in [-3, n + 62) on an axis of n >= 4 cells whose ends
 // have boundary kinds lo and hi, and whether the normal momentum of the value
 // loaded there is to be negated.  Ghosts of a periodic end wrap around, of a
-// wall mirror the edge cells (-1 -> 0, -2 -> 1), of an outflow end copy the
+// wall mirror the edge cells (-1 -> 0, -2 -> 1, -3 -> 2), of an outflow end copy the
 // edge cell; coordinates beyond the ghost layer (lanes that feed no interior
 // cell) are clamped into the axis.
 __device__ __forceinline__ int64_t axis_cell(int64_t j, int64_t n, int lo, int hi, bool& flip)
@@ -1110,6 +1114,129 @@ __device__ __forceinline__ void march1d_hllc(const InstDesc& d, const typename P
     }
 }
 
+// CSPH-TVD step (section 2.3) of the segments of work item `item`: lane l of
+// a segment holds the particle of cell sg * 58 - 3 + l (ghost particles by the
+// boundary rule, a wall ghost with its momentum negated).  Neighbours are one
+// lane away, so each stage is one DPP shift per quantity:
+//   predictor (eq. (10)) on lanes 1..62: U* = U^n + dt Y(U^n), xi* = dt (u^n +
+//     u*)/2, with every particle at its cell centre;
+//   corrector (eq. (11)) on lanes 2..61: U~ = (U^n + U*)/2 + dt/2 Y(U*, xi*),
+//     xi~ = xi*/2 + dt/2 (u^n + u~)/2;
+//   face j+1/2 on lanes 2..60: HLL (eq. (13)) between U^L = U^{n+1/2}_j +
+//     (h - xi~_j) Theta_j / 2 and U^R = U^{n+1/2}_{j+1} - (h + xi~_{j+1})
+//     Theta_{j+1} / 2 (eq. (14)), U^{n+1/2} = (U^n + U~)/2;
+//   update (eq. (9)) on lanes 3..60: U^{n+1} = U~ - dt/h (F_{j+1/2} - F_{j-1/2}).
+// FP64 only (the state is stored whole).
+template <class P, bool BC>
+__device__ __forceinline__ void march_csph(const InstDesc& d, const K64& k, int cur, int64_t item,
+                                           int lane, Acc<double>& acc)
+{
+    static_assert(std::is_same<typename P::K, K64>::value, "CSPH-TVD runs on the FP64 state");
+    constexpr int NC = 4;
+    const int64_t n = d.nx;
+    const Planes<double, NC> src(d.buf[cur], n);
+    const Planes<double, NC> dst(d.buf[cur ^ 1], n);
+    const int64_t s0 = item * d.rows_per_item;
+    const int64_t s1 = s0 + d.rows_per_item < d.nstrips ? s0 + d.rows_per_item : d.nstrips;
+    const double h = d.h, wn = 2.0 / (3.0 * (h * h));
+    // the predictor's particles sit at the centres: distances +-h exactly
+    const double g1 = csph_grad_w(h, h, wn), g2 = csph_grad_w(-h, h, wn);
+    const double dt = k.dt, hdt = k.hdt, dtdx = k.dtdx;
+    auto coord = [&](int64_t sg) { return sg * kCsphInterior - kCsphHalo + lane; };
+    auto boff = [&](int64_t sg) -> uint32_t {
+        bool f;
+        const int64_t x = BC ? axis_cell(coord(sg), n, d.bc[0], d.bc[1], f) : wrap_axis(coord(sg), n);
+        return (uint32_t)(x * (int64_t)sizeof(double));
+    };
+    double UA[NC], UB[NC];
+    src.load(boff(s0), UA);
+    auto seg = [&](int64_t sg, double* Un, double* Ux) {
+        const uint32_t o = boff(sg);
+        src.load(boff(sg + 1 < s1 ? sg + 1 : sg), Ux);
+        if (BC) {
+            bool f;
+            (void)axis_cell(coord(sg), n, d.bc[0], d.bc[1], f);
+            if (f) Un[1] = -Un[1];
+        }
+        // predictor
+        double un, pn, phin;
+        csph_prim(k, Un, un, pn, phin);
+        double Y[NC], sEp, sVp, sEc, sVc;
+        csph_y(k, h, g1, g2, from_left(phin), from_left(un), from_right(phin), from_right(un),
+               Un[0], un, pn, Un[3], phin, Y, sEp, sVp);
+        double Us[NC];
+        for (int c = 0; c < NC; c++) Us[c] = Un[c] + dt * Y[c];
+        double us, ps, phis;
+        csph_prim(k, Us, us, ps, phis);
+        const double xs = dt * (0.5 * (un + us));
+        // corrector, at the predicted positions
+        const double ga = csph_grad_w(h + (xs - from_left(xs)), h, wn);
+        const double gb = csph_grad_w(-h + (xs - from_right(xs)), h, wn);
+        csph_y(k, h, ga, gb, from_left(phis), from_left(us), from_right(phis), from_right(us),
+               Us[0], us, ps, Us[3], phis, Y, sEc, sVc);
+        double Ut[NC];
+        for (int c = 0; c < NC; c++) Ut[c] = 0.5 * (Un[c] + Us[c]) + hdt * Y[c];
+        const double ut = Ut[1] / Ut[0];
+        const double xt = 0.5 * xs + hdt * (0.5 * (un + ut));
+        // face j+1/2: this particle's profile gives U^L, the right neighbour's U^R
+        const double al = 0.5 * (h - xt), ar = 0.5 * (h + xt);
+        double UL[NC], UR[NC], F[NC];
+        for (int c = 0; c < NC; c++) {
+            const double l = from_left(Un[c]), r = from_right(Un[c]);
+            double a = Un[c] - l, b = r - Un[c];
+            pin(a);
+            pin(b);
+            const double th = minmod(a, b) / h;
+            const double hl = 0.5 * (Un[c] + Ut[c]);
+            UL[c] = hl + al * th;
+            UR[c] = from_right(hl - ar * th);
+        }
+        csph_flux(k, UL, UR, F);
+        double Uo[NC], Wn[NC];
+        for (int c = 0; c < NC; c++) {
+            double dF = F[c] - from_left(F[c]);
+            pin(dF);
+            Uo[c] = Ut[c] - dtdx * dF;
+        }
+        prim64<NC>(k, Uo, Wn);
+        const double s = speed64<NC>(k, Wn);
+        const bool inner = lane >= kCsphHalo && lane < kWave - kCsphHalo &&
+                           sg * kCsphInterior + (lane - kCsphHalo) < n;
+        if (inner) {
+            dst.store(o, Uo);
+            acc_cell<P, NC>(acc, k, Uo, Wn, s, hdt * sEp + hdt * sEc, hdt * sVp + hdt * sVc);
+        }
+    };
+    int64_t sg = s0;
+    for (; sg + 1 < s1; sg += 2) {
+        seg(sg, UA, UB);
+        seg(sg + 1, UB, UA);
+    }
+    if (sg < s1) seg(sg, UA, UB);
+}
+
+// the FP64 1D step of a solve under its scheme (the MUSCL step on the other
+// arithmetic)
+template <class P>
+__device__ __forceinline__ void march1d_any(const InstDesc& d, const typename P::K& k, int cur,
+                                            const double* gsrc, int64_t item, int lane,
+                                            Acc<typename P::R>& acc)
+{
+    if constexpr (std::is_same<typename P::K, K64>::value) {
+        if (d.scheme == kSchemeCsph) {
+            if (d.any_bc)
+                march_csph<P, true>(d, k, cur, item, lane, acc);
+            else
+                march_csph<P, false>(d, k, cur, item, lane, acc);
+            return;
+        }
+    }
+    if (d.riemann == 1)
+        march1d_bc<P, 1>(d, k, cur, gsrc, item, lane, acc);
+    else
+        march1d_hllc<P>(d, k, cur, gsrc, item, lane, acc);
+}
+
 // V as for step2d_kernel
 template <class P, int V>
 __global__ void __launch_bounds__(256) step1d_kernel(const InstDesc* __restrict__ descs,
@@ -1133,10 +1260,8 @@ __global__ void __launch_bounds__(256) step1d_kernel(const InstDesc* __restrict_
     if (item < d.nitems) {
         if constexpr (V > 0)
             march1d<P, 0, false, V - 1>(d, k, sc.cur, sc.gsrc, item, lane, acc);
-        else if (d.riemann == 1)
-            march1d_bc<P, 1>(d, k, sc.cur, sc.gsrc, item, lane, acc);
         else
-            march1d_hllc<P>(d, k, sc.cur, sc.gsrc, item, lane, acc);
+            march1d_any<P>(d, k, sc.cur, sc.gsrc, item, lane, acc);
     }
     acc_finish<P>(acc, k);
     Partial* parts = (Partial*)d.partials;
@@ -1184,10 +1309,11 @@ __global__ void __launch_bounds__(256) prime_kernel(const InstDesc* __restrict__
             seg0 = item * d.rows_per_item;
             seg1 = seg0 + d.rows_per_item < d.nstrips ? seg0 + d.rows_per_item : d.nstrips;
         }
+        const int w = NC == 5 ? kInterior : seg_cells(d.scheme);
         for (int64_t sg = seg0; sg < seg1; sg++) {
-            const int64_t xbase = NC == 5 ? xs : sg * kInterior;
+            const int64_t xbase = NC == 5 ? xs : sg * w;
             const int64_t xo = xbase + (lane - kHalo);
-            const bool inner = lane >= kHalo && lane < kWave - kHalo && xo < nx;
+            const bool inner = lane >= kHalo && lane < kHalo + w && xo < nx;
             if (!inner) continue;
             for (int64_t r = rows0; r < rows1; r++) {
                 St U[NC];
@@ -1250,10 +1376,7 @@ __global__ void __launch_bounds__(512) run_small_kernel(const InstDesc* __restri
                 else
                     march2d_hllc<P>(d, k, sc.cur, sc.gsrc, item, lane, acc);
             } else {
-                if (d.riemann == 1)
-                    march1d_bc<P, 1>(d, k, sc.cur, sc.gsrc, item, lane, acc);
-                else
-                    march1d_hllc<P>(d, k, sc.cur, sc.gsrc, item, lane, acc);
+                march1d_any<P>(d, k, sc.cur, sc.gsrc, item, lane, acc);
             }
         }
         acc_finish<P>(acc, k);

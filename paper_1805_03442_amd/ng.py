@@ -22,6 +22,7 @@ NG_BC_PERIODIC, NG_BC_WALL, NG_BC_OUTFLOW, NG_BC_SOURCE = 0, 1, 2, 3
 NG_HLLC, NG_HLL = 0, 1
 NG_MINMOD = 0
 NG_FP64, NG_FP32, NG_MIXED = 0, 1, 2
+NG_MUSCL, NG_CSPH_TVD = 0, 1
 NG_FLAG_NONFINITE, NG_FLAG_RHO, NG_FLAG_P, NG_FLAG_DONE = 1, 2, 4, 8
 
 GAS_FIELDS = ("gamma", "R", "Cv", "rho0", "T0", "tau0", "tau_rho", "tau_T",
@@ -53,7 +54,7 @@ class NgGrid(C.Structure):
 
 class NgNumerics(C.Structure):
     _fields_ = [("cfl", C.c_double), ("riemann", C.c_int32), ("limiter", C.c_int32),
-                ("precision", C.c_int32), ("reserved", C.c_int32), ("stiff_z", C.c_double)]
+                ("precision", C.c_int32), ("scheme", C.c_int32), ("stiff_z", C.c_double)]
 
 
 class NgDiag(C.Structure):
@@ -156,8 +157,10 @@ def make_grid(nx: int, ny: int = 1, h: float | None = None, bc=(NG_BC_PERIODIC,)
                   *src[:4], *[float(v) for v in wedge])
 
 
-def make_numerics(cfl=0.4, riemann=NG_HLLC, precision=NG_FP64, stiff_z=0.5) -> NgNumerics:
-    return NgNumerics(float(cfl), int(riemann), NG_MINMOD, int(precision), 0, float(stiff_z))
+def make_numerics(cfl=0.4, riemann=NG_HLLC, precision=NG_FP64, stiff_z=0.5,
+                  scheme=NG_MUSCL) -> NgNumerics:
+    return NgNumerics(float(cfl), int(riemann), NG_MINMOD, int(precision), int(scheme),
+                      float(stiff_z))
 
 
 def _dp(a: np.ndarray):
@@ -210,12 +213,13 @@ class Solver:
 
     def __init__(self, gas: dict, nx: int, ny: int = 1, W=None, U=None, h=None, cfl=0.4,
                  riemann=NG_HLLC, precision=NG_FP64, stiff_z=0.5, t0=0.0, stream=None,
-                 bc=(NG_BC_PERIODIC,) * 4, source=(0.0, 0.0), wedge=(0.0, 0.0, 0.0)):
+                 bc=(NG_BC_PERIODIC,) * 4, source=(0.0, 0.0), wedge=(0.0, 0.0, 0.0),
+                 scheme=NG_MUSCL):
         L = lib()
         self.nx, self.ny = int(nx), int(ny)
         self.gas = make_gas(gas)
         self.grid = make_grid(nx, ny, h, bc, source, wedge)
-        self.num = make_numerics(cfl, riemann, precision, stiff_z)
+        self.num = make_numerics(cfl, riemann, precision, stiff_z, scheme)
         nbytes = C.c_size_t(0)
         check(L.ng_state_bytes(C.byref(self.grid), C.byref(self.num), C.byref(nbytes)),
               "ng_state_bytes")
@@ -303,7 +307,8 @@ class Solver:
 
 def step_static(gas: dict, nx: int, ny: int, U_in, U_out, t: float = 0.0, t_end: float = 0.0,
                 h=None, cfl=0.4, riemann=NG_HLLC, stiff_z=0.5, bc=(NG_BC_PERIODIC,) * 4,
-                source=(0.0, 0.0), wedge=(0.0, 0.0, 0.0), stream=None, diag: bool = True):
+                source=(0.0, 0.0), wedge=(0.0, 0.0, 0.0), stream=None, diag: bool = True,
+                scheme=NG_MUSCL):
     """One FP64 step (``ng_step_static``) from the device buffer U_in to U_out
     (torch CUDA tensors or device addresses: FP64 conserved planes in the ABI
     layout), with the library's static scratch; returns the diagnostics dict
@@ -312,7 +317,7 @@ def step_static(gas: dict, nx: int, ny: int, U_in, U_out, t: float = 0.0, t_end:
         return int(x.data_ptr()) if hasattr(x, "data_ptr") else int(x)
     d = NgDiag()
     rc = lib().ng_step_static(C.byref(make_gas(gas)), C.byref(make_grid(nx, ny, h, bc, source, wedge)),
-                              C.byref(make_numerics(cfl, riemann, NG_FP64, stiff_z)),
+                              C.byref(make_numerics(cfl, riemann, NG_FP64, stiff_z, scheme)),
                               C.c_void_p(addr(U_in)), C.c_void_p(addr(U_out)), float(t),
                               float(t_end), C.c_void_p(stream_handle(stream)),
                               C.byref(d) if diag else None)
@@ -353,10 +358,10 @@ class Batch:
 
     def add(self, gas: dict, nx: int, ny: int, W, t_end: float, max_steps: int = 2**62,
             h=None, cfl=0.4, riemann=NG_HLLC, stiff_z=0.5, t0=0.0, bc=(NG_BC_PERIODIC,) * 4,
-            source=(0.0, 0.0), wedge=(0.0, 0.0, 0.0)):
+            source=(0.0, 0.0), wedge=(0.0, 0.0, 0.0), scheme=NG_MUSCL):
         """Returns the slot, or None when the batch is full (NG_EFULL)."""
         g, gr = make_gas(gas), make_grid(nx, ny, h, bc, source, wedge)
-        nm = make_numerics(cfl, riemann, self.precision, stiff_z)
+        nm = make_numerics(cfl, riemann, self.precision, stiff_z, scheme)
         arr = _planes(W, ny)
         slot = C.c_int32(-1)
         rc = lib().ng_batch_add(self.h, C.byref(g), C.byref(gr), C.byref(nm), _dp(arr),

@@ -199,6 +199,18 @@ def workload_1d_multimode(n: int = 1 << 20):
                 precision="fp32")
 
 
+def workload_csph_1d(n: int = 1 << 22):
+    """1D periodic, 2^22 cells, Q_T = 2: 64 random density modes in 1..256
+    with N(0, 1e-3) amplitudes (isentropic pressure) on a velocity wave
+    0.05 sin(2 pi 3 x), so that the particles of the CSPH-TVD step move;
+    FP64, HLL."""
+    gas = dict(BASE_GAS, Q_T=2.0)
+    W = multimode_1d(gas, n, rng(5), sigma=1e-3)
+    W[1, 0] = 0.05 * np.sin(2.0 * math.pi * 3.0 * cell_centres(n))
+    return dict(name=f"1d_csph_multimode_n{n}", gas=gas, W=W, nx=n, ny=1, steps=2000,
+                precision="fp64")
+
+
 def workload_2d_random(n: int = 4096):
     """2D periodic n x n (4096^2), Q_T = 2, isotropic k^-2 density field with
     |k| <= 64 and rms 1e-3, 5000 steps."""

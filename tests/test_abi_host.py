@@ -63,7 +63,10 @@ def test_state_bytes(ng):
                                          ("bc", (0, 1)), ("bc", (2, 3)), ("bc", (3, 0)),
                                          ("source", (0.0, 0.1)), ("source", (0.6, 0.1)),
                                          ("segment_1d", 0.1), ("wedge_1d", 0.3),
-                                         ("wedge_x0", -0.1), ("huge", 1 << 30)])
+                                         ("wedge_x0", -0.1), ("huge", 1 << 30),
+                                         ("scheme", 2), ("scheme", -1),
+                                         ("csph", "hllc"), ("csph", "fp32"), ("csph", "mixed"),
+                                         ("csph", "2d"), ("csph", "source")])
 def test_invalid_arguments_rejected_before_device_use(ng, field, value):
     import numpy as np
     from paper_1805_03442_amd import workloads as wl
@@ -71,6 +74,7 @@ def test_invalid_arguments_rejected_before_device_use(ng, field, value):
     gas = dict(wl.BASE_GAS)
     nx, ny = 64, 1
     cfl, riemann, prec = 0.4, ng.NG_HLLC, ng.NG_FP64
+    scheme = ng.NG_MUSCL
     if field in ("gamma", "tau0", "R"):
         gas[field] = value
     elif field == "cfl":
@@ -83,6 +87,19 @@ def test_invalid_arguments_rejected_before_device_use(ng, field, value):
         gas["fy"] = value
     elif field == "precision":
         prec = value
+    elif field == "scheme":
+        scheme = value
+    elif field == "csph":
+        # the CSPH-TVD step: 1D, FP64, HLL, no forced source only
+        scheme, riemann = ng.NG_CSPH_TVD, ng.NG_HLL
+        if value == "hllc":
+            riemann = ng.NG_HLLC
+        elif value == "fp32":
+            prec = ng.NG_FP32
+        elif value == "mixed":
+            prec = ng.NG_MIXED
+        elif value == "2d":
+            ny = 64
     bc = (0, 0, 0, 0)
     source = (0.0, 0.0)
     if field == "bc":
@@ -91,6 +108,8 @@ def test_invalid_arguments_rejected_before_device_use(ng, field, value):
         # a source end with a zero wavelength, or an amplitude of rho0 / 2 or more
         bc = (3, 2, 0, 0)
         source = (value[1], value[0]) if value[0] == 0.0 else value
+    if field == "csph" and value == "source":
+        bc, source = (3, 2, 0, 0), (1e-3, 0.1)
     wedge = (0.0, 0.0, 0.0)
     if field == "segment_1d":
         # a source segment needs a 2D grid
@@ -106,11 +125,11 @@ def test_invalid_arguments_rejected_before_device_use(ng, field, value):
         # 2^30 cells of FP64: byte offsets beyond 32 bits (the state is never read)
         grid = ng.make_grid(value, 1)
         nx = 64
-    W = wl.uniform_state(dict(wl.BASE_GAS), max(nx, 4))[:, :, :nx]
-    arr = np.ascontiguousarray(W[[0, 1, 3, 4]].reshape(4, -1))
+    W = wl.uniform_state(dict(wl.BASE_GAS), max(nx, 4), ny)[:, :, :nx]
+    arr = np.ascontiguousarray(W[[0, 1, 3, 4]].reshape(4, -1) if ny == 1 else W.reshape(5, -1))
     h = C.c_void_p(0)
     rc = L.ng_init_state(C.byref(ng.make_gas(gas)), C.byref(grid),
-                         C.byref(ng.make_numerics(cfl, riemann, prec)),
+                         C.byref(ng.make_numerics(cfl, riemann, prec, scheme=scheme)),
                          arr.ctypes.data_as(C.POINTER(C.c_double)), 0.0, C.c_void_p(256),
                          1 << 30, None, C.byref(h))
     assert rc == ng.NG_EINVAL

@@ -14,20 +14,21 @@ from paper_1805_03442_amd import workloads as wl
 pytestmark = pytest.mark.gpu
 
 
-def _step_static(ng, torch, gas, nx, ny, U, t=0.0, riemann=0, bc=(0, 0, 0, 0)):
+def _step_static(ng, torch, gas, nx, ny, U, t=0.0, riemann=0, bc=(0, 0, 0, 0), scheme=0):
     nc = 5 if ny > 1 else 4
     comps = [0, 1, 2, 3, 4] if ny > 1 else [0, 1, 3, 4]
     planes = np.ascontiguousarray(U[comps].reshape(nc, -1))
     din = torch.from_numpy(planes).cuda()
     dout = torch.full_like(din, float("nan"))
-    d = ng.step_static(gas, nx, ny, din, dout, t=t, riemann=riemann, bc=bc)
+    d = ng.step_static(gas, nx, ny, din, dout, t=t, riemann=riemann, bc=bc, scheme=scheme)
     out = np.zeros_like(U)
     out[comps] = dout.cpu().numpy().reshape(nc, ny, nx)
     return out, d
 
 
-def _step_solver(ng, gas, nx, ny, U, riemann=0, bc=(0, 0, 0, 0)):
-    s = ng.Solver(gas, nx, ny, U=U, precision=ng.NG_FP64, riemann=riemann, bc=bc)
+def _step_solver(ng, gas, nx, ny, U, riemann=0, bc=(0, 0, 0, 0), scheme=0):
+    s = ng.Solver(gas, nx, ny, U=U, precision=ng.NG_FP64, riemann=riemann, bc=bc,
+                  scheme=scheme)
     s.step(1)
     V = s.conserved()
     d = s.diagnostics()
@@ -35,13 +36,14 @@ def _step_solver(ng, gas, nx, ny, U, riemann=0, bc=(0, 0, 0, 0)):
     return V, d
 
 
-@pytest.mark.parametrize("case", ["2d_hllc_periodic", "1d_hll_walls"])
+@pytest.mark.parametrize("case", ["2d_hllc_periodic", "1d_hll_walls", "1d_csph_walls"])
 def test_static_step_equals_solver_step(case):
     import torch
     from paper_1805_03442_amd import ng
     assert torch.cuda.is_available()
     gas = dict(wl.BASE_GAS, Q_T=2.0)
     r = np.random.Generator(np.random.PCG64(31))
+    scheme = ng.NG_CSPH_TVD if case == "1d_csph_walls" else ng.NG_MUSCL
     if case == "2d_hllc_periodic":
         shapes, riemann, bc = [(300, 190), (130, 70)], 0, (0, 0, 0, 0)
     else:
@@ -58,8 +60,8 @@ def test_static_step_equals_solver_step(case):
         U = s0.conserved()
         s0.close()
         print(f"static step {case} {nx}x{ny}", flush=True)
-        A, da = _step_static(ng, torch, gas, nx, ny, U, riemann=riemann, bc=bc)
-        B, db = _step_solver(ng, gas, nx, ny, U, riemann=riemann, bc=bc)
+        A, da = _step_static(ng, torch, gas, nx, ny, U, riemann=riemann, bc=bc, scheme=scheme)
+        B, db = _step_solver(ng, gas, nx, ny, U, riemann=riemann, bc=bc, scheme=scheme)
         assert np.array_equal(A, B), (nx, ny, np.abs(A - B).max())
         assert da["t"] == db["t"] and da["dt_last"] == db["dt_last"] and da["steps"] == 1
         assert da["status"] == 0
