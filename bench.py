@@ -41,6 +41,10 @@ Prints one JSON line:
   forced_source_1d, sector_2d, blast_waves_1d  section 3's runs (1D also at
               102400 cells) and section 2.4's blast waves at 128000 cells,
               in FP32 and FP64 with the FP32 error against FP64
+  csph_1d     the CSPH-TVD step (section 2.3) in FP64 on a 2^22-cell periodic
+              grid: cell-updates/s, its roofline (vector ALU issue and HBM),
+              the oracle on two whole steps; and section 2.4's blast waves
+              (figure 2) on 200 and 1600 cells with CSPH-TVD and MUSCL
   cpu_baseline  the serial FP64 oracle on whole steps of the same grid (about
               10 s of one host core), the host CPU model, and batch_fleet: the
               512-instance 1D batch workload's sample on the oracle in one
@@ -64,6 +68,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_CELL_FP32 = 40.0   # 5 conserved planes read + 5 written, 4 B each
 BYTES_PER_CELL_FP64 = 80.0
+BYTES_PER_CELL_CSPH = 64.0   # 1D: 4 FP64 conserved planes read + 4 written
+CSPH_VALU_FILE = os.path.join(ROOT, "profiles", "step1d_csph_fp64_4m_valu.txt")
+CSPH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step1d_csph_fp64_4m_traffic.txt")
+CSPH_KERNEL = "step1d_kernel<ng::Plain64<4>, 0>"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step2d_fp32_4096_traffic.txt")
 VALU_FILE = os.path.join(ROOT, "profiles", "step2d_fp32_4096_valu.txt")
 # non-packed FP32 vector issue of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
@@ -113,13 +121,18 @@ def setup_solver(s):
         s.set_graph_steps(GRAPH_STEPS)
 
 
-def timed_run(ng, torch, gas, W, n, steps, warmup, precision, bc=(0, 0, 0, 0), reps=REPS):
+def timed_run(ng, torch, gas, W, n, steps, warmup, precision, bc=(0, 0, 0, 0), reps=REPS,
+              ny=None, tune=True, **kw):
     """Warm-up (>= WARMUP_SECONDS and >= warmup steps), ``reps`` windows of
     ``steps`` steps between HIP events on the solver's stream (median), then
     one window of max(steps, 100) steps whose every step kernel carries its
-    own start/end events (mean kernel duration)."""
-    s = ng.Solver(gas, n, n, W=W, precision=precision, bc=bc)
-    setup_solver(s)
+    own start/end events (mean kernel duration).  ny: n x n when None; kw go
+    to the solver (riemann, scheme); tune: apply the cached launch shape."""
+    s = ng.Solver(gas, n, n if ny is None else ny, W=W, precision=precision, bc=bc, **kw)
+    if tune:
+        setup_solver(s)
+    elif GRAPH_STEPS is not None:
+        s.set_graph_steps(GRAPH_STEPS)
     st = torch.cuda.current_stream()
     s.step(max(warmup, 1))
     torch.cuda.synchronize()
@@ -298,6 +311,95 @@ def error_vs(U, ref, U0, names):
     return {"rel_l1": full, "rel_l1_of_perturbation": pert}
 
 
+def csph_leg(ng, torch, np, wl, args, fine_rho=None):
+    """The CSPH-TVD step of section 2.3 (1D, FP64, HLL): throughput on the
+    2^22-cell periodic workload on the per-step path (timed windows, then
+    every step kernel timed by its own events), its roofline (vector ALU
+    issue from the committed SQ_INSTS_VALU count of the kernel, and HBM at
+    64 algorithmic bytes per cell), the paper's figure-2 runs (blast waves
+    between walls to t = 0.038 on 200 and 1600 cells, CSPH-TVD beside MUSCL,
+    L1 density difference from the 128000-cell MUSCL run when that leg ran;
+    skipped with the paper's other runs), and the oracle on two whole steps
+    of the same grid on one host core."""
+    wc = wl.workload_csph_1d()
+    nc = wc["nx"]
+    k = args.csph_steps
+    log(f"[bench] CSPH-TVD 1D {nc} cells: {REPS} windows of {k} steps")
+    r = timed_run(ng, torch, wc["gas"], wc["W"], nc, k, args.warmup, ng.NG_FP64, ny=1,
+                  tune=False, riemann=ng.NG_HLL, scheme=ng.NG_CSPH_TVD)
+    value = nc * k / (r["total_ms"] * 1e-3)
+    kern_s = r["step_ms"] * 1e-3
+    hbm = BYTES_PER_CELL_CSPH * nc / kern_s / 1e9
+    roof = {"bound": "alu", "kernel": CSPH_KERNEL, "kernel_ms": r["step_ms"],
+            "launches_timed": r["launches"], "finalize_ms": r["fin_ms"],
+            "hbm": {"achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": hbm / HBM_PEAK_GBS,
+                    "algorithmic_bytes_per_launch": BYTES_PER_CELL_CSPH * nc}}
+    vr = counter_record(CSPH_VALU_FILE)
+    if vr is not None and "SQ_INSTS_VALU" in vr["mean_per_dispatch"]:
+        insts = vr["mean_per_dispatch"]["SQ_INSTS_VALU"]
+        ach = insts * 64 / kern_s / 1e12
+        roof.update({"achieved": ach, "peak": VALU_PEAK_TLANEOPS, "unit": "T lane-op/s",
+                     "frac": ach / VALU_PEAK_TLANEOPS, "valu_insts_per_launch": insts,
+                     "lane_ops_per_cell_update": insts * 64 / nc})
+        m = vr["mean_per_dispatch"]
+        if "SQ_ACTIVE_INST_VALU" in m and "GRBM_GUI_ACTIVE" in m:
+            roof["valu_busy"] = m["SQ_ACTIVE_INST_VALU"] * 4 / 1024 / (m["GRBM_GUI_ACTIVE"] / 8)
+    else:
+        roof.update({"achieved": None, "peak": VALU_PEAK_TLANEOPS, "unit": "T lane-op/s",
+                     "frac": None})
+    tr = counter_record(CSPH_TRAFFIC_FILE)
+    roof["hbm"]["traffic"] = tr["bytes_per_launch"] if tr is not None else None
+    res = {"workload": wc["name"], "precision": "fp64", "riemann": "hll", "steps": k,
+           "value": value, "unit": "cell-updates/s", "us_per_step": 1e3 * r["total_ms"] / k,
+           "windows_ms": r["windows_ms"], "roofline": roof}
+    log(f"[bench] CSPH-TVD {value:.3e} cell-updates/s, step kernel {1e3 * r['step_ms']:.1f} us")
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build()
+        P = oracle.CsphProblem(wc["gas"], nc)
+        U0 = P.prim_to_cons(wc["W"])
+        t0 = time.perf_counter()
+        ref = P.run(U0, 2)
+        el = time.perf_counter() - t0
+        assert ref["status"] == 0
+        res["cpu_baseline"] = {"value": nc * 2 / el, "unit": "cell-updates/s", "cores": 1,
+                               "kind": "oracle", "sample": f"2 whole steps of the {nc}-cell grid"}
+    if args.no_source_runs:
+        return res
+    # figure 2: blast waves, CSPH-TVD and MUSCL on the same grids
+    gb = dict(wl.BASE_GAS, Cv=0.0, tau_rho=0.0, tau_T=0.0, Q0=0.0, Q_rho=0.0, Q_T=0.0,
+              I0=0.0, I_rho=0.0, I_T=0.0, tau0=1.0)
+    bw = {}
+    for nb in (200, 1600):
+        for name, scheme, riemann in (("csph_tvd", ng.NG_CSPH_TVD, ng.NG_HLL),
+                                      ("muscl", ng.NG_MUSCL, ng.NG_HLLC)):
+            best = None
+            for _ in range(2):      # the first run also loads the path's kernels
+                s = ng.Solver(gb, nb, 1, W=wl.blast_waves_1d(nb), precision=ng.NG_FP64,
+                              riemann=riemann, bc=(ng.NG_BC_WALL, ng.NG_BC_WALL, 0, 0),
+                              scheme=scheme)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                taken = s.run_to_time(0.038)
+                el = time.perf_counter() - t0
+                rho = s.conserved()[0, 0]
+                d = s.diagnostics()
+                s.close()
+                assert d["status"] == 0
+                best = el if best is None else min(best, el)
+            rec = {"steps": taken, "wall_ms": 1e3 * best, "us_per_step": 1e6 * best / taken,
+                   "rho_max": float(rho.max()),
+                   "x_rho_max": float((np.argmax(rho) + 0.5) / nb)}
+            if fine_rho is not None:
+                avg = fine_rho.reshape(nb, -1).mean(axis=1)
+                rec["l1_rho_vs_muscl_128000"] = float(np.mean(np.abs(rho - avg)))
+            bw[f"{name}_n{nb}"] = rec
+    res["blast_waves_t0038"] = bw
+    log(f"[bench] CSPH-TVD blast waves: {bw}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -313,7 +415,10 @@ def main():
     ap.add_argument("--bounded-steps", type=int, default=200)
     ap.add_argument("--steps-1d", type=int, default=20000)
     ap.add_argument("--no-source-runs", action="store_true",
-                    help="skip the forced-source runs of section 3 (1D and the 2D sector)")
+                    help="skip the paper's runs: section 3's forced-source runs (1D and the "
+                         "2D sector) and section 2.4's blast waves (MUSCL and CSPH-TVD)")
+    ap.add_argument("--csph-steps", type=int, default=200,
+                    help="steps per timed window of the CSPH-TVD leg (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain device copy of known size (for counter scaling)")
     ap.add_argument("--no-graphs", action="store_true",
@@ -330,6 +435,7 @@ def main():
         sys.exit(2)
 
     fleet = None
+    blast_fine_rho = None
     if not args.no_cpu_baseline:
         # before the GPU is touched: the oracle's worker processes are forked
         log("[bench] CPU fleet: the batch instances on the oracle, one process per core")
@@ -628,6 +734,7 @@ def main():
             assert d["status"] == 0
             rec[name] = {"steps": taken, "wall_ms": 1e3 * el,
                          "cell_updates_per_s": nb * taken / el}
+        blast_fine_rho = fin["fp64"][0, 0]
         rec["fp32"]["rel_l1_vs_fp64"] = {
             nm: float(np.abs(fin["fp32"][c] - fin["fp64"][c]).sum()
                       / np.abs(fin["fp64"][c]).sum())
@@ -666,6 +773,9 @@ def main():
                                 max_drho_in_wedge=float(drho[act].max()),
                                 max_drho_outside=float(drho[~act].max()))
         log(f"[bench] sector: {out['sector_2d']}")
+
+    if args.csph_steps > 0:
+        out["csph_1d"] = csph_leg(ng, torch, np, wl, args, blast_fine_rho)
 
     if args.calibrate_copy:
         nbytes = 1 << 30

@@ -634,7 +634,9 @@ int rebuild(ng_batch* b)
         for (int i = 0; i < b->capacity; i++) {
             const Slot& s = b->slots[i];
             if (!s.live || s.small || s.dim != dim) continue;
-            const int sv = (s.d.riemann == NG_HLLC && !s.d.any_bc) ? 1 + s.d.cl_recipe : 0;
+            const int sv = s.d.scheme == kSchemeCsph
+                               ? kVariantCsph
+                               : ((s.d.riemann == NG_HLLC && !s.d.any_bc) ? 1 + s.d.cl_recipe : 0);
             v = (v < 0 || v == sv) ? sv : 0;
         }
         b->variant[dim] = v < 0 ? 0 : v;
@@ -1597,7 +1599,8 @@ int ng_step_static(const ng_gas* gas, const ng_grid* grid, const ng_numerics* nu
     c.t = t;
     c.t_end = t_end > t ? t_end : INFINITY;
     c.max_steps = 1;
-    const int variant = (d.riemann == NG_HLLC && !d.any_bc) ? 1 : 0;
+    const int variant = d.scheme == kSchemeCsph ? kVariantCsph
+                                                : ((d.riemann == NG_HLLC && !d.any_bc) ? 1 : 0);
     hipStream_t st = (hipStream_t)hip_stream;
     e = launch_static_setup(d, c, descs, ctrls, insts, blocks, d.nblocks, st);
     if (e == hipSuccess)

@@ -60,6 +60,11 @@ struct K64 {
     int riemann;
 };
 
+// pow for the exponents without a short form, kept out of line: the step
+// kernels hold several closure evaluations, and inlined copies of pow would
+// make their code many times larger than the path they run
+__device__ __noinline__ double pow_general(double x, double a) { return pow(x, a); }
+
 // x^a of the power laws (6): exponents 0, 1, -1, 2 and 1/2 by the correctly
 // rounded IEEE operations (the exact power rounded once), others by pow.  The
 // exponent is the same for every lane, so the selection is a scalar branch.
@@ -70,7 +75,7 @@ __device__ __forceinline__ double powr64(double x, double a)
     if (a == -1.0) return 1.0 / x;
     if (a == 2.0) return x * x;
     if (a == 0.5) return sqrt(x);
-    return pow(x, a);
+    return pow_general(x, a);
 }
 
 // closures of eq. (6) at (rho, T); the predictor and corrector scale Q and I

@@ -47,6 +47,9 @@ constexpr int kBcSource = 3;   // x-low only: forced sound wave in the ghosts
 // Q ~ rho^1/2 T^Q_T) with Q_T = 2 and 1; a solve whose codes match a row runs
 // that recipe, any other the general form (row 0).
 constexpr int kRecipes = 2;
+// step kernel variant of a launch whose solves all take the CSPH-TVD step
+// (1D, FP64); the closure-recipe variants are 1 .. kRecipes + 1
+constexpr int kVariantCsph = kRecipes + 2;
 constexpr int kRecipeCodes[kRecipes + 1][6] = {
     {0, 0, 0, 0, 0, 0},
     {0, 2, -3, 4, -2, 4},

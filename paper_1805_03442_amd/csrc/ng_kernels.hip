@@ -380,7 +380,8 @@ __device__ __forceinline__ uint32_t acc_flags(const Acc<R>& a)
 // waves of the workgroup in wave order, and store the workgroup's record
 // (WT: with agent-scope stores, which write through to memory).
 template <class R, int MaxW = kMaxWaves, bool WT = false>
-__device__ void block_reduce_store(Acc<R>& a, Partial* out, int wave, int lane, int nwaves)
+__device__ __forceinline__ void block_reduce_store(Acc<R>& a, Partial* out, int wave, int lane,
+                                                   int nwaves)
 {
     __shared__ double sh[MaxW][11];
     __shared__ uint32_t shf[MaxW];
@@ -1237,7 +1238,8 @@ __device__ __forceinline__ void march1d_any(const InstDesc& d, const typename P:
         march1d_hllc<P>(d, k, cur, gsrc, item, lane, acc);
 }
 
-// V as for step2d_kernel
+// V as for step2d_kernel, or kVariantCsph: every solve of the launch takes the
+// CSPH-TVD step (a kernel with that path only)
 template <class P, int V>
 __global__ void __launch_bounds__(256) step1d_kernel(const InstDesc* __restrict__ descs,
                                                      InstCtrl* __restrict__ ctrls,
@@ -1258,10 +1260,16 @@ __global__ void __launch_bounds__(256) step1d_kernel(const InstDesc* __restrict_
     acc_init(acc);
     const int64_t item = (int64_t)br.local * nwaves + wave;
     if (item < d.nitems) {
-        if constexpr (V > 0)
+        if constexpr (V == kVariantCsph) {
+            if (d.any_bc)
+                march_csph<P, true>(d, k, sc.cur, item, lane, acc);
+            else
+                march_csph<P, false>(d, k, sc.cur, item, lane, acc);
+        } else if constexpr (V > 0) {
             march1d<P, 0, false, V - 1>(d, k, sc.cur, sc.gsrc, item, lane, acc);
-        else
+        } else {
             march1d_any<P>(d, k, sc.cur, sc.gsrc, item, lane, acc);
+        }
     }
     acc_finish<P>(acc, k);
     Partial* parts = (Partial*)d.partials;
@@ -1860,7 +1868,13 @@ static void launch_variant(int v, dim3 g, dim3 b, hipStream_t s, hipEvent_t e0, 
         }
     } else {
         if (v == 0) launch(step1d_kernel<P, 0>, g, b, s, e0, e1, descs, ctrls, blocks, remap, fused);
-        else if (v == 1 || !P::kRecipes)
+        else if constexpr (std::is_same<typename P::K, K64>::value) {
+            if (v == kVariantCsph)
+                launch(step1d_kernel<P, kVariantCsph>, g, b, s, e0, e1, descs, ctrls, blocks, remap,
+                       fused);
+            else
+                launch(step1d_kernel<P, 1>, g, b, s, e0, e1, descs, ctrls, blocks, remap, fused);
+        } else if (v == 1 || !P::kRecipes)
             launch(step1d_kernel<P, 1>, g, b, s, e0, e1, descs, ctrls, blocks, remap, fused);
         else if constexpr (P::kRecipes) {
             if (v == 2) launch(step1d_kernel<P, 2>, g, b, s, e0, e1, descs, ctrls, blocks, remap, fused);
@@ -1875,7 +1889,9 @@ hipError_t launch_step(int dim, int prec, int variant, const InstDesc* descs, In
 {
     static_assert(kRecipes == 2, "launch_variant instantiates variants 0..3");
     if (!grid_ok(nblocks) || waves < 1 || waves > 4) return hipErrorInvalidValue;
-    if (variant < 0 || variant > kRecipes + 1) return hipErrorInvalidValue;
+    if (variant < 0 || (variant > kRecipes + 1 &&
+                        !(variant == kVariantCsph && dim == 1 && prec == 0)))
+        return hipErrorInvalidValue;
     dim3 g((unsigned)nblocks), b((unsigned)(64 * waves));
     if (dim == 2) {
         if (prec == 0)

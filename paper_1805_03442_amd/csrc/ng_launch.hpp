@@ -13,7 +13,7 @@ namespace ng {
 
 // variant: 0 for any set of solves; 1 + r when every solve of the launch is
 // periodic with the HLLC flux and closure recipe r (a kernel with that path
-// only).
+// only); kVariantCsph (dim 1, FP64) when every solve takes the CSPH-TVD step.
 hipError_t launch_step(int dim, int prec, int variant, const InstDesc* descs, InstCtrl* ctrls,
                        const BlockRef* blocks, int64_t nblocks, int waves, int remap, int fused,
                        hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);

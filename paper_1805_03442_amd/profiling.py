@@ -26,6 +26,7 @@ import sys
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 KERNEL_SOURCES = ["paper_1805_03442_amd/csrc/ng_kernels.hip",
                   "paper_1805_03442_amd/csrc/ng_cell.hpp",
+                  "paper_1805_03442_amd/csrc/ng_csph.hpp",
                   "paper_1805_03442_amd/csrc/ng_internal.hpp"]
 
 
@@ -37,7 +38,8 @@ def kernel_hash(root: str = ROOT) -> str:
     return h.hexdigest()[:16]
 
 
-def stats_markdown(path: str, command: str, top: int = 12, bench_json: str | None = None) -> str:
+def stats_markdown(path: str, command: str, top: int = 12, bench_json: str | None = None,
+                   leg: str | None = None) -> str:
     rows = list(csv.DictReader(open(path)))
     out = [f"Command: `{command}`", "",
            "| kernel | calls | mean us | min us | max us | share |",
@@ -55,6 +57,10 @@ def stats_markdown(path: str, command: str, top: int = 12, bench_json: str | Non
         with open(bench_json) as f:
             line = [ln for ln in f if ln.startswith("{")][-1]
         b = json.loads(line)
+        if leg:
+            # a leg of the benchmark with a roofline of its own
+            b = b[leg]
+            b = dict(b, ms_per_step=b["us_per_step"] * 1e-3)
         r = b["roofline"]
         out += ["", f"Same run, bench.py's own measurement: `{r['kernel']}` mean "
                 f"{1e3 * r['kernel_ms']:.1f} us over the timed launches (HIP events carried by "
@@ -122,6 +128,8 @@ def main(argv=None):
     a.add_argument("--out", required=True)
     a.add_argument("--bench-json", default=None,
                    help="stdout of the profiled bench.py run (its JSON line)")
+    a.add_argument("--leg", default=None,
+                   help="key of the benchmark leg whose roofline the summary quotes")
     b = sub.add_parser("traffic")
     b.add_argument("fetch_csv")
     b.add_argument("write_csv")
@@ -151,7 +159,7 @@ def main(argv=None):
         print(md)
         return
     if args.cmd == "stats":
-        md = stats_markdown(args.csv, args.command, bench_json=args.bench_json)
+        md = stats_markdown(args.csv, args.command, bench_json=args.bench_json, leg=args.leg)
         with open(args.out, "w") as f:
             f.write(md)
         print(md)
