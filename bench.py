@@ -71,7 +71,7 @@ BYTES_PER_CELL_FP64 = 80.0
 BYTES_PER_CELL_CSPH = 64.0   # 1D: 4 FP64 conserved planes read + 4 written
 CSPH_VALU_FILE = os.path.join(ROOT, "profiles", "step1d_csph_fp64_4m_valu.txt")
 CSPH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step1d_csph_fp64_4m_traffic.txt")
-CSPH_KERNEL = "step1d_kernel<ng::Plain64<4>, 0>"
+CSPH_KERNEL = "step1d_kernel<ng::Plain64<4>, 4>"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step2d_fp32_4096_traffic.txt")
 VALU_FILE = os.path.join(ROOT, "profiles", "step2d_fp32_4096_valu.txt")
 # non-packed FP32 vector issue of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
