@@ -86,7 +86,9 @@ extern "C" {
                             the displaced face values of eq. (14), U^{n+1/2} =
                             (U^n + U~)/2, Theta the minmod slopes of U^n per
                             unit length.  Sources are explicit (stiff_z is not
-                            used); the time step is that of eq. (16)          */
+                            used); the time step is that of eq. (16).  Every
+                            path of a 1D solve takes it (per-step, persistent,
+                            cooperative, batches, ng_step_static)             */
 
 /* status flags of ng_diag.flags */
 #define NG_FLAG_NONFINITE 1u
@@ -250,7 +252,7 @@ int ng_set_graph_steps(ng_solver* s, int32_t steps);
 int ng_set_small_limit(ng_solver* s, int64_t max_cells);
 
 /* Cooperative path (the time loop of eq. (15) with the dt of eq. (16) chosen
- * after every step).  A MUSCL solve that is alone in its object, 1D, without a
+ * after every step).  A solve that is alone in its object, 1D, without a
  * forced source and of at most max_cells cells is advanced by one
  * cooperative launch per call (up to 65536 steps each): every step, its
  * workgroups -- all resident together -- update their segments, meet at a

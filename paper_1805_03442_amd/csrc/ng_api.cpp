@@ -502,7 +502,7 @@ void shape_solve(ng_batch* b, Slot& s, bool alone = true)
 // The cooperative path: a batch whose only live solve is 1D, has no forced
 // source and at most coop_limit cells, on a device that supports cooperative
 // launches.  Marks that solve (Slot::coop), sets coop_slot (else -1) and the
-// launch shape: while the 60-cell segments fit one per wave in workgroups of
+// launch shape: while the segments (60 cells, 58 for CSPH-TVD) fit one per wave in workgroups of
 // kCoopSmallWaves waves (one per SIMD) with at most one workgroup per CU,
 // that; else workgroups of the kernel's largest size, as many as stay
 // resident together (and have a segment for every wave); the kernel deals
@@ -521,8 +521,7 @@ int choose_coop(ng_batch* b)
     const int64_t lim = b->coop_limit >= 0 ? b->coop_limit : kCoopCells;
     if (live != 1 || lim == 0) return NG_OK;
     Slot& s = b->slots[cand];
-    if (s.dim != 1 || s.d.bc[0] == kBcSource || s.d.scheme != kSchemeMuscl || s.d.ncell > lim)
-        return NG_OK;
+    if (s.dim != 1 || s.d.bc[0] == kBcSource || s.d.ncell > lim) return NG_OK;
     if (b->dev_coop < 0) {
         int dev = 0, coop = 0, cus = 0;
         CK(b, hipGetDevice(&dev));
@@ -533,8 +532,10 @@ int choose_coop(ng_batch* b)
     }
     if (!b->dev_coop || b->dev_cus < 1) return NG_OK;
     const int kind = kind_of(b->prec);
-    const int v = (s.d.riemann == NG_HLLC && !s.d.any_bc) ? 1 + s.d.cl_recipe : 0;
-    const int64_t segs = cdiv(s.d.nx, kInterior);
+    const int v = s.d.scheme == kSchemeCsph
+                      ? kVariantCsph
+                      : ((s.d.riemann == NG_HLLC && !s.d.any_bc) ? 1 + s.d.cl_recipe : 0);
+    const int64_t segs = cdiv(s.d.nx, seg_cells(s.d.scheme));
     int per_cu = 0, maxw = 0;
     CK(b, coop_capacity(kind, v, kCoopSmallWaves, &per_cu, &maxw));
     int waves = kCoopSmallWaves;

@@ -1127,18 +1127,23 @@ __device__ __forceinline__ void march1d_hllc(const InstDesc& d, const typename P
 //     (h - xi~_j) Theta_j / 2 and U^R = U^{n+1/2}_{j+1} - (h + xi~_{j+1})
 //     Theta_{j+1} / 2 (eq. (14)), U^{n+1/2} = (U^n + U~)/2;
 //   update (eq. (9)) on lanes 3..60: U^{n+1} = U~ - dt/h (F_{j+1/2} - F_{j-1/2}).
-// FP64 only (the state is stored whole).
-template <class P, bool BC>
+// FP64 only (the state is stored whole).  With first >= 0 the segments first
+// .. end-1 (the cooperative kernel's share of a wave); Coh: agent-scope state
+// loads and stores (Planes).
+template <class P, bool BC, bool Coh = false>
 __device__ __forceinline__ void march_csph(const InstDesc& d, const K64& k, int cur, int64_t item,
-                                           int lane, Acc<double>& acc)
+                                           int lane, Acc<double>& acc, int64_t first = -1,
+                                           int64_t end = -1)
 {
     static_assert(std::is_same<typename P::K, K64>::value, "CSPH-TVD runs on the FP64 state");
     constexpr int NC = 4;
     const int64_t n = d.nx;
-    const Planes<double, NC> src(d.buf[cur], n);
-    const Planes<double, NC> dst(d.buf[cur ^ 1], n);
-    const int64_t s0 = item * d.rows_per_item;
-    const int64_t s1 = s0 + d.rows_per_item < d.nstrips ? s0 + d.rows_per_item : d.nstrips;
+    const Planes<double, NC, Coh> src(d.buf[cur], n);
+    const Planes<double, NC, Coh> dst(d.buf[cur ^ 1], n);
+    const int64_t s0 = first >= 0 ? first : item * d.rows_per_item;
+    const int64_t s1 = first >= 0 ? end
+                                  : (s0 + d.rows_per_item < d.nstrips ? s0 + d.rows_per_item
+                                                                      : d.nstrips);
     const double h = d.h, wn = 2.0 / (3.0 * (h * h));
     // the predictor's particles sit at the centres: distances +-h exactly
     const double g1 = csph_grad_w(h, h, wn), g2 = csph_grad_w(-h, h, wn);
@@ -1502,7 +1507,12 @@ __global__ void __launch_bounds__(P::kCoopThreads) run_coop1d_kernel(
         const int64_t W = (int64_t)G * nw, gw = (int64_t)b * nw + wave;
         const int64_t f0 = gw * d.nstrips / W, f1 = (gw + 1) * d.nstrips / W;
         if (f0 < f1) {
-            if constexpr (V > 0)
+            if constexpr (V == kVariantCsph) {
+                if (d.any_bc)
+                    march_csph<P, true, true>(d, k, cur, 0, lane, acc, f0, f1);
+                else
+                    march_csph<P, false, true>(d, k, cur, 0, lane, acc, f0, f1);
+            } else if constexpr (V > 0)
                 march1d<P, 0, false, V - 1, true>(d, k, cur, nullptr, 0, lane, acc, f0, f1);
             else if (d.riemann == 1)
                 march1d_bc<P, 1, true>(d, k, cur, nullptr, 0, lane, acc, f0, f1);
@@ -1977,6 +1987,9 @@ static const void* coop_kernel_of(int v)
 {
     using P = Pol<4>;
     if (v == 0) return (const void*)run_coop1d_kernel<P, 0>;
+    if constexpr (std::is_same<typename P::K, K64>::value) {
+        if (v == kVariantCsph) return (const void*)run_coop1d_kernel<P, kVariantCsph>;
+    }
     if (v == 1 || !P::kRecipes) return (const void*)run_coop1d_kernel<P, 1>;
     if constexpr (P::kRecipes) {
         if (v == 2) return (const void*)run_coop1d_kernel<P, 2>;
@@ -1987,7 +2000,8 @@ static const void* coop_kernel_of(int v)
 
 static const void* coop_kernel(int prec, int variant)
 {
-    if (variant < 0 || variant > kRecipes + 1) return nullptr;
+    if (variant < 0 || (variant > kRecipes + 1 && !(variant == kVariantCsph && prec == 0)))
+        return nullptr;
     if (prec == 0) return coop_kernel_of<Plain64>(variant);
     if (prec == 1) return coop_kernel_of<Dev32>(variant);
     if (prec == 2) return coop_kernel_of<Mix32>(variant);

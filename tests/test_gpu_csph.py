@@ -3,10 +3,11 @@ the C ABI against the oracle (oracle/csph_oracle.c), bit for bit: state, t
 and dt on periodic, wall and outflow ends, with sources and a body force,
 on grids of 4 cells to a few thousand (one to many 58-cell wave segments,
 ragged last segments), on every path a lone solve can take (one launch per
-step, the persistent one-workgroup kernel, captured graphs through
-run_to_time) and in several launch shapes; at the size the benchmark times
-(2^22 cells) on two whole steps; in a batch beside MUSCL solves; through
-the entry point that allocates nothing.  The paper's own use (figure 2): the
+step, the persistent one-workgroup kernel, the cooperative kernel with a
+grid barrier per step, captured graphs through run_to_time) and in several
+launch shapes; at the size the benchmark times (2^22 cells) on two whole
+steps; in a batch beside MUSCL solves; through the entry point that
+allocates nothing.  The paper's own use (figure 2): the
 blast waves of section 2.4 on 200 ... 1600 cells approach a fine MUSCL run.
 """
 import sys
@@ -60,8 +61,10 @@ def _solver(ng, gas, n, U, bc, path, launch=None):
     s = ng.Solver(gas, n, 1, U=U, precision=ng.NG_FP64, riemann=ng.NG_HLL, bc=bc,
                   scheme=ng.NG_CSPH_TVD)
     if path == "per_step":
+        s.set_coop(0)
         s.set_small_limit(0)
     elif path == "small":
+        s.set_coop(0)
         s.set_small_limit(1 << 30)
     if launch:
         s.set_launch(*launch)
@@ -83,7 +86,7 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("path", ["per_step", "small", "default"])
+@pytest.mark.parametrize("path", ["per_step", "small", "coop"])
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_csph_bitwise_against_oracle(ng, oracle_mod, case, path):
     name, n, gas, ends, seed = case
@@ -141,7 +144,7 @@ def test_csph_blast_waves_bitwise(ng, oracle_mod, n):
     P = oracle_mod.CsphProblem(EULER, n, bc=bc)
     U0 = P.prim_to_cons(wl.blast_waves_1d(n))
     say(f"csph blast waves n={n}")
-    for path in ("per_step", "small"):
+    for path in ("per_step", "small", "coop"):
         s = _solver(ng, EULER, n, U0, bc, path)
         taken = s.run_to_time(0.038)
         d = s.diagnostics()
@@ -176,19 +179,50 @@ def test_csph_full_size_two_steps(ng, oracle_mod):
     assert d["t"] == ref["t"]
 
 
-def test_csph_is_not_cooperative_and_shares_a_batch(ng, oracle_mod):
-    """A lone CSPH solve runs one step kernel per step (the cooperative
-    kernel is the MUSCL step's); in an FP64 batch beside MUSCL solves every
-    member equals its own lone run bit for bit."""
+@pytest.mark.parametrize("n", [3000, 1 << 17, 100003])
+def test_csph_cooperative_equals_one_launch_per_step(ng, n):
+    """A lone CSPH solve runs as one cooperative launch (one wave per SIMD
+    for a few segments, 8-wave workgroups with runs of segments beyond);
+    state, t and dt equal one launch per step bit for bit, and a second call
+    continues from the first."""
+    gas = dict(wl.BASE_GAS, Q_T=2.0)
+    W = _moving_state(gas, n, 31 + n % 7)
+    bc = (W_, O_, 0, 0) if n == 100003 else (0, 0, 0, 0)
+    say(f"csph cooperative n={n}")
+    a = ng.Solver(gas, n, 1, W=W, precision=ng.NG_FP64, riemann=ng.NG_HLL, bc=bc,
+                  scheme=ng.NG_CSPH_TVD)
+    a.enable_timing(150)
+    a.step(150)
+    assert a.kernel_time()[2] == 1
+    a.enable_timing(0)
+    b = ng.Solver(gas, n, 1, W=W, precision=ng.NG_FP64, riemann=ng.NG_HLL, bc=bc,
+                  scheme=ng.NG_CSPH_TVD)
+    b.set_coop(0)
+    b.set_small_limit(0)
+    b.step(150)
+    da, db = a.diagnostics(), b.diagnostics()
+    assert da["status"] == 0 and db["status"] == 0 and da["steps"] == db["steps"] == 150
+    for key in ("t", "dt_last", "dt_next", "smax", "rho_min", "p_min"):
+        assert da[key] == db[key], key
+    assert np.array_equal(a.conserved(), b.conserved())
+    a.run_to_time(da["t"] + 30 * da["dt_last"])
+    b.run_to_time(db["t"] + 30 * db["dt_last"])
+    assert a.diagnostics()["t"] == b.diagnostics()["t"]
+    assert np.array_equal(a.conserved(), b.conserved())
+    a.close()
+    b.close()
+
+
+def test_csph_shares_a_batch_with_muscl(ng, oracle_mod):
+    """In an FP64 batch beside MUSCL solves every member equals its own lone
+    run bit for bit (the batch's 1D launch takes the general kernel, which
+    branches per solve)."""
     gas = dict(wl.BASE_GAS, Q_T=2.0)
     n = 3000
     W = _moving_state(gas, n, 31)
-    s = ng.Solver(gas, n, 1, W=W, precision=ng.NG_FP64, riemann=ng.NG_HLL,
-                  scheme=ng.NG_CSPH_TVD)
-    s.enable_timing(25)
+    P = oracle_mod.CsphProblem(gas, n)
+    s = _solver(ng, gas, n, P.prim_to_cons(W), (0, 0, 0, 0), "per_step")
     s.step(25)
-    assert s.kernel_time()[2] == 25
-    s.enable_timing(0)
     lone_csph = s.conserved()
     s.close()
     m = ng.Solver(gas, n, 1, W=W, precision=ng.NG_FP64, riemann=ng.NG_HLL)
@@ -217,7 +251,7 @@ def _sink_case():
     return gas, wl.acoustic_mode_1d(gas, 300, 3, 1e-2), 300
 
 
-@pytest.mark.parametrize("path", ["per_step", "small"])
+@pytest.mark.parametrize("path", ["per_step", "small", "coop"])
 def test_csph_rejected_step_keeps_last_good_state(ng, oracle_mod, path):
     """The step that produces p <= 0 is rejected at the oracle's step
     (NG_EPHYS); the solve keeps the oracle's last good state bit for bit and
