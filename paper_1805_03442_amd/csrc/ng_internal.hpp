@@ -122,22 +122,28 @@ struct InstCtrl {
 
 // Grid barrier of a cooperative launch (one solve advanced many steps per
 // launch by workgroups that stay resident together), zeroed before each
-// launch.  Workgroup b arrives at the counter of group b % groups (one group
-// up to kCoopFlat workgroups, else kCoopGroups); the last arrival of a group
-// arrives at top; the last arrival at top decides the step and writes the
-// outcome to every group's line: three 8-byte words, each (step number << 32
-// | 32 bits of payload) -- the low and high halves of the next CFL step and
-// (accepted | failure flags << 1) -- so that a reader which sees the step
-// number in all three words holds one whole message.  Each counter and line
-// sits in a 128-byte cache line of its own.
+// launch.  Messages are three 8-byte words, each (step number << 32 | 32 bits
+// of payload), so that a reader which sees the step number in all three words
+// holds one whole message.
+// Up to kCoopFlat workgroups: each workgroup writes its step's signal speed
+// (low and high halves) and failure flags into its own slot (by step parity)
+// and reads every slot itself, so all of them reach the same next step
+// without a second hop; a workgroup can be at most one step ahead of any
+// other, so two parities suffice.
+// More workgroups: workgroup b arrives at the counter of group b %
+// kCoopGroups; the last arrival of a group arrives at top; the last arrival
+// at top decides the step and writes the outcome to every group's line --
+// the low and high halves of the next CFL step and (accepted | failure flags
+// << 1).  Each counter and line sits in a 128-byte cache line of its own.
 constexpr int kCoopGroups = 16;
-constexpr int kCoopFlat = 32;
+constexpr int kCoopFlat = 128;
 constexpr int kCoopMaxWaves = 16;   // waves per workgroup of a cooperative launch
 struct CoopSync {
     uint32_t grp[kCoopGroups][32];
     uint32_t top[32];
     uint64_t line[kCoopGroups][16];
     uint32_t stall[32];            // [0]: set by a workgroup whose wait ran out
+    uint64_t fslot[2][kCoopFlat][4];   // [parity][workgroup]: launches of <= kCoopFlat
 };
 
 // Per-workgroup data of a cooperative launch, in the solve's reduction space:

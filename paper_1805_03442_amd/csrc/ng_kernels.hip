@@ -1458,6 +1458,54 @@ __device__ __forceinline__ void wait_mem() { __builtin_amdgcn_s_waitcnt(0x0070);
 // runs out, and the solve keeps the last step a barrier accepted.  Solves
 // with a forced source are not run here (their ghosts follow t through the
 // control block).
+// Wave-wide wait of a cooperative launch of G <= kCoopFlat workgroups for
+// every workgroup's (step << 32 | payload) words of step gen: lane j reads
+// slot j (and slot j + 64 when Two), at most spin_limit polls after the first.
+// On return m and f hold the largest signal speed and the union of the flags
+// of this lane's slots; true when the wait ran out.
+static_assert(kCoopFlat <= 2 * kWave, "poll_slots reads at most two slots per lane");
+template <bool Two>
+__device__ __forceinline__ bool poll_slots(const uint64_t (*slot)[4], uint32_t G, uint32_t gen,
+                                           int lane, int32_t spin_limit, double& m, uint32_t& f)
+{
+    const bool mine = (uint32_t)lane < G, mine2 = Two && (uint32_t)lane + 64u < G;
+    const uint64_t* sl = slot[mine ? lane : 0];
+    const uint64_t* sl2 = slot[mine2 ? lane + 64 : 0];
+    uint64_t w0 = 0, w1 = 0, w2 = 0, x0 = 0, x1 = 0, x2 = 0;
+    bool stalled = false;
+    for (int32_t n = 0;; n++) {
+        if (mine) {
+            w0 = __hip_atomic_load(sl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            w1 = __hip_atomic_load(sl + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            w2 = __hip_atomic_load(sl + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (Two && mine2) {
+            x0 = __hip_atomic_load(sl2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            x1 = __hip_atomic_load(sl2 + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            x2 = __hip_atomic_load(sl2 + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        bool have = !mine || ((uint32_t)(w0 >> 32) == gen && (uint32_t)(w1 >> 32) == gen &&
+                              (uint32_t)(w2 >> 32) == gen);
+        if (Two)
+            have = have && (!mine2 || ((uint32_t)(x0 >> 32) == gen &&
+                                       (uint32_t)(x1 >> 32) == gen &&
+                                       (uint32_t)(x2 >> 32) == gen));
+        if (__builtin_amdgcn_ballot_w64(!have) == 0ull) break;
+        if (n >= spin_limit) {
+            stalled = true;
+            break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+    m = mine ? __longlong_as_double((long long)((w0 & 0xffffffffull) | (w1 << 32))) : 0.0;
+    f = mine ? (uint32_t)w2 : 0u;
+    if (Two && mine2) {
+        m = fmax(m, __longlong_as_double((long long)((x0 & 0xffffffffull) | (x1 << 32))));
+        f |= (uint32_t)x2;
+    }
+    return stalled;
+}
+
 template <class P, int V>
 __global__ void __launch_bounds__(P::kCoopThreads) run_coop1d_kernel(
     const InstDesc* __restrict__ descs, const InstCtrl* __restrict__ ctrls, int inst,
@@ -1539,16 +1587,25 @@ __global__ void __launch_bounds__(P::kCoopThreads) run_coop1d_kernel(
                 m = fmax(m, s_sm[w]);
                 f |= s_fl[w];
             }
-            __hip_atomic_store(&slots[b].smax, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&slots[b].flags, f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            wait_mem();
             int role = 0;
-            const uint32_t pg = __hip_atomic_fetch_add(&cs->grp[grp][0], 1u, __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT);
-            if (pg == gen * gsize - 1u) {
-                if (ng == 1u) {
-                    role = 1;
-                } else {
+            if (ng == 1u) {
+                // a small launch: publish, every workgroup reads all slots
+                const uint64_t tag = (uint64_t)gen << 32;
+                const uint64_t mb = (uint64_t)__double_as_longlong(m);
+                uint64_t* sl = &cs->fslot[st & 1][b][0];
+                __hip_atomic_store(sl, tag | (mb & 0xffffffffull), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(sl + 1, tag | (mb >> 32), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(sl + 2, tag | (uint64_t)f, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                __hip_atomic_store(&slots[b].smax, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&slots[b].flags, f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                wait_mem();
+                const uint32_t pg = __hip_atomic_fetch_add(&cs->grp[grp][0], 1u, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+                if (pg == gen * gsize - 1u) {
                     const uint32_t pt = __hip_atomic_fetch_add(&cs->top[0], 1u, __ATOMIC_RELAXED,
                                                                __HIP_MEMORY_SCOPE_AGENT);
                     role = pt == gen * ng - 1u ? 1 : 0;
@@ -1596,7 +1653,41 @@ __global__ void __launch_bounds__(P::kCoopThreads) run_coop1d_kernel(
             r.p_min = v[8];
             r.step = (uint32_t)st;
         };
-        if (s_role == 1) {
+        if (ng == 1u) {
+            // every workgroup takes the step's outcome from all slots itself
+            // (lane j of wave 0 reads slot j): the same largest signal speed,
+            // union of the flags and next dt in each
+            if (threadIdx.x == 0) fold_rec();
+            if (wave == 0) {
+                // lane j reads slot j and, beyond 64 workgroups, slot j + 64
+                double m = 0.0;
+                uint32_t f = 0u;
+                bool stalled;
+                if (G <= 64u)
+                    stalled = poll_slots<false>(cs->fslot[st & 1], G, gen, lane, spin_limit, m, f);
+                else
+                    stalled = poll_slots<true>(cs->fslot[st & 1], G, gen, lane, spin_limit, m, f);
+                for (int mm = 32; mm >= 1; mm >>= 1) {
+                    m = fmax(m, lane_xor(m, lane, mm));
+                    f |= (uint32_t)__builtin_amdgcn_ds_bpermute(((lane ^ mm) & 63) << 2, (int)f);
+                }
+                if (lane == 0) {
+                    if (stalled) {
+                        __hip_atomic_fetch_or(&cs->stall[0], 1u, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+                        s_role = 2;
+                    } else {
+                        const uint32_t fb = f & 7u;
+                        const double dtc = fb ? dt_cfl : d.cfl * d.h / m;
+                        const uint64_t db = (uint64_t)__double_as_longlong(dtc);
+                        const uint64_t tag = (uint64_t)gen << 32;
+                        s_msg[0] = tag | (db & 0xffffffffull);
+                        s_msg[1] = tag | (db >> 32);
+                        s_msg[2] = tag | (uint64_t)(fb ? fb << 1 : 1u);
+                    }
+                }
+            }
+        } else if (s_role == 1) {
             // the step over all workgroups: the largest signal speed and the
             // union of the failure flags
             double m = 0.0;
