@@ -147,13 +147,13 @@ struct CoopSync {
 };
 
 // Per-workgroup data of a cooperative launch, in the solve's reduction space:
-// records of the workgroup's last two steps (by step parity), the step's
-// signal speed and flags for the barrier, and the workgroup's view of the
-// solve's control when it left.
+// records of the workgroup's last two steps (by step parity), written when
+// the launch ends, the step's signal speed and flags for the barrier, and
+// the workgroup's view of the solve's control when it left.
 struct CoopRec {
     double tot[5];      // sums of U^{n+1} over the workgroup's cells
-    double src[2];      // sums of the step's source increments
-    double bud[2];      // sums of the source increments of the launch's earlier accepted steps
+    double src[2];      // sums of the source increments of the launch's
+                        // accepted steps up to this step, this one included
     double smax, rho_min, p_min;
     uint32_t flags, step;
 };

@@ -1523,9 +1523,7 @@ __global__ void __launch_bounds__(P::kCoopThreads) run_coop1d_kernel(
     CoopRec* recs = (CoopRec*)d.partials;                // [parity][G]
     CoopSlot* slots = (CoopSlot*)(recs + 2 * (size_t)G);
     CoopView* views = (CoopView*)(slots + G);
-    __shared__ CoopRec s_rec[2];
-    __shared__ double s_bud[2];
-    __shared__ double s_sum[kCoopMaxWaves][9];
+    __shared__ double s_sum[kCoopMaxWaves][10];
     __shared__ double s_sm[kCoopMaxWaves];
     __shared__ uint32_t s_fl[kCoopMaxWaves];
     __shared__ int s_role;   // 0: waits, 1: decides the step, 2: its wait ran out
@@ -1538,18 +1536,24 @@ __global__ void __launch_bounds__(P::kCoopThreads) run_coop1d_kernel(
     int cur = c.cur, status = c.status;
     uint32_t bad = 0;
     bool active = status == 0 && t < t_end && steps < max_steps;
-    if (threadIdx.x == 0) {
-        s_bud[0] = s_bud[1] = 0.0;
-        s_rec[0].step = s_rec[1].step = 0xffffffffu;
-    }
-    __syncthreads();
+    // Per lane, the sums of the last computed step (acc), of the last
+    // accepted one (last) and the source increments of every accepted step
+    // (bud); they are folded into the workgroup's records once, when the
+    // launch ends, not at every step.
+    Acc<R> acc, last;
+    acc_init(acc);
+    acc_init(last);
+    double bud0 = 0.0, bud1 = 0.0;
+    int64_t st_c = -1;     // last computed step
+    bool cur_ok = false;   // ... and whether this workgroup saw it accepted
     for (int64_t st = 0; st < nsteps && active; st++) {
         const uint32_t gen = (uint32_t)(st + 1);
         double dt = dt_cfl;
         if (t + dt > t_end) dt = t_end - t;
         const typename P::K k = P::make(d, dt);
-        Acc<R> acc;
         acc_init(acc);
+        st_c = st;
+        cur_ok = false;
         // this wave's run of consecutive segments: the equal share
         // [g S / W, (g + 1) S / W) of the S segments over the launch's W waves
         const int64_t W = (int64_t)G * nw, gw = (int64_t)b * nw + wave;
@@ -1612,52 +1616,12 @@ __global__ void __launch_bounds__(P::kCoopThreads) run_coop1d_kernel(
                 }
             }
             s_role = role;
-            s_rec[st & 1].smax = m;
-            s_rec[st & 1].flags = f;
-        }
-        // this workgroup's FP64 sums of the step (lanes, then waves in order),
-        // while the last arrivals are on their way
-        {
-            double v[9];
-            for (int q = 0; q < 5; q++) v[q] = acc.tot[q];
-            v[5] = acc.src[0];
-            v[6] = acc.src[1];
-            v[7] = (double)acc.rmin;
-            v[8] = (double)acc.pmin;
-            for (int m = 32; m >= 1; m >>= 1) {
-                for (int q = 0; q < 7; q++) v[q] += lane_xor(v[q], lane, m);
-                v[7] = fmin(v[7], lane_xor(v[7], lane, m));
-                v[8] = fmin(v[8], lane_xor(v[8], lane, m));
-            }
-            if (lane == 0)
-                for (int q = 0; q < 9; q++) s_sum[wave][q] = v[q];
         }
         __syncthreads();
-        // thread 0: the waves' sums into the step's record (waves in order)
-        auto fold_rec = [&]() {
-            CoopRec& r = s_rec[st & 1];
-            double v[9];
-            for (int q = 0; q < 7; q++) v[q] = 0.0;
-            v[7] = v[8] = INFINITY;
-            for (int w = 0; w < nw; w++) {
-                for (int q = 0; q < 7; q++) v[q] += s_sum[w][q];
-                v[7] = fmin(v[7], s_sum[w][7]);
-                v[8] = fmin(v[8], s_sum[w][8]);
-            }
-            for (int q = 0; q < 5; q++) r.tot[q] = v[q];
-            r.src[0] = v[5];
-            r.src[1] = v[6];
-            r.bud[0] = s_bud[0];
-            r.bud[1] = s_bud[1];
-            r.rho_min = v[7];
-            r.p_min = v[8];
-            r.step = (uint32_t)st;
-        };
         if (ng == 1u) {
             // every workgroup takes the step's outcome from all slots itself
             // (lane j of wave 0 reads slot j): the same largest signal speed,
             // union of the flags and next dt in each
-            if (threadIdx.x == 0) fold_rec();
             if (wave == 0) {
                 // lane j reads slot j and, beyond 64 workgroups, slot j + 64
                 double m = 0.0;
@@ -1725,9 +1689,7 @@ __global__ void __launch_bounds__(P::kCoopThreads) run_coop1d_kernel(
                 for (int w = 0; w < 3; w++)
                     __hip_atomic_store(&cs->line[threadIdx.x][w], s_msg[w], __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
-            if (threadIdx.x == 0) fold_rec();
         } else if (threadIdx.x == 0) {
-            fold_rec();
             int32_t n = 0;
             for (;;) {
                 uint64_t mw[3];
@@ -1761,21 +1723,69 @@ __global__ void __launch_bounds__(P::kCoopThreads) run_coop1d_kernel(
                 (long long)((s_msg[0] & 0xffffffffull) | (s_msg[1] << 32)));
             nacc++;
             active = t < t_end && steps < max_steps;
-            if (threadIdx.x == 0) {
-                s_bud[0] += s_rec[st & 1].src[0];
-                s_bud[1] += s_rec[st & 1].src[1];
-            }
+            bud0 += acc.src[0];
+            bud1 += acc.src[1];
+            last = acc;
+            cur_ok = true;
         } else {
             status = -3;   // NG_EPHYS
             bad = out >> 1;
             active = false;
         }
-        __syncthreads();   // s_msg, s_role and s_bud are rewritten in the next step
+        __syncthreads();   // s_msg and s_role are rewritten in the next step
     }
-    // leave the workgroup's last two records and its view of the control
+    // The workgroup's records (lanes, then waves in order): the sums of the
+    // last computed step and, when this workgroup did not see that step
+    // accepted, of the last accepted one.  The after-kernel folds the records
+    // of the last step the most advanced workgroup accepted, found by its
+    // parity.
+    auto put_rec = [&](const Acc<R>& a, double b0, double b1, int64_t step) {
+        double v[10];
+        for (int q = 0; q < 5; q++) v[q] = a.tot[q];
+        v[5] = b0;
+        v[6] = b1;
+        v[7] = (double)a.smax;
+        v[8] = (double)a.rmin;
+        v[9] = (double)a.pmin;
+        for (int m = 32; m >= 1; m >>= 1) {
+            for (int q = 0; q < 7; q++) v[q] += lane_xor(v[q], lane, m);
+            v[7] = fmax(v[7], lane_xor(v[7], lane, m));
+            v[8] = fmin(v[8], lane_xor(v[8], lane, m));
+            v[9] = fmin(v[9], lane_xor(v[9], lane, m));
+        }
+        if (lane == 0)
+            for (int q = 0; q < 10; q++) s_sum[wave][q] = v[q];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int w = 1; w < nw; w++) {
+                for (int q = 0; q < 7; q++) v[q] += s_sum[w][q];
+                v[7] = fmax(v[7], s_sum[w][7]);
+                v[8] = fmin(v[8], s_sum[w][8]);
+                v[9] = fmin(v[9], s_sum[w][9]);
+            }
+            CoopRec r;
+            for (int q = 0; q < 5; q++) r.tot[q] = v[q];
+            r.src[0] = v[5];
+            r.src[1] = v[6];
+            r.smax = v[7];
+            r.rho_min = v[8];
+            r.p_min = v[9];
+            r.flags = 0u;
+            r.step = (uint32_t)step;
+            recs[(size_t)(step & 1) * G + b] = r;
+        }
+        __syncthreads();
+    };
+    if (st_c >= 0) {
+        if (cur_ok) {
+            put_rec(acc, bud0, bud1, st_c);
+        } else {
+            put_rec(acc, bud0 + acc.src[0], bud1 + acc.src[1], st_c);
+            if (st_c >= 1) put_rec(last, bud0, bud1, st_c - 1);
+        }
+    }
+    // and its view of the control
     if (threadIdx.x == 0) {
-        recs[b] = s_rec[0];
-        recs[G + b] = s_rec[1];
         CoopView w;
         w.t = t;
         w.dt_cfl = dt_cfl;
@@ -1832,8 +1842,8 @@ __global__ void __launch_bounds__(256) coop_after_kernel(const InstDesc* __restr
         for (int j = t; j < G; j += blockDim.x) {
             const CoopRec& r = recs[(size_t)p * G + j];
             for (int q = 0; q < 5; q++) v[q] += r.tot[q];
-            v[5] += r.bud[0] + r.src[0];
-            v[6] += r.bud[1] + r.src[1];
+            v[5] += r.src[0];
+            v[6] += r.src[1];
             v[7] = fmax(v[7], r.smax);
             v[8] = fmin(v[8], r.rho_min);
             v[9] = fmin(v[9], r.p_min);
