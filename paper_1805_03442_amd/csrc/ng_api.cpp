@@ -502,11 +502,12 @@ void shape_solve(ng_batch* b, Slot& s, bool alone = true)
 // The cooperative path: a batch whose only live solve is 1D, has no forced
 // source and at most coop_limit cells, on a device that supports cooperative
 // launches.  Marks that solve (Slot::coop), sets coop_slot (else -1) and the
-// launch shape: while the segments (60 cells, 58 for CSPH-TVD) fit one per wave in workgroups of
-// kCoopSmallWaves waves (one per SIMD) with at most one workgroup per CU,
-// that; else workgroups of the kernel's largest size, as many as stay
-// resident together (and have a segment for every wave); the kernel deals
-// the segments to the waves in turn.
+// launch shape: while the segments (60 cells, 58 for CSPH-TVD) fit one per
+// wave in workgroups of kCoopSmallWaves waves (one per SIMD) with at most one
+// workgroup per CU, that; else workgroups of the kernel's largest size, as
+// many as stay resident together (and have a segment for every wave), at
+// most kCoopFlat (the slots of the grid barrier); the kernel deals the
+// segments to the waves in runs.
 int choose_coop(ng_batch* b)
 {
     b->coop_slot = -1;
@@ -544,7 +545,8 @@ int choose_coop(ng_batch* b)
         CK(b, coop_capacity(kind, v, waves, &per_cu, &maxw));
     }
     const int64_t resident = (int64_t)per_cu * b->dev_cus;
-    const int64_t grid = std::min<int64_t>(cdiv(segs, waves), resident);
+    const int64_t grid = std::min<int64_t>(std::min<int64_t>(cdiv(segs, waves), resident),
+                                           kCoopFlat);
     if (grid < 1 || coop_space((uint64_t)grid) > (uint64_t)s.partial_cap * sizeof(Partial))
         return NG_OK;
     s.coop = true;

@@ -121,45 +121,31 @@ struct InstCtrl {
 };
 
 // Grid barrier of a cooperative launch (one solve advanced many steps per
-// launch by workgroups that stay resident together), zeroed before each
-// launch.  Messages are three 8-byte words, each (step number << 32 | 32 bits
-// of payload), so that a reader which sees the step number in all three words
-// holds one whole message.
-// Up to kCoopFlat workgroups: each workgroup writes its step's signal speed
-// (low and high halves) and failure flags into its own slot (by step parity)
-// and reads every slot itself, so all of them reach the same next step
-// without a second hop; a workgroup can be at most one step ahead of any
-// other, so two parities suffice.
-// More workgroups: workgroup b arrives at the counter of group b %
-// kCoopGroups; the last arrival of a group arrives at top; the last arrival
-// at top decides the step and writes the outcome to every group's line --
-// the low and high halves of the next CFL step and (accepted | failure flags
-// << 1).  Each counter and line sits in a 128-byte cache line of its own.
-constexpr int kCoopGroups = 16;
-constexpr int kCoopFlat = 128;
+// launch by at most kCoopFlat workgroups that stay resident together), zeroed
+// before each launch.  Each step every workgroup writes its signal speed (low
+// and high halves) and failure flags into its own slot -- three 8-byte words,
+// each (step number << 32 | 32 bits of payload), so that a reader which sees
+// the step number in all three words holds one whole message -- and reads
+// every slot itself, so that all of them reach the same next dt and
+// acceptance.  A workgroup can be at most one step ahead of any other (it
+// needs their slots of its current step), so slots by step parity suffice.
+constexpr int kCoopFlat = 256;
 constexpr int kCoopMaxWaves = 16;   // waves per workgroup of a cooperative launch
 struct CoopSync {
-    uint32_t grp[kCoopGroups][32];
-    uint32_t top[32];
-    uint64_t line[kCoopGroups][16];
-    uint32_t stall[32];            // [0]: set by a workgroup whose wait ran out
-    uint64_t fslot[2][kCoopFlat][4];   // [parity][workgroup]: launches of <= kCoopFlat
+    uint32_t stall[32];                // [0]: set by a workgroup whose wait ran out
+    uint64_t fslot[2][kCoopFlat][4];   // [step parity][workgroup]
 };
 
 // Per-workgroup data of a cooperative launch, in the solve's reduction space:
 // records of the workgroup's last two steps (by step parity), written when
-// the launch ends, the step's signal speed and flags for the barrier, and
-// the workgroup's view of the solve's control when it left.
+// the launch ends, and the workgroup's view of the solve's control when it
+// left.
 struct CoopRec {
     double tot[5];      // sums of U^{n+1} over the workgroup's cells
     double src[2];      // sums of the source increments of the launch's
                         // accepted steps up to this step, this one included
     double smax, rho_min, p_min;
     uint32_t flags, step;
-};
-struct CoopSlot {
-    double smax;
-    uint32_t flags, pad;
 };
 struct CoopView {
     double t, dt_cfl, dt_last;
@@ -170,7 +156,7 @@ struct CoopView {
 // bytes of reduction space a cooperative launch of G workgroups uses
 constexpr uint64_t coop_space(uint64_t G)
 {
-    return G * (2 * sizeof(CoopRec) + sizeof(CoopSlot) + sizeof(CoopView));
+    return G * (2 * sizeof(CoopRec) + sizeof(CoopView));
 }
 
 // Status of a solve whose cooperative launch ended at a wait that ran out of

@@ -193,10 +193,10 @@ struct Dev32 {
     using St = float;   // stored state: FP32 deviations
     using K = K32;
     static constexpr int kMinWaves = 1;
-    // eight waves, as in FP64: two such workgroups share a CU when the kernel
-    // fits 128 registers (sixteen-wave workgroups, which force 128, spill and
-    // were slower: 2^20 cells 17.6 against 14.6 us per step)
-    static constexpr int kCoopThreads = 512;
+    // twelve waves (three per SIMD at up to 168 registers, one workgroup per
+    // CU): 2^20 cells 12.3 against 13.2 us per step with eight; sixteen-wave
+    // workgroups, which force 128 registers, spill and were slower
+    static constexpr int kCoopThreads = 768;
     // the raw rows stay in registers until their update
     static constexpr bool kKeepRows = true;
     // the energy slot holds e = E - E_nu (deviation from e_r)
@@ -1441,15 +1441,15 @@ __device__ __forceinline__ void wait_mem() { __builtin_amdgcn_s_waitcnt(0x0070);
 // launch takes the run [g S / W, (g + 1) S / W) of the S segments: equal
 // counts to within one, neighbours' halos in the same cache lines) with
 // agent-scope state loads and stores (the stores write through to memory and
-// the loads never take a stale line of its own XCD's L2), reduces its signal
-// speed and failure flags, stores them to its slot, waits for the stores and
-// arrives at the two-level counter of the CoopSync block.  The last arrival
-// reads the G slots, decides the step (eq. (16)'s next CFL step, or
-// rejection) and writes the outcome to every group's line; the others poll
-// their group's line.  The FP64 sums of the step (totals, source budgets,
-// extrema) never cross the barrier: each workgroup folds its own into a
-// record while it waits, and a kernel after the launch (coop_after_kernel)
-// folds the records of the last accepted step into the control block.  Per-
+// the loads never take a stale line of its own XCD's L2); each workgroup
+// reduces its signal speed and failure flags, writes them to its slot of the
+// CoopSync block, and reads all G slots: every workgroup then decides the
+// step alike (eq. (16)'s next CFL step, or rejection).  The FP64 sums of the
+// steps (totals, source budgets, extrema) never cross the barrier: each lane
+// keeps those of its last computed and last accepted step, each workgroup
+// folds them into its records when the launch ends, and a kernel after the
+// launch (coop_after_kernel) folds the records of the last accepted step into
+// the control block.  Per-
 // cell arithmetic, t and dt follow the step kernels and the finalize kernel
 // operation for operation, so the state, t and dt are bitwise those of one
 // launch per step; only the summation order of the FP64 totals differs.
@@ -1458,12 +1458,54 @@ __device__ __forceinline__ void wait_mem() { __builtin_amdgcn_s_waitcnt(0x0070);
 // runs out, and the solve keeps the last step a barrier accepted.  Solves
 // with a forced source are not run here (their ghosts follow t through the
 // control block).
+
 // Wave-wide wait of a cooperative launch of G <= kCoopFlat workgroups for
 // every workgroup's (step << 32 | payload) words of step gen: lane j reads
 // slot j (and slot j + 64 when Two), at most spin_limit polls after the first.
 // On return m and f hold the largest signal speed and the union of the flags
 // of this lane's slots; true when the wait ran out.
-static_assert(kCoopFlat <= 2 * kWave, "poll_slots reads at most two slots per lane");
+static_assert(kCoopFlat <= 4 * kWave, "the slot waits read at most four slots per lane");
+
+// The same wait for 128 < G <= 256 workgroups: lane j reads slots j, j + 64,
+// j + 128, j + 192; a slot seen whole is folded at once (max and or are
+// idempotent, so a slot folded in an earlier poll may be folded again).  Out
+// of line: inlined, its twelve loads in flight cost the step loop registers.
+__device__ __noinline__ bool poll_slots4(const uint64_t (*slot)[4], uint32_t G, uint32_t gen,
+                                            int lane, int32_t spin_limit, double& m, uint32_t& f)
+{
+    m = 0.0;
+    f = 0u;
+    for (int32_t n = 0;; n++) {
+        bool have = true;
+        uint64_t w[4][3];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const uint32_t j = (uint32_t)lane + 64u * (uint32_t)q;
+            const uint64_t* sl = slot[j < G ? j : 0];
+#pragma unroll
+            for (int x = 0; x < 3; x++)
+                w[q][x] = j < G ? __hip_atomic_load(sl + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                : ((uint64_t)gen << 32);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const uint32_t j = (uint32_t)lane + 64u * (uint32_t)q;
+            if ((uint32_t)(w[q][0] >> 32) == gen && (uint32_t)(w[q][1] >> 32) == gen &&
+                (uint32_t)(w[q][2] >> 32) == gen) {
+                if (j < G) {
+                    m = fmax(m, __longlong_as_double(
+                                    (long long)((w[q][0] & 0xffffffffull) | (w[q][1] << 32))));
+                    f |= (uint32_t)w[q][2];
+                }
+            } else {
+                have = false;
+            }
+        }
+        if (__builtin_amdgcn_ballot_w64(!have) == 0ull) return false;
+        if (n >= spin_limit) return true;
+        __builtin_amdgcn_s_sleep(2);
+    }
+}
 template <bool Two>
 __device__ __forceinline__ bool poll_slots(const uint64_t (*slot)[4], uint32_t G, uint32_t gen,
                                            int lane, int32_t spin_limit, double& m, uint32_t& f)
@@ -1517,16 +1559,12 @@ __global__ void __launch_bounds__(P::kCoopThreads) run_coop1d_kernel(
     const uint32_t G = gridDim.x, b = blockIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int nw = blockDim.x >> 6;
-    const uint32_t ng = G <= (uint32_t)kCoopFlat ? 1u : (uint32_t)kCoopGroups;
-    const uint32_t grp = b % ng;
-    const uint32_t gsize = (G - 1u - grp) / ng + 1u;   // workgroups b' < G with b' % ng == grp
     CoopRec* recs = (CoopRec*)d.partials;                // [parity][G]
-    CoopSlot* slots = (CoopSlot*)(recs + 2 * (size_t)G);
-    CoopView* views = (CoopView*)(slots + G);
+    CoopView* views = (CoopView*)(recs + 2 * (size_t)G);
     __shared__ double s_sum[kCoopMaxWaves][10];
     __shared__ double s_sm[kCoopMaxWaves];
     __shared__ uint32_t s_fl[kCoopMaxWaves];
-    __shared__ int s_role;   // 0: waits, 1: decides the step, 2: its wait ran out
+    __shared__ int s_stall;  // this workgroup's wait ran out
     __shared__ uint64_t s_msg[3];
     // the solve's control, as every workgroup tracks it
     const double t_end = c.t_end;
@@ -1591,127 +1629,55 @@ __global__ void __launch_bounds__(P::kCoopThreads) run_coop1d_kernel(
                 m = fmax(m, s_sm[w]);
                 f |= s_fl[w];
             }
-            int role = 0;
-            if (ng == 1u) {
-                // a small launch: publish, every workgroup reads all slots
-                const uint64_t tag = (uint64_t)gen << 32;
-                const uint64_t mb = (uint64_t)__double_as_longlong(m);
-                uint64_t* sl = &cs->fslot[st & 1][b][0];
-                __hip_atomic_store(sl, tag | (mb & 0xffffffffull), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(sl + 1, tag | (mb >> 32), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(sl + 2, tag | (uint64_t)f, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            } else {
-                __hip_atomic_store(&slots[b].smax, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(&slots[b].flags, f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                wait_mem();
-                const uint32_t pg = __hip_atomic_fetch_add(&cs->grp[grp][0], 1u, __ATOMIC_RELAXED,
-                                                           __HIP_MEMORY_SCOPE_AGENT);
-                if (pg == gen * gsize - 1u) {
-                    const uint32_t pt = __hip_atomic_fetch_add(&cs->top[0], 1u, __ATOMIC_RELAXED,
-                                                               __HIP_MEMORY_SCOPE_AGENT);
-                    role = pt == gen * ng - 1u ? 1 : 0;
-                }
-            }
-            s_role = role;
+            // publish: three (step << 32 | payload) words in this
+            // workgroup's slot -- the low and high halves of its signal speed
+            // and its flags
+            const uint64_t tag = (uint64_t)gen << 32;
+            const uint64_t mb = (uint64_t)__double_as_longlong(m);
+            uint64_t* sl = &cs->fslot[st & 1][b][0];
+            __hip_atomic_store(sl, tag | (mb & 0xffffffffull), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(sl + 1, tag | (mb >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(sl + 2, tag | (uint64_t)f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_stall = 0;
         }
         __syncthreads();
-        if (ng == 1u) {
-            // every workgroup takes the step's outcome from all slots itself
-            // (lane j of wave 0 reads slot j): the same largest signal speed,
-            // union of the flags and next dt in each
-            if (wave == 0) {
-                // lane j reads slot j and, beyond 64 workgroups, slot j + 64
-                double m = 0.0;
-                uint32_t f = 0u;
-                bool stalled;
-                if (G <= 64u)
-                    stalled = poll_slots<false>(cs->fslot[st & 1], G, gen, lane, spin_limit, m, f);
-                else
-                    stalled = poll_slots<true>(cs->fslot[st & 1], G, gen, lane, spin_limit, m, f);
-                for (int mm = 32; mm >= 1; mm >>= 1) {
-                    m = fmax(m, lane_xor(m, lane, mm));
-                    f |= (uint32_t)__builtin_amdgcn_ds_bpermute(((lane ^ mm) & 63) << 2, (int)f);
-                }
-                if (lane == 0) {
-                    if (stalled) {
-                        __hip_atomic_fetch_or(&cs->stall[0], 1u, __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT);
-                        s_role = 2;
-                    } else {
-                        const uint32_t fb = f & 7u;
-                        const double dtc = fb ? dt_cfl : d.cfl * d.h / m;
-                        const uint64_t db = (uint64_t)__double_as_longlong(dtc);
-                        const uint64_t tag = (uint64_t)gen << 32;
-                        s_msg[0] = tag | (db & 0xffffffffull);
-                        s_msg[1] = tag | (db >> 32);
-                        s_msg[2] = tag | (uint64_t)(fb ? fb << 1 : 1u);
-                    }
-                }
-            }
-        } else if (s_role == 1) {
-            // the step over all workgroups: the largest signal speed and the
-            // union of the failure flags
+        // every workgroup takes the step's outcome from all slots itself
+        // (lane j of wave 0 reads slot j, ...): the same largest signal speed,
+        // union of the flags and next dt in each
+        if (wave == 0) {
+            // lane j reads slot j and, beyond 64 workgroups, slot j + 64
             double m = 0.0;
-            uint32_t f = 0;
-            for (uint32_t j = threadIdx.x; j < G; j += blockDim.x) {
-                m = fmax(m, __hip_atomic_load(&slots[j].smax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-                f |= __hip_atomic_load(&slots[j].flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
+            uint32_t f = 0u;
+            bool stalled;
+            if (G <= 64u)
+                stalled = poll_slots<false>(cs->fslot[st & 1], G, gen, lane, spin_limit, m, f);
+            else if (G <= 128u)
+                stalled = poll_slots<true>(cs->fslot[st & 1], G, gen, lane, spin_limit, m, f);
+            else
+                stalled = poll_slots4(cs->fslot[st & 1], G, gen, lane, spin_limit, m, f);
             for (int mm = 32; mm >= 1; mm >>= 1) {
                 m = fmax(m, lane_xor(m, lane, mm));
                 f |= (uint32_t)__builtin_amdgcn_ds_bpermute(((lane ^ mm) & 63) << 2, (int)f);
             }
-            // (thread 0 read the arrival's s_sm / s_fl before the last barrier)
             if (lane == 0) {
-                s_sm[wave] = m;
-                s_fl[wave] = f;
-            }
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                for (int w = 1; w < nw; w++) {
-                    m = fmax(m, s_sm[w]);
-                    f |= s_fl[w];
-                }
-                const uint32_t fb = f & 7u;
-                // eq. (16) for the new state, as the finalize kernel computes it
-                const double dtc = fb ? dt_cfl : d.cfl * d.h / m;
-                const uint64_t db = (uint64_t)__double_as_longlong(dtc);
-                const uint64_t tag = (uint64_t)gen << 32;
-                s_msg[0] = tag | (db & 0xffffffffull);
-                s_msg[1] = tag | (db >> 32);
-                s_msg[2] = tag | (uint64_t)(fb ? fb << 1 : 1u);
-            }
-            __syncthreads();
-            if (threadIdx.x < ng)
-                for (int w = 0; w < 3; w++)
-                    __hip_atomic_store(&cs->line[threadIdx.x][w], s_msg[w], __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-        } else if (threadIdx.x == 0) {
-            int32_t n = 0;
-            for (;;) {
-                uint64_t mw[3];
-                for (int w = 0; w < 3; w++)
-                    mw[w] = __hip_atomic_load(&cs->line[grp][w], __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT);
-                if ((uint32_t)(mw[0] >> 32) == gen && (uint32_t)(mw[1] >> 32) == gen &&
-                    (uint32_t)(mw[2] >> 32) == gen) {
-                    for (int w = 0; w < 3; w++) s_msg[w] = mw[w];
-                    break;
-                }
-                if (++n > spin_limit) {
+                if (stalled) {
                     __hip_atomic_fetch_or(&cs->stall[0], 1u, __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT);
-                    s_role = 2;
-                    break;
+                    s_stall = 1;
+                } else {
+                    const uint32_t fb = f & 7u;
+                    const double dtc = fb ? dt_cfl : d.cfl * d.h / m;
+                    const uint64_t db = (uint64_t)__double_as_longlong(dtc);
+                    const uint64_t tag = (uint64_t)gen << 32;
+                    s_msg[0] = tag | (db & 0xffffffffull);
+                    s_msg[1] = tag | (db >> 32);
+                    s_msg[2] = tag | (uint64_t)(fb ? fb << 1 : 1u);
                 }
-                __builtin_amdgcn_s_sleep(2);
             }
         }
         __syncthreads();
-        if (s_role == 2) break;
+        if (s_stall) break;
         const uint32_t out = (uint32_t)s_msg[2];
         if (out & 1u) {
             // accepted: as accept_step advances the control block
@@ -1732,7 +1698,7 @@ __global__ void __launch_bounds__(P::kCoopThreads) run_coop1d_kernel(
             bad = out >> 1;
             active = false;
         }
-        __syncthreads();   // s_msg and s_role are rewritten in the next step
+        __syncthreads();   // s_msg and s_stall are rewritten in the next step
     }
     // The workgroup's records (lanes, then waves in order): the sums of the
     // last computed step and, when this workgroup did not see that step
@@ -1813,7 +1779,7 @@ __global__ void __launch_bounds__(256) coop_after_kernel(const InstDesc* __restr
     const InstDesc& d = descs[inst];
     InstCtrl& c = ctrls[inst];
     const CoopRec* recs = (const CoopRec*)d.partials;
-    const CoopView* views = (const CoopView*)((const CoopSlot*)(recs + 2 * (size_t)G) + G);
+    const CoopView* views = (const CoopView*)(recs + 2 * (size_t)G);
     __shared__ uint64_t s_key[4];
     __shared__ double sh[4][10];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
