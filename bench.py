@@ -122,17 +122,20 @@ def setup_solver(s):
 
 
 def timed_run(ng, torch, gas, W, n, steps, warmup, precision, bc=(0, 0, 0, 0), reps=REPS,
-              ny=None, tune=True, **kw):
+              ny=None, tune=True, coop=None, **kw):
     """Warm-up (>= WARMUP_SECONDS and >= warmup steps), ``reps`` windows of
     ``steps`` steps between HIP events on the solver's stream (median), then
     one window of max(steps, 100) steps whose every step kernel carries its
     own start/end events (mean kernel duration).  ny: n x n when None; kw go
-    to the solver (riemann, scheme); tune: apply the cached launch shape."""
+    to the solver (riemann, scheme); tune: apply the cached launch shape;
+    coop: ng_set_coop's cell limit (0: one launch per step for a 1D solve)."""
     s = ng.Solver(gas, n, n if ny is None else ny, W=W, precision=precision, bc=bc, **kw)
     if tune:
         setup_solver(s)
     elif GRAPH_STEPS is not None:
         s.set_graph_steps(GRAPH_STEPS)
+    if coop is not None:
+        s.set_coop(coop)
     st = torch.cuda.current_stream()
     s.step(max(warmup, 1))
     torch.cuda.synchronize()
@@ -325,8 +328,11 @@ def csph_leg(ng, torch, np, wl, args, fine_rho=None):
     nc = wc["nx"]
     k = args.csph_steps
     log(f"[bench] CSPH-TVD 1D {nc} cells: {REPS} windows of {k} steps")
+    # one launch per step (the cooperative path would take this grid too, at
+    # about the same rate: 2^22 cells are compute-bound either way), so that
+    # the timed kernel is the step kernel whose roofline is reported
     r = timed_run(ng, torch, wc["gas"], wc["W"], nc, k, args.warmup, ng.NG_FP64, ny=1,
-                  tune=False, riemann=ng.NG_HLL, scheme=ng.NG_CSPH_TVD)
+                  tune=False, coop=0, riemann=ng.NG_HLL, scheme=ng.NG_CSPH_TVD)
     value = nc * k / (r["total_ms"] * 1e-3)
     kern_s = r["step_ms"] * 1e-3
     hbm = BYTES_PER_CELL_CSPH * nc / kern_s / 1e9
@@ -351,6 +357,7 @@ def csph_leg(ng, torch, np, wl, args, fine_rho=None):
     tr = counter_record(CSPH_TRAFFIC_FILE)
     roof["hbm"]["traffic"] = tr["bytes_per_launch"] if tr is not None else None
     res = {"workload": wc["name"], "precision": "fp64", "riemann": "hll", "steps": k,
+           "path": "one launch per step",
            "value": value, "unit": "cell-updates/s", "us_per_step": 1e3 * r["total_ms"] / k,
            "windows_ms": r["windows_ms"], "roofline": roof}
     log(f"[bench] CSPH-TVD {value:.3e} cell-updates/s, step kernel {1e3 * r['step_ms']:.1f} us")
