@@ -1,6 +1,8 @@
-"""The oracle built with AddressSanitizer and UndefinedBehaviorSanitizer (host
-code, gcc) and driven through every boundary kind, both fluxes and the stiff
-branch on small 1D and 2D grids: no invalid access, no undefined behaviour."""
+"""The oracles built with AddressSanitizer and UndefinedBehaviorSanitizer (host
+code, gcc): the MUSCL oracle through every boundary kind, both fluxes and the
+stiff branch on small 1D and 2D grids, the CSPH-TVD oracle through every 1D
+boundary kind from 4 cells up (and its refusals): no invalid access, no
+undefined behaviour."""
 import os
 import shutil
 import subprocess
@@ -14,6 +16,20 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 def test_oracle_under_address_and_ub_sanitizers(tmp_path):
     exe = tmp_path / "oracle_driver"
     src = os.path.join(HERE, "sanitize", "oracle_driver.c")
+    subprocess.check_call(["gcc", "-O1", "-g", "-fno-omit-frame-pointer", "-ffp-contract=off",
+                           "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                           "-o", str(exe), src, "-lm"])
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:verify_asan_link_order=0",
+               UBSAN_OPTIONS="print_stacktrace=1")
+    r = subprocess.run([str(exe)], capture_output=True, text=True, env=env, timeout=300)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "0 failures" in r.stdout
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="needs gcc")
+def test_csph_oracle_under_address_and_ub_sanitizers(tmp_path):
+    exe = tmp_path / "csph_driver"
+    src = os.path.join(HERE, "sanitize", "csph_driver.c")
     subprocess.check_call(["gcc", "-O1", "-g", "-fno-omit-frame-pointer", "-ffp-contract=off",
                            "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
                            "-o", str(exe), src, "-lm"])
