@@ -86,7 +86,10 @@ extern "C" {
                             the displaced face values of eq. (14), U^{n+1/2} =
                             (U^n + U~)/2, Theta the minmod slopes of U^n per
                             unit length.  Sources are explicit (stiff_z is not
-                            used); the time step is that of eq. (16).  Every
+                            used: the relaxation of eq. (4) is stable while
+                            dt/tau stays below about 2, else the step fails
+                            with NG_EPHYS); the time step is that of eq. (16).
+                            Every
                             path of a 1D solve takes it (per-step, persistent,
                             cooperative, batches, ng_step_static)             */
 
