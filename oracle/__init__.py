@@ -92,7 +92,7 @@ def lib():
         # as the MUSCL mutation tests make)
         if hasattr(L, "cs_step"):
             L.cs_step.argtypes = [C.POINTER(OrGas), C.POINTER(OrGrid), C.POINTER(OrNum), dp,
-                                  dp, C.c_double, dp, dp]
+                                  dp, C.c_double, C.c_double, dp, dp]
             L.cs_step.restype = C.c_int
             L.cs_run.argtypes = L.or_run.argtypes
             L.cs_run.restype = C.c_int
@@ -196,16 +196,17 @@ class Problem:
 
 class CsphProblem(Problem):
     """The CSPH-TVD scheme of section 2.3 (eqs. (9)-(14)) on a 1D grid with
-    periodic, wall or outflow ends: same gas, grid, time step (eq. (16)) and
-    state layout as ``Problem``; ``riemann`` and ``stiff_z`` are not used (HLL,
-    explicit sources)."""
+    periodic, wall or outflow ends or a forced source at the x-low end: same
+    gas, grid, time step (eq. (16)), source and state layout as ``Problem``;
+    ``riemann`` and ``stiff_z`` are not used (HLL, explicit sources)."""
 
     def __init__(self, gas: dict, nx: int, h: float | None = None, cfl: float = 0.4,
-                 bc=(BC_PERIODIC,) * 4):
-        super().__init__(gas, nx, 1, h=h, cfl=cfl, riemann=HLL, bc=bc)
+                 bc=(BC_PERIODIC,) * 4, source=(0.0, 0.0)):
+        super().__init__(gas, nx, 1, h=h, cfl=cfl, riemann=HLL, bc=bc, source=source)
 
     def step(self, U: np.ndarray, dt: float, t: float = 0.0, xi: bool = False):
-        """One step with a given dt.  Returns (status, U_new, src[2]), and with
+        """One step with a given dt from the state U at time t.  Returns
+        (status, U_new, src[2]), and with
         ``xi`` also the particles' displacements at the end of the Lagrangian
         stage (eq. (11)), one per cell."""
         U = np.ascontiguousarray(U, dtype=np.float64).reshape(5, 1, self.nx)
@@ -213,7 +214,7 @@ class CsphProblem(Problem):
         src = np.zeros(2)
         X = np.zeros(self.nx)
         st = lib().cs_step(C.byref(self._g), C.byref(self._gr), C.byref(self._nm), _p(U),
-                           _p(V), float(dt), _p(src), _p(X) if xi else None)
+                           _p(V), float(t), float(dt), _p(src), _p(X) if xi else None)
         return (st, V, src, X) if xi else (st, V, src)
 
     def run(self, U: np.ndarray, nsteps: int, t0: float = 0.0, t_end: float = 0.0):

@@ -52,7 +52,9 @@
  *   - Theta: minmod-limited slopes of the conserved values at t^n, per unit
  *     length (the limiter the MUSCL oracle takes).
  *   - Boundaries: the ghost particles are the ghost cells of the MUSCL rule
- *     (periodic image, or mirror with the normal momentum reversed); a
+ *     (periodic image, or mirror with the normal momentum reversed; before a
+ *     forced source, the three particles x = -h/2, -3h/2, -5h/2 carry the
+ *     source's plane wave at the step's start time, or_source_ghost); a
  *     ghost's displacement follows from its own velocity like any particle's.
  *   - No stiff branch: the sources are explicit in both stages.
  *
@@ -147,19 +149,19 @@ static void cs_flux(const or_gas* g, const double UL[4], const double UR[4], dou
 }
 
 /*
- * One CSPH-TVD step from U_in (1D, ny = 1, 5 planes with rho v = 0) to U_out
- * with a given dt.  src[0] receives the energy sources of the step
+ * One CSPH-TVD step from U_in (1D, ny = 1, 5 planes with rho v = 0), the state
+ * at time t, to U_out with a given dt.  src[0] receives the energy sources of the step
  * (dt/2 of the predictor's plus dt/2 of the corrector's, summed over cells)
  * and src[1] those of E_nu.  xi_out, when not NULL, receives the n
  * displacements xi^{n+1} the Lagrangian stage leaves.  Returns OR_OK, or OR_EPHYS if a density or
  * pressure of U_out is not positive or a value is not finite; OR_EINVAL for a
- * 2D grid or a source end.
+ * 2D grid.
  */
 int cs_step(const or_gas* g, const or_grid* gr, const or_num* nm, const double* U_in,
-            double* U_out, double dt, double* src, double* xi_out)
+            double* U_out, double t, double dt, double* src, double* xi_out)
 {
     (void)nm;
-    if (gr->ny != 1 || gr->bc[0] == OR_BC_SOURCE) return OR_EINVAL;
+    if (gr->ny != 1) return OR_EINVAL;
     const int64_t n = gr->nx;
     const int64_t G = 3;                 /* stencil radius of the step    */
     const int64_t ne = n + 2 * G;
@@ -181,14 +183,24 @@ int cs_step(const or_gas* g, const or_grid* gr, const or_num* nm, const double* 
 #define AT(A, c, j) (A)[(c) * ne + (j) + G]
 
     /* particles at the cell centres with the cell values (ghosts by the
-     * boundary rule; a wall ghost carries the reversed momentum) */
+     * boundary rule; a wall ghost carries the reversed momentum, a source
+     * ghost the forced wave at time t) */
     for (j = -G; j < n + G; j++) {
         int flip;
         int64_t s = or_ghost(j, n, gr->bc[0], gr->bc[1], &flip);
-        AT(Un, 0, j) = U_in[s];
-        AT(Un, 1, j) = flip ? -U_in[n + s] : U_in[n + s];
-        AT(Un, 2, j) = U_in[3 * n + s];
-        AT(Un, 3, j) = U_in[4 * n + s];
+        if (j < 0 && gr->bc[0] == OR_BC_SOURCE) {
+            double Ug[5];
+            or_source_ghost(g, gr, t, j, 0, Ug);
+            AT(Un, 0, j) = Ug[0];
+            AT(Un, 1, j) = Ug[1];
+            AT(Un, 2, j) = Ug[3];
+            AT(Un, 3, j) = Ug[4];
+        } else {
+            AT(Un, 0, j) = U_in[s];
+            AT(Un, 1, j) = flip ? -U_in[n + s] : U_in[n + s];
+            AT(Un, 2, j) = U_in[3 * n + s];
+            AT(Un, 3, j) = U_in[4 * n + s];
+        }
         un[j + G] = AT(Un, 1, j) / AT(Un, 0, j);
     }
 
@@ -298,7 +310,7 @@ int cs_run(const or_gas* g, const or_grid* gr, const or_num* nm, double* U, int6
         double dt = or_dt(g, gr, nm, U);
         if (t_end > 0.0 && *t + dt > t_end) dt = t_end - *t;
         double src[2];
-        st = cs_step(g, gr, nm, U, V, dt, src, NULL);
+        st = cs_step(g, gr, nm, U, V, *t, dt, src, NULL);
         if (st != OR_OK) break;
         memcpy(U, V, (size_t)(5 * n) * sizeof(double));
         *t += dt;

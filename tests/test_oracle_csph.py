@@ -285,3 +285,94 @@ def test_walls_equal_the_mirrored_periodic_domain(oracle_lib):
     for c in (0, 1, 3, 4):
         assert np.max(np.abs(a[c] - b[c])) <= 1e-12 * scale[c], c
     assert rw["t"] == rp["t"]
+
+
+RESULTS_UNSTABLE = dict(gamma=1.4, R=1.0, Cv=0.1, rho0=1.0, T0=1.0, tau0=0.05, tau_rho=-1.0,
+                        tau_T=-1.5, Q0=10.0, Q_rho=0.0, Q_T=0.0, I0=10.0, I_rho=0.0, I_T=0.0,
+                        fx=0.0, fy=0.0)
+
+
+def _csph_forced_wave(oracle_lib, gas, n, lam=0.1, amp=1e-4, t_end=0.85):
+    """A forced source at x = 0 (outflow at x = 1) from the uniform
+    background until the front is near x = 1: the envelope's spatial growth
+    rate, its value at x = 0 over the amplitude, the wavenumber and the phase
+    offset phi of sin(omega t - Re k x + phi), over 0.1 < x < 0.7."""
+    P = oracle_lib.CsphProblem(gas, n, bc=(oracle_lib.BC_SOURCE, oracle_lib.BC_OUTFLOW, 0, 0),
+                               source=(amp, lam))
+    r = P.run(P.prim_to_cons(wl.uniform_state(gas, n)), 10 ** 7, t_end=t_end)
+    assert r["status"] == 0 and r["t"] == t_end
+    d = r["U"][0, 0] - gas["rho0"]
+    x = (np.arange(n) + 0.5) / n
+    m = int(round(lam * n))
+    cs, amps = [], []
+    for i0 in range(0, n - m, m // 2):
+        seg = d[i0:i0 + m]
+        cs.append(x[i0:i0 + m].mean())
+        amps.append(0.5 * (seg.max() - seg.min()))
+    cs, amps = np.array(cs), np.array(amps)
+    sel = (cs > 0.1) & (cs < 0.7)
+    rate, icpt = np.polyfit(cs[sel], np.log(amps[sel]), 1)
+    zc = np.array([x[i] + (x[i + 1] - x[i]) * d[i] / (d[i] - d[i + 1])
+                   for i in range(int(0.1 * n), int(0.7 * n)) if d[i] * d[i + 1] < 0])
+    kre = math.pi / np.polyfit(np.arange(len(zc)), zc, 1)[0]
+    c = math.sqrt(gas["gamma"] * gas["R"] * gas["T0"])
+    om = c * 2 * math.pi / lam
+    k = D.spatial_k(gas, om)
+    ph = np.mod(k.real * zc - om * t_end, math.pi)
+    phi = float(np.angle(np.mean(np.exp(2j * ph))) / 2)
+    return rate, math.exp(icpt) / amp, kre, phi
+
+
+def test_forced_source_against_the_signalling_roots(oracle_lib):
+    """Section 3's forced source into the unstable medium: a source of real
+    frequency omega = c k0 (lambda = 0.1) launches a wave whose envelope grows
+    along x at -Im k, k the right-going root of eq. (8) at that omega, with
+    wavenumber Re k; amplitude and phase at x = 0 are what the source's
+    incoming characteristic transmits.  The split scheme is first order for
+    sound, so the growth rate converges at about first order: its error falls
+    by more than 3.5 over two doublings (1000 to 4000 cells) and is below 0.1
+    at 4000; there the wavenumber is within 5e-4, the amplitude within 0.02
+    and the phase within 0.008 (a ghost one cell off shifts it by Re k h =
+    0.016)."""
+    gas = RESULTS_UNSTABLE
+    c = math.sqrt(gas["gamma"] * gas["R"] * gas["T0"])
+    om = c * 2 * math.pi / 0.1
+    k = D.spatial_k(gas, om)
+    T = D.source_transmission(gas, om)
+    assert k.imag < 0
+    errs = []
+    for n in (1000, 2000, 4000):
+        rate, a0, kre, phi = _csph_forced_wave(oracle_lib, gas, n)
+        errs.append(abs(rate + k.imag))
+    assert errs[0] > errs[1] > errs[2] and errs[0] / errs[2] > 3.5, errs
+    assert errs[2] < 0.1, errs
+    assert kre == pytest.approx(k.real, rel=5e-4), (kre, k)
+    assert a0 == pytest.approx(abs(T), abs=0.02), (a0, T)
+    assert phi == pytest.approx(-np.angle(T), abs=0.008), (phi, T)
+
+
+def test_forced_source_steady_at_zero_amplitude_and_follows_time(oracle_lib):
+    """With zero amplitude the source's ghost particles are the background:
+    the pumped uniform background stays bitwise uniform.  With a wave, the
+    source is a function of the time of the state a step starts from:
+    stepping a state stored at time t with that time equals the same steps
+    taken from t in one run, and differs from stepping it as if at t = 0."""
+    gas = RESULTS_UNSTABLE
+    n = 200
+    bc = (oracle_lib.BC_SOURCE, oracle_lib.BC_OUTFLOW, 0, 0)
+    P = oracle_lib.CsphProblem(gas, n, bc=bc, source=(0.0, 0.1))
+    U0 = P.prim_to_cons(wl.uniform_state(gas, n))
+    r = P.run(U0, 40)
+    assert r["status"] == 0 and np.array_equal(r["U"], U0)
+    P = oracle_lib.CsphProblem(gas, n, bc=bc, source=(1e-3, 0.1))
+    a = P.run(U0, 30)
+    b = P.run(a["U"], 10, t0=a["t"])
+    U, t = a["U"], a["t"]
+    for _ in range(10):
+        dt = P.dt(U)
+        st, U, _ = P.step(U, dt, t)
+        assert st == 0
+        t += dt
+    assert np.array_equal(U, b["U"]) and t == b["t"]
+    dt = P.dt(a["U"])
+    assert not np.array_equal(P.step(a["U"], dt, 0.0)[1], P.step(a["U"], dt, a["t"])[1])

@@ -46,6 +46,10 @@ MUTATIONS = {
     "slope_not_per_length": [("                                  AT(Un, c, j + 1) - AT(Un, c, j)) / h;",
                               "                                  AT(Un, c, j + 1) - AT(Un, c, j));")],
     "budget_full_step": [("        yE[j + G] = hdt * se;", "        yE[j + G] = dt * se;")],
+    "source_ghost_one_cell_off": [("            or_source_ghost(g, gr, t, j, 0, Ug);",
+                                   "            or_source_ghost(g, gr, t, j + 1, 0, Ug);")],
+    "source_ignores_time": [("            or_source_ghost(g, gr, t, j, 0, Ug);",
+                             "            or_source_ghost(g, gr, 0.0, j, 0, Ug);")],
 }
 
 
