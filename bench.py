@@ -321,9 +321,10 @@ def csph_leg(ng, torch, np, wl, args, fine_rho=None):
     issue from the committed SQ_INSTS_VALU count of the kernel, and HBM at
     64 algorithmic bytes per cell), the paper's figure-2 runs (blast waves
     between walls to t = 0.038 on 200 and 1600 cells, CSPH-TVD beside MUSCL,
-    L1 density difference from the 128000-cell MUSCL run when that leg ran;
-    skipped with the paper's other runs), and the oracle on two whole steps
-    of the same grid on one host core."""
+    L1 density difference from the 128000-cell MUSCL run when that leg ran)
+    and section 3's forced-source runs with both schemes (skipped with the
+    paper's other runs), and the oracle on two whole steps of the same grid
+    on one host core."""
     wc = wl.workload_csph_1d()
     nc = wc["nx"]
     k = args.csph_steps
@@ -404,6 +405,34 @@ def csph_leg(ng, torch, np, wl, args, fine_rho=None):
             bw[f"{name}_n{nb}"] = rec
     res["blast_waves_t0038"] = bw
     log(f"[bench] CSPH-TVD blast waves: {bw}")
+    # section 3's forced-source runs to t = 0.8 with both schemes (FP64): the
+    # relative L1 difference of the velocity fields at the paper's sizes and
+    # at 12800 cells
+    xc = {}
+    for stage in ("linear", "nonlinear"):
+        ws = wl.workload_forced_source(stage)
+        for n in (ws["nx"], 12800):
+            u, rec = {}, {}
+            for name, scheme, riemann in (("csph_tvd", ng.NG_CSPH_TVD, ng.NG_HLL),
+                                          ("muscl", ng.NG_MUSCL, ng.NG_HLLC)):
+                s = ng.Solver(ws["gas"], n, 1, W=wl.uniform_state(ws["gas"], n),
+                              precision=ng.NG_FP64, riemann=riemann, bc=ws["bc"],
+                              source=ws["source"], scheme=scheme)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                taken = s.run_to_time(ws["t_end"])
+                el = time.perf_counter() - t0
+                U = s.conserved()
+                d = s.diagnostics()
+                s.close()
+                assert d["status"] == 0
+                u[name] = U[1, 0] / U[0, 0]
+                rec[name] = {"steps": taken, "wall_ms": 1e3 * el}
+            rec["rel_l1_u_csph_vs_muscl"] = float(np.abs(u["csph_tvd"] - u["muscl"]).sum()
+                                                  / np.abs(u["muscl"]).sum())
+            xc[f"{stage}_n{n}"] = rec
+    res["forced_source_t08"] = xc
+    log(f"[bench] CSPH-TVD against MUSCL, forced source: {xc}")
     return res
 
 

@@ -75,7 +75,7 @@ extern "C" {
                             and each step's FP32 increment is added in FP64   */
 #define NG_MUSCL 0       /* the Eulerian MUSCL step of eq. (15)                 */
 #define NG_CSPH_TVD 1    /* the CSPH-TVD step of section 2.3 (1D, NG_FP64,
-                            NG_HLL, no forced source): particles at the cell
+                            NG_HLL): particles at the cell
                             centres move by the predictor (10) and corrector
                             (11) under eq. (12) -- SPH pressure force and work
                             over the two neighbours with the cubic-spline
@@ -150,8 +150,9 @@ typedef struct {
  * E_nu equation (4), relaxation and pump together, is integrated exactly over
  * the (half) step with E_nue, tau and Q frozen: E_nu relaxes toward
  * E_nue + tau rho Q by the factor exp(-dt/tau).  scheme: NG_MUSCL, or
- * NG_CSPH_TVD with a 1D grid, NG_FP64, NG_HLL and no forced source (any other
- * combination, or another value, is NG_EINVAL). */
+ * NG_CSPH_TVD with a 1D grid, NG_FP64 and NG_HLL (any other combination, or
+ * another value, is NG_EINVAL); with a forced source its three ghost
+ * particles x = -h/2, -3h/2, -5h/2 carry the source's wave. */
 typedef struct {
     double cfl;
     int32_t riemann;   /* NG_HLLC or NG_HLL */

@@ -213,9 +213,8 @@ int validate(const ng_gas* gas, const ng_grid* grid, const ng_numerics* num, std
     if (!(num->stiff_z >= 0.0)) { err = "stiff_z must be >= 0"; return NG_EINVAL; }
     if (num->scheme != NG_MUSCL && num->scheme != NG_CSPH_TVD) { err = "unknown scheme"; return NG_EINVAL; }
     if (num->scheme == NG_CSPH_TVD &&
-        (grid->ndim != 1 || num->precision != NG_FP64 || num->riemann != NG_HLL ||
-         grid->bc[0] == NG_BC_SOURCE)) {
-        err = "the CSPH-TVD step needs a 1D grid, NG_FP64, NG_HLL and no forced source";
+        (grid->ndim != 1 || num->precision != NG_FP64 || num->riemann != NG_HLL)) {
+        err = "the CSPH-TVD step needs a 1D grid, NG_FP64 and NG_HLL";
         return NG_EINVAL;
     }
     return NG_OK;

@@ -116,8 +116,9 @@ struct InstCtrl {
     double rho_min, p_min, smax;
     uint32_t arrive;          // workgroups of the current step that have finished
     uint32_t pad;
-    double src_ghost[2][5];   // forced source: full conserved state of the ghosts
-                              // x = -h/2, -3h/2 at time t (set with t)
+    double src_ghost[3][5];   // forced source: full conserved state of the ghosts
+                              // x = -h/2, -3h/2, -5h/2 at time t (set with t;
+                              // the third for the CSPH-TVD step's particles)
 };
 
 // Grid barrier of a cooperative launch (one solve advanced many steps per

@@ -495,12 +495,12 @@ __device__ __forceinline__ void load_cell_cached(const R* __restrict__ base, int
 // (swap buffers, advance t, next dt from eq. (16)).  mode 1: priming (no step
 // taken, only the totals and the first dt).
 // Ghost states of a forced source at the x-low end for the time c.t: the
-// plane sound wave s = a sin(omega t - k x) at x = -h/2 and -3h/2 about the
+// plane sound wave s = a sin(omega t - k x) at x = -h/2, -3h/2, -5h/2 about the
 // background (section 3's forced oscillations), as conserved FP64 values
 // (eq. (5)).
 __device__ __noinline__ void source_ghosts(const InstDesc& d, InstCtrl& c)
 {
-    for (int g = 0; g < 2; g++) {
+    for (int g = 0; g < 3; g++) {
         const double x = ((double)(-1 - g) + 0.5) * d.h;
         const double s = d.src_amp * sin(d.src_omega * c.t - d.src_k * x);
         const double rho = d.src_rho + s;
@@ -1117,7 +1117,8 @@ __device__ __forceinline__ void march1d_hllc(const InstDesc& d, const typename P
 
 // CSPH-TVD step (section 2.3) of the segments of work item `item`: lane l of
 // a segment holds the particle of cell sg * 58 - 3 + l (ghost particles by the
-// boundary rule, a wall ghost with its momentum negated).  Neighbours are one
+// boundary rule, a wall ghost with its momentum negated, the three before a
+// forced source with its wave at the step's start time, gsrc).  Neighbours are one
 // lane away, so each stage is one DPP shift per quantity:
 //   predictor (eq. (10)) on lanes 1..62: U* = U^n + dt Y(U^n), xi* = dt (u^n +
 //     u*)/2, with every particle at its cell centre;
@@ -1131,8 +1132,9 @@ __device__ __forceinline__ void march1d_hllc(const InstDesc& d, const typename P
 // .. end-1 (the cooperative kernel's share of a wave); Coh: agent-scope state
 // loads and stores (Planes).
 template <class P, bool BC, bool Coh = false>
-__device__ __forceinline__ void march_csph(const InstDesc& d, const K64& k, int cur, int64_t item,
-                                           int lane, Acc<double>& acc, int64_t first = -1,
+__device__ __forceinline__ void march_csph(const InstDesc& d, const K64& k, int cur,
+                                           const double* gsrc, int64_t item, int lane,
+                                           Acc<double>& acc, int64_t first = -1,
                                            int64_t end = -1)
 {
     static_assert(std::is_same<typename P::K, K64>::value, "CSPH-TVD runs on the FP64 state");
@@ -1161,7 +1163,10 @@ __device__ __forceinline__ void march_csph(const InstDesc& d, const K64& k, int 
         src.load(boff(sg + 1 < s1 ? sg + 1 : sg), Ux);
         if (BC) {
             bool f;
-            (void)axis_cell(coord(sg), n, d.bc[0], d.bc[1], f);
+            const int64_t xr = coord(sg);
+            (void)axis_cell(xr, n, d.bc[0], d.bc[1], f);
+            if (d.bc[0] == kBcSource && xr < 0 && xr >= -kCsphHalo)
+                source_cell<double, NC, false>(d, gsrc + 5 * (-1 - xr), Un);
             if (f) Un[1] = -Un[1];
         }
         // predictor
@@ -1231,9 +1236,9 @@ __device__ __forceinline__ void march1d_any(const InstDesc& d, const typename P:
     if constexpr (std::is_same<typename P::K, K64>::value) {
         if (d.scheme == kSchemeCsph) {
             if (d.any_bc)
-                march_csph<P, true>(d, k, cur, item, lane, acc);
+                march_csph<P, true>(d, k, cur, gsrc, item, lane, acc);
             else
-                march_csph<P, false>(d, k, cur, item, lane, acc);
+                march_csph<P, false>(d, k, cur, gsrc, item, lane, acc);
             return;
         }
     }
@@ -1267,9 +1272,9 @@ __global__ void __launch_bounds__(256) step1d_kernel(const InstDesc* __restrict_
     if (item < d.nitems) {
         if constexpr (V == kVariantCsph) {
             if (d.any_bc)
-                march_csph<P, true>(d, k, sc.cur, item, lane, acc);
+                march_csph<P, true>(d, k, sc.cur, sc.gsrc, item, lane, acc);
             else
-                march_csph<P, false>(d, k, sc.cur, item, lane, acc);
+                march_csph<P, false>(d, k, sc.cur, sc.gsrc, item, lane, acc);
         } else if constexpr (V > 0) {
             march1d<P, 0, false, V - 1>(d, k, sc.cur, sc.gsrc, item, lane, acc);
         } else {
@@ -1599,9 +1604,9 @@ __global__ void __launch_bounds__(P::kCoopThreads) run_coop1d_kernel(
         if (f0 < f1) {
             if constexpr (V == kVariantCsph) {
                 if (d.any_bc)
-                    march_csph<P, true, true>(d, k, cur, 0, lane, acc, f0, f1);
+                    march_csph<P, true, true>(d, k, cur, nullptr, 0, lane, acc, f0, f1);
                 else
-                    march_csph<P, false, true>(d, k, cur, 0, lane, acc, f0, f1);
+                    march_csph<P, false, true>(d, k, cur, nullptr, 0, lane, acc, f0, f1);
             } else if constexpr (V > 0)
                 march1d<P, 0, false, V - 1, true>(d, k, cur, nullptr, 0, lane, acc, f0, f1);
             else if (d.riemann == 1)

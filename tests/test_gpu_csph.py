@@ -7,8 +7,10 @@ step, the persistent one-workgroup kernel, the cooperative kernel with a
 grid barrier per step, captured graphs through run_to_time) and in several
 launch shapes; at the size the benchmark times (2^22 cells) on two whole
 steps; in a batch beside MUSCL solves; through the entry point that
-allocates nothing.  The paper's own use (figure 2): the
-blast waves of section 2.4 on 200 ... 1600 cells approach a fine MUSCL run.
+allocates nothing; with a forced source (section 3).  The paper's own use
+of the scheme as a cross-check: the blast waves of section 2.4 on 200 ...
+1600 cells approach a fine MUSCL run (figure 2), and on section 3's
+forced-source runs the two schemes agree better with every doubling.
 """
 import sys
 
@@ -57,9 +59,9 @@ def _moving_state(gas, n, seed):
     return W
 
 
-def _solver(ng, gas, n, U, bc, path, launch=None):
+def _solver(ng, gas, n, U, bc, path, launch=None, source=(0.0, 0.0)):
     s = ng.Solver(gas, n, 1, U=U, precision=ng.NG_FP64, riemann=ng.NG_HLL, bc=bc,
-                  scheme=ng.NG_CSPH_TVD)
+                  scheme=ng.NG_CSPH_TVD, source=source)
     if path == "per_step":
         s.set_coop(0)
         s.set_small_limit(0)
@@ -308,3 +310,61 @@ def test_csph_blast_waves_approach_the_fine_muscl_run(ng):
     jf = int(np.argmax(rf))
     assert abs((np.argmax(rho) + 0.5) / 1600 - (jf + 0.5) / nf) < 0.01
     assert abs(rho.max() - rf.max()) < 0.1 * rf.max()
+
+
+@pytest.mark.parametrize("path", ["per_step", "small"])
+@pytest.mark.parametrize("stage", ["linear", "nonlinear"])
+def test_csph_forced_source_against_oracle(ng, oracle_mod, stage, path):
+    """Section 3's forced source with the CSPH-TVD step: the three ghost
+    particles before x = 0 carry the source's wave at each step's start time.
+    400 steps of both runs' media; FP64 within 1e-12 of the oracle per
+    component (the device sine of the source may differ from libm's in the
+    last bit, so not bit for bit), t within 1e-13."""
+    ws = wl.workload_forced_source(stage)
+    n, steps = ws["nx"], 400
+    P = oracle_mod.CsphProblem(ws["gas"], n, bc=ws["bc"], source=ws["source"])
+    U0 = P.prim_to_cons(ws["W"])
+    ref = P.run(U0, steps)
+    assert ref["status"] == 0
+    say(f"csph forced source {stage} {path}")
+    s = _solver(ng, ws["gas"], n, U0, ws["bc"], path, source=ws["source"])
+    s.step(steps)
+    d = s.diagnostics()
+    U = s.conserved()
+    s.close()
+    assert d["status"] == 0 and d["steps"] == steps
+    for c in (0, 1, 3, 4):
+        den = np.max(np.abs(ref["U"][c]))
+        assert np.max(np.abs(U[c] - ref["U"][c])) <= 1e-12 * den, c
+    assert d["t"] == pytest.approx(ref["t"], rel=1e-13)
+    # the wave has entered the domain
+    dr = np.abs(ref["U"][0, 0] - ws["gas"]["rho0"])
+    assert dr[: n // 20].max() > 0.1 * ws["source"][0]
+
+
+@pytest.mark.parametrize("stage", ["linear", "nonlinear"])
+def test_csph_cross_checks_muscl_on_the_forced_source_runs(ng, stage):
+    """The paper's use of its second scheme: section 3's two forced-source
+    runs to t = 0.8 (the linear stage and the shock train) with CSPH-TVD and
+    with MUSCL on 800, 1600 and 3200 cells.  The velocity fields agree
+    better with every doubling (relative L1 difference halving: CSPH-TVD is
+    first order for sound, reading 22) and within 6 % on 3200 cells."""
+    ws = wl.workload_forced_source(stage)
+    diffs = []
+    for n in (800, 1600, 3200):
+        u = {}
+        for name, scheme, riemann in (("csph", ng.NG_CSPH_TVD, ng.NG_HLL),
+                                      ("muscl", ng.NG_MUSCL, ng.NG_HLLC)):
+            s = ng.Solver(ws["gas"], n, 1, W=wl.uniform_state(ws["gas"], n),
+                          precision=ng.NG_FP64, riemann=riemann, bc=ws["bc"],
+                          source=ws["source"], scheme=scheme)
+            s.run_to_time(ws["t_end"])
+            d = s.diagnostics()
+            U = s.conserved()
+            s.close()
+            assert d["status"] == 0 and d["t"] == ws["t_end"]
+            u[name] = U[1, 0] / U[0, 0]
+        diffs.append(float(np.abs(u["csph"] - u["muscl"]).sum() / np.abs(u["muscl"]).sum()))
+        say(f"forced source {stage} n={n}: CSPH against MUSCL {diffs[-1]:.4f}")
+    assert all(a / b > 1.8 for a, b in zip(diffs, diffs[1:])), diffs
+    assert diffs[-1] < 0.06, diffs
