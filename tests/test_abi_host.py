@@ -66,7 +66,7 @@ def test_state_bytes(ng):
                                          ("wedge_x0", -0.1), ("huge", 1 << 30),
                                          ("scheme", 2), ("scheme", -1),
                                          ("csph", "hllc"), ("csph", "fp32"), ("csph", "mixed"),
-                                         ("csph", "2d"), ("csph", "source")])
+                                         ("csph", "2d"), ("csph", "segment")])
 def test_invalid_arguments_rejected_before_device_use(ng, field, value):
     import numpy as np
     from paper_1805_03442_amd import workloads as wl
@@ -90,7 +90,7 @@ def test_invalid_arguments_rejected_before_device_use(ng, field, value):
     elif field == "scheme":
         scheme = value
     elif field == "csph":
-        # the CSPH-TVD step: 1D, FP64, HLL, no forced source only
+        # the CSPH-TVD step: 1D, FP64 and HLL only
         scheme, riemann = ng.NG_CSPH_TVD, ng.NG_HLL
         if value == "hllc":
             riemann = ng.NG_HLLC
@@ -108,8 +108,9 @@ def test_invalid_arguments_rejected_before_device_use(ng, field, value):
         # a source end with a zero wavelength, or an amplitude of rho0 / 2 or more
         bc = (3, 2, 0, 0)
         source = (value[1], value[0]) if value[0] == 0.0 else value
-    if field == "csph" and value == "source":
-        bc, source = (3, 2, 0, 0), (1e-3, 0.1)
+    if field == "csph" and value == "segment":
+        # a source segment needs a 2D grid, for either scheme
+        bc, source = (3, 2, 0, 0), (1e-3, 0.1, 0.5, 0.1)
     wedge = (0.0, 0.0, 0.0)
     if field == "segment_1d":
         # a source segment needs a 2D grid
