@@ -256,14 +256,15 @@ int ng_set_graph_steps(ng_solver* s, int32_t steps);
 int ng_set_small_limit(ng_solver* s, int64_t max_cells);
 
 /* Cooperative path (the time loop of eq. (15) with the dt of eq. (16) chosen
- * after every step).  A solve that is alone in its object, 1D, without a
- * forced source and of at most max_cells cells is advanced by one
- * cooperative launch per call (up to 65536 steps each): every step, its
- * workgroups -- all resident together -- update their segments, meet at a
- * grid barrier in device memory, and the last to arrive folds the step's
- * records, accepts the step and sends the next dt to the others.  No launch
- * or host round trip per step; the state, t and dt are bitwise those of one
- * launch per step (only the summation order of the FP64 totals differs).
+ * after every step).  A solve that is alone in its object, 1D and of at most
+ * max_cells cells is advanced by one cooperative launch per call (up to 65536
+ * steps each): every step, its workgroups -- all resident together -- update
+ * their segments, publish their largest signal speed and failure flags in
+ * device memory, and each reads those of all the others and accepts or
+ * rejects the step and takes the next dt alike (a forced source's ghosts
+ * follow its own t).  No launch or host round trip per step; the state, t
+ * and dt are bitwise those of one launch per step (only the summation order
+ * of the FP64 totals differs).
  * max_cells: -1 restores the default (4194304), 0 turns the path off (the
  * persistent one-workgroup path or one launch per step take over).
  * spin_limit: polls of memory (about a microsecond each) a workgroup spends

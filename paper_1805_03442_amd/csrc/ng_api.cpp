@@ -521,7 +521,7 @@ int choose_coop(ng_batch* b)
     const int64_t lim = b->coop_limit >= 0 ? b->coop_limit : kCoopCells;
     if (live != 1 || lim == 0) return NG_OK;
     Slot& s = b->slots[cand];
-    if (s.dim != 1 || s.d.bc[0] == kBcSource || s.d.ncell > lim) return NG_OK;
+    if (s.dim != 1 || s.d.ncell > lim) return NG_OK;
     if (b->dev_coop < 0) {
         int dev = 0, coop = 0, cus = 0;
         CK(b, hipGetDevice(&dev));

@@ -490,32 +490,43 @@ __device__ __forceinline__ void load_cell_cached(const R* __restrict__ base, int
 
 // ==================================================== accepting a step
 
+// Ghost g (cell -1 - g, centre x = -h/2 - g h) of a forced source at the
+// x-low end for the time t: the plane sound wave s = a sin(omega t - k x)
+// about the background (section 3's forced oscillations), as conserved FP64
+// values (eq. (5)).  The step kernels take it from the control block, the
+// cooperative kernel computes it itself: the same arithmetic in both.
+__device__ __forceinline__ void source_ghost(const InstDesc& d, double t, int g, double* U)
+{
+    const double x = ((double)(-1 - g) + 0.5) * d.h;
+    const double s = d.src_amp * sin(d.src_omega * t - d.src_k * x);
+    const double rho = d.src_rho + s;
+    const double u = d.src_uc * s;
+    const double v = 0.0;
+    const double p = d.src_p + d.src_c2 * s;
+    const double e = d.src_ev + d.src_er * s;
+    U[0] = rho;
+    U[1] = rho * u;
+    U[2] = rho * v;
+    U[3] = p / d.gm1 + 0.5 * rho * (u * u + v * v) + e;
+    U[4] = e;
+}
+
+// the three ghosts for the time c.t, into the control block
+__device__ __noinline__ void source_ghosts(const InstDesc& d, InstCtrl& c)
+{
+    for (int g = 0; g < 3; g++) source_ghost(d, c.t, g, c.src_ghost[g]);
+}
+// one ghost, out of line: inlined, the sine's registers would count against
+// the cooperative kernel's step loop
+__device__ __noinline__ void source_ghost_at(const InstDesc& d, double t, int g, double* U)
+{
+    source_ghost(d, t, g, U);
+}
+
 // Apply a folded step record v = (tot[5], src[2], smax, rho_min, p_min) with
 // flags to a solve: reject (sticky NG_EPHYS, buffers not swapped) or accept
 // (swap buffers, advance t, next dt from eq. (16)).  mode 1: priming (no step
 // taken, only the totals and the first dt).
-// Ghost states of a forced source at the x-low end for the time c.t: the
-// plane sound wave s = a sin(omega t - k x) at x = -h/2, -3h/2, -5h/2 about the
-// background (section 3's forced oscillations), as conserved FP64 values
-// (eq. (5)).
-__device__ __noinline__ void source_ghosts(const InstDesc& d, InstCtrl& c)
-{
-    for (int g = 0; g < 3; g++) {
-        const double x = ((double)(-1 - g) + 0.5) * d.h;
-        const double s = d.src_amp * sin(d.src_omega * c.t - d.src_k * x);
-        const double rho = d.src_rho + s;
-        const double u = d.src_uc * s;
-        const double v = 0.0;
-        const double p = d.src_p + d.src_c2 * s;
-        const double e = d.src_ev + d.src_er * s;
-        c.src_ghost[g][0] = rho;
-        c.src_ghost[g][1] = rho * u;
-        c.src_ghost[g][2] = rho * v;
-        c.src_ghost[g][3] = p / d.gm1 + 0.5 * rho * (u * u + v * v) + e;
-        c.src_ghost[g][4] = e;
-    }
-}
-
 __device__ void accept_step(const InstDesc& d, InstCtrl& c, const StepCtl& sc, const double* v,
                             uint32_t flags, int mode)
 {
@@ -1460,9 +1471,10 @@ __device__ __forceinline__ void wait_mem() { __builtin_amdgcn_s_waitcnt(0x0070);
 // launch per step; only the summation order of the FP64 totals differs.
 // Every wait is bounded by spin_limit polls: a workgroup whose wait runs out
 // sets the stall word and leaves, the others leave when their own next wait
-// runs out, and the solve keeps the last step a barrier accepted.  Solves
-// with a forced source are not run here (their ghosts follow t through the
-// control block).
+// runs out, and the solve keeps the last step a barrier accepted.  A forced
+// source's ghosts follow t: every workgroup computes them for its own t (the
+// same arithmetic as the control block's), and the after-kernel leaves the
+// control block's for the last accepted step.
 
 // Wave-wide wait of a cooperative launch of G <= kCoopFlat workgroups for
 // every workgroup's (step << 32 | payload) words of step gen: lane j reads
@@ -1571,6 +1583,7 @@ __global__ void __launch_bounds__(P::kCoopThreads) run_coop1d_kernel(
     __shared__ uint32_t s_fl[kCoopMaxWaves];
     __shared__ int s_stall;  // this workgroup's wait ran out
     __shared__ uint64_t s_msg[3];
+    __shared__ double s_gsrc[3][5];  // a forced source's ghosts at the step's start
     // the solve's control, as every workgroup tracks it
     const double t_end = c.t_end;
     const int64_t max_steps = c.max_steps;
@@ -1589,6 +1602,13 @@ __global__ void __launch_bounds__(P::kCoopThreads) run_coop1d_kernel(
     double bud0 = 0.0, bud1 = 0.0;
     int64_t st_c = -1;     // last computed step
     bool cur_ok = false;   // ... and whether this workgroup saw it accepted
+    // (a forced source needs the boundary variants: V = 0 or CSPH)
+    const bool src = (V == 0 || V == kVariantCsph) && d.bc[0] == kBcSource;
+    const double* gsrc = src ? &s_gsrc[0][0] : nullptr;
+    if (src) {
+        if (threadIdx.x < 3) source_ghost_at(d, t, (int)threadIdx.x, s_gsrc[threadIdx.x]);
+        __syncthreads();
+    }
     for (int64_t st = 0; st < nsteps && active; st++) {
         const uint32_t gen = (uint32_t)(st + 1);
         double dt = dt_cfl;
@@ -1604,15 +1624,15 @@ __global__ void __launch_bounds__(P::kCoopThreads) run_coop1d_kernel(
         if (f0 < f1) {
             if constexpr (V == kVariantCsph) {
                 if (d.any_bc)
-                    march_csph<P, true, true>(d, k, cur, nullptr, 0, lane, acc, f0, f1);
+                    march_csph<P, true, true>(d, k, cur, gsrc, 0, lane, acc, f0, f1);
                 else
-                    march_csph<P, false, true>(d, k, cur, nullptr, 0, lane, acc, f0, f1);
+                    march_csph<P, false, true>(d, k, cur, gsrc, 0, lane, acc, f0, f1);
             } else if constexpr (V > 0)
                 march1d<P, 0, false, V - 1, true>(d, k, cur, nullptr, 0, lane, acc, f0, f1);
             else if (d.riemann == 1)
-                march1d_bc<P, 1, true>(d, k, cur, nullptr, 0, lane, acc, f0, f1);
+                march1d_bc<P, 1, true>(d, k, cur, gsrc, 0, lane, acc, f0, f1);
             else
-                march1d_hllc<P, kRecipes, true>(d, k, cur, nullptr, 0, lane, acc, f0, f1);
+                march1d_hllc<P, kRecipes, true>(d, k, cur, gsrc, 0, lane, acc, f0, f1);
         }
         acc_finish<P>(acc, k);
         // the barrier needs only the signal speed and the failure flags
@@ -1698,12 +1718,14 @@ __global__ void __launch_bounds__(P::kCoopThreads) run_coop1d_kernel(
             bud1 += acc.src[1];
             last = acc;
             cur_ok = true;
+            // the ghosts of the next step (every wave has marched this one)
+            if (src && threadIdx.x < 3) source_ghost_at(d, t, (int)threadIdx.x, s_gsrc[threadIdx.x]);
         } else {
             status = -3;   // NG_EPHYS
             bad = out >> 1;
             active = false;
         }
-        __syncthreads();   // s_msg and s_stall are rewritten in the next step
+        __syncthreads();   // s_msg, s_stall and s_gsrc are rewritten in the next step
     }
     // The workgroup's records (lanes, then waves in order): the sums of the
     // last computed step and, when this workgroup did not see that step
@@ -1850,6 +1872,7 @@ __global__ void __launch_bounds__(256) coop_after_kernel(const InstDesc* __restr
         c.dt_cfl = w.dt_cfl;
         c.dt_last = w.dt_last;
         c.flags = 0u;
+        if (d.bc[0] == kBcSource) source_ghosts(d, c);
     }
     if (w.status != 0) {
         c.status = w.status;

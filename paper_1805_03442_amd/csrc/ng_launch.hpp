@@ -30,7 +30,7 @@ hipError_t launch_small(int dim, int prec, const InstDesc* descs, InstCtrl* ctrl
 hipError_t launch_set_limits(InstCtrl* ctrls, const int32_t* insts, int n, double t_end,
                              int64_t max_steps_from_now, hipStream_t s);
 
-// Cooperative launch of one 1D solve (solve `inst`, no forced source) for up
+// Cooperative launch of one 1D solve (solve `inst`) for up
 // to nsteps <= kCoopMaxSteps steps: grid workgroups of `waves` waves, all
 // resident together (the runtime refuses a grid that does not fit); cs is the
 // batch's barrier block, cleared here first.  coop_capacity gives the

@@ -6,7 +6,8 @@ the general closures, HLL, walls and outflow), in every precision and in
 both launch shapes (one wave per SIMD, and the largest workgroups the
 kernel takes: 12 waves in FP32, 8 in FP64 and mixed; ragged tails).
 A barrier wait that runs out of polls ends the launch with every kernel
-exiting and leaves the solve at its last accepted step (NG_ESTALL)."""
+exiting and leaves the solve at its last accepted step (NG_ESTALL).  Solves
+with a forced source take the path too, MUSCL and CSPH-TVD."""
 import sys
 
 import numpy as np
@@ -161,18 +162,13 @@ def test_coop_stall_ends_the_launch(ng, n):
     t.close()
 
 
-def test_coop_is_not_taken_with_company_or_a_source(ng):
-    """A forced source and a batch of two solves keep their own paths (the
-    cooperative path serves a lone 1D solve without a source); a batch whose
-    only solve is 1D takes it; results equal the per-step path."""
+def test_coop_is_not_taken_with_company(ng):
+    """A batch of two solves keeps its own path (the cooperative path serves a
+    lone 1D solve); a batch whose only solve is 1D takes it; results equal the
+    per-step path."""
     gas = dict(wl.BASE_GAS, Q_T=2.0)
     n = 6000
     W = _state(gas, n, 9)
-    s = ng.Solver(gas, n, 1, W=W, precision=ng.NG_FP32, bc=(3, 2, 0, 0), source=(1e-3, 0.1))
-    s.enable_timing(30)
-    s.step(30)
-    assert s.kernel_time()[2] == 30
-    s.close()
     b = ng.Batch(2, 1 << 26, precision=ng.NG_FP32)
     i = b.add(gas, n, 1, W, 10.0)
     b.run(30)
@@ -187,4 +183,63 @@ def test_coop_is_not_taken_with_company_or_a_source(ng):
     ref.step(30)
     assert np.array_equal(b.conserved(i), ref.conserved())
     ref.close()
+    b.close()
+
+
+# forced sources (section 3) on the cooperative path: (name, cells, precision,
+# scheme, riemann); the source's gas and wave are those of the paper's linear
+# run, the cells give 14 to 100 segments and ragged last ones
+SOURCE_CASES = [
+    ("muscl_fp64_hllc_800", 800, "fp64", 0, 0),
+    ("muscl_fp64_hll_3001", 3001, "fp64", 0, 1),
+    ("muscl_fp32_hllc_6000", 6000, "fp32", 0, 0),
+    ("muscl_mixed_hllc_2000", 2000, "mixed", 0, 0),
+    ("csph_fp64_hll_1600", 1600, "fp64", 1, 1),
+    ("csph_fp64_hll_5801", 5801, "fp64", 1, 1),
+]
+
+
+@pytest.mark.parametrize("case", SOURCE_CASES, ids=[c[0] for c in SOURCE_CASES])
+def test_coop_with_a_forced_source_equals_one_launch_per_step(ng, case):
+    """Every workgroup computes the source's ghosts for its own t each step
+    (the wave at x = 0 reads them); the state, t and dt equal bit for bit
+    those of one launch per step, whose ghosts come from the control block.
+    After a cooperative call the control block holds the ghosts of its last
+    step: per-step calls that follow continue bit for bit."""
+    name, n, prec_name, scheme, riemann = case
+    prec = {"fp64": ng.NG_FP64, "fp32": ng.NG_FP32, "mixed": ng.NG_MIXED}[prec_name]
+    ws = wl.workload_forced_source("linear")
+    gas, bc, src = ws["gas"], ws["bc"], ws["source"]
+    W = wl.uniform_state(gas, n)
+    steps = 300
+    say(f"coop source case {name}: {steps} steps")
+
+    def solver():
+        return ng.Solver(gas, n, 1, W=W, precision=prec, riemann=riemann, bc=bc, source=src,
+                         scheme=scheme)
+
+    a = solver()
+    a.enable_timing(steps)
+    a.step(steps)
+    assert a.kernel_time()[2] == 1    # one cooperative launch
+    a.enable_timing(0)
+    b = solver()
+    b.set_coop(0)
+    b.set_small_limit(0)
+    b.step(steps)
+    da, db = a.diagnostics(), b.diagnostics()
+    assert da["status"] == 0 and db["status"] == 0 and da["steps"] == steps
+    for key in ("t", "dt_last", "dt_next", "smax", "rho_min", "p_min"):
+        assert da[key] == db[key], key
+    assert np.array_equal(a.conserved(), b.conserved())
+    # the wave has entered the domain
+    assert np.abs(b.conserved()[0, :20] - gas["rho0"]).max() > 0.1 * src[0]
+    # then one launch per step from the ghosts the cooperative call left
+    a.set_coop(0)
+    a.set_small_limit(0)
+    a.step(40)
+    b.step(40)
+    assert a.diagnostics()["t"] == b.diagnostics()["t"]
+    assert np.array_equal(a.conserved(), b.conserved())
+    a.close()
     b.close()

@@ -312,7 +312,7 @@ def test_csph_blast_waves_approach_the_fine_muscl_run(ng):
     assert abs(rho.max() - rf.max()) < 0.1 * rf.max()
 
 
-@pytest.mark.parametrize("path", ["per_step", "small"])
+@pytest.mark.parametrize("path", ["per_step", "small", "coop"])
 @pytest.mark.parametrize("stage", ["linear", "nonlinear"])
 def test_csph_forced_source_against_oracle(ng, oracle_mod, stage, path):
     """Section 3's forced source with the CSPH-TVD step: the three ghost

@@ -701,15 +701,16 @@ SRC_GAS = dict(gamma=1.4, R=1.0, Cv=0.1, rho0=1.0, T0=1.0, tau0=0.05, tau_rho=-1
                fx=0.0, fy=0.0)
 
 
-@pytest.mark.parametrize("path", ["persistent", "per_step"])
+@pytest.mark.parametrize("path", ["cooperative", "persistent", "per_step"])
 def test_forced_source_1d(ng, path):
     """The acoustically unstable set driven by a source at x = 0 (outflow at
-    x = 1), on the persistent small-solve kernel and on the per-step kernels.
-    FP64 within 1e-12 of the oracle (the device sine of the source may differ
-    from libm's in the last bit); FP32 and mixed within 1e-5 relative L1."""
+    x = 1), on the cooperative kernel, the persistent small-solve kernel and
+    the per-step kernels.  FP64 within 1e-12 of the oracle (the device sine of
+    the source may differ from libm's in the last bit); FP32 and mixed within
+    1e-5 relative L1."""
     n, steps = 500, 400
     W = wl.uniform_state(SRC_GAS, n)
-    small = None if path == "persistent" else 0
+    small = {"cooperative": None, "persistent": 1 << 20, "per_step": 0}[path]
     for prec in (ng.NG_FP64, ng.NG_FP32, ng.NG_MIXED):
         for riemann in ((0, 1) if prec == ng.NG_FP64 else (0,)):
             U, ref, d, U0 = run_both(ng, SRC_GAS, W, n, 1, steps, prec, riemann,
