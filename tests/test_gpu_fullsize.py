@@ -5,7 +5,8 @@ so for each sampled cell the oracle steps a window of half-width 2K + 3 cut
 from the same initial state (periodic wrap; its edges go wrong and the error
 moves in 2 cells per step) K times with the GPU's dt sequence, and its centre
 is compared with the GPU's cell.  Samples include the grid's corners, strip
-edges and random cells.  K = 5.
+edges and random cells.  K = 5.  Each step's dt is checked against eq. (16)
+over the whole grid, evaluated by the oracle.
 
 Bars: FP64 bit for bit; FP32 within 1e-5 relative L1 of the full values over
 the samples, and, on the change over the K steps, within ten times what the
@@ -57,18 +58,30 @@ def samples_2d(n, count, seed):
     return pts
 
 
-def k_steps_gpu(ng, gas, W, nx, ny, prec):
+def k_steps_gpu(ng, oracle_mod, gas, W, nx, ny, prec):
     """K steps on the GPU in the benchmark's launch shape: the state before
-    and after, and the dt of each step."""
+    and after, and the dt of each step.  Each dt is also checked against eq.
+    (16) evaluated by the oracle over the whole grid the GPU stepped from (the
+    GPU's reduction of the signal speed over every workgroup): FP64 bit for
+    bit; FP32 within 1e-6 (the FP32 path takes the speed from its FP32
+    deviations, the oracle from the FP64 values they stand for)."""
     from paper_1805_03442_amd import autotune
     s = ng.Solver(gas, nx, ny, W=W, precision=prec)
     autotune.apply(s)
+    full = oracle_mod.Problem(gas, nx, ny, h=1.0 / nx)
     U0 = s.conserved()
     dts = []
+    U = U0
     for _ in range(K):
+        want = full.dt(U)
         s.step(1)
         dts.append(s.diagnostics()["dt_last"])
-    U1 = s.conserved()
+        if prec == ng.NG_FP64:
+            assert dts[-1] == want, (len(dts), dts[-1], want)
+        else:
+            assert dts[-1] == pytest.approx(want, rel=1e-6), (len(dts), dts[-1], want)
+        U = s.conserved()
+    U1 = U
     assert s.diagnostics()["status"] == 0
     s.close()
     return U0, U1, dts
@@ -117,7 +130,7 @@ def test_2d_4096_sampled_cells(ng, oracle_mod, prec_name):
     w = wl.workload_2d_random(4096)
     n = 4096
     say(f"full-size 2D {n}^2 {prec_name}: {K} GPU steps")
-    U0, U1, dts = k_steps_gpu(ng, w["gas"], w["W"], n, n, prec)
+    U0, U1, dts = k_steps_gpu(ng, oracle_mod, w["gas"], w["W"], n, n, prec)
     # the oracle steps windows of the state the GPU started from (as read back)
     P = oracle_mod.Problem(w["gas"], 2 * R + 1, 2 * R + 1, h=1.0 / n)
     bars = Bars(background_cons(w["gas"], [0, 1, 2, 3, 4]))
@@ -139,7 +152,7 @@ def test_1d_2e20_sampled_cells(ng, oracle_mod, prec_name):
     w = wl.workload_1d_multimode()
     n = w["nx"]
     say(f"full-size 1D {n} {prec_name}: {K} GPU steps")
-    U0, U1, dts = k_steps_gpu(ng, w["gas"], w["W"], n, 1, prec)
+    U0, U1, dts = k_steps_gpu(ng, oracle_mod, w["gas"], w["W"], n, 1, prec)
     P = oracle_mod.Problem(w["gas"], 2 * R + 1, 1, h=1.0 / n)
     r = np.random.Generator(np.random.PCG64(6))
     pts = [0, 1, n - 1, n - 2, 59, 60, 61] + [int(v) for v in r.integers(0, n, size=64)]
