@@ -14,21 +14,24 @@ from paper_1805_03442_amd import workloads as wl
 pytestmark = pytest.mark.gpu
 
 
-def _step_static(ng, torch, gas, nx, ny, U, t=0.0, riemann=0, bc=(0, 0, 0, 0), scheme=0):
+def _step_static(ng, torch, gas, nx, ny, U, t=0.0, riemann=0, bc=(0, 0, 0, 0), scheme=0,
+                 source=(0.0, 0.0)):
     nc = 5 if ny > 1 else 4
     comps = [0, 1, 2, 3, 4] if ny > 1 else [0, 1, 3, 4]
     planes = np.ascontiguousarray(U[comps].reshape(nc, -1))
     din = torch.from_numpy(planes).cuda()
     dout = torch.full_like(din, float("nan"))
-    d = ng.step_static(gas, nx, ny, din, dout, t=t, riemann=riemann, bc=bc, scheme=scheme)
+    d = ng.step_static(gas, nx, ny, din, dout, t=t, riemann=riemann, bc=bc, scheme=scheme,
+                       source=source)
     out = np.zeros_like(U)
     out[comps] = dout.cpu().numpy().reshape(nc, ny, nx)
     return out, d
 
 
-def _step_solver(ng, gas, nx, ny, U, riemann=0, bc=(0, 0, 0, 0), scheme=0):
+def _step_solver(ng, gas, nx, ny, U, t=0.0, riemann=0, bc=(0, 0, 0, 0), scheme=0,
+                 source=(0.0, 0.0)):
     s = ng.Solver(gas, nx, ny, U=U, precision=ng.NG_FP64, riemann=riemann, bc=bc,
-                  scheme=scheme)
+                  scheme=scheme, t0=t, source=source)
     s.step(1)
     V = s.conserved()
     d = s.diagnostics()
@@ -36,16 +39,24 @@ def _step_solver(ng, gas, nx, ny, U, riemann=0, bc=(0, 0, 0, 0), scheme=0):
     return V, d
 
 
-@pytest.mark.parametrize("case", ["2d_hllc_periodic", "1d_hll_walls", "1d_csph_walls"])
+@pytest.mark.parametrize("case", ["2d_hllc_periodic", "1d_hll_walls", "1d_csph_walls",
+                                  "1d_hllc_source", "1d_csph_source"])
 def test_static_step_equals_solver_step(case):
+    """The source cases step from t = 0.37 (section 3's forced source: the
+    ghosts follow the time the call is given)."""
     import torch
     from paper_1805_03442_amd import ng
     assert torch.cuda.is_available()
     gas = dict(wl.BASE_GAS, Q_T=2.0)
     r = np.random.Generator(np.random.PCG64(31))
-    scheme = ng.NG_CSPH_TVD if case == "1d_csph_walls" else ng.NG_MUSCL
+    scheme = ng.NG_CSPH_TVD if case.startswith("1d_csph") else ng.NG_MUSCL
+    t, source = 0.0, (0.0, 0.0)
     if case == "2d_hllc_periodic":
         shapes, riemann, bc = [(300, 190), (130, 70)], 0, (0, 0, 0, 0)
+    elif case.endswith("_source"):
+        ws = wl.workload_forced_source("linear")
+        gas, bc, source, t = ws["gas"], ws["bc"], ws["source"], 0.37
+        shapes, riemann = [(6000, 1), (800, 1)], 1 if scheme == ng.NG_CSPH_TVD else 0
     else:
         shapes, riemann, bc = [(70000, 1), (5000, 1)], 1, (1, 1, 0, 0)
     for nx, ny in shapes:
@@ -60,8 +71,10 @@ def test_static_step_equals_solver_step(case):
         U = s0.conserved()
         s0.close()
         print(f"static step {case} {nx}x{ny}", flush=True)
-        A, da = _step_static(ng, torch, gas, nx, ny, U, riemann=riemann, bc=bc, scheme=scheme)
-        B, db = _step_solver(ng, gas, nx, ny, U, riemann=riemann, bc=bc, scheme=scheme)
+        A, da = _step_static(ng, torch, gas, nx, ny, U, t=t, riemann=riemann, bc=bc,
+                             scheme=scheme, source=source)
+        B, db = _step_solver(ng, gas, nx, ny, U, t=t, riemann=riemann, bc=bc, scheme=scheme,
+                             source=source)
         assert np.array_equal(A, B), (nx, ny, np.abs(A - B).max())
         assert da["t"] == db["t"] and da["dt_last"] == db["dt_last"] and da["steps"] == 1
         assert da["status"] == 0
