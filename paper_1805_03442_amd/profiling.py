@@ -119,6 +119,43 @@ def counters_markdown(path: str, kernel: str, command: str) -> str:
     return "\n".join(out) + "\n"
 
 
+def coop_markdown(trace_csv: str, command: str, specs: list, bench_json: str | None) -> str:
+    """Per-step times of cooperative launches from a kernel trace.  specs:
+    "name-part:steps:workgroups:label" -- the longest launch of a kernel whose
+    name holds name-part with that many workgroups ran `steps` steps."""
+    rows = list(csv.DictReader(open(trace_csv)))
+    out = [f"Command: `{command}`", "",
+           "| run | kernel | workgroups x threads | launch us | steps | us per step |",
+           "|---|---|---|---|---|---|"]
+    for spec in specs:
+        part, steps, groups, label = spec.split(":", 3)
+        best = None
+        for r in rows:
+            g = int(r["Grid_Size_X"]) // int(r["Workgroup_Size_X"])
+            if part in r["Kernel_Name"] and g == int(groups):
+                d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+                if best is None or d > best[0]:
+                    best = (d, r)
+        if best is None:
+            raise SystemExit(f"no launch of {part} with {groups} workgroups")
+        d, r = best
+        name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+        out.append(f"| {label} | `{name}` | {groups} x {r['Workgroup_Size_X']} | {d:.1f} | "
+                   f"{steps} | {d / int(steps):.2f} |")
+    if bench_json:
+        with open(bench_json) as f:
+            b = json.loads([ln for ln in f if ln.startswith("{")][-1])
+        p1 = b.get("periodic_1d_2e20", {})
+        ac = b.get("acoustic_1d_1024", {})
+        figs = [f"{k} {p1[k]['us_per_step']:.2f}" for k in ("fp32", "fp64", "mixed") if k in p1]
+        out += ["", "Same run, bench.py's own measurement (HIP events around the call that "
+                "takes the steps): 2^20 cells "
+                + ", ".join(figs) + " us per step"
+                + (f"; 1024 cells FP64 {ac['us_per_step']:.2f} us per step" if ac else "") + "."]
+    out += ["", f"Kernel source hash: {kernel_hash()}"]
+    return "\n".join(out) + "\n"
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -139,6 +176,13 @@ def main(argv=None):
     b.add_argument("--command", required=True)
     b.add_argument("--out-json", required=True)
     b.add_argument("--out-md", required=True)
+    d = sub.add_parser("coop")
+    d.add_argument("trace_csv")
+    d.add_argument("--command", required=True)
+    d.add_argument("--out", required=True)
+    d.add_argument("--bench-json", default=None)
+    d.add_argument("--launch", action="append", required=True,
+                   help="name-part:steps:workgroups:label of a cooperative run")
     c = sub.add_parser("counters")
     c.add_argument("csv")
     c.add_argument("--kernel", default="step2d_kernel<ng::Dev32<5>")
@@ -156,6 +200,12 @@ def main(argv=None):
                        mean_per_dispatch={k: statistics.mean(v) for k, v in by.items()})
             with open(args.out_json, "w") as f:
                 json.dump(rec, f, indent=1)
+        print(md)
+        return
+    if args.cmd == "coop":
+        md = coop_markdown(args.trace_csv, args.command, args.launch, args.bench_json)
+        with open(args.out, "w") as f:
+            f.write(md)
         print(md)
         return
     if args.cmd == "stats":
