@@ -243,3 +243,49 @@ def test_coop_with_a_forced_source_equals_one_launch_per_step(ng, case):
     assert np.array_equal(a.conserved(), b.conserved())
     a.close()
     b.close()
+
+
+def test_coop_random_configurations_equal_one_launch_per_step(ng):
+    """30 seeded random configurations -- 5 to 2^20 cells; FP64, FP32, mixed;
+    MUSCL with HLLC or HLL and CSPH-TVD; periodic, wall and outflow ends and
+    section 3's forced source; closure exponents Q_T in {0, 1, 1.5, 2}; 1 to
+    120 steps -- advance bit for bit alike on the cooperative path and with
+    one launch per step (state, t, next dt, steps, status)."""
+    r = np.random.Generator(np.random.PCG64(2026))
+    src_gas = wl.workload_forced_source("linear")["gas"]
+    for case in range(30):
+        n = int(np.exp(r.uniform(np.log(5), np.log(1 << 20))))
+        prec = [ng.NG_FP64, ng.NG_FP32, ng.NG_MIXED][int(r.integers(0, 3))]
+        csph = prec == ng.NG_FP64 and r.random() < 0.3
+        scheme = ng.NG_CSPH_TVD if csph else ng.NG_MUSCL
+        riemann = ng.NG_HLL if csph else int(r.integers(0, 2))
+        kind = int(r.integers(0, 3))
+        qt = float(r.choice([0.0, 1.0, 1.5, 2.0]))
+        gas, src = dict(wl.BASE_GAS, Q_T=qt), (0.0, 0.0)
+        if kind == 0:
+            bc = (0, 0, 0, 0)
+        elif kind == 1:
+            bc = (int(r.integers(1, 3)), int(r.integers(1, 3)), 0, 0)
+        else:
+            bc, src, gas = (3, 2, 0, 0), (1e-3, 0.1), src_gas
+        if n >= 16:
+            W = wl.multimode_1d(gas, n, r, nmodes=min(16, n // 8), kmax=min(64, n // 8),
+                                sigma=1e-3)
+        else:
+            W = wl.uniform_state(gas, n)
+        steps = int(r.integers(1, 120))
+        say(f"random coop case {case}: n={n} prec={prec} scheme={scheme} riemann={riemann} "
+            f"bc={bc} Q_T={qt} steps={steps}")
+        res = []
+        for coop in (True, False):
+            s = ng.Solver(gas, n, 1, W=W, precision=prec, riemann=riemann, bc=bc, source=src,
+                          scheme=scheme)
+            if not coop:
+                s.set_coop(0)
+                s.set_small_limit(0)
+            s.step(steps)
+            d = s.diagnostics()
+            res.append((s.conserved(), d["t"], d["dt_next"], d["steps"], d["status"]))
+            s.close()
+        assert np.array_equal(res[0][0], res[1][0]), case
+        assert res[0][1:] == res[1][1:], (case, res[0][1:], res[1][1:])
