@@ -66,6 +66,7 @@ def stats_markdown(path: str, command: str, top: int = 12, bench_json: str | Non
                 f"{1e3 * r['kernel_ms']:.1f} us over the timed launches (HIP events carried by "
                 f"each launch), {b['ms_per_step'] * 1e3:.1f} us per step, value "
                 f"{b['value']:.3e} {b['unit']}."]
+    out += ["", f"Kernel source hash: {kernel_hash()}"]
     return "\n".join(out) + "\n"
 
 
