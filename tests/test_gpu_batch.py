@@ -164,3 +164,67 @@ def test_graph_replay_equals_direct_launches(ng):
         a.close()
         b.close()
         c.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_of_every_kind_equals_alone(ng, precision):
+    """Twelve seeded solves of every kind in one batch -- 1D and 2D; periodic,
+    wall and outflow ends and section 3's forced source; HLLC and HLL; in
+    FP64 also CSPH-TVD beside MUSCL -- each equal to the same solve run alone
+    (the cooperative path for a lone 1D solve) bit for bit, at its own end
+    time."""
+    prec = {"fp32": ng.NG_FP32, "fp64": ng.NG_FP64}[precision]
+    r = np.random.Generator(np.random.PCG64(12))
+    src_gas = wl.workload_forced_source("linear")["gas"]
+    insts = []
+    for i in range(12):
+        gas = dict(wl.BASE_GAS, tau0=float(r.uniform(0.05, 0.3)),
+                   Q_T=float(r.choice([0.0, 1.0, 2.0])))
+        two_d = i % 4 == 3
+        kind = i % 3
+        src = (0.0, 0.0)
+        if kind == 0:
+            bc = (0, 0, 0, 0)
+        elif kind == 1:
+            bc = (1, 2, 2, 1)
+        else:
+            bc, src, gas = (3, 2, 1, 1), (1e-3, 0.1), src_gas
+        scheme = ng.NG_MUSCL
+        riemann = int(r.integers(0, 2))
+        if prec == ng.NG_FP64 and not two_d and i % 2 == 0:
+            scheme, riemann = ng.NG_CSPH_TVD, ng.NG_HLL
+        if two_d:
+            n = int(r.integers(40, 120))
+            W = wl.random_field_2d(gas, n, r, kmax=6, rms=1e-2)
+            ny = n
+        else:
+            n = int(r.integers(64, 3000))
+            W = wl.multimode_1d(gas, n, r, nmodes=8, kmax=32, sigma=1e-3)
+            ny = 1
+        insts.append(dict(gas=gas, nx=n, ny=ny, W=W, bc=bc, src=src, scheme=scheme,
+                          riemann=riemann, t_end=float(r.uniform(0.002, 0.01))))
+    say(f"batch of every kind, {len(insts)} solves, {precision}")
+    b = ng.Batch(len(insts), arena_bytes(ng, insts, prec), precision=prec)
+    slots = [b.add(i["gas"], i["nx"], i["ny"], i["W"], t_end=i["t_end"], bc=i["bc"],
+                   source=i["src"], scheme=i["scheme"], riemann=i["riemann"]) for i in insts]
+    assert all(s is not None for s in slots)
+    done = set()
+    for _ in range(10000):
+        b.run(32)
+        done.update(b.poll())
+        if len(done) == len(insts):
+            break
+    assert len(done) == len(insts)
+    for k, (inst, slot) in enumerate(zip(insts, slots)):
+        s = ng.Solver(inst["gas"], inst["nx"], inst["ny"], W=inst["W"], precision=prec,
+                      bc=inst["bc"], source=inst["src"], scheme=inst["scheme"],
+                      riemann=inst["riemann"])
+        s.run_to_time(inst["t_end"])
+        Ua, da = s.conserved(), s.diagnostics()
+        s.close()
+        db = b.diagnostics(slot)
+        assert db["status"] == da["status"] == 0, k
+        assert db["t"] == inst["t_end"] == da["t"], k
+        assert db["steps"] == da["steps"], k
+        assert np.array_equal(b.conserved(slot), Ua), (k, inst["nx"], inst["ny"])
+    b.close()
